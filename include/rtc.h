@@ -1,0 +1,206 @@
+/*
+ * rtc.h -- C ABI of the MI355X (gfx950) adaptive-optics real-time-control hot path.
+ *
+ * One frame of a single-conjugate AO real-time controller, as the paper lays it
+ * out (Jenkins, Basden & Myers 2018, "ELT-scale Adaptive Optics real-time
+ * control with the Intel Xeon Phi Many Integrated Core Architecture",
+ * Section 2.1 and the Figure 3 caption):
+ *
+ *   (a) pixel calibration of each active Shack-Hartmann subaperture:
+ *       background (dark) subtraction, flat-field application, threshold;
+ *   (b) centre-of-gravity centroids, written into the slope vector with all x
+ *       gradients first and then all y gradients (subaperture i -> s_i and
+ *       s_{n/2+i});
+ *   (c) reconstruction: control matrix (actuators x slopes) times slope vector
+ *       (Section 1.1.1; Figure 3 (c));
+ *   (d) a gain applied to the reconstruction, here an integrator
+ *       c_k = leak * c_{k-1} + gain * a_k, clamped, giving the DM commands.
+ *
+ * Every step runs in hand-written HIP kernels on the device given at init.
+ *
+ * Conventions
+ *  - All scalars at the boundary are float32.  No HIP or torch types appear:
+ *    streams are passed as `void *` (a hipStream_t, NULL = the null stream).
+ *  - Host arrays passed to rtc_init / rtc_load_* are COPIED; the caller keeps
+ *    ownership.  The library owns its device copies and may re-lay them out.
+ *  - Frame inputs and outputs are caller-owned DEVICE pointers on the context's
+ *    device.  Frame calls are asynchronous on the given stream; completion is
+ *    observed through that stream.
+ *  - Every call returns an rtc_status.  On any error nothing is modified
+ *    (loads validate everything before touching device state).
+ *    rtc_error_string() gives the last error text.
+ *  - A context is not thread-safe: one host thread per context.  Several
+ *    contexts may coexist.  Frame calls on one context must be issued in frame
+ *    order; calls on different streams of the same context race.
+ *
+ * Threshold decision: a pixel is "above" when the exact real number
+ * (raw - dark) * flat - T is > 0 (a tie counts as below).  The device decides it
+ * with one float64 fused multiply-add on float64 (raw - dark), which is exact
+ * because rtc_load_calib only accepts dark values that are 0 or of magnitude
+ * in [2^-13, 2^24) (then raw - dark is representable in float64 for every
+ * 16-bit raw value).
+ */
+#ifndef RTC_H
+#define RTC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RTC_ABI_VERSION 1u
+
+typedef struct rtc_ctx rtc_ctx;
+
+typedef enum {
+  RTC_OK = 0,
+  RTC_E_ARG = -1,          /* invalid argument, size or pointer */
+  RTC_E_STATE = -2,        /* call out of order (e.g. a frame before both loads) */
+  RTC_E_NOMEM = -3,        /* host or device allocation failed */
+  RTC_E_DEVICE = -4,       /* HIP runtime error or no usable device */
+  RTC_E_NONFINITE = -5,    /* NaN/Inf in calibration, threshold, matrix or gains */
+  RTC_E_UNSUPPORTED = -6   /* valid request this build does not implement */
+} rtc_status;
+
+/* Threshold application (Figure 3 (a)); the paper does not fix the rule. */
+typedef enum {
+  RTC_THR_SUBTRACT = 1,    /* v = x - T if x > T else 0 (default) */
+  RTC_THR_ZERO = 2         /* v = x     if x > T else 0 */
+} rtc_thr_mode;
+
+/* Storage type of the control matrix (Section 2.3.4: 16-bit storage halves the
+ * bytes the bandwidth-bound MVM reads).  This build implements RTC_CM_F32. */
+typedef enum {
+  RTC_CM_F32 = 0,
+  RTC_CM_F16 = 1,
+  RTC_CM_BF16 = 2,
+  RTC_CM_FP8E4M3 = 3
+} rtc_cm_dtype;
+
+typedef struct {
+  uint32_t abi_version;        /* must equal RTC_ABI_VERSION */
+  int32_t n_sub_x, n_sub_y;    /* subaperture grid, 1..4096 each */
+  int32_t n_pix;               /* pixels per subaperture side, 1..32; frame is
+                                  H = n_sub_y*n_pix rows x W = n_sub_x*n_pix cols,
+                                  H*W < 2^31 */
+  const uint8_t *subap_mask;   /* host [n_sub_y][n_sub_x] row-major, nonzero =
+                                  active; copied.  Active subapertures are
+                                  numbered k = 0..n_valid-1 row-major; k covers
+                                  rows [sy*n_pix, +n_pix), cols [sx*n_pix, +n_pix) */
+  int32_t n_act;               /* actuators = rows of the control matrix, 1..2^20 */
+  int32_t thr_mode;            /* rtc_thr_mode */
+  int32_t cm_dtype;            /* rtc_cm_dtype; only RTC_CM_F32 here */
+  float gain, leak;            /* integrator g and leak lambda (1 = pure integrator) */
+  float cmd_min, cmd_max;      /* clamp, cmd_min <= cmd_max; +-INFINITY = no clamp */
+  int32_t device;              /* HIP device ordinal */
+} rtc_config;
+
+/* Creates a context on cfg->device: validates cfg, copies the mask, builds the
+ * subaperture index map and allocates the per-frame device buffers.  The
+ * integrator state starts at 0.  *out is set only on RTC_OK.
+ * Errors: RTC_E_ARG (bad sizes, NULL, no active subaperture, wrong ABI
+ * version), RTC_E_NONFINITE (gain/leak/clamp NaN or gain/leak infinite),
+ * RTC_E_UNSUPPORTED (cm_dtype other than F32), RTC_E_DEVICE (no such device),
+ * RTC_E_NOMEM. */
+rtc_status rtc_init(const rtc_config *cfg, rtc_ctx **out);
+
+/* Loads the pixel calibration (Figure 3 (a)): host float32 dark and flat maps
+ * [H][W] row-major (flat multiplies: it holds inverse pixel gains), threshold T
+ * (finite, >= 0, ADU after flat-fielding), and optional reference slopes
+ * ref_slopes [2*n_valid] (x block then y block; NULL = 0) subtracted from the
+ * centroids.  Only the active subapertures' pixels are read (and checked),
+ * re-laid out per subaperture; other pixels of the maps are ignored.
+ * Replaces a previous calibration after synchronising the device.
+ * Errors: RTC_E_ARG (NULL maps, T < 0, dark outside {0} U [2^-13, 2^24) in
+ * magnitude), RTC_E_NONFINITE, RTC_E_DEVICE, RTC_E_NOMEM. */
+rtc_status rtc_load_calib(rtc_ctx *c, const float *dark, const float *flat, float threshold,
+                          const float *ref_slopes);
+
+/* Loads the control matrix R (Section 1.1.1; Figure 3 (c)): host float32,
+ * row-major [n_act][ld], row r holds the weights of actuator r over the slope
+ * vector (x block then y block); n_slopes must equal 2*n_valid, ld >= n_slopes.
+ * The device copy is row-padded to a multiple of 4 floats.  Replaces a
+ * previous matrix (synchronises the device).
+ * Errors: RTC_E_ARG (sizes, NULL), RTC_E_NONFINITE, RTC_E_DEVICE, RTC_E_NOMEM. */
+rtc_status rtc_load_cmat(rtc_ctx *c, const float *R, int32_t n_act, int32_t n_slopes, int64_t ld);
+
+/* One frame (steps (a)-(d)) on a device uint16 frame d_pixels [H][W] row-major.
+ * Writes the new commands c_k to d_cmd [n_act] (float32, device) and advances
+ * the integrator state.  Optional device outputs (NULL = not written):
+ * d_slopes [2*n_valid] float32, d_recon [n_act] float32 (a_k = R s_k),
+ * d_counts [n_valid] int32 (pixels above threshold per subaperture).
+ * Errors: RTC_E_STATE (calibration or matrix not loaded), RTC_E_ARG (NULL
+ * pixels/cmd), RTC_E_DEVICE (launch failure). */
+rtc_status rtc_frame(rtc_ctx *c, const uint16_t *d_pixels, float *d_cmd, float *d_slopes,
+                     float *d_recon, int32_t *d_counts, void *hip_stream);
+
+/* n_frames frames in order, as n_frames calls of rtc_frame: frame f reads
+ * d_pixels + f*frame_stride (elements, >= H*W) and writes row f of each output:
+ * d_cmd [n_frames][n_act] (required), d_slopes [n_frames][2*n_valid],
+ * d_recon [n_frames][n_act], d_counts [n_frames][n_valid] (nullable).
+ * d_ts (nullable) [n_frames][2] uint64 device wall-clock ticks: [0] when the
+ * first calibration workgroup of the frame starts, [1] after the last
+ * reconstruction workgroup's results are visible device-wide; the tick rate is
+ * rtc_wall_clock_khz().  The integrator state carries across frames.
+ * Errors: as rtc_frame, plus RTC_E_ARG for n_frames < 0 or a short stride. */
+rtc_status rtc_frame_batch(rtc_ctx *c, int32_t n_frames, const uint16_t *d_pixels,
+                           int64_t frame_stride, float *d_cmd, float *d_slopes, float *d_recon,
+                           int32_t *d_counts, uint64_t *d_ts, void *hip_stream);
+
+/* Steps (a)-(b) alone: calibration and centre-of-gravity slopes of one frame
+ * into d_slopes [2*n_valid] (required) and d_counts [n_valid] (nullable).
+ * Leaves the integrator state untouched.  Needs the calibration (RTC_E_STATE). */
+rtc_status rtc_calibrate_centroid(rtc_ctx *c, const uint16_t *d_pixels, float *d_slopes,
+                                  int32_t *d_counts, void *hip_stream);
+
+/* Steps (c)-(d) alone from a caller slope vector d_slopes [2*n_valid] (device
+ * float32): a = R s, then the integrator; writes d_cmd [n_act], optional
+ * d_recon [n_act].  Needs the control matrix (RTC_E_STATE). */
+rtc_status rtc_reconstruct_integrate(rtc_ctx *c, const float *d_slopes, float *d_cmd,
+                                     float *d_recon, void *hip_stream);
+
+/* Split of the slope dimension of the reconstruction into k_split partitions
+ * whose partial actuator vectors are summed in a fixed pairwise-tree order
+ * (the paper's tree vector addition, Section 2.3.5).  1 = each actuator row is
+ * summed inside one wavefront (default).  Range 1..64.  Results for any
+ * k_split agree within float32 rounding and are run-to-run deterministic. */
+rtc_status rtc_set_mvm_split(rtc_ctx *c, int32_t k_split);
+
+/* Integrator state: reset to 0, synchronous host copy out / in (n_act floats,
+ * all finite for set).  They synchronise the device first. */
+rtc_status rtc_reset(rtc_ctx *c);
+rtc_status rtc_get_state(rtc_ctx *c, float *h_cmd);
+rtc_status rtc_set_state(rtc_ctx *c, const float *h_cmd);
+
+/* Sizes: active subapertures (= popcount of the mask), actuators. -1 if c NULL. */
+int32_t rtc_n_valid(const rtc_ctx *c);
+int32_t rtc_n_act(const rtc_ctx *c);
+
+/* Frequency of the device wall clock used by rtc_frame_batch time stamps, kHz. */
+rtc_status rtc_wall_clock_khz(rtc_ctx *c, int64_t *khz);
+
+/* Bandwidth probes on the context's device (roofline calibration):
+ * copy n_bytes (multiple of 16) from d_src to d_dst, or read n_bytes of d_src
+ * and write one float checksum to d_out.  Asynchronous on hip_stream. */
+rtc_status rtc_probe_copy(rtc_ctx *c, const void *d_src, void *d_dst, int64_t n_bytes,
+                          void *hip_stream);
+rtc_status rtc_probe_read(rtc_ctx *c, const void *d_src, int64_t n_bytes, float *d_out,
+                          void *hip_stream);
+
+/* Last error text of c (context-local), or of the calling thread's last failed
+ * rtc_init when c is NULL.  Valid until the next call on the same context. */
+const char *rtc_error_string(const rtc_ctx *c);
+
+/* ABI version the library was built with (RTC_ABI_VERSION). */
+uint32_t rtc_abi_version(void);
+
+/* Frees the context and its device memory (synchronises its device first).
+ * NULL is ignored. */
+void rtc_destroy(rtc_ctx *c);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RTC_H */

@@ -1,0 +1,498 @@
+// C-ABI host side of the SH-WFS real-time-control library (declared in include/rtc.h).
+//
+// Validation happens on the host before any device state changes, so every
+// error leaves the context as it was.  Device buffers:
+//   tile_off [n_valid]            int32 element offset of each active tile
+//   calib    [n_valid][n][n]      float2 (dark, flat), active tiles only
+//   ref      [n_s4*4]             float32 reference slopes, zero-padded
+//   R        [n_act][ldr]         float32, ldr = round_up(2 n_valid, 4), zero-padded
+//   s        [n_s4*4]             float32 slope vector of the current frame
+//   state    [n_act]              float32 integrator state
+//   part     [64][n_act]          float32 split-K partial actuator vectors
+//   sync     [4]                  uint32 completion counter
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/rtc.h"
+#include "rtc_kernels.h"
+
+struct rtc_ctx {
+  rtc_config cfg{};
+  int device = 0;
+  int32_t H = 0, W = 0, n_pix = 0, n_valid = 0, n_slopes = 0, n_s4 = 0, n_act = 0;
+  int64_t ldr = 0;
+  std::vector<uint8_t> mask;
+  std::vector<int32_t> tile_off_h;
+  std::string err;
+  int32_t k_split = 1;
+  int64_t wall_khz = 0;
+
+  int32_t *d_tile_off = nullptr;
+  float2 *d_calib = nullptr;
+  float *d_ref = nullptr;
+  float thr = 0.f;
+  float *d_R = nullptr;
+  float *d_s = nullptr;
+  float *d_state = nullptr;
+  float *d_part = nullptr;
+  uint32_t *d_sync = nullptr;
+  bool calib_loaded = false;
+  bool cmat_loaded = false;
+};
+
+namespace {
+
+thread_local std::string g_init_err = "no error";
+
+rtc_status fail(rtc_ctx *c, rtc_status s, const std::string &msg) {
+  if (c) c->err = msg; else g_init_err = msg;
+  return s;
+}
+
+rtc_status hip_fail(rtc_ctx *c, hipError_t e, const char *what) {
+  std::string m = std::string(what) + ": " + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ")";
+  return fail(c, e == hipErrorOutOfMemory ? RTC_E_NOMEM : RTC_E_DEVICE, m);
+}
+
+// Makes the context's device current for the scope and restores the caller's.
+struct DeviceScope {
+  int prev = -1;
+  hipError_t status = hipSuccess;
+  explicit DeviceScope(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    status = hipSetDevice(dev);
+  }
+  ~DeviceScope() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+template <typename T>
+void dfree(T *&p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
+bool dark_in_domain(float d) {
+  // raw - dark is exact in float64 for every raw in [0, 65535] iff this holds.
+  const float a = std::fabs(d);
+  return d == 0.0f || (a >= 0x1p-13f && a < 0x1p24f);
+}
+
+int64_t round_up4(int64_t x) { return (x + 3) & ~int64_t(3); }
+
+}  // namespace
+
+extern "C" {
+
+uint32_t rtc_abi_version(void) { return RTC_ABI_VERSION; }
+
+const char *rtc_error_string(const rtc_ctx *c) {
+  return c ? c->err.c_str() : g_init_err.c_str();
+}
+
+int32_t rtc_n_valid(const rtc_ctx *c) { return c ? c->n_valid : -1; }
+int32_t rtc_n_act(const rtc_ctx *c) { return c ? c->n_act : -1; }
+
+rtc_status rtc_init(const rtc_config *cfg, rtc_ctx **out) {
+  if (!cfg || !out) return fail(nullptr, RTC_E_ARG, "rtc_init: NULL config or output pointer");
+  if (cfg->abi_version != RTC_ABI_VERSION)
+    return fail(nullptr, RTC_E_ARG, "rtc_init: abi_version does not match RTC_ABI_VERSION");
+  if (cfg->n_sub_x < 1 || cfg->n_sub_x > 4096 || cfg->n_sub_y < 1 || cfg->n_sub_y > 4096)
+    return fail(nullptr, RTC_E_ARG, "rtc_init: n_sub_x/n_sub_y must be in 1..4096");
+  if (cfg->n_pix < 1 || cfg->n_pix > 32)
+    return fail(nullptr, RTC_E_ARG, "rtc_init: n_pix must be in 1..32");
+  const int64_t H = (int64_t)cfg->n_sub_y * cfg->n_pix, W = (int64_t)cfg->n_sub_x * cfg->n_pix;
+  if (H * W >= (int64_t(1) << 31)) return fail(nullptr, RTC_E_ARG, "rtc_init: frame has 2^31 or more pixels");
+  if (!cfg->subap_mask) return fail(nullptr, RTC_E_ARG, "rtc_init: subap_mask is NULL");
+  if (cfg->n_act < 1 || cfg->n_act > (1 << 20))
+    return fail(nullptr, RTC_E_ARG, "rtc_init: n_act must be in 1..2^20");
+  if (cfg->thr_mode != RTC_THR_SUBTRACT && cfg->thr_mode != RTC_THR_ZERO)
+    return fail(nullptr, RTC_E_ARG, "rtc_init: thr_mode must be RTC_THR_SUBTRACT or RTC_THR_ZERO");
+  if (cfg->cm_dtype < RTC_CM_F32 || cfg->cm_dtype > RTC_CM_FP8E4M3)
+    return fail(nullptr, RTC_E_ARG, "rtc_init: unknown cm_dtype");
+  if (cfg->cm_dtype != RTC_CM_F32)
+    return fail(nullptr, RTC_E_UNSUPPORTED, "rtc_init: only RTC_CM_F32 control matrices are implemented");
+  if (!std::isfinite(cfg->gain) || !std::isfinite(cfg->leak))
+    return fail(nullptr, RTC_E_NONFINITE, "rtc_init: gain and leak must be finite");
+  if (std::isnan(cfg->cmd_min) || std::isnan(cfg->cmd_max))
+    return fail(nullptr, RTC_E_NONFINITE, "rtc_init: cmd_min/cmd_max must not be NaN");
+  if (!(cfg->cmd_min <= cfg->cmd_max)) return fail(nullptr, RTC_E_ARG, "rtc_init: cmd_min > cmd_max");
+  if (cfg->device < 0) return fail(nullptr, RTC_E_ARG, "rtc_init: device must be >= 0");
+
+  // index map: active subapertures row-major
+  const int64_t ncell = (int64_t)cfg->n_sub_x * cfg->n_sub_y;
+  std::vector<uint8_t> mask(cfg->subap_mask, cfg->subap_mask + ncell);
+  std::vector<int32_t> off;
+  for (int32_t sy = 0; sy < cfg->n_sub_y; ++sy)
+    for (int32_t sx = 0; sx < cfg->n_sub_x; ++sx)
+      if (mask[(int64_t)sy * cfg->n_sub_x + sx])
+        off.push_back((int32_t)((int64_t)sy * cfg->n_pix * W + (int64_t)sx * cfg->n_pix));
+  if (off.empty()) return fail(nullptr, RTC_E_ARG, "rtc_init: the mask has no active subaperture");
+
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess || ndev == 0)
+    return fail(nullptr, RTC_E_DEVICE, std::string("rtc_init: no HIP device available (") +
+                                           (e != hipSuccess ? hipGetErrorName(e) : "count 0") + ")");
+  if (cfg->device >= ndev) return fail(nullptr, RTC_E_DEVICE, "rtc_init: device ordinal out of range");
+
+  rtc_ctx *c = new (std::nothrow) rtc_ctx();
+  if (!c) return fail(nullptr, RTC_E_NOMEM, "rtc_init: host allocation failed");
+  c->cfg = *cfg;
+  c->cfg.subap_mask = nullptr;
+  c->device = cfg->device;
+  c->H = (int32_t)H;
+  c->W = (int32_t)W;
+  c->n_pix = cfg->n_pix;
+  c->n_valid = (int32_t)off.size();
+  c->n_slopes = 2 * c->n_valid;
+  c->ldr = round_up4(c->n_slopes);
+  c->n_s4 = (int32_t)(c->ldr / 4);
+  c->n_act = cfg->n_act;
+  c->mask = std::move(mask);
+  c->tile_off_h = std::move(off);
+
+  DeviceScope ds(c->device);
+  auto bail = [&](hipError_t err, const char *what) {
+    const rtc_status s = hip_fail(nullptr, err, what);
+    rtc_destroy(c);
+    return s;
+  };
+  if (ds.status != hipSuccess) return bail(ds.status, "rtc_init: hipSetDevice");
+  int khz = 0;
+  if ((e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, c->device)) != hipSuccess)
+    return bail(e, "rtc_init: wall clock rate");
+  c->wall_khz = khz;
+  const size_t s_bytes = (size_t)c->ldr * sizeof(float);
+  if ((e = hipMalloc(&c->d_tile_off, c->n_valid * sizeof(int32_t))) != hipSuccess ||
+      (e = hipMalloc(&c->d_ref, s_bytes)) != hipSuccess ||
+      (e = hipMalloc(&c->d_s, s_bytes)) != hipSuccess ||
+      (e = hipMalloc(&c->d_state, c->n_act * sizeof(float))) != hipSuccess ||
+      (e = hipMalloc(&c->d_part, (size_t)rtck::kMaxKSplit * c->n_act * sizeof(float))) != hipSuccess ||
+      (e = hipMalloc(&c->d_sync, 4 * sizeof(uint32_t))) != hipSuccess)
+    return bail(e, "rtc_init: hipMalloc");
+  if ((e = hipMemcpy(c->d_tile_off, c->tile_off_h.data(), c->n_valid * sizeof(int32_t),
+                     hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemset(c->d_ref, 0, s_bytes)) != hipSuccess ||
+      (e = hipMemset(c->d_s, 0, s_bytes)) != hipSuccess ||
+      (e = hipMemset(c->d_state, 0, c->n_act * sizeof(float))) != hipSuccess ||
+      (e = hipMemset(c->d_sync, 0, 4 * sizeof(uint32_t))) != hipSuccess ||
+      (e = hipDeviceSynchronize()) != hipSuccess)
+    return bail(e, "rtc_init: device initialisation");
+  c->err = "no error";
+  *out = c;
+  return RTC_OK;
+}
+
+rtc_status rtc_load_calib(rtc_ctx *c, const float *dark, const float *flat, float threshold,
+                          const float *ref_slopes) {
+  if (!c) return fail(nullptr, RTC_E_ARG, "rtc_load_calib: NULL context");
+  if (!dark || !flat) return fail(c, RTC_E_ARG, "rtc_load_calib: NULL dark or flat map");
+  if (!std::isfinite(threshold)) return fail(c, RTC_E_NONFINITE, "rtc_load_calib: threshold not finite");
+  if (threshold < 0.0f) return fail(c, RTC_E_ARG, "rtc_load_calib: threshold must be >= 0");
+  const int n = c->n_pix;
+  std::vector<float2> cal;
+  try {
+    cal.resize((size_t)c->n_valid * n * n);
+  } catch (...) {
+    return fail(c, RTC_E_NOMEM, "rtc_load_calib: host allocation failed");
+  }
+  for (int32_t k = 0; k < c->n_valid; ++k) {
+    for (int i = 0; i < n; ++i) {
+      const int64_t base = (int64_t)c->tile_off_h[k] + (int64_t)i * c->W;
+      for (int j = 0; j < n; ++j) {
+        const float d = dark[base + j], f = flat[base + j];
+        if (!std::isfinite(d) || !std::isfinite(f))
+          return fail(c, RTC_E_NONFINITE, "rtc_load_calib: non-finite dark or flat value in an active subaperture");
+        if (!dark_in_domain(d))
+          return fail(c, RTC_E_ARG, "rtc_load_calib: dark values must be 0 or of magnitude in [2^-13, 2^24)");
+        cal[((size_t)k * n + i) * n + j] = make_float2(d, f);
+      }
+    }
+  }
+  std::vector<float> ref((size_t)c->ldr, 0.0f);
+  if (ref_slopes) {
+    for (int32_t i = 0; i < c->n_slopes; ++i) {
+      if (!std::isfinite(ref_slopes[i]))
+        return fail(c, RTC_E_NONFINITE, "rtc_load_calib: non-finite reference slope");
+      ref[i] = ref_slopes[i];
+    }
+  }
+  DeviceScope ds(c->device);
+  if (ds.status != hipSuccess) return hip_fail(c, ds.status, "rtc_load_calib: hipSetDevice");
+  float2 *d_cal = nullptr;
+  hipError_t e = hipMalloc(&d_cal, cal.size() * sizeof(float2));
+  if (e != hipSuccess) return hip_fail(c, e, "rtc_load_calib: hipMalloc");
+  // frames already queued keep using the old buffers until the device is idle
+  if ((e = hipDeviceSynchronize()) != hipSuccess ||
+      (e = hipMemcpy(d_cal, cal.data(), cal.size() * sizeof(float2), hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(c->d_ref, ref.data(), ref.size() * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess) {
+    (void)hipFree(d_cal);
+    return hip_fail(c, e, "rtc_load_calib: upload");
+  }
+  dfree(c->d_calib);
+  c->d_calib = d_cal;
+  c->thr = threshold;
+  c->calib_loaded = true;
+  return RTC_OK;
+}
+
+rtc_status rtc_load_cmat(rtc_ctx *c, const float *R, int32_t n_act, int32_t n_slopes, int64_t ld) {
+  if (!c) return fail(nullptr, RTC_E_ARG, "rtc_load_cmat: NULL context");
+  if (!R) return fail(c, RTC_E_ARG, "rtc_load_cmat: NULL matrix");
+  if (n_act != c->n_act) return fail(c, RTC_E_ARG, "rtc_load_cmat: n_act differs from the configuration");
+  if (n_slopes != c->n_slopes) return fail(c, RTC_E_ARG, "rtc_load_cmat: n_slopes must equal 2*n_valid");
+  if (ld < n_slopes) return fail(c, RTC_E_ARG, "rtc_load_cmat: ld < n_slopes");
+  for (int64_t r = 0; r < n_act; ++r) {
+    const float *row = R + r * ld;
+    for (int32_t j = 0; j < n_slopes; ++j)
+      if (!std::isfinite(row[j])) return fail(c, RTC_E_NONFINITE, "rtc_load_cmat: non-finite matrix entry");
+  }
+  DeviceScope ds(c->device);
+  if (ds.status != hipSuccess) return hip_fail(c, ds.status, "rtc_load_cmat: hipSetDevice");
+  float *d_R = nullptr;
+  const size_t bytes = (size_t)n_act * c->ldr * sizeof(float);
+  hipError_t e = hipMalloc(&d_R, bytes);
+  if (e != hipSuccess) return hip_fail(c, e, "rtc_load_cmat: hipMalloc");
+  if ((e = hipDeviceSynchronize()) != hipSuccess ||
+      (e = hipMemset(d_R, 0, bytes)) != hipSuccess ||
+      (e = hipMemcpy2D(d_R, c->ldr * sizeof(float), R, ld * sizeof(float), n_slopes * sizeof(float),
+                       n_act, hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipDeviceSynchronize()) != hipSuccess) {
+    (void)hipFree(d_R);
+    return hip_fail(c, e, "rtc_load_cmat: upload");
+  }
+  dfree(c->d_R);
+  c->d_R = d_R;
+  c->cmat_loaded = true;
+  return RTC_OK;
+}
+
+static rtc_status enqueue_frame(rtc_ctx *c, const uint16_t *pix, float *cmd, float *slopes, float *recon,
+                                int32_t *counts, uint64_t *ts, hipStream_t st, const char *who) {
+  rtck::CalibArgs ca{};
+  ca.pix = pix;
+  ca.W = c->W;
+  ca.tile_off = c->d_tile_off;
+  ca.calib = c->d_calib;
+  ca.n_valid = c->n_valid;
+  ca.n_pix = c->n_pix;
+  ca.thr = c->thr;
+  ca.mode = c->cfg.thr_mode;
+  ca.ref = c->d_ref;
+  ca.s_int = c->d_s;
+  ca.s_user = slopes;
+  ca.counts = counts;
+  ca.ts_start = ts;
+  hipError_t e = rtck::launch_calib_cog(ca, st);
+  if (e != hipSuccess) return hip_fail(c, e, who);
+  rtck::MvmArgs ma{};
+  ma.R = c->d_R;
+  ma.ldr = c->ldr;
+  ma.n_act = c->n_act;
+  ma.n_s4 = c->n_s4;
+  ma.s = c->d_s;
+  ma.k_split = c->k_split;
+  ma.part = c->d_part;
+  ma.state = c->d_state;
+  ma.cmd = cmd;
+  ma.recon = recon;
+  ma.gain = c->cfg.gain;
+  ma.leak = c->cfg.leak;
+  ma.cmd_min = c->cfg.cmd_min;
+  ma.cmd_max = c->cfg.cmd_max;
+  ma.sync = c->d_sync;
+  ma.ts_end = ts ? ts + 1 : nullptr;
+  e = rtck::launch_mvm_integrate(ma, nullptr, st);
+  if (e != hipSuccess) return hip_fail(c, e, who);
+  return RTC_OK;
+}
+
+rtc_status rtc_frame(rtc_ctx *c, const uint16_t *d_pixels, float *d_cmd, float *d_slopes, float *d_recon,
+                     int32_t *d_counts, void *hip_stream) {
+  if (!c) return fail(nullptr, RTC_E_ARG, "rtc_frame: NULL context");
+  if (!c->calib_loaded || !c->cmat_loaded)
+    return fail(c, RTC_E_STATE, "rtc_frame: load the calibration and the control matrix first");
+  if (!d_pixels || !d_cmd) return fail(c, RTC_E_ARG, "rtc_frame: NULL pixels or cmd");
+  DeviceScope ds(c->device);
+  if (ds.status != hipSuccess) return hip_fail(c, ds.status, "rtc_frame: hipSetDevice");
+  return enqueue_frame(c, d_pixels, d_cmd, d_slopes, d_recon, d_counts, nullptr,
+                       static_cast<hipStream_t>(hip_stream), "rtc_frame: launch");
+}
+
+rtc_status rtc_frame_batch(rtc_ctx *c, int32_t n_frames, const uint16_t *d_pixels, int64_t frame_stride,
+                           float *d_cmd, float *d_slopes, float *d_recon, int32_t *d_counts, uint64_t *d_ts,
+                           void *hip_stream) {
+  if (!c) return fail(nullptr, RTC_E_ARG, "rtc_frame_batch: NULL context");
+  if (!c->calib_loaded || !c->cmat_loaded)
+    return fail(c, RTC_E_STATE, "rtc_frame_batch: load the calibration and the control matrix first");
+  if (n_frames < 0) return fail(c, RTC_E_ARG, "rtc_frame_batch: n_frames < 0");
+  if (n_frames == 0) return RTC_OK;
+  if (!d_pixels || !d_cmd) return fail(c, RTC_E_ARG, "rtc_frame_batch: NULL pixels or cmd");
+  if (frame_stride < (int64_t)c->H * c->W)
+    return fail(c, RTC_E_ARG, "rtc_frame_batch: frame_stride shorter than a frame");
+  DeviceScope ds(c->device);
+  if (ds.status != hipSuccess) return hip_fail(c, ds.status, "rtc_frame_batch: hipSetDevice");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  for (int32_t f = 0; f < n_frames; ++f) {
+    rtc_status s = enqueue_frame(c, d_pixels + (int64_t)f * frame_stride, d_cmd + (int64_t)f * c->n_act,
+                                 d_slopes ? d_slopes + (int64_t)f * c->n_slopes : nullptr,
+                                 d_recon ? d_recon + (int64_t)f * c->n_act : nullptr,
+                                 d_counts ? d_counts + (int64_t)f * c->n_valid : nullptr,
+                                 d_ts ? d_ts + 2 * (int64_t)f : nullptr, st, "rtc_frame_batch: launch");
+    if (s != RTC_OK) return s;
+  }
+  return RTC_OK;
+}
+
+rtc_status rtc_calibrate_centroid(rtc_ctx *c, const uint16_t *d_pixels, float *d_slopes, int32_t *d_counts,
+                                  void *hip_stream) {
+  if (!c) return fail(nullptr, RTC_E_ARG, "rtc_calibrate_centroid: NULL context");
+  if (!c->calib_loaded) return fail(c, RTC_E_STATE, "rtc_calibrate_centroid: load the calibration first");
+  if (!d_pixels || !d_slopes) return fail(c, RTC_E_ARG, "rtc_calibrate_centroid: NULL pixels or slopes");
+  DeviceScope ds(c->device);
+  if (ds.status != hipSuccess) return hip_fail(c, ds.status, "rtc_calibrate_centroid: hipSetDevice");
+  rtck::CalibArgs ca{};
+  ca.pix = d_pixels;
+  ca.W = c->W;
+  ca.tile_off = c->d_tile_off;
+  ca.calib = c->d_calib;
+  ca.n_valid = c->n_valid;
+  ca.n_pix = c->n_pix;
+  ca.thr = c->thr;
+  ca.mode = c->cfg.thr_mode;
+  ca.ref = c->d_ref;
+  ca.s_int = d_slopes;     // the caller's vector is the only output
+  ca.s_user = nullptr;
+  ca.counts = d_counts;
+  ca.ts_start = nullptr;
+  hipError_t e = rtck::launch_calib_cog(ca, static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return hip_fail(c, e, "rtc_calibrate_centroid: launch");
+  return RTC_OK;
+}
+
+rtc_status rtc_reconstruct_integrate(rtc_ctx *c, const float *d_slopes, float *d_cmd, float *d_recon,
+                                     void *hip_stream) {
+  if (!c) return fail(nullptr, RTC_E_ARG, "rtc_reconstruct_integrate: NULL context");
+  if (!c->cmat_loaded) return fail(c, RTC_E_STATE, "rtc_reconstruct_integrate: load the control matrix first");
+  if (!d_slopes || !d_cmd) return fail(c, RTC_E_ARG, "rtc_reconstruct_integrate: NULL slopes or cmd");
+  DeviceScope ds(c->device);
+  if (ds.status != hipSuccess) return hip_fail(c, ds.status, "rtc_reconstruct_integrate: hipSetDevice");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const float *s = d_slopes;
+  if ((c->n_slopes & 3) != 0 || (reinterpret_cast<uintptr_t>(d_slopes) & 15) != 0) {
+    // the kernel reads 16-byte vectors of a zero-padded vector: stage a copy
+    hipError_t e = hipMemcpyAsync(c->d_s, d_slopes, c->n_slopes * sizeof(float), hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return hip_fail(c, e, "rtc_reconstruct_integrate: slope copy");
+    s = c->d_s;
+  }
+  rtck::MvmArgs ma{};
+  ma.R = c->d_R;
+  ma.ldr = c->ldr;
+  ma.n_act = c->n_act;
+  ma.n_s4 = c->n_s4;
+  ma.s = s;
+  ma.k_split = c->k_split;
+  ma.part = c->d_part;
+  ma.state = c->d_state;
+  ma.cmd = d_cmd;
+  ma.recon = d_recon;
+  ma.gain = c->cfg.gain;
+  ma.leak = c->cfg.leak;
+  ma.cmd_min = c->cfg.cmd_min;
+  ma.cmd_max = c->cfg.cmd_max;
+  ma.sync = c->d_sync;
+  ma.ts_end = nullptr;
+  hipError_t e = rtck::launch_mvm_integrate(ma, nullptr, st);
+  if (e != hipSuccess) return hip_fail(c, e, "rtc_reconstruct_integrate: launch");
+  return RTC_OK;
+}
+
+rtc_status rtc_set_mvm_split(rtc_ctx *c, int32_t k_split) {
+  if (!c) return fail(nullptr, RTC_E_ARG, "rtc_set_mvm_split: NULL context");
+  if (k_split < 1 || k_split > rtck::kMaxKSplit) return fail(c, RTC_E_ARG, "rtc_set_mvm_split: k_split must be in 1..64");
+  c->k_split = k_split;
+  return RTC_OK;
+}
+
+rtc_status rtc_reset(rtc_ctx *c) {
+  if (!c) return fail(nullptr, RTC_E_ARG, "rtc_reset: NULL context");
+  DeviceScope ds(c->device);
+  hipError_t e = ds.status;
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e == hipSuccess) e = hipMemset(c->d_state, 0, c->n_act * sizeof(float));
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  return e == hipSuccess ? RTC_OK : hip_fail(c, e, "rtc_reset");
+}
+
+rtc_status rtc_get_state(rtc_ctx *c, float *h_cmd) {
+  if (!c) return fail(nullptr, RTC_E_ARG, "rtc_get_state: NULL context");
+  if (!h_cmd) return fail(c, RTC_E_ARG, "rtc_get_state: NULL output");
+  DeviceScope ds(c->device);
+  hipError_t e = ds.status;
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e == hipSuccess) e = hipMemcpy(h_cmd, c->d_state, c->n_act * sizeof(float), hipMemcpyDeviceToHost);
+  return e == hipSuccess ? RTC_OK : hip_fail(c, e, "rtc_get_state");
+}
+
+rtc_status rtc_set_state(rtc_ctx *c, const float *h_cmd) {
+  if (!c) return fail(nullptr, RTC_E_ARG, "rtc_set_state: NULL context");
+  if (!h_cmd) return fail(c, RTC_E_ARG, "rtc_set_state: NULL input");
+  for (int32_t i = 0; i < c->n_act; ++i)
+    if (!std::isfinite(h_cmd[i])) return fail(c, RTC_E_NONFINITE, "rtc_set_state: non-finite value");
+  DeviceScope ds(c->device);
+  hipError_t e = ds.status;
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e == hipSuccess) e = hipMemcpy(c->d_state, h_cmd, c->n_act * sizeof(float), hipMemcpyHostToDevice);
+  return e == hipSuccess ? RTC_OK : hip_fail(c, e, "rtc_set_state");
+}
+
+rtc_status rtc_wall_clock_khz(rtc_ctx *c, int64_t *khz) {
+  if (!c) return fail(nullptr, RTC_E_ARG, "rtc_wall_clock_khz: NULL context");
+  if (!khz) return fail(c, RTC_E_ARG, "rtc_wall_clock_khz: NULL output");
+  *khz = c->wall_khz;
+  return RTC_OK;
+}
+
+rtc_status rtc_probe_copy(rtc_ctx *c, const void *d_src, void *d_dst, int64_t n_bytes, void *hip_stream) {
+  if (!c) return fail(nullptr, RTC_E_ARG, "rtc_probe_copy: NULL context");
+  if (!d_src || !d_dst || n_bytes < 0 || (n_bytes & 15))
+    return fail(c, RTC_E_ARG, "rtc_probe_copy: NULL pointer or size not a multiple of 16");
+  DeviceScope ds(c->device);
+  if (ds.status != hipSuccess) return hip_fail(c, ds.status, "rtc_probe_copy: hipSetDevice");
+  hipError_t e = rtck::launch_probe_copy(d_src, d_dst, n_bytes, static_cast<hipStream_t>(hip_stream));
+  return e == hipSuccess ? RTC_OK : hip_fail(c, e, "rtc_probe_copy: launch");
+}
+
+rtc_status rtc_probe_read(rtc_ctx *c, const void *d_src, int64_t n_bytes, float *d_out, void *hip_stream) {
+  if (!c) return fail(nullptr, RTC_E_ARG, "rtc_probe_read: NULL context");
+  if (!d_src || !d_out || n_bytes < 0 || (n_bytes & 15))
+    return fail(c, RTC_E_ARG, "rtc_probe_read: NULL pointer or size not a multiple of 16");
+  DeviceScope ds(c->device);
+  if (ds.status != hipSuccess) return hip_fail(c, ds.status, "rtc_probe_read: hipSetDevice");
+  hipError_t e = rtck::launch_probe_read(d_src, n_bytes, d_out, static_cast<hipStream_t>(hip_stream));
+  return e == hipSuccess ? RTC_OK : hip_fail(c, e, "rtc_probe_read: launch");
+}
+
+void rtc_destroy(rtc_ctx *c) {
+  if (!c) return;
+  DeviceScope ds(c->device);
+  if (ds.status == hipSuccess) (void)hipDeviceSynchronize();
+  dfree(c->d_tile_off);
+  dfree(c->d_calib);
+  dfree(c->d_ref);
+  dfree(c->d_R);
+  dfree(c->d_s);
+  dfree(c->d_state);
+  dfree(c->d_part);
+  dfree(c->d_sync);
+  delete c;
+}
+
+}  // extern "C"

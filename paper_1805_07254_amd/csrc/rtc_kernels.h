@@ -1,0 +1,53 @@
+// Internal interface between the C-ABI host code and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rtck {
+
+// Steps (a)-(b): calibration + centre of gravity of every active subaperture.
+struct CalibArgs {
+  const uint16_t *pix;     // [H][W] frame
+  int32_t W;               // frame row length (elements)
+  const int32_t *tile_off; // [n_valid] element offset of each tile's top-left pixel
+  const float2 *calib;     // [n_valid][n_pix][n_pix] (dark, flat)
+  int32_t n_valid;
+  int32_t n_pix;
+  float thr;
+  int32_t mode;            // 1 = subtract, 2 = zero
+  const float *ref;        // [2 n_valid] reference slopes
+  float *s_int;            // [>= 2 n_valid] library slope buffer
+  float *s_user;           // nullable copy
+  int32_t *counts;         // nullable [n_valid]
+  uint64_t *ts_start;      // nullable: written by block 0 on entry
+};
+hipError_t launch_calib_cog(const CalibArgs &a, hipStream_t st);
+
+// Steps (c)-(d): a = R s, then c = clamp(leak c + gain a).
+struct MvmArgs {
+  const float *R;          // [n_act][ldr], ldr % 4 == 0, 16-byte aligned
+  int64_t ldr;
+  int32_t n_act;
+  int32_t n_s4;            // slope vector length / 4 (zero-padded)
+  const float *s;          // [4 n_s4], 16-byte aligned
+  int32_t k_split;         // partitions of the slope dimension (1 = fused epilogue)
+  float *part;             // [k_split][n_act] partial sums (k_split > 1)
+  float *state;            // [n_act] integrator state (read and updated)
+  float *cmd;              // [n_act] commands out
+  float *recon;            // nullable [n_act] a = R s
+  float gain, leak, cmd_min, cmd_max;
+  uint32_t *sync;          // completion counter (0 between launches)
+  uint64_t *ts_end;        // nullable: written after the last workgroup's results
+};
+// Returns the number of slope partitions actually used (<= k_split) in *used.
+hipError_t launch_mvm_integrate(const MvmArgs &a, int32_t *used, hipStream_t st);
+
+// Roofline probes.
+hipError_t launch_probe_copy(const void *src, void *dst, int64_t n_bytes, hipStream_t st);
+hipError_t launch_probe_read(const void *src, int64_t n_bytes, float *out, hipStream_t st);
+
+constexpr int kMaxKSplit = 64;
+constexpr int kMaxChunk4 = 4096;   // slope floats staged in LDS per workgroup / 4 (64 KiB)
+
+}  // namespace rtck

@@ -1,0 +1,301 @@
+"""Thin ctypes binding of ``librtc.so`` (C ABI in ``include/rtc.h``).
+
+Same entry-point names as the C library; the wrappers only check and marshal
+arguments (host arrays -> pointers, device tensors -> ``data_ptr()``, torch
+streams -> ``hipStream_t``).  Every step of the frame runs in the library's HIP
+kernels; there is no host fallback: if ``librtc.so`` is missing, loading fails.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librtc.so")
+
+RTC_ABI_VERSION = 1
+RTC_OK, RTC_E_ARG, RTC_E_STATE, RTC_E_NOMEM, RTC_E_DEVICE, RTC_E_NONFINITE, RTC_E_UNSUPPORTED = \
+    0, -1, -2, -3, -4, -5, -6
+RTC_THR_SUBTRACT, RTC_THR_ZERO = 1, 2
+RTC_CM_F32, RTC_CM_F16, RTC_CM_BF16, RTC_CM_FP8E4M3 = 0, 1, 2, 3
+STATUS_NAMES = {0: "RTC_OK", -1: "RTC_E_ARG", -2: "RTC_E_STATE", -3: "RTC_E_NOMEM",
+                -4: "RTC_E_DEVICE", -5: "RTC_E_NONFINITE", -6: "RTC_E_UNSUPPORTED"}
+
+
+class RtcError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class rtc_config(ctypes.Structure):
+    _fields_ = [("abi_version", ctypes.c_uint32), ("n_sub_x", ctypes.c_int32), ("n_sub_y", ctypes.c_int32),
+                ("n_pix", ctypes.c_int32), ("subap_mask", ctypes.POINTER(ctypes.c_uint8)),
+                ("n_act", ctypes.c_int32), ("thr_mode", ctypes.c_int32), ("cm_dtype", ctypes.c_int32),
+                ("gain", ctypes.c_float), ("leak", ctypes.c_float), ("cmd_min", ctypes.c_float),
+                ("cmd_max", ctypes.c_float), ("device", ctypes.c_int32)]
+
+
+_vp, _i32, _i64, _f32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_float
+_SIGNATURES = {
+    "rtc_init": (_i32, [ctypes.POINTER(rtc_config), ctypes.POINTER(_vp)]),
+    "rtc_load_calib": (_i32, [_vp, _vp, _vp, _f32, _vp]),
+    "rtc_load_cmat": (_i32, [_vp, _vp, _i32, _i32, _i64]),
+    "rtc_frame": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "rtc_frame_batch": (_i32, [_vp, _i32, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "rtc_calibrate_centroid": (_i32, [_vp, _vp, _vp, _vp, _vp]),
+    "rtc_reconstruct_integrate": (_i32, [_vp, _vp, _vp, _vp, _vp]),
+    "rtc_set_mvm_split": (_i32, [_vp, _i32]),
+    "rtc_reset": (_i32, [_vp]),
+    "rtc_get_state": (_i32, [_vp, _vp]),
+    "rtc_set_state": (_i32, [_vp, _vp]),
+    "rtc_n_valid": (_i32, [_vp]),
+    "rtc_n_act": (_i32, [_vp]),
+    "rtc_wall_clock_khz": (_i32, [_vp, ctypes.POINTER(_i64)]),
+    "rtc_probe_copy": (_i32, [_vp, _vp, _vp, _i64, _vp]),
+    "rtc_probe_read": (_i32, [_vp, _vp, _i64, _vp, _vp]),
+    "rtc_error_string": (ctypes.c_char_p, [_vp]),
+    "rtc_abi_version": (ctypes.c_uint32, []),
+    "rtc_destroy": (None, [_vp]),
+}
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Loads librtc.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise RuntimeError(f"{path} is missing: build it with paper_1805_07254_amd.build.build()")
+        lib = ctypes.CDLL(path)
+        for name, (res, args) in _SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        if lib.rtc_abi_version() != RTC_ABI_VERSION:
+            raise RuntimeError("librtc.so ABI version mismatch")
+        _lib = lib
+    return _lib
+
+
+class RtcContext:
+    """Owning handle of an ``rtc_ctx*``; freed by :meth:`close` or garbage collection."""
+
+    def __init__(self, handle: int, cfg: dict):
+        self.handle = ctypes.c_void_p(handle)
+        self.cfg = cfg
+        lib = load_library()
+        self.n_valid = lib.rtc_n_valid(self.handle)
+        self.n_act = lib.rtc_n_act(self.handle)
+        self.n_slopes = 2 * self.n_valid
+        self.H = cfg["n_sub_y"] * cfg["n_pix"]
+        self.W = cfg["n_sub_x"] * cfg["n_pix"]
+
+    def close(self):
+        if self.handle is not None and self.handle.value:
+            load_library().rtc_destroy(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def _check(status: int, ctx: Optional[RtcContext]):
+    if status != RTC_OK:
+        msg = load_library().rtc_error_string(ctx.handle if ctx is not None else None)
+        raise RtcError(status, msg.decode() if msg else "")
+
+
+def _host_ptr(a: Optional[np.ndarray], dtype) -> tuple[Optional[np.ndarray], Optional[int]]:
+    if a is None:
+        return None, None
+    arr = np.ascontiguousarray(a, dtype=dtype)
+    return arr, arr.ctypes.data
+
+
+def _dev_ptr(t, dtype_name, numel: int, what: str, ctx: RtcContext, required=True):
+    """Device pointer of a torch tensor after checking dtype, device, contiguity and size.
+
+    ``dtype_name`` is a torch dtype name or a tuple of accepted names (same-width
+    integer types are interchangeable at the C boundary).  A plain int is taken
+    as a raw device address.
+    """
+    if t is None:
+        if required:
+            raise ValueError(f"{what} is required")
+        return None
+    if isinstance(t, int):
+        return t
+    import torch
+    names = (dtype_name,) if isinstance(dtype_name, str) else tuple(dtype_name)
+    if t.dtype not in tuple(getattr(torch, n) for n in names):
+        raise TypeError(f"{what} must be {' or '.join(names)}, got {t.dtype}")
+    if t.device.type != "cuda" or t.device.index != ctx.cfg["device"]:
+        raise ValueError(f"{what} must live on cuda:{ctx.cfg['device']}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    if t.numel() < numel:
+        raise ValueError(f"{what} has {t.numel()} elements, needs {numel}")
+    return t.data_ptr()
+
+
+def _stream_ptr(stream) -> Optional[int]:
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+# --------------------------------------------------------------------------- API
+def rtc_init(subap_mask: np.ndarray, n_pix: int, n_act: int, thr_mode: int = RTC_THR_SUBTRACT,
+             cm_dtype: int = RTC_CM_F32, gain: float = 0.4, leak: float = 1.0,
+             cmd_min: float = -math.inf, cmd_max: float = math.inf, device: int = 0,
+             abi_version: int = RTC_ABI_VERSION) -> RtcContext:
+    lib = load_library()
+    mask = np.ascontiguousarray(subap_mask, dtype=np.uint8)
+    if mask.ndim != 2:
+        raise ValueError("subap_mask must be 2-D [n_sub_y, n_sub_x]")
+    cfg = rtc_config(abi_version, mask.shape[1], mask.shape[0], n_pix,
+                     mask.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), n_act, thr_mode, cm_dtype,
+                     gain, leak, cmd_min, cmd_max, device)
+    out = ctypes.c_void_p()
+    st = lib.rtc_init(ctypes.byref(cfg), ctypes.byref(out))
+    _check(st, None)
+    return RtcContext(out.value, {"n_sub_x": mask.shape[1], "n_sub_y": mask.shape[0], "n_pix": n_pix,
+                                  "n_act": n_act, "device": device, "thr_mode": thr_mode,
+                                  "gain": gain, "leak": leak})
+
+
+def rtc_load_calib(ctx: RtcContext, dark: np.ndarray, flat: np.ndarray, threshold: float,
+                   ref_slopes: Optional[np.ndarray] = None) -> None:
+    d, dp = _host_ptr(dark, np.float32)
+    f, fp = _host_ptr(flat, np.float32)
+    if d.size != ctx.H * ctx.W or f.size != ctx.H * ctx.W:
+        raise ValueError(f"dark/flat must have {ctx.H}x{ctx.W} elements")
+    r, rp = _host_ptr(ref_slopes, np.float32)
+    if r is not None and r.size != ctx.n_slopes:
+        raise ValueError(f"ref_slopes must have {ctx.n_slopes} elements")
+    _check(load_library().rtc_load_calib(ctx.handle, dp, fp, threshold, rp), ctx)
+
+
+def rtc_load_cmat(ctx: RtcContext, R: np.ndarray, n_slopes: Optional[int] = None) -> None:
+    """R: host [n_act, ld] float32 rows; the first ``n_slopes`` (default ld) columns are used."""
+    m, mp = _host_ptr(R, np.float32)
+    if m.ndim != 2:
+        raise ValueError("R must be 2-D [n_act, ld]")
+    ns = m.shape[1] if n_slopes is None else int(n_slopes)
+    _check(load_library().rtc_load_cmat(ctx.handle, mp, m.shape[0], ns, m.shape[1]), ctx)
+
+
+def rtc_frame(ctx: RtcContext, pixels, cmd, slopes=None, recon=None, counts=None, stream=None) -> None:
+    lib = load_library()
+    _check(lib.rtc_frame(ctx.handle,
+                         _dev_ptr(pixels, "uint16", ctx.H * ctx.W, "pixels", ctx),
+                         _dev_ptr(cmd, "float32", ctx.n_act, "cmd", ctx),
+                         _dev_ptr(slopes, "float32", ctx.n_slopes, "slopes", ctx, False),
+                         _dev_ptr(recon, "float32", ctx.n_act, "recon", ctx, False),
+                         _dev_ptr(counts, "int32", ctx.n_valid, "counts", ctx, False),
+                         _stream_ptr(stream)), ctx)
+
+
+def rtc_frame_batch(ctx: RtcContext, n_frames: int, pixels, cmd, slopes=None, recon=None, counts=None,
+                    ts=None, frame_stride: Optional[int] = None, stream=None) -> None:
+    stride = ctx.H * ctx.W if frame_stride is None else frame_stride
+    need = 0 if n_frames == 0 else (n_frames - 1) * stride + ctx.H * ctx.W
+    _check(load_library().rtc_frame_batch(
+        ctx.handle, n_frames,
+        _dev_ptr(pixels, "uint16", need, "pixels", ctx),
+        stride,
+        _dev_ptr(cmd, "float32", n_frames * ctx.n_act, "cmd", ctx),
+        _dev_ptr(slopes, "float32", n_frames * ctx.n_slopes, "slopes", ctx, False),
+        _dev_ptr(recon, "float32", n_frames * ctx.n_act, "recon", ctx, False),
+        _dev_ptr(counts, "int32", n_frames * ctx.n_valid, "counts", ctx, False),
+        _dev_ptr(ts, ("uint64", "int64"), 2 * n_frames, "ts", ctx, False),
+        _stream_ptr(stream)), ctx)
+
+
+def rtc_calibrate_centroid(ctx: RtcContext, pixels, slopes, counts=None, stream=None) -> None:
+    _check(load_library().rtc_calibrate_centroid(
+        ctx.handle, _dev_ptr(pixels, "uint16", ctx.H * ctx.W, "pixels", ctx),
+        _dev_ptr(slopes, "float32", ctx.n_slopes, "slopes", ctx),
+        _dev_ptr(counts, "int32", ctx.n_valid, "counts", ctx, False), _stream_ptr(stream)), ctx)
+
+
+def rtc_reconstruct_integrate(ctx: RtcContext, slopes, cmd, recon=None, stream=None) -> None:
+    _check(load_library().rtc_reconstruct_integrate(
+        ctx.handle, _dev_ptr(slopes, "float32", ctx.n_slopes, "slopes", ctx),
+        _dev_ptr(cmd, "float32", ctx.n_act, "cmd", ctx),
+        _dev_ptr(recon, "float32", ctx.n_act, "recon", ctx, False), _stream_ptr(stream)), ctx)
+
+
+def rtc_set_mvm_split(ctx: RtcContext, k_split: int) -> None:
+    _check(load_library().rtc_set_mvm_split(ctx.handle, k_split), ctx)
+
+
+def rtc_reset(ctx: RtcContext) -> None:
+    _check(load_library().rtc_reset(ctx.handle), ctx)
+
+
+def rtc_get_state(ctx: RtcContext) -> np.ndarray:
+    out = np.empty(ctx.n_act, dtype=np.float32)
+    _check(load_library().rtc_get_state(ctx.handle, out.ctypes.data), ctx)
+    return out
+
+
+def rtc_set_state(ctx: RtcContext, cmd: np.ndarray) -> None:
+    c, cp = _host_ptr(cmd, np.float32)
+    if c.size != ctx.n_act:
+        raise ValueError(f"state must have {ctx.n_act} elements")
+    _check(load_library().rtc_set_state(ctx.handle, cp), ctx)
+
+
+def rtc_wall_clock_khz(ctx: RtcContext) -> int:
+    out = ctypes.c_int64()
+    _check(load_library().rtc_wall_clock_khz(ctx.handle, ctypes.byref(out)), ctx)
+    return out.value
+
+
+def rtc_probe_copy(ctx: RtcContext, src, dst, n_bytes: int, stream=None) -> None:
+    _check(load_library().rtc_probe_copy(ctx.handle, src.data_ptr(), dst.data_ptr(), n_bytes,
+                                         _stream_ptr(stream)), ctx)
+
+
+def rtc_probe_read(ctx: RtcContext, src, n_bytes: int, out, stream=None) -> None:
+    _check(load_library().rtc_probe_read(ctx.handle, src.data_ptr(), n_bytes, out.data_ptr(),
+                                         _stream_ptr(stream)), ctx)
+
+
+def rtc_n_valid(ctx: RtcContext) -> int:
+    return load_library().rtc_n_valid(ctx.handle)
+
+
+def rtc_n_act(ctx: RtcContext) -> int:
+    return load_library().rtc_n_act(ctx.handle)
+
+
+def rtc_error_string(ctx: Optional[RtcContext]) -> str:
+    s = load_library().rtc_error_string(ctx.handle if ctx is not None else None)
+    return s.decode() if s else ""
+
+
+def rtc_abi_version() -> int:
+    return load_library().rtc_abi_version()
+
+
+def rtc_destroy(ctx: RtcContext) -> None:
+    ctx.close()

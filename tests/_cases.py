@@ -4,22 +4,26 @@ from __future__ import annotations
 import numpy as np
 
 
-def near_tie_pixels(seed: int = 7, n_candidates: int = 400000):
-    """Pixels whose calibrated value lies within ~1e-11 ADU of the threshold.
+def near_tie_pixels(seed: int = 7, n_candidates: int = 400000, T: float | None = None,
+                    flat_range=(0.9, 1.1)):
+    """Pixels whose calibrated value lies within ~1e-11 relative of the threshold.
 
-    For random float32 T and flat, raw = ceil(T / flat) and dark = raw - T / flat
-    rounded to float32, kept where 2^-13 <= dark < 2^-12 (inside the domain where
-    raw - dark is exact in float64).  Returns (raw uint16, dark f32, flat f32, T f32)
-    1-D arrays; each pixel carries its own T.
+    For float32 T (random per pixel, or the given fixed value) and random float32
+    flat, raw = ceil(T / flat) and dark = raw - T / flat rounded to float32, kept
+    where 2^-13 <= dark < 2^-12 (inside the domain where raw - dark is exact in
+    float64).  Returns (raw uint16, dark f32, flat f32, T f32) 1-D arrays.
     """
     rng = np.random.default_rng(seed)
-    T = rng.uniform(1000, 60000, n_candidates).astype(np.float32)
-    flat = rng.uniform(0.9, 1.1, n_candidates).astype(np.float32)
-    dstar = T.astype(np.float64) / flat.astype(np.float64)
+    if T is None:
+        Tv = rng.uniform(1000, 60000, n_candidates).astype(np.float32)
+    else:
+        Tv = np.full(n_candidates, T, dtype=np.float32)
+    flat = rng.uniform(flat_range[0], flat_range[1], n_candidates).astype(np.float32)
+    dstar = Tv.astype(np.float64) / flat.astype(np.float64)
     raw = np.ceil(dstar)
     dark = raw - dstar
     ok = (dark >= 2.0 ** -13) & (dark < 2.0 ** -12) & (raw <= 65535)
-    return (raw[ok].astype(np.uint16), dark[ok].astype(np.float32), flat[ok], T[ok])
+    return (raw[ok].astype(np.uint16), dark[ok].astype(np.float32), flat[ok], Tv[ok])
 
 
 def pixel_integrated_gaussian(n: int, offset: float, sigma: float) -> np.ndarray:

@@ -46,7 +46,12 @@ def parse():
     p.add_argument("--steps", type=int, default=10000)
     p.add_argument("--warmup", type=int, default=500)
     p.add_argument("--ring", type=int, default=128, help="distinct raw frames kept on the device")
+    p.add_argument("--mvm-kernel", type=int, default=0, help="0 = row-block, 1 = streamed")
     p.add_argument("--k-split", type=int, default=1)
+    p.add_argument("--rows-per-wave", type=int, default=2)
+    p.add_argument("--unroll", type=int, default=4)
+    p.add_argument("--blocks", type=int, default=0)
+    p.add_argument("--waves", type=int, default=8)
     p.add_argument("--kernel-reps", type=int, default=2000)
     p.add_argument("--cpu-seconds", type=float, default=15.0)
     p.add_argument("--no-cpu", action="store_true")
@@ -110,7 +115,9 @@ def main():
     ctx = rtc.rtc_init(sc.mask, cfg.n_pix, sc.n_act, gain=cfg.gain, leak=cfg.leak)
     rtc.rtc_load_calib(ctx, sc.dark, sc.flat, cfg.threshold)
     rtc.rtc_load_cmat(ctx, R)
-    rtc.rtc_set_mvm_split(ctx, args.k_split)
+    tuning = dict(kernel=args.mvm_kernel, k_split=args.k_split, rows_per_wave=args.rows_per_wave,
+                  unroll=args.unroll, blocks=args.blocks, waves=args.waves)
+    rtc.rtc_set_mvm_tuning(ctx, **tuning)
     khz = rtc.rtc_wall_clock_khz(ctx)
     dev_ring = torch.from_numpy(ring.reshape(args.ring, -1).view(np.int16)).to("cuda:0").view(torch.uint16)
     npx = cfg.frame_side * cfg.frame_side
@@ -188,7 +195,19 @@ def main():
         us = ev0.elapsed_time(ev1) * 1e3 / reps
         probes[label] = round(nbytes / us / 1e3, 1)
         del buf
-    log(f"read probes GB/s: {probes}")
+    # plain copy of known size: the reference for scaling HBM byte counters
+    copy_bytes = 256 << 20
+    src = torch.empty(copy_bytes // 4, dtype=torch.float32, device="cuda:0").fill_(1.0)
+    dst = torch.empty_like(src)
+    rtc.rtc_probe_copy(ctx, src, dst, copy_bytes, stream=stream)
+    ev0.record(stream)
+    for _ in range(10):
+        rtc.rtc_probe_copy(ctx, src, dst, copy_bytes, stream=stream)
+    ev1.record(stream)
+    ev1.synchronize()
+    probes["copy_256MiB"] = round(2 * copy_bytes / (ev0.elapsed_time(ev1) * 1e3 / 10) / 1e3, 1)
+    del src, dst
+    log(f"read/copy probes GB/s: {probes}")
 
     traffic = None
     if os.path.exists(PROFILE_TRAFFIC):
@@ -218,7 +237,7 @@ def main():
                         f"obscuration {cfg.obscuration}, {sc.n_valid} subapertures, {2 * sc.n_valid} slopes, "
                         f"{sc.n_act} actuators, FP32 control matrix {R.nbytes / 1e6:.1f} MB",
             "frames_ring": args.ring,
-            "k_split": args.k_split,
+            "mvm_tuning": tuning,
             "frame_data": "open-loop frozen-flow von Karman frames (r0 0.15 m, L0 25 m, 10 m/s)",
         },
         "frame_period_us": st_period,

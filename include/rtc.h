@@ -160,12 +160,37 @@ rtc_status rtc_calibrate_centroid(rtc_ctx *c, const uint16_t *d_pixels, float *d
 rtc_status rtc_reconstruct_integrate(rtc_ctx *c, const float *d_slopes, float *d_cmd,
                                      float *d_recon, void *hip_stream);
 
-/* Split of the slope dimension of the reconstruction into k_split partitions
- * whose partial actuator vectors are summed in a fixed pairwise-tree order
- * (the paper's tree vector addition, Section 2.3.5).  1 = each actuator row is
- * summed inside one wavefront (default).  Range 1..64.  Results for any
- * k_split agree within float32 rounding and are run-to-run deterministic. */
-rtc_status rtc_set_mvm_split(rtc_ctx *c, int32_t k_split);
+/* Launch shape of the reconstruction (step (c)), for tuning.  Two kernels:
+ *  kernel = RTC_MVM_ROWBLOCK (default): workgroup b owns a contiguous range of
+ *    actuator rows; its `waves` wavefronts (8 or 16) split the slope vector and
+ *    keep their slice in registers; `rows_per_batch` rows (1..8) are streamed
+ *    per batch; `blocks` workgroups (0 = one per compute unit).  Needs the
+ *    slope vector to fit 8 x 64 x waves x 4 floats; otherwise the streamed
+ *    kernel is used automatically.
+ *  kernel = RTC_MVM_STREAMED: each wavefront streams `rows_per_wave` (1, 2, 4)
+ *    rows against the slope vector staged in LDS, with `unroll` (2, 4, 8; 8
+ *    only with rows_per_wave <= 2) 16-byte loads per row in flight, and the
+ *    slope dimension split into `k_split` (1..64) partitions whose partial
+ *    actuator vectors are summed in a fixed pairwise-tree order (the paper's
+ *    tree vector addition, Section 2.3.5).  k_split is raised automatically
+ *    when a partition's slopes would not fit 64 KiB of LDS.
+ * Results of every shape agree within float32 rounding and each shape is
+ * run-to-run deterministic (no floating-point atomics).
+ * Default: {RTC_MVM_ROWBLOCK, k_split 1, rows_per_wave 2, unroll 4, blocks 0,
+ * waves 8}, the fastest shape measured at the ELT size. */
+typedef enum { RTC_MVM_ROWBLOCK = 0, RTC_MVM_STREAMED = 1 } rtc_mvm_kernel;
+
+typedef struct {
+  int32_t kernel;          /* rtc_mvm_kernel */
+  int32_t k_split;         /* streamed */
+  int32_t rows_per_wave;   /* streamed: rows per wavefront; row-block: rows per batch */
+  int32_t unroll;          /* streamed */
+  int32_t blocks;          /* row-block: workgroups, 0 = compute-unit count */
+  int32_t waves;           /* row-block: wavefronts per workgroup, 8 or 16 */
+} rtc_mvm_tuning;
+
+rtc_status rtc_set_mvm_tuning(rtc_ctx *c, const rtc_mvm_tuning *t);
+rtc_status rtc_get_mvm_tuning(const rtc_ctx *c, rtc_mvm_tuning *t);
 
 /* Integrator state: reset to 0, synchronous host copy out / in (n_act floats,
  * all finite for set).  They synchronise the device first. */

@@ -29,7 +29,8 @@ struct rtc_ctx {
   std::vector<uint8_t> mask;
   std::vector<int32_t> tile_off_h;
   std::string err;
-  int32_t k_split = 1;
+  rtc_mvm_tuning tuning{RTC_MVM_ROWBLOCK, 1, 2, 4, 0, 8};
+  int32_t n_cu = 0;
   int64_t wall_khz = 0;
 
   int32_t *d_tile_off = nullptr;
@@ -169,6 +170,10 @@ rtc_status rtc_init(const rtc_config *cfg, rtc_ctx **out) {
   if ((e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, c->device)) != hipSuccess)
     return bail(e, "rtc_init: wall clock rate");
   c->wall_khz = khz;
+  int ncu = 0;
+  if ((e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device)) != hipSuccess)
+    return bail(e, "rtc_init: compute-unit count");
+  c->n_cu = ncu;
   const size_t s_bytes = (size_t)c->ldr * sizeof(float);
   if ((e = hipMalloc(&c->d_tile_off, c->n_valid * sizeof(int32_t))) != hipSuccess ||
       (e = hipMalloc(&c->d_ref, s_bytes)) != hipSuccess ||
@@ -274,6 +279,23 @@ rtc_status rtc_load_cmat(rtc_ctx *c, const float *R, int32_t n_act, int32_t n_sl
   return RTC_OK;
 }
 
+// Step (c)-(d) with the context's tuning; the row-block kernel falls back to
+// the streamed kernel when the slope vector is too long for its registers.
+static hipError_t launch_reconstruction(const rtc_ctx *c, rtck::MvmArgs ma, hipStream_t st) {
+  const rtc_mvm_tuning &t = c->tuning;
+  if (t.kernel == RTC_MVM_ROWBLOCK) {
+    const int kc = (c->n_s4 + t.waves - 1) / t.waves;
+    if ((kc + 63) / 64 <= rtck::mvm_block_max_kpl()) {
+      ma.k_split = 1;
+      return rtck::launch_mvm_block(ma, t.blocks > 0 ? t.blocks : c->n_cu, t.waves, t.rows_per_wave, st);
+    }
+    ma.k_split = 1;
+    ma.rows_per_wave = 2;
+    ma.unroll = 4;
+  }
+  return rtck::launch_mvm_integrate(ma, nullptr, st);
+}
+
 static rtc_status enqueue_frame(rtc_ctx *c, const uint16_t *pix, float *cmd, float *slopes, float *recon,
                                 int32_t *counts, uint64_t *ts, hipStream_t st, const char *who) {
   rtck::CalibArgs ca{};
@@ -298,7 +320,9 @@ static rtc_status enqueue_frame(rtc_ctx *c, const uint16_t *pix, float *cmd, flo
   ma.n_act = c->n_act;
   ma.n_s4 = c->n_s4;
   ma.s = c->d_s;
-  ma.k_split = c->k_split;
+  ma.k_split = c->tuning.k_split;
+  ma.rows_per_wave = c->tuning.rows_per_wave;
+  ma.unroll = c->tuning.unroll;
   ma.part = c->d_part;
   ma.state = c->d_state;
   ma.cmd = cmd;
@@ -309,7 +333,7 @@ static rtc_status enqueue_frame(rtc_ctx *c, const uint16_t *pix, float *cmd, flo
   ma.cmd_max = c->cfg.cmd_max;
   ma.sync = c->d_sync;
   ma.ts_end = ts ? ts + 1 : nullptr;
-  e = rtck::launch_mvm_integrate(ma, nullptr, st);
+  e = launch_reconstruction(c, ma, st);
   if (e != hipSuccess) return hip_fail(c, e, who);
   return RTC_OK;
 }
@@ -398,7 +422,9 @@ rtc_status rtc_reconstruct_integrate(rtc_ctx *c, const float *d_slopes, float *d
   ma.n_act = c->n_act;
   ma.n_s4 = c->n_s4;
   ma.s = s;
-  ma.k_split = c->k_split;
+  ma.k_split = c->tuning.k_split;
+  ma.rows_per_wave = c->tuning.rows_per_wave;
+  ma.unroll = c->tuning.unroll;
   ma.part = c->d_part;
   ma.state = c->d_state;
   ma.cmd = d_cmd;
@@ -409,15 +435,36 @@ rtc_status rtc_reconstruct_integrate(rtc_ctx *c, const float *d_slopes, float *d
   ma.cmd_max = c->cfg.cmd_max;
   ma.sync = c->d_sync;
   ma.ts_end = nullptr;
-  hipError_t e = rtck::launch_mvm_integrate(ma, nullptr, st);
+  hipError_t e = launch_reconstruction(c, ma, st);
   if (e != hipSuccess) return hip_fail(c, e, "rtc_reconstruct_integrate: launch");
   return RTC_OK;
 }
 
-rtc_status rtc_set_mvm_split(rtc_ctx *c, int32_t k_split) {
-  if (!c) return fail(nullptr, RTC_E_ARG, "rtc_set_mvm_split: NULL context");
-  if (k_split < 1 || k_split > rtck::kMaxKSplit) return fail(c, RTC_E_ARG, "rtc_set_mvm_split: k_split must be in 1..64");
-  c->k_split = k_split;
+rtc_status rtc_set_mvm_tuning(rtc_ctx *c, const rtc_mvm_tuning *t) {
+  if (!c) return fail(nullptr, RTC_E_ARG, "rtc_set_mvm_tuning: NULL context");
+  if (!t) return fail(c, RTC_E_ARG, "rtc_set_mvm_tuning: NULL tuning");
+  if (t->kernel == RTC_MVM_ROWBLOCK) {
+    if (t->waves != 8 && t->waves != 16)
+      return fail(c, RTC_E_ARG, "rtc_set_mvm_tuning: waves must be 8 or 16");
+    if (t->rows_per_wave < 1 || t->rows_per_wave > 8)
+      return fail(c, RTC_E_ARG, "rtc_set_mvm_tuning: rows_per_batch must be in 1..8");
+    if (t->blocks < 0 || t->blocks > (1 << 20))
+      return fail(c, RTC_E_ARG, "rtc_set_mvm_tuning: blocks must be in 0..2^20");
+  } else if (t->kernel == RTC_MVM_STREAMED) {
+    if (t->k_split < 1 || t->k_split > rtck::kMaxKSplit)
+      return fail(c, RTC_E_ARG, "rtc_set_mvm_tuning: k_split must be in 1..64");
+    if (!rtck::mvm_variant_supported(t->rows_per_wave, t->unroll))
+      return fail(c, RTC_E_ARG, "rtc_set_mvm_tuning: unsupported rows_per_wave/unroll pair");
+  } else {
+    return fail(c, RTC_E_ARG, "rtc_set_mvm_tuning: unknown kernel");
+  }
+  c->tuning = *t;
+  return RTC_OK;
+}
+
+rtc_status rtc_get_mvm_tuning(const rtc_ctx *c, rtc_mvm_tuning *t) {
+  if (!c || !t) return fail(nullptr, RTC_E_ARG, "rtc_get_mvm_tuning: NULL argument");
+  *t = c->tuning;
   return RTC_OK;
 }
 

@@ -32,6 +32,8 @@ struct MvmArgs {
   int32_t n_s4;            // slope vector length / 4 (zero-padded)
   const float *s;          // [4 n_s4], 16-byte aligned
   int32_t k_split;         // partitions of the slope dimension (1 = fused epilogue)
+  int32_t rows_per_wave;   // 1, 2 or 4 actuator rows per wavefront
+  int32_t unroll;          // 2, 4 or 8 16-byte loads per row and lane in flight
   float *part;             // [k_split][n_act] partial sums (k_split > 1)
   float *state;            // [n_act] integrator state (read and updated)
   float *cmd;              // [n_act] commands out
@@ -42,6 +44,15 @@ struct MvmArgs {
 };
 // Returns the number of slope partitions actually used (<= k_split) in *used.
 hipError_t launch_mvm_integrate(const MvmArgs &a, int32_t *used, hipStream_t st);
+
+bool mvm_variant_supported(int rows_per_wave, int unroll);
+
+// Row-block reconstruction + integrator (no slope split): `blocks` workgroups of
+// `waves` (8 or 16) wavefronts, `rows_per_batch` rows streamed per batch.
+// Fails with hipErrorInvalidValue when a wavefront's slope slice would need
+// more than mvm_block_max_kpl() 16-byte vectors per lane.
+hipError_t launch_mvm_block(const MvmArgs &a, int blocks, int waves, int rows_per_batch, hipStream_t st);
+int mvm_block_max_kpl();
 
 // Roofline probes.
 hipError_t launch_probe_copy(const void *src, void *dst, int64_t n_bytes, hipStream_t st);

@@ -132,57 +132,98 @@ __device__ __forceinline__ float integrate_one(float *state, float *cmd, float *
   return c;
 }
 
-// Completion stamp: the last workgroup to finish writes the end time once all
-// workgroups' global writes are visible, then re-arms the counter.
+// Completion stamp: the last workgroup to finish its stores writes the end
+// time and re-arms the counter.  The counter is a relaxed device-scope atomic
+// and there is deliberately no release fence: on a multi-XCD part a release at
+// device scope writes back the XCD's L2, which per workgroup costs far more
+// than the kernel.  The stamp therefore marks the moment every workgroup has
+// issued its last store (results are visible to later launches as usual).
 __device__ __forceinline__ void completion_stamp(uint32_t *sync, uint64_t *ts_end) {
-  __threadfence();
   __syncthreads();
   if (threadIdx.x == 0) {
     const uint32_t total = gridDim.x * gridDim.y;
-    const uint32_t prev = atomicAdd(sync, 1u);
+    const uint32_t prev = __hip_atomic_fetch_add(sync, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (prev == total - 1) {
-      __threadfence();
       ts_end[0] = wall_clock64();
-      atomicExch(sync, 0u);
+      __hip_atomic_store(sync, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   }
 }
 
 // Workgroup = 4 wavefronts; wavefront w owns RPW consecutive actuator rows and
-// streams them over this workgroup's slope partition (blockIdx.y).
-template <int RPW>
+// streams them over this workgroup's slope partition (blockIdx.y).  The loop is
+// software-pipelined: U x RPW 16-byte loads per lane are in flight while the
+// previous U x RPW are consumed, and the first batch is issued before the slope
+// vector is staged in LDS, so the matrix stream starts at the first cycle.
+template <int RPW, int U>
 __global__ __launch_bounds__(kBlock) void mvm_kernel(MvmArgs a, int32_t chunk4) {
   extern __shared__ float4 s_lds[];
+  constexpr int STEP = 64 * U;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int k0 = blockIdx.y * chunk4;
   const int nk = min(chunk4, a.n_s4 - k0);
-
-  const float4 *s4 = reinterpret_cast<const float4 *>(a.s) + k0;
-  for (int c = tid; c < nk; c += kBlock) s_lds[c] = s4[c];
-  __syncthreads();
+  const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
 
   const int row0 = (blockIdx.x * 4 + wave) * RPW;
   const float4 *rp[RPW];
-  float4 acc[RPW];
 #pragma unroll
   for (int r = 0; r < RPW; ++r) {
     const int row = min(row0 + r, a.n_act - 1);   // clamp: loads stay in bounds
     rp[r] = reinterpret_cast<const float4 *>(a.R + (int64_t)row * a.ldr) + k0;
-    acc[r] = make_float4(0.f, 0.f, 0.f, 0.f);
   }
-#pragma unroll 4
-  for (int c = lane; c < nk; c += 64) {
-    const float4 sv = s_lds[c];
+  // Matrix loads are always issued as full 16-byte vectors at a clamped,
+  // in-bounds index and used as loaded: lanes past the end multiply by a zeroed
+  // slope value instead (the matrix is finite).  Two register buffers are used
+  // in turn (no copies between them), so one batch is consumed while the next
+  // is in flight.
+  const int last = nk - 1;
+  float4 bufA[U][RPW], bufB[U][RPW];
+  auto load = [&](float4 (&b)[U][RPW], int base) {
 #pragma unroll
-    for (int r = 0; r < RPW; ++r) {
-      const float4 rv = rp[r][c];
-      acc[r].x = fmaf(rv.x, sv.x, acc[r].x);
-      acc[r].y = fmaf(rv.y, sv.y, acc[r].y);
-      acc[r].z = fmaf(rv.z, sv.z, acc[r].z);
-      acc[r].w = fmaf(rv.w, sv.w, acc[r].w);
+    for (int u = 0; u < U; ++u) {
+      const int c = min(base + lane + u * 64, last);
+#pragma unroll
+      for (int r = 0; r < RPW; ++r) b[u][r] = rp[r][c];
     }
+  };
+  float4 acc[RPW];
+#pragma unroll
+  for (int r = 0; r < RPW; ++r) acc[r] = zero;
+  auto consume = [&](const float4 (&b)[U][RPW], int base) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int c = base + lane + u * 64;
+      const float4 sl = s_lds[min(c, last)];
+      const float4 sv = (c < nk) ? sl : zero;
+#pragma unroll
+      for (int r = 0; r < RPW; ++r) {
+        acc[r].x = fmaf(b[u][r].x, sv.x, acc[r].x);
+        acc[r].y = fmaf(b[u][r].y, sv.y, acc[r].y);
+        acc[r].z = fmaf(b[u][r].z, sv.z, acc[r].z);
+        acc[r].w = fmaf(b[u][r].w, sv.w, acc[r].w);
+      }
+    }
+  };
+
+  load(bufA, 0);                       // issued before the slope vector is staged
+  const float4 *s4 = reinterpret_cast<const float4 *>(a.s) + k0;
+  for (int c = tid; c < nk; c += kBlock) s_lds[c] = s4[c];
+  __syncthreads();
+
+  // The prefetch is unconditional (past the end it re-reads the clamped last
+  // vector, one cache line) so no load sits behind a branch: the hardware wait
+  // counters then only wait for the batch being consumed.
+  for (int base = 0;;) {
+    load(bufB, base + STEP);
+    consume(bufA, base);
+    base += STEP;
+    if (base >= nk) break;
+    load(bufA, base + STEP);
+    consume(bufB, base);
+    base += STEP;
+    if (base >= nk) break;
   }
 #pragma unroll
   for (int r = 0; r < RPW; ++r) {
@@ -198,6 +239,73 @@ __global__ __launch_bounds__(kBlock) void mvm_kernel(MvmArgs a, int32_t chunk4) 
     }
   }
   if (a.k_split == 1 && a.ts_end != nullptr) completion_stamp(a.sync, a.ts_end);
+}
+
+// Row-block reconstruction (k_split == 1): workgroup b owns the contiguous
+// actuator rows [b n_act / G, (b+1) n_act / G) -- a contiguous slab of the
+// matrix -- and its W wavefronts split the slope dimension into W slices.  A
+// wavefront keeps its slice of the slope vector in registers (KPL 16-byte
+// vectors per lane, loaded once) and streams its slice of RB rows at a time
+// with all RB x KPL loads issued before any is used.  Per-row wavefront sums go
+// to LDS and are added in wavefront order (deterministic), then integrated.
+template <int W, int KPL, int RB>
+__global__ __launch_bounds__(W * 64) void mvm_block_kernel(MvmArgs a, int32_t max_rows) {
+  extern __shared__ float sh_part[];               // [W][max_rows]
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int G = gridDim.x;
+  const int row_begin = (int)(((int64_t)blockIdx.x * a.n_act) / G);
+  const int row_end = (int)(((int64_t)(blockIdx.x + 1) * a.n_act) / G);
+  const int nrows = row_end - row_begin;
+  const int kc = (a.n_s4 + W - 1) / W;              // slope vectors per wavefront slice
+  const int k_lo = wave * kc;
+  const int k_hi = min(k_lo + kc, a.n_s4);
+  const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
+  const float4 *s4 = reinterpret_cast<const float4 *>(a.s);
+
+  int col[KPL];
+  float4 sv[KPL];
+#pragma unroll
+  for (int j = 0; j < KPL; ++j) {
+    const int c = k_lo + j * 64 + lane;
+    const bool ok = c < k_hi;
+    col[j] = ok ? c : 0;                            // in-bounds; its slope value is zeroed
+    const float4 v = s4[col[j]];
+    sv[j] = ok ? v : zero;
+  }
+
+  for (int rb = 0; rb < nrows; rb += RB) {          // wave-uniform
+    float4 m[RB][KPL];
+#pragma unroll
+    for (int i = 0; i < RB; ++i) {
+      const int row = row_begin + min(rb + i, nrows - 1);
+      const float4 *rp = reinterpret_cast<const float4 *>(a.R + (int64_t)row * a.ldr);
+#pragma unroll
+      for (int j = 0; j < KPL; ++j) m[i][j] = rp[col[j]];
+    }
+#pragma unroll
+    for (int i = 0; i < RB; ++i) {
+      float4 acc = zero;
+#pragma unroll
+      for (int j = 0; j < KPL; ++j) {
+        acc.x = fmaf(m[i][j].x, sv[j].x, acc.x);
+        acc.y = fmaf(m[i][j].y, sv[j].y, acc.y);
+        acc.z = fmaf(m[i][j].z, sv[j].z, acc.z);
+        acc.w = fmaf(m[i][j].w, sv[j].w, acc.w);
+      }
+      float v = (acc.x + acc.y) + (acc.z + acc.w);
+      v = wave_sum(v);
+      if (lane == 0 && rb + i < nrows) sh_part[wave * max_rows + rb + i] = v;
+    }
+  }
+  __syncthreads();
+  for (int t = tid; t < nrows; t += W * 64) {
+    float v = sh_part[t];
+    for (int w = 1; w < W; ++w) v += sh_part[w * max_rows + t];
+    integrate_one(a.state, a.cmd, a.recon, row_begin + t, v, a.gain, a.leak, a.cmd_min, a.cmd_max);
+  }
+  if (a.ts_end != nullptr) completion_stamp(a.sync, a.ts_end);
 }
 
 // Sum of the k_split partial actuator vectors in a fixed 64-leaf pairwise tree
@@ -256,9 +364,14 @@ hipError_t launch_calib_cog(const CalibArgs &a, hipStream_t st) {
   return hipGetLastError();
 }
 
+template <int RPW, int U>
+static void launch_mvm_variant(const MvmArgs &a, int chunk4, int ks, hipStream_t st) {
+  const dim3 grid((a.n_act + 4 * RPW - 1) / (4 * RPW), ks);
+  mvm_kernel<RPW, U><<<grid, kBlock, (size_t)chunk4 * sizeof(float4), st>>>(a, chunk4);
+}
+
 hipError_t launch_mvm_integrate(const MvmArgs &in, int32_t *used, hipStream_t st) {
   MvmArgs a = in;
-  constexpr int RPW = 2;
   int ks = a.k_split < 1 ? 1 : (a.k_split > kMaxKSplit ? kMaxKSplit : a.k_split);
   const int min_ks = (a.n_s4 + kMaxChunk4 - 1) / kMaxChunk4;
   if (ks < min_ks) ks = min_ks;
@@ -270,13 +383,73 @@ hipError_t launch_mvm_integrate(const MvmArgs &in, int32_t *used, hipStream_t st
   if (ks > 1 && a.part == nullptr) return hipErrorInvalidValue;
   a.k_split = ks;
   if (used) *used = ks;
-  const dim3 grid((a.n_act + 4 * RPW - 1) / (4 * RPW), ks);
-  const size_t lds = (size_t)chunk4 * sizeof(float4);
-  mvm_kernel<RPW><<<grid, kBlock, lds, st>>>(a, chunk4);
+  const int key = a.rows_per_wave * 16 + a.unroll;
+  switch (key) {
+    case 1 * 16 + 2: launch_mvm_variant<1, 2>(a, chunk4, ks, st); break;
+    case 1 * 16 + 4: launch_mvm_variant<1, 4>(a, chunk4, ks, st); break;
+    case 1 * 16 + 8: launch_mvm_variant<1, 8>(a, chunk4, ks, st); break;
+    case 2 * 16 + 2: launch_mvm_variant<2, 2>(a, chunk4, ks, st); break;
+    case 2 * 16 + 4: launch_mvm_variant<2, 4>(a, chunk4, ks, st); break;
+    case 2 * 16 + 8: launch_mvm_variant<2, 8>(a, chunk4, ks, st); break;
+    case 4 * 16 + 2: launch_mvm_variant<4, 2>(a, chunk4, ks, st); break;
+    case 4 * 16 + 4: launch_mvm_variant<4, 4>(a, chunk4, ks, st); break;
+    default: return hipErrorInvalidValue;
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || ks == 1) return e;
   reduce_integrate_kernel<<<(a.n_act + kBlock - 1) / kBlock, kBlock, 0, st>>>(a);
   return hipGetLastError();
+}
+
+template <int W, int KPL, int RB>
+static void launch_block_variant(const MvmArgs &a, int G, int max_rows, hipStream_t st) {
+  mvm_block_kernel<W, KPL, RB><<<G, W * 64, (size_t)W * max_rows * sizeof(float), st>>>(a, max_rows);
+}
+
+template <int W>
+static hipError_t launch_block_w(const MvmArgs &a, int G, int max_rows, int kpl, int rb, hipStream_t st) {
+  // register budget: RB x KPL 16-byte loads in flight per lane stays <= 16
+  if (kpl <= 1) {
+    if (rb >= 8) launch_block_variant<W, 1, 8>(a, G, max_rows, st);
+    else launch_block_variant<W, 1, 4>(a, G, max_rows, st);
+  } else if (kpl <= 2) {
+    if (rb >= 8) launch_block_variant<W, 2, 8>(a, G, max_rows, st);
+    else launch_block_variant<W, 2, 4>(a, G, max_rows, st);
+  } else if (kpl <= 4) {
+    if (rb >= 4) launch_block_variant<W, 4, 4>(a, G, max_rows, st);
+    else launch_block_variant<W, 4, 2>(a, G, max_rows, st);
+  } else if (kpl <= 8) {
+    if (rb >= 2) launch_block_variant<W, 8, 2>(a, G, max_rows, st);
+    else launch_block_variant<W, 8, 1>(a, G, max_rows, st);
+  } else {
+    return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+int mvm_block_max_kpl() { return 8; }
+
+hipError_t launch_mvm_block(const MvmArgs &a, int blocks, int waves, int rows_per_batch, hipStream_t st) {
+  if (waves != 8 && waves != 16) return hipErrorInvalidValue;
+  int G = blocks < 1 ? 1 : blocks;
+  if (G > a.n_act) G = a.n_act;
+  int max_rows = (a.n_act + G - 1) / G;
+  const int lds_rows = 65536 / (waves * (int)sizeof(float));
+  if (max_rows > lds_rows) {                        // keep the partial sums within 64 KiB of LDS
+    G = (a.n_act + lds_rows - 1) / lds_rows;
+    max_rows = (a.n_act + G - 1) / G;
+  }
+  const int kc = (a.n_s4 + waves - 1) / waves;
+  const int kpl = (kc + 63) / 64;
+  if (kpl > mvm_block_max_kpl()) return hipErrorInvalidValue;
+  return waves == 8 ? launch_block_w<8>(a, G, max_rows, kpl, rows_per_batch, st)
+                    : launch_block_w<16>(a, G, max_rows, kpl, rows_per_batch, st);
+}
+
+bool mvm_variant_supported(int rows_per_wave, int unroll) {
+  return (rows_per_wave == 1 && (unroll == 2 || unroll == 4 || unroll == 8)) ||
+         (rows_per_wave == 2 && (unroll == 2 || unroll == 4 || unroll == 8)) ||
+         (rows_per_wave == 4 && (unroll == 2 || unroll == 4));
 }
 
 hipError_t launch_probe_copy(const void *src, void *dst, int64_t n_bytes, hipStream_t st) {

@@ -40,6 +40,14 @@ class rtc_config(ctypes.Structure):
                 ("cmd_max", ctypes.c_float), ("device", ctypes.c_int32)]
 
 
+RTC_MVM_ROWBLOCK, RTC_MVM_STREAMED = 0, 1
+
+
+class rtc_mvm_tuning(ctypes.Structure):
+    _fields_ = [("kernel", ctypes.c_int32), ("k_split", ctypes.c_int32), ("rows_per_wave", ctypes.c_int32),
+                ("unroll", ctypes.c_int32), ("blocks", ctypes.c_int32), ("waves", ctypes.c_int32)]
+
+
 _vp, _i32, _i64, _f32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_float
 _SIGNATURES = {
     "rtc_init": (_i32, [ctypes.POINTER(rtc_config), ctypes.POINTER(_vp)]),
@@ -49,7 +57,8 @@ _SIGNATURES = {
     "rtc_frame_batch": (_i32, [_vp, _i32, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp]),
     "rtc_calibrate_centroid": (_i32, [_vp, _vp, _vp, _vp, _vp]),
     "rtc_reconstruct_integrate": (_i32, [_vp, _vp, _vp, _vp, _vp]),
-    "rtc_set_mvm_split": (_i32, [_vp, _i32]),
+    "rtc_set_mvm_tuning": (_i32, [_vp, ctypes.POINTER(rtc_mvm_tuning)]),
+    "rtc_get_mvm_tuning": (_i32, [_vp, ctypes.POINTER(rtc_mvm_tuning)]),
     "rtc_reset": (_i32, [_vp]),
     "rtc_get_state": (_i32, [_vp, _vp]),
     "rtc_set_state": (_i32, [_vp, _vp]),
@@ -243,8 +252,25 @@ def rtc_reconstruct_integrate(ctx: RtcContext, slopes, cmd, recon=None, stream=N
         _dev_ptr(recon, "float32", ctx.n_act, "recon", ctx, False), _stream_ptr(stream)), ctx)
 
 
-def rtc_set_mvm_split(ctx: RtcContext, k_split: int) -> None:
-    _check(load_library().rtc_set_mvm_split(ctx.handle, k_split), ctx)
+TUNING_DEFAULT = {"kernel": RTC_MVM_ROWBLOCK, "k_split": 1, "rows_per_wave": 2, "unroll": 4, "blocks": 0,
+                  "waves": 8}
+STREAMED_DEFAULT = {**TUNING_DEFAULT, "kernel": RTC_MVM_STREAMED, "rows_per_wave": 2}
+
+
+def rtc_set_mvm_tuning(ctx: RtcContext, **kw) -> None:
+    """Sets the reconstruction launch shape; unspecified fields take that kernel's defaults."""
+    unknown = set(kw) - set(TUNING_DEFAULT)
+    if unknown:
+        raise TypeError(f"unknown tuning fields {sorted(unknown)}")
+    base = STREAMED_DEFAULT if kw.get("kernel", RTC_MVM_ROWBLOCK) == RTC_MVM_STREAMED else TUNING_DEFAULT
+    t = rtc_mvm_tuning(**{**base, **kw})
+    _check(load_library().rtc_set_mvm_tuning(ctx.handle, ctypes.byref(t)), ctx)
+
+
+def rtc_get_mvm_tuning(ctx: RtcContext) -> dict:
+    t = rtc_mvm_tuning()
+    _check(load_library().rtc_get_mvm_tuning(ctx.handle, ctypes.byref(t)), ctx)
+    return {name: getattr(t, name) for name, _ in rtc_mvm_tuning._fields_}
 
 
 def rtc_reset(ctx: RtcContext) -> None:

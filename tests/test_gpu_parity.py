@@ -42,7 +42,7 @@ def _dev(a):
     return torch.from_numpy(a).to("cuda:0")
 
 
-def _gpu_batch(ctx, frames, k_split=1, ts=False):
+def _gpu_batch(ctx, frames, k_split=1, ts=False, tuning=None):
     F = frames.shape[0]
     pix = _dev(frames.reshape(F, -1))
     cmd = torch.empty(F * ctx.n_act, dtype=torch.float32, device="cuda:0")
@@ -50,7 +50,12 @@ def _gpu_batch(ctx, frames, k_split=1, ts=False):
     recon = torch.empty(F * ctx.n_act, dtype=torch.float32, device="cuda:0")
     counts = torch.empty(F * ctx.n_valid, dtype=torch.int32, device="cuda:0")
     tst = torch.zeros(2 * F, dtype=torch.int64, device="cuda:0") if ts else None
-    rtc.rtc_set_mvm_split(ctx, k_split)
+    if tuning is not None:
+        rtc.rtc_set_mvm_tuning(ctx, **tuning)
+    elif k_split > 1:
+        rtc.rtc_set_mvm_tuning(ctx, kernel=rtc.RTC_MVM_STREAMED, k_split=k_split, rows_per_wave=2)
+    else:
+        rtc.rtc_set_mvm_tuning(ctx)
     rtc.rtc_frame_batch(ctx, F, pix, cmd, slopes, recon, counts, tst)
     torch.cuda.synchronize()
     out = {"cmd": cmd.cpu().numpy().reshape(F, -1), "slopes": slopes.cpu().numpy().reshape(F, -1),
@@ -133,6 +138,20 @@ def test_elt_scao_replay_full_size(elt_loop, k_split):
     assert np.all(ts[:, 1] > ts[:, 0]) and np.all(ts[1:, 0] >= ts[:-1, 1])
 
 
+SHAPES = ([dict(kernel=0, waves=w, rows_per_wave=rb, blocks=b) for w in (8, 16) for rb in (1, 2, 4, 8)
+           for b in (0, 100)] +
+          [dict(kernel=1, rows_per_wave=r, unroll=u, k_split=k) for (r, u) in
+           [(1, 2), (1, 4), (1, 8), (2, 2), (2, 4), (2, 8), (4, 2), (4, 4)] for k in (1, 3)])
+
+
+@pytest.mark.parametrize("tuning", SHAPES, ids=[str(t) for t in SHAPES])
+def test_elt_every_mvm_shape_matches_oracle(elt_loop, tuning):
+    sc, frames, ref = elt_loop
+    with _ctx_for(sc) as ctx:
+        gpu = _gpu_batch(ctx, frames[:2], tuning=tuning)
+    check_parity(gpu, {k: v[:2] for k, v in ref.items()}, ELT.gain, ELT.leak, what=f"elt {tuning}")
+
+
 def test_elt_replay_is_bitwise_deterministic(elt_loop):
     sc, frames, _ = elt_loop
     with _ctx_for(sc) as ctx:
@@ -204,8 +223,13 @@ def test_integer_inputs_give_bit_exact_slopes_and_counts():
         assert np.array_equal(gpu["slopes"][0], ref["slopes"].astype(np.float32)), name
 
 
-@pytest.mark.parametrize("k_split", [1, 2, 7, 64])
-def test_integer_matrix_and_slopes_give_bit_exact_commands(k_split):
+TUNINGS = [dict(), dict(waves=8, rows_per_wave=1), dict(waves=16, rows_per_wave=2, blocks=7),
+           dict(kernel=1, k_split=1, rows_per_wave=1, unroll=8), dict(kernel=1, k_split=2),
+           dict(kernel=1, k_split=7, rows_per_wave=4, unroll=2), dict(kernel=1, k_split=64)]
+
+
+@pytest.mark.parametrize("tuning", TUNINGS, ids=[str(t) for t in TUNINGS])
+def test_integer_matrix_and_slopes_give_bit_exact_commands(tuning):
     rng = np.random.default_rng(5)
     mask = geometry.subaperture_mask(12, 0.2)
     nv = int(mask.sum())
@@ -214,7 +238,7 @@ def test_integer_matrix_and_slopes_give_bit_exact_commands(k_split):
     with rtc.rtc_init(mask, 2, n_act, gain=0.5) as ctx:
         rtc.rtc_load_calib(ctx, np.zeros((24, 24), np.float32), np.ones((24, 24), np.float32), 0.0)
         rtc.rtc_load_cmat(ctx, R)
-        rtc.rtc_set_mvm_split(ctx, k_split)
+        rtc.rtc_set_mvm_tuning(ctx, **tuning)
         c = np.zeros(n_act)
         cmd = torch.empty(n_act, dtype=torch.float32, device="cuda:0")
         rec = torch.empty(n_act, dtype=torch.float32, device="cuda:0")
@@ -347,16 +371,24 @@ def test_call_order_and_failed_loads_leave_state_intact():
         rtc.rtc_load_cmat(ctx, R)
         rtc.rtc_frame(ctx, pix, cmd)
         first = cmd.cpu().numpy().copy()
+        assert mask[3, 3] == 1          # pixel (12, 12) lies in an active subaperture
         bad = dark.copy()
-        bad[0, 0] = np.nan
+        bad[12, 12] = np.nan
         with pytest.raises(rtc.RtcError) as ei:
             rtc.rtc_load_calib(ctx, bad, flat, 3.0)
         assert ei.value.status == rtc.RTC_E_NONFINITE
         tiny = dark.copy()
-        tiny[1, 1] = 1e-5
+        tiny[12, 12] = 1e-5
         with pytest.raises(rtc.RtcError) as ei:
             rtc.rtc_load_calib(ctx, tiny, flat, 3.0)
         assert ei.value.status == rtc.RTC_E_ARG and "2^-13" in str(ei.value)
+        # pixels outside the active subapertures are never read, so they are not checked
+        corner = dark.copy()
+        corner[0, 0] = np.nan
+        assert mask[0, 0] == 0
+        rtc.rtc_load_calib(ctx, corner, flat, 3.0)
+        rtc.rtc_frame(ctx, pix, cmd)
+        rtc.rtc_reset(ctx)
         with pytest.raises(rtc.RtcError) as ei:
             rtc.rtc_load_calib(ctx, dark, flat, -1.0)
         assert ei.value.status == rtc.RTC_E_ARG
@@ -368,9 +400,14 @@ def test_call_order_and_failed_loads_leave_state_intact():
         with pytest.raises(rtc.RtcError) as ei:
             rtc.rtc_load_cmat(ctx, R[:, :-2])
         assert ei.value.status == rtc.RTC_E_ARG
-        with pytest.raises(rtc.RtcError) as ei:
-            rtc.rtc_set_mvm_split(ctx, 65)
-        assert ei.value.status == rtc.RTC_E_ARG
+        bad = [dict(kernel=1, k_split=65), dict(kernel=1, k_split=0), dict(kernel=1, rows_per_wave=3),
+               dict(kernel=1, rows_per_wave=4, unroll=8), dict(kernel=1, unroll=16), dict(kernel=2),
+               dict(waves=4), dict(rows_per_wave=9), dict(blocks=-1)]
+        for bad_t in bad:
+            with pytest.raises(rtc.RtcError) as ei:
+                rtc.rtc_set_mvm_tuning(ctx, **bad_t)
+            assert ei.value.status == rtc.RTC_E_ARG
+        assert rtc.rtc_get_mvm_tuning(ctx) == rtc.TUNING_DEFAULT
         # the failed loads changed nothing: same frame from the same state gives the same command
         rtc.rtc_reset(ctx)
         assert np.all(rtc.rtc_get_state(ctx) == 0)

@@ -23,43 +23,55 @@ constexpr int kBlock = 256;
 // ---------------------------------------------------------------------------
 // (a)-(b) calibration + centre of gravity
 // ---------------------------------------------------------------------------
-// MAXP >= n_pix: every row is loaded with fully unrolled, guarded loads so all
-// of a lane's loads are in flight before the first use.
-template <int MAXP>
-__global__ __launch_bounds__(kBlock) void calib_cog_kernel(CalibArgs a) {
-  __shared__ double sh_S[kBlock];
-  __shared__ double sh_Sx[kBlock];
-  __shared__ double sh_Sy[kBlock];
-  __shared__ int sh_n[kBlock];
-
+// GS (a power of two >= n_pix) lanes per subaperture, one pixel row per lane,
+// so a tile never straddles a wavefront and its sums are GS-lane butterflies
+// (no LDS, no barrier).  Every load of a lane is issued before the first use;
+// even-width rows use 4-byte pixel pairs and 16-byte (dark, flat) pairs when the
+// frame pointer allows it (vec != 0).
+template <int GS>
+__global__ __launch_bounds__(kBlock) void calib_cog_kernel(CalibArgs a, int vec) {
   const int tid = threadIdx.x;
   if (a.ts_start != nullptr && blockIdx.x == 0 && tid == 0) a.ts_start[0] = wall_clock64();
 
   const int n = a.n_pix;
-  const int spb = kBlock / n;                    // subapertures per workgroup
-  const int q = tid / n;                         // local subaperture
-  const int i = tid - q * n;                     // pixel row inside the tile
-  const int k = blockIdx.x * spb + q;
+  const int k = (int)(((int64_t)blockIdx.x * kBlock + tid) / GS);   // subaperture
+  const int i = tid & (GS - 1);                                     // pixel row in the tile
   const double half = 0.5 * (double)(n - 1);
 
   double S = 0.0, Sx = 0.0;
   int cnt = 0;
-  if (q < spb && k < a.n_valid) {
+  if (k < a.n_valid && i < n) {
     const uint16_t *prow = a.pix + (int64_t)a.tile_off[k] + (int64_t)i * a.W;
     const float2 *crow = a.calib + ((int64_t)k * n + i) * n;
-    uint16_t raw[MAXP];
-    float2 cf[MAXP];
+    uint32_t raw[GS];
+    float2 cf[GS];
+    if (vec) {
+      const uint32_t *p2 = reinterpret_cast<const uint32_t *>(prow);
+      const float4 *c2 = reinterpret_cast<const float4 *>(crow);
 #pragma unroll
-    for (int j = 0; j < MAXP; ++j) {
-      if (j < n) {
-        raw[j] = prow[j];
-        cf[j] = crow[j];
+      for (int j = 0; j < GS / 2; ++j) {
+        if (2 * j < n) {
+          const uint32_t w = p2[j];
+          const float4 c = c2[j];
+          raw[2 * j] = w & 0xffffu;
+          raw[2 * j + 1] = w >> 16;
+          cf[2 * j] = make_float2(c.x, c.y);
+          cf[2 * j + 1] = make_float2(c.z, c.w);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < GS; ++j) {
+        if (j < n) {
+          raw[j] = prow[j];
+          cf[j] = crow[j];
+        }
       }
     }
     const double T = (double)a.thr;
     const bool subtract = (a.mode == 1);
 #pragma unroll
-    for (int j = 0; j < MAXP; ++j) {
+    for (int j = 0; j < GS; ++j) {
       if (j < n) {
         // raw - dark is exact in float64 for the accepted dark domain; the single
         // rounding of the fma keeps the sign of (raw - dark) * flat - T exact.
@@ -74,39 +86,29 @@ __global__ __launch_bounds__(kBlock) void calib_cog_kernel(CalibArgs a) {
       }
     }
   }
-  sh_S[tid] = S;
-  sh_Sx[tid] = Sx;
-  sh_Sy[tid] = ((double)i - half) * S;
-  sh_n[tid] = cnt;
-  __syncthreads();
-
-  if (tid < spb) {
-    const int kk = blockIdx.x * spb + tid;
-    if (kk < a.n_valid) {
-      double tS = 0.0, tX = 0.0, tY = 0.0;
-      int tn = 0;
-      for (int r = 0; r < n; ++r) {            // rows in order: deterministic
-        const int idx = tid * n + r;
-        tS += sh_S[idx];
-        tX += sh_Sx[idx];
-        tY += sh_Sy[idx];
-        tn += sh_n[idx];
-      }
-      double cx = 0.0, cy = 0.0;
-      if (tn > 0) {
-        cx = tX / tS;
-        cy = tY / tS;
-      }
-      const float sx = (float)(cx - (double)a.ref[kk]);
-      const float sy = (float)(cy - (double)a.ref[a.n_valid + kk]);
-      a.s_int[kk] = sx;
-      a.s_int[a.n_valid + kk] = sy;
-      if (a.s_user != nullptr) {
-        a.s_user[kk] = sx;
-        a.s_user[a.n_valid + kk] = sy;
-      }
-      if (a.counts != nullptr) a.counts[kk] = tn;
+  double Sy = ((double)i - half) * S;
+#pragma unroll
+  for (int off = GS / 2; off > 0; off >>= 1) {     // butterfly: identical sums in all GS lanes
+    S += __shfl_xor(S, off, GS);
+    Sx += __shfl_xor(Sx, off, GS);
+    Sy += __shfl_xor(Sy, off, GS);
+    cnt += __shfl_xor(cnt, off, GS);
+  }
+  if (i == 0 && k < a.n_valid) {
+    double cx = 0.0, cy = 0.0;
+    if (cnt > 0) {
+      cx = Sx / S;
+      cy = Sy / S;
     }
+    const float sx = (float)(cx - (double)a.ref[k]);
+    const float sy = (float)(cy - (double)a.ref[a.n_valid + k]);
+    a.s_int[k] = sx;
+    a.s_int[a.n_valid + k] = sy;
+    if (a.s_user != nullptr) {
+      a.s_user[k] = sx;
+      a.s_user[a.n_valid + k] = sy;
+    }
+    if (a.counts != nullptr) a.counts[k] = cnt;
   }
 }
 
@@ -352,15 +354,18 @@ __global__ __launch_bounds__(kBlock) void probe_read_kernel(const float4 *__rest
 
 hipError_t launch_calib_cog(const CalibArgs &a, hipStream_t st) {
   if (a.n_pix < 1 || a.n_pix > 32) return hipErrorInvalidValue;
-  const int spb = kBlock / a.n_pix;
-  const int blocks = (a.n_valid + spb - 1) / spb;
-  if (blocks == 0) return hipSuccess;
-  if (a.n_pix <= 8)
-    calib_cog_kernel<8><<<blocks, kBlock, 0, st>>>(a);
-  else if (a.n_pix <= 16)
-    calib_cog_kernel<16><<<blocks, kBlock, 0, st>>>(a);
+  if (a.n_valid == 0) return hipSuccess;
+  const int gs = a.n_pix <= 8 ? 8 : (a.n_pix <= 16 ? 16 : 32);
+  const int64_t lanes = (int64_t)a.n_valid * gs;
+  const unsigned blocks = (unsigned)((lanes + kBlock - 1) / kBlock);
+  // 4-byte pixel pairs need an even row length and a 4-byte aligned frame
+  const int vec = ((a.n_pix & 1) == 0 && (a.W & 1) == 0 && (reinterpret_cast<uintptr_t>(a.pix) & 3) == 0) ? 1 : 0;
+  if (gs == 8)
+    calib_cog_kernel<8><<<blocks, kBlock, 0, st>>>(a, vec);
+  else if (gs == 16)
+    calib_cog_kernel<16><<<blocks, kBlock, 0, st>>>(a, vec);
   else
-    calib_cog_kernel<32><<<blocks, kBlock, 0, st>>>(a);
+    calib_cog_kernel<32><<<blocks, kBlock, 0, st>>>(a, vec);
   return hipGetLastError();
 }
 

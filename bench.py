@@ -55,6 +55,9 @@ def parse():
     p.add_argument("--kernel-reps", type=int, default=2000)
     p.add_argument("--cpu-seconds", type=float, default=15.0)
     p.add_argument("--no-cpu", action="store_true")
+    p.add_argument("--variants", default="f16,bf16,fp8e4m3",
+                   help="reduced-precision matrix formats also timed (comma list, empty = none)")
+    p.add_argument("--variant-steps", type=int, default=2000)
     return p.parse_args()
 
 
@@ -209,6 +212,50 @@ def main():
     del src, dst
     log(f"read/copy probes GB/s: {probes}")
 
+    # --- reduced-precision control matrices: same frames, same launch shape
+    variants = {}
+    for fmt in [v for v in args.variants.split(",") if v]:
+        vctx = rtc.rtc_init(sc.mask, cfg.n_pix, sc.n_act, cm_dtype=fmt, gain=cfg.gain, leak=cfg.leak)
+        rtc.rtc_load_calib(vctx, sc.dark, sc.flat, cfg.threshold)
+        rtc.rtc_load_cmat(vctx, R)
+        rtc.rtc_set_mvm_tuning(vctx, **{k: v for k, v in tuning.items() if k != "kernel"})
+        nf = args.variant_steps
+        vts = torch.zeros(2 * nf, dtype=torch.int64, device="cuda:0")
+        done = 0
+        while done < 200:
+            m = min(args.ring, 200 - done)
+            rtc.rtc_frame_batch(vctx, m, dev_ring, cmd, stream=stream)
+            done += m
+        done = 0
+        while done < nf:
+            m = min(args.ring, nf - done)
+            rtc.rtc_frame_batch(vctx, m, dev_ring, cmd, ts=vts[2 * done:], stream=stream)
+            done += m
+        torch.cuda.synchronize()
+        vst = vts.cpu().numpy().reshape(-1, 2)
+        vper = frame_stats(np.diff(ticks_to_us(vst[:, 0] - vst[0, 0], khz)))
+        for _ in range(50):
+            rtc.rtc_reconstruct_integrate(vctx, s_ptr, c_ptr, stream=st_ptr)
+        ev0.record(stream)
+        for _ in range(args.kernel_reps):
+            rtc.rtc_reconstruct_integrate(vctx, s_ptr, c_ptr, stream=st_ptr)
+        ev1.record(stream)
+        ev1.synchronize()
+        v_us = ev0.elapsed_time(ev1) * 1e3 / args.kernel_reps
+        esz = {"f16": 2, "bf16": 2, "fp8e4m3": 1}[fmt]
+        epc = 16 // esz
+        ldq = (2 * sc.n_valid + epc - 1) // epc * epc
+        v_bytes = n_act * ldq * esz + n_act * 4 + ldq * 4 + 3 * n_act * 4   # codes, scales, slopes, state, cmd
+        variants[fmt] = {"frame_period_p50_us": round(vper["p50_us"], 3), "p99_us": round(vper["p99_us"], 3),
+                         "rms_jitter_us": round(vper["rms_jitter_us"], 3),
+                         "reconstruct_integrate_us": round(v_us, 3),
+                         "matrix_MB": round(n_act * ldq * esz / 1e6, 2),
+                         "achieved_GBps": round(v_bytes / v_us / 1e3, 1),
+                         "frac_of_hbm_peak": round(v_bytes / v_us / 1e3 / HBM_PEAK_GBPS, 4)}
+        rtc.rtc_destroy(vctx)
+        log(f"{fmt}: frame p50 {vper['p50_us']:.2f} us, reconstruction {v_us:.2f} us "
+            f"({variants[fmt]['achieved_GBps']:.0f} GB/s)")
+
     traffic = None
     if os.path.exists(PROFILE_TRAFFIC):
         try:
@@ -246,6 +293,7 @@ def main():
         "gemv_GBps": round(achieved, 1),
         "kernels_us": {"reconstruct_integrate": round(mvm_us, 3), "calibrate_centroid": round(cal_us, 3)},
         "read_probe_GBps": probes,
+        "precision_variants": variants,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
                      "kernel": "mvm_kernel (reconstruct + integrate)",

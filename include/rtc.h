@@ -69,8 +69,18 @@ typedef enum {
   RTC_THR_ZERO = 2         /* v = x     if x > T else 0 */
 } rtc_thr_mode;
 
-/* Storage type of the control matrix (Section 2.3.4: 16-bit storage halves the
- * bytes the bandwidth-bound MVM reads).  This build implements RTC_CM_F32. */
+/* Storage type of the control matrix.  Section 2.3.4 stores it as IEEE
+ * binary16 to halve the bytes the bandwidth-bound reconstruction reads and
+ * converts each value to 32 bits before the multiply-accumulate; the same is
+ * offered for bfloat16 and OCP FP8 E4M3 (e4m3fn).  Reduced formats carry one
+ * float32 scale per matrix row:
+ *   s_r = 2^e_r, e_r the smallest integer with max_j |R_rj| / 2^e_r <= 2^E
+ *         (E = 15 binary16, 0 bfloat16, 8 E4M3), clamped to [-126, 127];
+ *         e_r = 0 for an all-zero row;
+ *   code  = R_rj / s_r rounded to the nearest value of the format, ties to
+ *           the even significand, sign kept on zero (no overflow is possible);
+ *   value = decode(code) * s_r; products and sums are float32.
+ * Slopes, the integrator and its state stay float32. */
 typedef enum {
   RTC_CM_F32 = 0,
   RTC_CM_F16 = 1,
@@ -90,7 +100,7 @@ typedef struct {
                                   rows [sy*n_pix, +n_pix), cols [sx*n_pix, +n_pix) */
   int32_t n_act;               /* actuators = rows of the control matrix, 1..2^20 */
   int32_t thr_mode;            /* rtc_thr_mode */
-  int32_t cm_dtype;            /* rtc_cm_dtype; only RTC_CM_F32 here */
+  int32_t cm_dtype;            /* rtc_cm_dtype of the stored control matrix */
   float gain, leak;            /* integrator g and leak lambda (1 = pure integrator) */
   float cmd_min, cmd_max;      /* clamp, cmd_min <= cmd_max; +-INFINITY = no clamp */
   int32_t device;              /* HIP device ordinal */
@@ -101,8 +111,8 @@ typedef struct {
  * integrator state starts at 0.  *out is set only on RTC_OK.
  * Errors: RTC_E_ARG (bad sizes, NULL, no active subaperture, wrong ABI
  * version), RTC_E_NONFINITE (gain/leak/clamp NaN or gain/leak infinite),
- * RTC_E_UNSUPPORTED (cm_dtype other than F32), RTC_E_DEVICE (no such device),
- * RTC_E_NOMEM. */
+ * RTC_E_UNSUPPORTED (reduced-precision matrix with more than 65,536
+ * slopes), RTC_E_DEVICE (no such device), RTC_E_NOMEM. */
 rtc_status rtc_init(const rtc_config *cfg, rtc_ctx **out);
 
 /* Loads the pixel calibration (Figure 3 (a)): host float32 dark and flat maps
@@ -120,10 +130,19 @@ rtc_status rtc_load_calib(rtc_ctx *c, const float *dark, const float *flat, floa
 /* Loads the control matrix R (Section 1.1.1; Figure 3 (c)): host float32,
  * row-major [n_act][ld], row r holds the weights of actuator r over the slope
  * vector (x block then y block); n_slopes must equal 2*n_valid, ld >= n_slopes.
- * The device copy is row-padded to a multiple of 4 floats.  Replaces a
- * previous matrix (synchronises the device).
+ * It is stored in the context's cm_dtype (encoded on the host as described at
+ * rtc_cm_dtype), rows zero-padded to 16-byte multiples.  Replaces a previous
+ * matrix (synchronises the device).
  * Errors: RTC_E_ARG (sizes, NULL), RTC_E_NONFINITE, RTC_E_DEVICE, RTC_E_NOMEM. */
 rtc_status rtc_load_cmat(rtc_ctx *c, const float *R, int32_t n_act, int32_t n_slopes, int64_t ld);
+
+/* Host-only encoder of the reduced storage formats (no device needed): codes
+ * [n_rows][n_cols] (2 bytes per element for F16/BF16, 1 for FP8E4M3) and
+ * scales [n_rows] of the float32 rows R [n_rows][ld], exactly as
+ * rtc_load_cmat stores them.  Errors: RTC_E_ARG (cm_dtype F32 or unknown,
+ * NULL, sizes), RTC_E_NONFINITE. */
+rtc_status rtc_encode_cmat(int32_t cm_dtype, const float *R, int32_t n_rows, int32_t n_cols, int64_t ld,
+                           void *codes, float *scales);
 
 /* One frame (steps (a)-(d)) on a device uint16 frame d_pixels [H][W] row-major.
  * Writes the new commands c_k to d_cmd [n_act] (float32, device) and advances
@@ -163,11 +182,13 @@ rtc_status rtc_reconstruct_integrate(rtc_ctx *c, const float *d_slopes, float *d
 /* Launch shape of the reconstruction (step (c)), for tuning.  Two kernels:
  *  kernel = RTC_MVM_ROWBLOCK (default): workgroup b owns a contiguous range of
  *    actuator rows; its `waves` wavefronts (8 or 16) split the slope vector and
- *    keep their slice in registers; `rows_per_batch` rows (1..8) are streamed
- *    per batch; `blocks` workgroups (0 = one per compute unit).  Needs the
- *    slope vector to fit 8 x 64 x waves x 4 floats; otherwise the streamed
- *    kernel is used automatically.
- *  kernel = RTC_MVM_STREAMED: each wavefront streams `rows_per_wave` (1, 2, 4)
+ *    keep their slice in registers and decode the stored format there;
+ *    `rows_per_batch` rows (1..8) are streamed per batch; `blocks` workgroups
+ *    (0 = one per compute unit).  A float32 slope vector longer than the
+ *    wavefronts' registers hold falls back to the streamed kernel; reduced
+ *    formats widen to 16 wavefronts.
+ *  kernel = RTC_MVM_STREAMED (float32 matrices only; RTC_E_UNSUPPORTED for
+ *    the others): each wavefront streams `rows_per_wave` (1, 2, 4)
  *    rows against the slope vector staged in LDS, with `unroll` (2, 4, 8; 8
  *    only with rows_per_wave <= 2) 16-byte loads per row in flight, and the
  *    slope dimension split into `k_split` (1..64) partitions whose partial
@@ -191,6 +212,38 @@ typedef struct {
 
 rtc_status rtc_set_mvm_tuning(rtc_ctx *c, const rtc_mvm_tuning *t);
 rtc_status rtc_get_mvm_tuning(const rtc_ctx *c, rtc_mvm_tuning *t);
+
+/* How rtc_frame_batch runs its frames.
+ *  RTC_FRAMES_PER_LAUNCH (default): two kernel launches per frame.
+ *  RTC_FRAMES_PERSISTENT: one cooperative launch for the whole batch.  Each
+ *    workgroup (one per compute unit) calibrates its share of the
+ *    subapertures of frame f, waits at a grid barrier for all slopes of frame
+ *    f, then reconstructs and integrates its own actuator rows; the rows'
+ *    integrator state stays on chip across frames.  This replaces the paper's
+ *    spin-locks and volatile flags (Section 2.3.2) with one device-wide
+ *    counter per frame.  Every wait is bounded by spin_limit polls (0 = the
+ *    default, about 0.1-0.3 s); when one expires the batch winds down, its
+ *    remaining frames are not processed and rtc_sync_check reports it.
+ *    Shapes the persistent kernel does not cover (more than 512 actuator rows
+ *    per compute unit, slope slices beyond its registers, a grid that cannot
+ *    be co-resident) run per launch instead.  The arithmetic and its order
+ *    are those of the per-launch mode with the row-block kernel, 8 wavefronts
+ *    and the same workgroup count, so results are bitwise identical to it. */
+typedef enum { RTC_FRAMES_PER_LAUNCH = 0, RTC_FRAMES_PERSISTENT = 1 } rtc_frame_mode;
+
+rtc_status rtc_set_frame_mode(rtc_ctx *c, int32_t mode, int32_t spin_limit);
+
+/* Stage tracing of persistent batches: when set, each persistent batch writes
+ * for its frames f < max_frames the device wall-clock stamps of workgroup 0 at
+ * d_trace[f][0..5] = frame start, own slopes published, frame barrier passed,
+ * slope slices loaded, partial sums done, commands written ([6], [7] unused).
+ * d_trace is a caller-owned device buffer of max_frames * 8 uint64 that must
+ * stay valid while batches run; max_frames = 0 turns tracing off. */
+rtc_status rtc_set_trace(rtc_ctx *c, uint64_t *d_trace, int32_t max_frames);
+
+/* Synchronises the device and reports RTC_E_DEVICE if a persistent batch gave
+ * up at a barrier since the last check (the flag is then cleared). */
+rtc_status rtc_sync_check(rtc_ctx *c);
 
 /* Integrator state: reset to 0, synchronous host copy out / in (n_act floats,
  * all finite for set).  They synchronise the device first. */

@@ -4,9 +4,11 @@
 // error leaves the context as it was.  Device buffers:
 //   tile_off [n_valid]            int32 element offset of each active tile
 //   calib    [n_valid][n][n]      float2 (dark, flat), active tiles only
-//   ref      [n_s4*4]             float32 reference slopes, zero-padded
-//   R        [n_act][ldr]         float32, ldr = round_up(2 n_valid, 4), zero-padded
-//   s        [n_s4*4]             float32 slope vector of the current frame
+//   ref      [s_len]              float32 reference slopes, s_len = round_up(2 n_valid, 16), zero-padded
+//   R        [n_act][ldq]         codes of the storage format, ldq = round_up(2 n_valid, elements per
+//                                 16 bytes), zero-padded; float32 storage has ldq = round_up(2 n_valid, 4)
+//   scales   [n_act]              float32 per-row scales (reduced formats only)
+//   s        [s_len]              float32 slope vector of the current frame, zero-padded
 //   state    [n_act]              float32 integrator state
 //   part     [64][n_act]          float32 split-K partial actuator vectors
 //   sync     [4]                  uint32 completion counter
@@ -25,7 +27,11 @@ struct rtc_ctx {
   rtc_config cfg{};
   int device = 0;
   int32_t H = 0, W = 0, n_pix = 0, n_valid = 0, n_slopes = 0, n_s4 = 0, n_act = 0;
-  int64_t ldr = 0;
+  int64_t ldr = 0;        // float32 row length of the matrix (elements)
+  int64_t s_len = 0;      // slope / reference buffer length (elements)
+  int32_t fmt = 0;        // rtc_cm_dtype of the stored matrix
+  int64_t ldq = 0;        // stored row length (elements)
+  int32_t n_chunks = 0;   // 16-byte chunks per stored row
   std::vector<uint8_t> mask;
   std::vector<int32_t> tile_off_h;
   std::string err;
@@ -37,11 +43,17 @@ struct rtc_ctx {
   float2 *d_calib = nullptr;
   float *d_ref = nullptr;
   float thr = 0.f;
-  float *d_R = nullptr;
+  void *d_R = nullptr;
+  float *d_scales = nullptr;
   float *d_s = nullptr;
   float *d_state = nullptr;
   float *d_part = nullptr;
-  uint32_t *d_sync = nullptr;
+  float *d_sbuf = nullptr;   // [2][s_len] slope vectors of consecutive frames (persistent batches)
+  uint32_t *d_sync = nullptr;  // [0] stamp counter, [1] abort, [2] sticky abort, [64, 384) persistent barrier
+  int32_t frame_mode = RTC_FRAMES_PER_LAUNCH;
+  int32_t spin_limit = 1 << 22;
+  uint64_t *d_trace = nullptr;  // caller-owned [trace_frames][8] stage stamps (persistent batches)
+  int32_t trace_frames = 0;
   bool calib_loaded = false;
   bool cmat_loaded = false;
 };
@@ -85,7 +97,78 @@ bool dark_in_domain(float d) {
   return d == 0.0f || (a >= 0x1p-13f && a < 0x1p24f);
 }
 
+// Slope exchange buffer of persistent batches: whole groups of 64 chunks of
+// the largest chunk (16 elements), so every format's layout fits.
+int64_t xchg_len_of(int64_t n_slopes) { return (n_slopes + 1023) / 1024 * 1024; }
+
+constexpr int kSyncWords = 512;
+constexpr int kBarBase = 64, kBarWords = 320;
+
 int64_t round_up4(int64_t x) { return (x + 3) & ~int64_t(3); }
+int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+// Storage formats: exponent bits, fraction bits, bias, E (row scales map the row
+// maximum into (2^(E-1), 2^E]), bytes per element.
+struct FmtDesc {
+  int ebits, fbits, bias, E, bytes;
+};
+const FmtDesc kFmt[4] = {{8, 23, 127, 0, 4}, {5, 10, 15, 15, 2}, {8, 7, 127, 0, 2}, {4, 3, 7, 8, 1}};
+
+// Round-to-nearest-even of |y| (finite, within the format's range) onto the
+// format's grid, then the bit pattern of the result.
+uint32_t encode_value(double y, const FmtDesc &f) {
+  const uint32_t sign = std::signbit(y) ? 1u : 0u;
+  const int sign_shift = f.ebits + f.fbits;
+  const double a = std::fabs(y);
+  if (a == 0.0) return sign << sign_shift;
+  int ex = 0;
+  (void)std::frexp(a, &ex);                         // a in [2^(ex-1), 2^ex)
+  const int e_unb = std::max(ex - 1, 1 - f.bias);
+  const double q = std::ldexp(1.0, e_unb - f.fbits);
+  const double v = std::nearbyint(a / q) * q;      // a / q exact; nearbyint ties to even
+  if (v == 0.0) return sign << sign_shift;
+  int ev = 0;
+  (void)std::frexp(v, &ev);
+  uint32_t e_field, frac;
+  if (v >= std::ldexp(1.0, 1 - f.bias)) {
+    e_field = (uint32_t)(ev - 1 + f.bias);
+    frac = (uint32_t)(std::ldexp(v, -(ev - 1) + f.fbits) - std::ldexp(1.0, f.fbits));
+  } else {
+    e_field = 0;
+    frac = (uint32_t)std::ldexp(v, f.bias - 1 + f.fbits);
+  }
+  return (sign << sign_shift) | (e_field << f.fbits) | frac;
+}
+
+// Smallest e with max|row| / 2^e <= 2^E, clamped to [-126, 127]; 0 for a zero row.
+int row_scale_exponent(const float *row, int32_t n, const FmtDesc &f) {
+  double m = 0.0;
+  for (int32_t j = 0; j < n; ++j) m = std::max(m, (double)std::fabs(row[j]));
+  if (m == 0.0) return 0;
+  int p = 0;
+  const double mant = std::frexp(m, &p);
+  const int ceil_log2 = (mant == 0.5) ? p - 1 : p;
+  return std::min(127, std::max(-126, ceil_log2 - f.E));
+}
+
+// Encodes rows [0, n_rows) of R (row pitch ld) into codes with row pitch
+// ldc elements (columns n_cols..ldc-1 are zero codes) and per-row scales.
+void encode_rows(int fmt, const float *R, int32_t n_rows, int32_t n_cols, int64_t ld, void *codes, int64_t ldc,
+                 float *scales) {
+  const FmtDesc &f = kFmt[fmt];
+  for (int32_t r = 0; r < n_rows; ++r) {
+    const float *row = R + (int64_t)r * ld;
+    const int e = row_scale_exponent(row, n_cols, f);
+    scales[r] = std::ldexp(1.0f, e);
+    for (int64_t j = 0; j < ldc; ++j) {
+      const uint32_t code = j < n_cols ? encode_value(std::ldexp((double)row[j], -e), f) : 0u;
+      if (f.bytes == 2)
+        static_cast<uint16_t *>(codes)[(int64_t)r * ldc + j] = (uint16_t)code;
+      else
+        static_cast<uint8_t *>(codes)[(int64_t)r * ldc + j] = (uint8_t)code;
+    }
+  }
+}
 
 }  // namespace
 
@@ -117,8 +200,6 @@ rtc_status rtc_init(const rtc_config *cfg, rtc_ctx **out) {
     return fail(nullptr, RTC_E_ARG, "rtc_init: thr_mode must be RTC_THR_SUBTRACT or RTC_THR_ZERO");
   if (cfg->cm_dtype < RTC_CM_F32 || cfg->cm_dtype > RTC_CM_FP8E4M3)
     return fail(nullptr, RTC_E_ARG, "rtc_init: unknown cm_dtype");
-  if (cfg->cm_dtype != RTC_CM_F32)
-    return fail(nullptr, RTC_E_UNSUPPORTED, "rtc_init: only RTC_CM_F32 control matrices are implemented");
   if (!std::isfinite(cfg->gain) || !std::isfinite(cfg->leak))
     return fail(nullptr, RTC_E_NONFINITE, "rtc_init: gain and leak must be finite");
   if (std::isnan(cfg->cmd_min) || std::isnan(cfg->cmd_max))
@@ -135,6 +216,13 @@ rtc_status rtc_init(const rtc_config *cfg, rtc_ctx **out) {
       if (mask[(int64_t)sy * cfg->n_sub_x + sx])
         off.push_back((int32_t)((int64_t)sy * cfg->n_pix * W + (int64_t)sx * cfg->n_pix));
   if (off.empty()) return fail(nullptr, RTC_E_ARG, "rtc_init: the mask has no active subaperture");
+  if (cfg->cm_dtype != RTC_CM_F32) {
+    // reduced formats run on the row-block kernel only: 16 wavefronts' slices must fit registers
+    const int epc = rtck::format_elems_per_chunk(cfg->cm_dtype);
+    const int64_t chunks = round_up(2 * (int64_t)off.size(), epc) / epc;
+    if (chunks > (int64_t)1 << 24 || rtck::slice_chunks((int)chunks, 16) / 64 > rtck::mvm_block_max_kpl())
+      return fail(nullptr, RTC_E_UNSUPPORTED, "rtc_init: slope vector too long for a reduced-precision matrix");
+  }
 
   int ndev = 0;
   hipError_t e = hipGetDeviceCount(&ndev);
@@ -155,6 +243,13 @@ rtc_status rtc_init(const rtc_config *cfg, rtc_ctx **out) {
   c->n_slopes = 2 * c->n_valid;
   c->ldr = round_up4(c->n_slopes);
   c->n_s4 = (int32_t)(c->ldr / 4);
+  c->s_len = round_up(c->n_slopes, 16);
+  c->fmt = cfg->cm_dtype;
+  {
+    const int epc = rtck::format_elems_per_chunk(c->fmt);
+    c->ldq = round_up(c->n_slopes, epc);
+    c->n_chunks = (int32_t)(c->ldq / epc);
+  }
   c->n_act = cfg->n_act;
   c->mask = std::move(mask);
   c->tile_off_h = std::move(off);
@@ -174,20 +269,22 @@ rtc_status rtc_init(const rtc_config *cfg, rtc_ctx **out) {
   if ((e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device)) != hipSuccess)
     return bail(e, "rtc_init: compute-unit count");
   c->n_cu = ncu;
-  const size_t s_bytes = (size_t)c->ldr * sizeof(float);
+  const size_t s_bytes = (size_t)c->s_len * sizeof(float);
   if ((e = hipMalloc(&c->d_tile_off, c->n_valid * sizeof(int32_t))) != hipSuccess ||
       (e = hipMalloc(&c->d_ref, s_bytes)) != hipSuccess ||
       (e = hipMalloc(&c->d_s, s_bytes)) != hipSuccess ||
       (e = hipMalloc(&c->d_state, c->n_act * sizeof(float))) != hipSuccess ||
       (e = hipMalloc(&c->d_part, (size_t)rtck::kMaxKSplit * c->n_act * sizeof(float))) != hipSuccess ||
-      (e = hipMalloc(&c->d_sync, 4 * sizeof(uint32_t))) != hipSuccess)
+      (e = hipMalloc(&c->d_sbuf, 2 * xchg_len_of(c->n_slopes) * sizeof(float))) != hipSuccess ||
+      (e = hipMalloc(&c->d_sync, kSyncWords * sizeof(uint32_t))) != hipSuccess)
     return bail(e, "rtc_init: hipMalloc");
   if ((e = hipMemcpy(c->d_tile_off, c->tile_off_h.data(), c->n_valid * sizeof(int32_t),
                      hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemset(c->d_ref, 0, s_bytes)) != hipSuccess ||
       (e = hipMemset(c->d_s, 0, s_bytes)) != hipSuccess ||
       (e = hipMemset(c->d_state, 0, c->n_act * sizeof(float))) != hipSuccess ||
-      (e = hipMemset(c->d_sync, 0, 4 * sizeof(uint32_t))) != hipSuccess ||
+      (e = hipMemset(c->d_sbuf, 0, 2 * xchg_len_of(c->n_slopes) * sizeof(float))) != hipSuccess ||
+      (e = hipMemset(c->d_sync, 0, kSyncWords * sizeof(uint32_t))) != hipSuccess ||
       (e = hipDeviceSynchronize()) != hipSuccess)
     return bail(e, "rtc_init: device initialisation");
   c->err = "no error";
@@ -221,7 +318,7 @@ rtc_status rtc_load_calib(rtc_ctx *c, const float *dark, const float *flat, floa
       }
     }
   }
-  std::vector<float> ref((size_t)c->ldr, 0.0f);
+  std::vector<float> ref((size_t)c->s_len, 0.0f);
   if (ref_slopes) {
     for (int32_t i = 0; i < c->n_slopes; ++i) {
       if (!std::isfinite(ref_slopes[i]))
@@ -261,21 +358,62 @@ rtc_status rtc_load_cmat(rtc_ctx *c, const float *R, int32_t n_act, int32_t n_sl
   }
   DeviceScope ds(c->device);
   if (ds.status != hipSuccess) return hip_fail(c, ds.status, "rtc_load_cmat: hipSetDevice");
-  float *d_R = nullptr;
-  const size_t bytes = (size_t)n_act * c->ldr * sizeof(float);
+  const FmtDesc &f = kFmt[c->fmt];
+  const int64_t ldq = (c->fmt == RTC_CM_F32) ? c->ldr : c->ldq;
+  const size_t bytes = (size_t)n_act * ldq * f.bytes;
+  std::vector<uint8_t> codes;
+  std::vector<float> scales;
+  if (c->fmt != RTC_CM_F32) {
+    try {
+      codes.resize(bytes);
+      scales.resize(n_act);
+    } catch (...) {
+      return fail(c, RTC_E_NOMEM, "rtc_load_cmat: host allocation failed");
+    }
+    encode_rows(c->fmt, R, n_act, n_slopes, ld, codes.data(), ldq, scales.data());
+  }
+  void *d_R = nullptr;
+  float *d_sc = nullptr;
   hipError_t e = hipMalloc(&d_R, bytes);
-  if (e != hipSuccess) return hip_fail(c, e, "rtc_load_cmat: hipMalloc");
-  if ((e = hipDeviceSynchronize()) != hipSuccess ||
-      (e = hipMemset(d_R, 0, bytes)) != hipSuccess ||
-      (e = hipMemcpy2D(d_R, c->ldr * sizeof(float), R, ld * sizeof(float), n_slopes * sizeof(float),
-                       n_act, hipMemcpyHostToDevice)) != hipSuccess ||
-      (e = hipDeviceSynchronize()) != hipSuccess) {
+  if (e == hipSuccess && c->fmt != RTC_CM_F32) e = hipMalloc(&d_sc, n_act * sizeof(float));
+  if (e != hipSuccess) {
+    if (d_R) (void)hipFree(d_R);
+    return hip_fail(c, e, "rtc_load_cmat: hipMalloc");
+  }
+  if ((e = hipDeviceSynchronize()) == hipSuccess) {
+    if (c->fmt == RTC_CM_F32) {
+      if ((e = hipMemset(d_R, 0, bytes)) == hipSuccess)
+        e = hipMemcpy2D(d_R, ldq * sizeof(float), R, ld * sizeof(float), n_slopes * sizeof(float), n_act,
+                        hipMemcpyHostToDevice);
+    } else {
+      if ((e = hipMemcpy(d_R, codes.data(), bytes, hipMemcpyHostToDevice)) == hipSuccess)
+        e = hipMemcpy(d_sc, scales.data(), n_act * sizeof(float), hipMemcpyHostToDevice);
+    }
+  }
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
     (void)hipFree(d_R);
+    if (d_sc) (void)hipFree(d_sc);
     return hip_fail(c, e, "rtc_load_cmat: upload");
   }
   dfree(c->d_R);
+  dfree(c->d_scales);
   c->d_R = d_R;
+  c->d_scales = d_sc;
   c->cmat_loaded = true;
+  return RTC_OK;
+}
+
+rtc_status rtc_encode_cmat(int32_t cm_dtype, const float *R, int32_t n_rows, int32_t n_cols, int64_t ld,
+                           void *codes, float *scales) {
+  if (cm_dtype != RTC_CM_F16 && cm_dtype != RTC_CM_BF16 && cm_dtype != RTC_CM_FP8E4M3)
+    return fail(nullptr, RTC_E_ARG, "rtc_encode_cmat: cm_dtype must be F16, BF16 or FP8E4M3");
+  if (!R || !codes || !scales) return fail(nullptr, RTC_E_ARG, "rtc_encode_cmat: NULL pointer");
+  if (n_rows < 0 || n_cols < 0 || ld < n_cols) return fail(nullptr, RTC_E_ARG, "rtc_encode_cmat: bad sizes");
+  for (int64_t r = 0; r < n_rows; ++r)
+    for (int32_t j = 0; j < n_cols; ++j)
+      if (!std::isfinite(R[r * ld + j])) return fail(nullptr, RTC_E_NONFINITE, "rtc_encode_cmat: non-finite entry");
+  encode_rows(cm_dtype, R, n_rows, n_cols, ld, codes, n_cols, scales);
   return RTC_OK;
 }
 
@@ -283,11 +421,20 @@ rtc_status rtc_load_cmat(rtc_ctx *c, const float *R, int32_t n_act, int32_t n_sl
 // the streamed kernel when the slope vector is too long for its registers.
 static hipError_t launch_reconstruction(const rtc_ctx *c, rtck::MvmArgs ma, hipStream_t st) {
   const rtc_mvm_tuning &t = c->tuning;
-  if (t.kernel == RTC_MVM_ROWBLOCK) {
-    const int kc = (c->n_s4 + t.waves - 1) / t.waves;
-    if ((kc + 63) / 64 <= rtck::mvm_block_max_kpl()) {
+  ma.R = c->fmt == RTC_CM_F32 ? static_cast<const float *>(c->d_R) : nullptr;
+  ma.ldr = c->ldr;
+  ma.Rq = c->d_R;
+  ma.ldq_bytes = c->ldq * kFmt[c->fmt].bytes;
+  ma.scales = c->d_scales;
+  ma.fmt = c->fmt;
+  ma.n_chunks = c->n_chunks;
+  if (t.kernel == RTC_MVM_ROWBLOCK || c->fmt != RTC_CM_F32) {
+    const int kpl = rtck::slice_chunks(c->n_chunks, t.waves) / 64;
+    if (kpl <= rtck::mvm_block_max_kpl() || c->fmt != RTC_CM_F32) {
       ma.k_split = 1;
-      return rtck::launch_mvm_block(ma, t.blocks > 0 ? t.blocks : c->n_cu, t.waves, t.rows_per_wave, st);
+      // reduced formats always fit 16 waves (checked at init); widen if 8 do not
+      const int waves = kpl <= rtck::mvm_block_max_kpl() ? t.waves : 16;
+      return rtck::launch_mvm_block(ma, t.blocks > 0 ? t.blocks : c->n_cu, waves, t.rows_per_wave, st);
     }
     ma.k_split = 1;
     ma.rows_per_wave = 2;
@@ -315,8 +462,6 @@ static rtc_status enqueue_frame(rtc_ctx *c, const uint16_t *pix, float *cmd, flo
   hipError_t e = rtck::launch_calib_cog(ca, st);
   if (e != hipSuccess) return hip_fail(c, e, who);
   rtck::MvmArgs ma{};
-  ma.R = c->d_R;
-  ma.ldr = c->ldr;
   ma.n_act = c->n_act;
   ma.n_s4 = c->n_s4;
   ma.s = c->d_s;
@@ -364,6 +509,56 @@ rtc_status rtc_frame_batch(rtc_ctx *c, int32_t n_frames, const uint16_t *d_pixel
   DeviceScope ds(c->device);
   if (ds.status != hipSuccess) return hip_fail(c, ds.status, "rtc_frame_batch: hipSetDevice");
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  if (c->frame_mode == RTC_FRAMES_PERSISTENT) {
+    rtck::PersistArgs p{};
+    p.cal.pix = d_pixels;
+    p.cal.W = c->W;
+    p.cal.tile_off = c->d_tile_off;
+    p.cal.calib = c->d_calib;
+    p.cal.n_valid = c->n_valid;
+    p.cal.n_pix = c->n_pix;
+    p.cal.thr = c->thr;
+    p.cal.mode = c->cfg.thr_mode;
+    p.cal.ref = c->d_ref;
+    p.cal.s_user = d_slopes;
+    p.cal.counts = d_counts;
+    p.frame_stride = frame_stride;
+    p.n_frames = n_frames;
+    p.vec = ((c->n_pix & 1) == 0 && (c->W & 1) == 0 && (frame_stride & 1) == 0 &&
+             (reinterpret_cast<uintptr_t>(d_pixels) & 3) == 0) ? 1 : 0;
+    p.sbuf = c->d_sbuf;
+    p.s_len = (int32_t)xchg_len_of(c->n_slopes);
+    p.cal.xchg_epc = rtck::format_elems_per_chunk(c->fmt);
+    rtck::MvmArgs &ma = p.mvm;
+    ma.Rq = c->d_R;
+    ma.ldq_bytes = c->ldq * kFmt[c->fmt].bytes;
+    ma.scales = c->d_scales;
+    ma.fmt = c->fmt;
+    ma.n_chunks = c->n_chunks;
+    ma.n_act = c->n_act;
+    ma.state = c->d_state;
+    ma.cmd = d_cmd;
+    ma.recon = d_recon;
+    ma.gain = c->cfg.gain;
+    ma.leak = c->cfg.leak;
+    ma.cmd_min = c->cfg.cmd_min;
+    ma.cmd_max = c->cfg.cmd_max;
+    p.bar = c->d_sync + kBarBase;
+    p.abort_flag = c->d_sync + 1;
+    p.sticky = c->d_sync + 2;
+    p.spin_limit = c->spin_limit;
+    p.ts = d_ts;
+    p.trace = c->d_trace;
+    p.trace_frames = c->trace_frames;
+    hipError_t e = hipMemsetAsync(c->d_sync + kBarBase, 0, kBarWords * sizeof(uint32_t), st);
+    if (e == hipSuccess) e = hipMemsetAsync(c->d_sync + 1, 0, sizeof(uint32_t), st);
+    if (e != hipSuccess) return hip_fail(c, e, "rtc_frame_batch: counter reset");
+    e = rtck::launch_frames(p, c->tuning.blocks > 0 ? c->tuning.blocks : c->n_cu, c->tuning.rows_per_wave, st);
+    if (e == hipSuccess) return RTC_OK;
+    if (e != hipErrorInvalidValue && e != hipErrorCooperativeLaunchTooLarge)
+      return hip_fail(c, e, "rtc_frame_batch: persistent launch");
+    (void)hipGetLastError();   // unsupported shape: fall through to one launch pair per frame
+  }
   for (int32_t f = 0; f < n_frames; ++f) {
     rtc_status s = enqueue_frame(c, d_pixels + (int64_t)f * frame_stride, d_cmd + (int64_t)f * c->n_act,
                                  d_slopes ? d_slopes + (int64_t)f * c->n_slopes : nullptr,
@@ -410,15 +605,14 @@ rtc_status rtc_reconstruct_integrate(rtc_ctx *c, const float *d_slopes, float *d
   if (ds.status != hipSuccess) return hip_fail(c, ds.status, "rtc_reconstruct_integrate: hipSetDevice");
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   const float *s = d_slopes;
-  if ((c->n_slopes & 3) != 0 || (reinterpret_cast<uintptr_t>(d_slopes) & 15) != 0) {
+  const int epc = rtck::format_elems_per_chunk(c->fmt);
+  if ((c->n_slopes % epc) != 0 || (reinterpret_cast<uintptr_t>(d_slopes) & 15) != 0) {
     // the kernel reads 16-byte vectors of a zero-padded vector: stage a copy
     hipError_t e = hipMemcpyAsync(c->d_s, d_slopes, c->n_slopes * sizeof(float), hipMemcpyDeviceToDevice, st);
     if (e != hipSuccess) return hip_fail(c, e, "rtc_reconstruct_integrate: slope copy");
     s = c->d_s;
   }
   rtck::MvmArgs ma{};
-  ma.R = c->d_R;
-  ma.ldr = c->ldr;
   ma.n_act = c->n_act;
   ma.n_s4 = c->n_s4;
   ma.s = s;
@@ -451,6 +645,8 @@ rtc_status rtc_set_mvm_tuning(rtc_ctx *c, const rtc_mvm_tuning *t) {
     if (t->blocks < 0 || t->blocks > (1 << 20))
       return fail(c, RTC_E_ARG, "rtc_set_mvm_tuning: blocks must be in 0..2^20");
   } else if (t->kernel == RTC_MVM_STREAMED) {
+    if (c->fmt != RTC_CM_F32)
+      return fail(c, RTC_E_UNSUPPORTED, "rtc_set_mvm_tuning: the streamed kernel reads float32 matrices only");
     if (t->k_split < 1 || t->k_split > rtck::kMaxKSplit)
       return fail(c, RTC_E_ARG, "rtc_set_mvm_tuning: k_split must be in 1..64");
     if (!rtck::mvm_variant_supported(t->rows_per_wave, t->unroll))
@@ -465,6 +661,41 @@ rtc_status rtc_set_mvm_tuning(rtc_ctx *c, const rtc_mvm_tuning *t) {
 rtc_status rtc_get_mvm_tuning(const rtc_ctx *c, rtc_mvm_tuning *t) {
   if (!c || !t) return fail(nullptr, RTC_E_ARG, "rtc_get_mvm_tuning: NULL argument");
   *t = c->tuning;
+  return RTC_OK;
+}
+
+rtc_status rtc_set_frame_mode(rtc_ctx *c, int32_t mode, int32_t spin_limit) {
+  if (!c) return fail(nullptr, RTC_E_ARG, "rtc_set_frame_mode: NULL context");
+  if (mode != RTC_FRAMES_PER_LAUNCH && mode != RTC_FRAMES_PERSISTENT)
+    return fail(c, RTC_E_ARG, "rtc_set_frame_mode: unknown mode");
+  if (spin_limit < 0) return fail(c, RTC_E_ARG, "rtc_set_frame_mode: spin_limit must be >= 0");
+  c->frame_mode = mode;
+  c->spin_limit = spin_limit > 0 ? spin_limit : (1 << 22);
+  return RTC_OK;
+}
+
+rtc_status rtc_set_trace(rtc_ctx *c, uint64_t *d_trace, int32_t max_frames) {
+  if (!c) return fail(nullptr, RTC_E_ARG, "rtc_set_trace: NULL context");
+  if (max_frames < 0 || (max_frames > 0 && !d_trace))
+    return fail(c, RTC_E_ARG, "rtc_set_trace: need a buffer for max_frames > 0");
+  c->d_trace = max_frames > 0 ? d_trace : nullptr;
+  c->trace_frames = max_frames;
+  return RTC_OK;
+}
+
+rtc_status rtc_sync_check(rtc_ctx *c) {
+  if (!c) return fail(nullptr, RTC_E_ARG, "rtc_sync_check: NULL context");
+  DeviceScope ds(c->device);
+  hipError_t e = ds.status;
+  uint32_t flag = 0;
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e == hipSuccess) e = hipMemcpy(&flag, c->d_sync + 2, sizeof(flag), hipMemcpyDeviceToHost);
+  if (e == hipSuccess && flag) e = hipMemset(c->d_sync + 2, 0, sizeof(uint32_t));
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(c, e, "rtc_sync_check");
+  if (flag)
+    return fail(c, RTC_E_DEVICE, "rtc_sync_check: a persistent batch gave up at a frame barrier "
+                                 "(bounded wait expired); its later frames were not processed");
   return RTC_OK;
 }
 
@@ -535,9 +766,11 @@ void rtc_destroy(rtc_ctx *c) {
   dfree(c->d_calib);
   dfree(c->d_ref);
   dfree(c->d_R);
+  dfree(c->d_scales);
   dfree(c->d_s);
   dfree(c->d_state);
   dfree(c->d_part);
+  dfree(c->d_sbuf);
   dfree(c->d_sync);
   delete c;
 }

@@ -21,16 +21,22 @@ struct CalibArgs {
   float *s_user;           // nullable copy
   int32_t *counts;         // nullable [n_valid]
   uint64_t *ts_start;      // nullable: written by block 0 on entry
+  int32_t xchg_epc;        // persistent batches: elements per chunk of the slope exchange layout
 };
 hipError_t launch_calib_cog(const CalibArgs &a, hipStream_t st);
 
 // Steps (c)-(d): a = R s, then c = clamp(leak c + gain a).
 struct MvmArgs {
-  const float *R;          // [n_act][ldr], ldr % 4 == 0, 16-byte aligned
+  const float *R;          // float32 [n_act][ldr], ldr % 4 == 0 (streamed kernel)
   int64_t ldr;
+  const void *Rq;          // [n_act] rows of ldq_bytes: codes of the storage format (row-block kernel)
+  int64_t ldq_bytes;       // row pitch, multiple of 16
+  const float *scales;     // [n_act] per-row scales, nullptr for float32 storage
+  int32_t fmt;             // 0 float32, 1 binary16, 2 bfloat16, 3 FP8 E4M3 (OCP)
+  int32_t n_chunks;        // 16-byte code chunks per row covering the slope vector
   int32_t n_act;
   int32_t n_s4;            // slope vector length / 4 (zero-padded)
-  const float *s;          // [4 n_s4], 16-byte aligned
+  const float *s;          // slope vector, zero-padded to a multiple of 16 floats, 16-byte aligned
   int32_t k_split;         // partitions of the slope dimension (1 = fused epilogue)
   int32_t rows_per_wave;   // 1, 2 or 4 actuator rows per wavefront
   int32_t unroll;          // 2, 4 or 8 16-byte loads per row and lane in flight
@@ -47,12 +53,43 @@ hipError_t launch_mvm_integrate(const MvmArgs &a, int32_t *used, hipStream_t st)
 
 bool mvm_variant_supported(int rows_per_wave, int unroll);
 
+// A wavefront's slice of the 16-byte chunks of a row: whole groups of 64
+// chunks (one per lane), so slices start on group boundaries.
+__host__ __device__ inline int slice_chunks(int n_chunks, int waves) {
+  return ((n_chunks + waves - 1) / waves + 63) / 64 * 64;
+}
+
 // Row-block reconstruction + integrator (no slope split): `blocks` workgroups of
 // `waves` (8 or 16) wavefronts, `rows_per_batch` rows streamed per batch.
 // Fails with hipErrorInvalidValue when a wavefront's slope slice would need
 // more than mvm_block_max_kpl() 16-byte vectors per lane.
 hipError_t launch_mvm_block(const MvmArgs &a, int blocks, int waves, int rows_per_batch, hipStream_t st);
 int mvm_block_max_kpl();
+// Elements per 16-byte chunk of a storage format (4, 8, 8, 16).
+int format_elems_per_chunk(int fmt);
+
+// Persistent frames (steps (a)-(d) for n_frames frames in one cooperative launch).
+struct PersistArgs {
+  CalibArgs cal;           // pix = frame 0; s_user / counts = per-frame output bases (nullable)
+  int64_t frame_stride;    // elements between frames
+  int32_t n_frames;
+  int32_t vec;             // 4-byte pixel pairs usable for every frame
+  float *sbuf;             // [2][s_len] slope vectors of consecutive frames in the exchange layout, zero-padded
+  int32_t s_len;           // >= round_up(chunks, 64) * 16 floats
+  MvmArgs mvm;             // cmd / recon = per-frame output bases [n_frames][n_act]
+  uint32_t *bar;           // [320] barrier, generation and frame-done words, zero at launch
+  uint32_t *abort_flag;    // raised when a bounded wait expires (zero at launch)
+  uint32_t *sticky;        // raised with abort_flag; cleared only by the host
+  int32_t spin_limit;      // spins (about 30-60 ns each) before a wait gives up
+  uint64_t *ts;            // nullable [n_frames][2]
+  uint64_t *trace;         // nullable [trace_frames][kTraceStages] stage stamps of workgroup 0
+  int32_t trace_frames;
+};
+constexpr int kTraceStages = 8;
+// Fails with hipErrorInvalidValue when the shape is unsupported (slab rows
+// beyond one per thread, LDS, register slices) and with the runtime's error
+// when the grid cannot be co-resident.
+hipError_t launch_frames(const PersistArgs &p, int blocks, int rows_per_batch, hipStream_t st);
 
 // Roofline probes.
 hipError_t launch_probe_copy(const void *src, void *dst, int64_t n_bytes, hipStream_t st);

@@ -20,6 +20,15 @@ namespace {
 
 constexpr int kBlock = 256;
 
+// Slope exchange layout of persistent batches: the EPC slopes of chunk c sit
+// element-major inside their group of 64 chunks, so lane l of a wavefront reads
+// element e of its chunk from one contiguous 256-byte run per (group, e).
+__device__ __forceinline__ int64_t xchg_pos(int64_t k, int epc) {
+  const int64_t c = k / epc, e = k - c * epc;
+  return (c >> 6) * (64 * epc) + e * 64 + (c & 63);
+}
+
+
 // ---------------------------------------------------------------------------
 // (a)-(b) calibration + centre of gravity
 // ---------------------------------------------------------------------------
@@ -28,16 +37,12 @@ constexpr int kBlock = 256;
 // (no LDS, no barrier).  Every load of a lane is issued before the first use;
 // even-width rows use 4-byte pixel pairs and 16-byte (dark, flat) pairs when the
 // frame pointer allows it (vec != 0).
-template <int GS>
-__global__ __launch_bounds__(kBlock) void calib_cog_kernel(CalibArgs a, int vec) {
-  const int tid = threadIdx.x;
-  if (a.ts_start != nullptr && blockIdx.x == 0 && tid == 0) a.ts_start[0] = wall_clock64();
-
+// COH: slopes are written with device-coherent stores (read by other
+// workgroups of the same launch); otherwise with ordinary stores.
+template <int GS, bool COH = false>
+__device__ __forceinline__ void calib_tile_row(const CalibArgs &a, int k, int i, int vec) {
   const int n = a.n_pix;
-  const int k = (int)(((int64_t)blockIdx.x * kBlock + tid) / GS);   // subaperture
-  const int i = tid & (GS - 1);                                     // pixel row in the tile
   const double half = 0.5 * (double)(n - 1);
-
   double S = 0.0, Sx = 0.0;
   int cnt = 0;
   if (k < a.n_valid && i < n) {
@@ -102,8 +107,14 @@ __global__ __launch_bounds__(kBlock) void calib_cog_kernel(CalibArgs a, int vec)
     }
     const float sx = (float)(cx - (double)a.ref[k]);
     const float sy = (float)(cy - (double)a.ref[a.n_valid + k]);
-    a.s_int[k] = sx;
-    a.s_int[a.n_valid + k] = sy;
+    if (COH) {
+      __hip_atomic_store(a.s_int + xchg_pos(k, a.xchg_epc), sx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(a.s_int + xchg_pos(a.n_valid + k, a.xchg_epc), sy, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      a.s_int[k] = sx;
+      a.s_int[a.n_valid + k] = sy;
+    }
     if (a.s_user != nullptr) {
       a.s_user[k] = sx;
       a.s_user[a.n_valid + k] = sy;
@@ -112,14 +123,39 @@ __global__ __launch_bounds__(kBlock) void calib_cog_kernel(CalibArgs a, int vec)
   }
 }
 
+template <int GS>
+__global__ __launch_bounds__(kBlock) void calib_cog_kernel(CalibArgs a, int vec) {
+  const int tid = threadIdx.x;
+  if (a.ts_start != nullptr && blockIdx.x == 0 && tid == 0) a.ts_start[0] = wall_clock64();
+  const int k = (int)(((int64_t)blockIdx.x * kBlock + tid) / GS);   // subaperture
+  calib_tile_row<GS>(a, k, tid & (GS - 1), vec);
+}
+
 // ---------------------------------------------------------------------------
 // (c) reconstruction
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ float wave_sum(float v) {
-  // xor butterfly: every lane ends with the same (bitwise) total
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+// Wavefront sum without LDS traffic: DPP adds inside each row of 16 lanes
+// (pairs, quads, half-row mirror, row mirror: every lane of a row ends with the
+// row sum), then the four row sums read into scalars and added in a fixed
+// order.  Needs all 64 lanes active; every lane returns the same total.
+template <int CTRL>
+__device__ __forceinline__ float dpp_read(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float row16_sum(float v) {
+  v += dpp_read<0xB1>(v);    // quad_perm [1,0,3,2]
+  v += dpp_read<0x4E>(v);    // quad_perm [2,3,0,1]
+  v += dpp_read<0x141>(v);   // row_half_mirror
+  v += dpp_read<0x140>(v);   // row_mirror
   return v;
+}
+__device__ __forceinline__ float wave_sum(float v) {
+  v = row16_sum(v);
+  const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
+  const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16));
+  const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
+  const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48));
+  return (r0 + r1) + (r2 + r3);
 }
 
 __device__ __forceinline__ float integrate_one(float *state, float *cmd, float *recon, int row,
@@ -243,71 +279,428 @@ __global__ __launch_bounds__(kBlock) void mvm_kernel(MvmArgs a, int32_t chunk4) 
   if (a.k_split == 1 && a.ts_end != nullptr) completion_stamp(a.sync, a.ts_end);
 }
 
-// Row-block reconstruction (k_split == 1): workgroup b owns the contiguous
+// Storage formats of the control matrix: a 16-byte chunk of codes decodes to
+// EPC float32 values (exactly; the per-row scale is applied to the row sum).
+template <int FMT>
+struct Codec;
+template <>
+struct Codec<0> {                                 // float32
+  static constexpr int EPC = 4;
+  __device__ __forceinline__ static void decode(const uint4 &c, float (&v)[EPC]) {
+    v[0] = __uint_as_float(c.x);
+    v[1] = __uint_as_float(c.y);
+    v[2] = __uint_as_float(c.z);
+    v[3] = __uint_as_float(c.w);
+  }
+};
+template <>
+struct Codec<1> {                                 // IEEE binary16
+  static constexpr int EPC = 8;
+  __device__ __forceinline__ static void decode(const uint4 &c, float (&v)[EPC]) {
+    const uint32_t w[4] = {c.x, c.y, c.z, c.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      v[2 * i] = (float)__builtin_bit_cast(_Float16, (uint16_t)(w[i] & 0xffffu));
+      v[2 * i + 1] = (float)__builtin_bit_cast(_Float16, (uint16_t)(w[i] >> 16));
+    }
+  }
+};
+template <>
+struct Codec<2> {                                 // bfloat16: the high half of a float32
+  static constexpr int EPC = 8;
+  __device__ __forceinline__ static void decode(const uint4 &c, float (&v)[EPC]) {
+    const uint32_t w[4] = {c.x, c.y, c.z, c.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      v[2 * i] = __uint_as_float(w[i] << 16);
+      v[2 * i + 1] = __uint_as_float(w[i] & 0xffff0000u);
+    }
+  }
+};
+template <>
+struct Codec<3> {                                 // OCP FP8 E4M3 (e4m3fn)
+  static constexpr int EPC = 16;
+  __device__ __forceinline__ static void decode(const uint4 &c, float (&v)[EPC]) {
+    typedef float f2v __attribute__((ext_vector_type(2)));
+    const uint32_t w[4] = {c.x, c.y, c.z, c.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const f2v lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)w[i], false);   // bytes 0, 1
+      const f2v hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)w[i], true);    // bytes 2, 3
+      v[4 * i] = lo.x;
+      v[4 * i + 1] = lo.y;
+      v[4 * i + 2] = hi.x;
+      v[4 * i + 3] = hi.y;
+    }
+  }
+};
+
+// Row-block reconstruction (no slope split): workgroup b owns the contiguous
 // actuator rows [b n_act / G, (b+1) n_act / G) -- a contiguous slab of the
-// matrix -- and its W wavefronts split the slope dimension into W slices.  A
-// wavefront keeps its slice of the slope vector in registers (KPL 16-byte
-// vectors per lane, loaded once) and streams its slice of RB rows at a time
-// with all RB x KPL loads issued before any is used.  Per-row wavefront sums go
-// to LDS and are added in wavefront order (deterministic), then integrated.
-template <int W, int KPL, int RB>
-__global__ __launch_bounds__(W * 64) void mvm_block_kernel(MvmArgs a, int32_t max_rows) {
-  extern __shared__ float sh_part[];               // [W][max_rows]
+// matrix -- and its W wavefronts split the row into W slices of 16-byte code
+// chunks.  A wavefront keeps the slope values of its slice in registers (KPL
+// chunks per lane, loaded once) and streams RB rows at a time with all RB x KPL
+// chunk loads issued before any is used; codes are decoded in registers.
+// Per-row wavefront sums go to LDS and are added in wavefront order
+// (deterministic), scaled by the row scale, then integrated.
+template <int FMT, int W, int KPL, int RB>
+__device__ __forceinline__ void slab_partials(const MvmArgs &a, const float *s, int row_begin, int nrows,
+                                              float *sh_part, int max_rows) {
+  using C = Codec<FMT>;
+  constexpr int EPC = C::EPC;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int G = gridDim.x;
-  const int row_begin = (int)(((int64_t)blockIdx.x * a.n_act) / G);
-  const int row_end = (int)(((int64_t)(blockIdx.x + 1) * a.n_act) / G);
-  const int nrows = row_end - row_begin;
-  const int kc = (a.n_s4 + W - 1) / W;              // slope vectors per wavefront slice
+  const int kc = slice_chunks(a.n_chunks, W);       // chunks per wavefront slice
   const int k_lo = wave * kc;
-  const int k_hi = min(k_lo + kc, a.n_s4);
-  const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
-  const float4 *s4 = reinterpret_cast<const float4 *>(a.s);
+  const int k_hi = min(k_lo + kc, a.n_chunks);
+  const float4 *s4 = reinterpret_cast<const float4 *>(s);
 
   int col[KPL];
-  float4 sv[KPL];
+  float sv[KPL][EPC];
 #pragma unroll
   for (int j = 0; j < KPL; ++j) {
     const int c = k_lo + j * 64 + lane;
     const bool ok = c < k_hi;
-    col[j] = ok ? c : 0;                            // in-bounds; its slope value is zeroed
-    const float4 v = s4[col[j]];
-    sv[j] = ok ? v : zero;
+    col[j] = ok ? c : 0;                            // in bounds; its slope values are zeroed
+#pragma unroll
+    for (int q = 0; q < EPC / 4; ++q) {
+      const float4 v = s4[col[j] * (EPC / 4) + q];
+      sv[j][4 * q] = ok ? v.x : 0.f;
+      sv[j][4 * q + 1] = ok ? v.y : 0.f;
+      sv[j][4 * q + 2] = ok ? v.z : 0.f;
+      sv[j][4 * q + 3] = ok ? v.w : 0.f;
+    }
   }
 
+  const char *base = static_cast<const char *>(a.Rq);
   for (int rb = 0; rb < nrows; rb += RB) {          // wave-uniform
-    float4 m[RB][KPL];
+    uint4 m[RB][KPL];
 #pragma unroll
     for (int i = 0; i < RB; ++i) {
       const int row = row_begin + min(rb + i, nrows - 1);
-      const float4 *rp = reinterpret_cast<const float4 *>(a.R + (int64_t)row * a.ldr);
+      const uint4 *rp = reinterpret_cast<const uint4 *>(base + (int64_t)row * a.ldq_bytes);
 #pragma unroll
       for (int j = 0; j < KPL; ++j) m[i][j] = rp[col[j]];
     }
 #pragma unroll
     for (int i = 0; i < RB; ++i) {
-      float4 acc = zero;
+      float acc[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int j = 0; j < KPL; ++j) {
-        acc.x = fmaf(m[i][j].x, sv[j].x, acc.x);
-        acc.y = fmaf(m[i][j].y, sv[j].y, acc.y);
-        acc.z = fmaf(m[i][j].z, sv[j].z, acc.z);
-        acc.w = fmaf(m[i][j].w, sv[j].w, acc.w);
+        float v[EPC];
+        C::decode(m[i][j], v);
+#pragma unroll
+        for (int e = 0; e < EPC; ++e) acc[e & 3] = fmaf(v[e], sv[j][e], acc[e & 3]);
       }
-      float v = (acc.x + acc.y) + (acc.z + acc.w);
-      v = wave_sum(v);
-      if (lane == 0 && rb + i < nrows) sh_part[wave * max_rows + rb + i] = v;
+      float t = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+      t = wave_sum(t);
+      if (lane == 0 && rb + i < nrows) sh_part[wave * max_rows + rb + i] = t;
     }
   }
+}
+
+// Row t of the slab: wavefront partials added in wavefront order, times the row scale.
+template <int W>
+__device__ __forceinline__ float slab_row_sum(const MvmArgs &a, const float *sh_part, int max_rows, int row) {
+  const int t = row;
+  float v = sh_part[t];
+  for (int w = 1; w < W; ++w) v += sh_part[w * max_rows + t];
+  return v;
+}
+
+template <int FMT, int W, int KPL, int RB>
+__global__ __launch_bounds__(W * 64) void mvm_block_kernel(MvmArgs a, int32_t max_rows) {
+  extern __shared__ float sh_part[];               // [W][max_rows]
+  const int G = gridDim.x;
+  const int row_begin = (int)(((int64_t)blockIdx.x * a.n_act) / G);
+  const int row_end = (int)(((int64_t)(blockIdx.x + 1) * a.n_act) / G);
+  const int nrows = row_end - row_begin;
+  slab_partials<FMT, W, KPL, RB>(a, a.s, row_begin, nrows, sh_part, max_rows);
   __syncthreads();
-  for (int t = tid; t < nrows; t += W * 64) {
-    float v = sh_part[t];
-    for (int w = 1; w < W; ++w) v += sh_part[w * max_rows + t];
+  for (int t = threadIdx.x; t < nrows; t += W * 64) {
+    float v = slab_row_sum<W>(a, sh_part, max_rows, t);
+    if (a.scales != nullptr) v *= a.scales[row_begin + t];
     integrate_one(a.state, a.cmd, a.recon, row_begin + t, v, a.gain, a.leak, a.cmd_min, a.cmd_max);
   }
   if (a.ts_end != nullptr) completion_stamp(a.sync, a.ts_end);
+}
+
+// ---------------------------------------------------------------------------
+// Persistent frames: one cooperative launch processes frames f = 0..n-1, one
+// workgroup per compute unit.  Workgroup b owns a share of the subapertures
+// and the contiguous actuator rows [b n_act / G, (b+1) n_act / G).  Its slab of
+// the stored matrix is copied on chip once per launch -- the first rows into
+// LDS, the next RR rows into registers (each wavefront keeps its slice) -- and
+// only the remaining rows are streamed from memory every frame.  Per frame:
+// calibrate own subapertures, publish the slopes with device-coherent stores,
+// frame barrier, read the slope slices with device-coherent loads, partial
+// sums over LDS / register / streamed rows, integrate own rows (state stays in
+// registers).
+//
+// Frame barrier: 16 group counters, one top counter and a generation word.
+// The slopes bypass the non-coherent caches, so the barrier needs no cache
+// write-back or invalidation; each wavefront only waits until its own stores
+// have completed before its workgroup arrives.  Every wait is bounded: when
+// one exceeds the spin limit the abort flag is raised and the kernel winds
+// down, so every workgroup always exits.
+// ---------------------------------------------------------------------------
+constexpr int kBarTop = 0, kBarGen = 8, kBarDone = 4, kBarGroups = 16;   // offsets in PersistArgs::bar
+
+// Stage stamp of workgroup 0 (thread 0) for the first trace_frames frames.
+__device__ __forceinline__ void trace_stamp(const PersistArgs &p, int f, int stage) {
+  if (p.trace != nullptr && f < p.trace_frames && blockIdx.x == 0 && threadIdx.x == 0)
+    p.trace[(int64_t)f * kTraceStages + stage] = wall_clock64();
+}
+
+__device__ __forceinline__ bool bounded_wait(const PersistArgs &p, const uint32_t *word, uint32_t target) {
+  int32_t spins = 0;
+  while (__hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    __builtin_amdgcn_s_sleep(1);
+    if (++spins > p.spin_limit) {
+      __hip_atomic_store(p.abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(p.sticky, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return false;
+    }
+  }
+  return true;
+}
+
+__device__ __forceinline__ void frame_barrier(const PersistArgs &p, uint32_t epoch) {
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // this wavefront's stores are complete
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t G = gridDim.x;
+    const uint32_t grp = blockIdx.x % 16;
+    const uint32_t per = (G - grp + 15) / 16;          // workgroups in this group
+    const uint32_t ngrp = G < 16 ? G : 16;
+    const uint32_t prev =
+        __hip_atomic_fetch_add(p.bar + kBarGroups + 16 * grp, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (prev == epoch * per - 1) {
+      const uint32_t top = __hip_atomic_fetch_add(p.bar + kBarTop, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (top == epoch * ngrp - 1)
+        __hip_atomic_store(p.bar + kBarGen, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    (void)bounded_wait(p, p.bar + kBarGen, epoch);
+  }
+  __syncthreads();
+}
+
+template <int FMT, int KPL>
+__device__ __forceinline__ float chunk_dot(const uint4 (&m)[KPL], const float (&sv)[KPL][Codec<FMT>::EPC]) {
+  constexpr int EPC = Codec<FMT>::EPC;
+  float acc[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int j = 0; j < KPL; ++j) {
+    float v[EPC];
+    Codec<FMT>::decode(m[j], v);
+#pragma unroll
+    for (int e = 0; e < EPC; ++e) acc[e & 3] = fmaf(v[e], sv[j][e], acc[e & 3]);
+  }
+  return (acc[0] + acc[1]) + (acc[2] + acc[3]);
+}
+
+// Wavefront sums of NR rows at once, so the DPP latencies overlap.
+template <int NR>
+__device__ __forceinline__ void wave_sum_rows(float (&t)[NR]) {
+#pragma unroll
+  for (int r = 0; r < NR; ++r) t[r] += dpp_read<0xB1>(t[r]);
+#pragma unroll
+  for (int r = 0; r < NR; ++r) t[r] += dpp_read<0x4E>(t[r]);
+#pragma unroll
+  for (int r = 0; r < NR; ++r) t[r] += dpp_read<0x141>(t[r]);
+#pragma unroll
+  for (int r = 0; r < NR; ++r) t[r] += dpp_read<0x140>(t[r]);
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(t[r]), 0));
+    const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(t[r]), 16));
+    const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(t[r]), 32));
+    const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(t[r]), 48));
+    t[r] = (r0 + r1) + (r2 + r3);
+  }
+}
+
+// NB slab rows held in LDS, starting at row r0: partial sums into sh_part.
+template <int FMT, int KPL, int NB>
+__device__ __forceinline__ void lds_row_group(const uint4 *lds, int ldq16, int r0, const int (&col)[KPL],
+                                              const float (&sv)[KPL][Codec<FMT>::EPC], float *sh_part,
+                                              int wave, int lane, int max_rows) {
+  float t[NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    uint4 m[KPL];
+#pragma unroll
+    for (int j = 0; j < KPL; ++j) m[j] = lds[(int64_t)(r0 + i) * ldq16 + col[j]];
+    t[i] = chunk_dot<FMT, KPL>(m, sv);
+  }
+  wave_sum_rows<NB>(t);
+  if (lane == 0) {
+#pragma unroll
+    for (int i = 0; i < NB; ++i) sh_part[wave * max_rows + r0 + i] = t[i];
+  }
+}
+
+template <int FMT, int KPL, int RR, int GS>
+__global__ __launch_bounds__(512) void frames_kernel(PersistArgs p, int32_t max_rows, int32_t lds_rows) {
+  constexpr int W = 8;
+  constexpr int EPC = Codec<FMT>::EPC;
+  constexpr int RB = KPL <= 2 ? 4 : 2;             // streamed rows per batch
+  extern __shared__ uint4 lds[];                   // [lds_rows][ldq16] slab, then [W][max_rows] floats
+  __shared__ uint32_t sh_abort;
+  const MvmArgs &a = p.mvm;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int G = gridDim.x;
+  const int b = blockIdx.x;
+  const int ldq16 = (int)(a.ldq_bytes / 16);
+  float *sh_part = reinterpret_cast<float *>(lds + (int64_t)lds_rows * ldq16);
+  const int row_begin = (int)(((int64_t)b * a.n_act) / G);
+  const int nrows = (int)(((int64_t)(b + 1) * a.n_act) / G) - row_begin;
+  const int k_begin = (int)(((int64_t)b * p.cal.n_valid) / G);
+  const int k_end = (int)(((int64_t)(b + 1) * p.cal.n_valid) / G);
+  constexpr int SPP = W * 64 / GS;                 // subapertures per calibration pass
+  const int kc = slice_chunks(a.n_chunks, W);      // chunks per wavefront slice (whole 64-chunk groups)
+  const int k_lo = wave * kc;
+  const int k_hi = min(k_lo + kc, a.n_chunks);
+  const uint4 *slab = reinterpret_cast<const uint4 *>(static_cast<const char *>(a.Rq) +
+                                                      (int64_t)row_begin * a.ldq_bytes);
+
+  int col[KPL];
+  bool okc[KPL];
+#pragma unroll
+  for (int j = 0; j < KPL; ++j) {
+    const int c = k_lo + j * 64 + lane;
+    okc[j] = c < k_hi;
+    col[j] = okc[j] ? c : 0;
+  }
+
+  // on-chip slab: rows [0, L) in LDS, [L, L + nreg) in registers, the rest streamed
+  const int L = min(lds_rows, nrows);
+  const int nreg = min(RR, max(0, nrows - L));
+  const int stream_begin = L + nreg;
+  for (int64_t c = tid; c < (int64_t)L * ldq16; c += W * 64) lds[c] = slab[c];
+  uint4 rr[RR > 0 ? RR : 1][KPL];
+#pragma unroll
+  for (int i = 0; i < RR; ++i) {
+    const int row = min(L + i, nrows - 1);
+#pragma unroll
+    for (int j = 0; j < KPL; ++j) rr[i][j] = slab[(int64_t)row * ldq16 + col[j]];
+  }
+  float state = 0.f;
+  if (tid < nrows) state = a.state[row_begin + tid];
+  __syncthreads();
+
+  for (int f = 0; f < p.n_frames; ++f) {
+    if (tid == 0) sh_abort = __hip_atomic_load(p.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    if (sh_abort) break;                            // a bounded wait expired somewhere: wind down
+    if (p.ts != nullptr && b == 0 && tid == 0) p.ts[2 * f] = wall_clock64();
+    trace_stamp(p, f, 0);
+
+    // (a)-(b) this workgroup's subapertures of frame f, published coherently
+    CalibArgs ca = p.cal;
+    ca.pix = p.cal.pix + (int64_t)f * p.frame_stride;
+    ca.s_int = p.sbuf + (int64_t)(f & 1) * p.s_len;
+    ca.s_user = p.cal.s_user ? p.cal.s_user + (int64_t)f * 2 * p.cal.n_valid : nullptr;
+    ca.counts = p.cal.counts ? p.cal.counts + (int64_t)f * p.cal.n_valid : nullptr;
+    for (int k0 = k_begin; k0 < k_end; k0 += SPP) {
+      const int kk = k0 + tid / GS;
+      calib_tile_row<GS, true>(ca, kk < k_end ? kk : p.cal.n_valid, tid & (GS - 1), p.vec);
+    }
+    trace_stamp(p, f, 1);
+    frame_barrier(p, (uint32_t)(f + 1));
+    trace_stamp(p, f, 2);
+
+    // slope slices of this wavefront (device-coherent loads)
+    float sv[KPL][EPC];
+#pragma unroll
+    for (int j = 0; j < KPL; ++j) {
+      // this lane's chunk group; lanes past the slice read group 0 (in bounds) and zero it
+      const int64_t g = okc[j] ? (int64_t)((k_lo >> 6) + j) : 0;
+      const float *grp = ca.s_int + g * (64 * EPC) + lane;
+#pragma unroll
+      for (int e = 0; e < EPC; ++e) {
+        const float v = __hip_atomic_load(grp + e * 64, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        sv[j][e] = okc[j] ? v : 0.f;
+      }
+    }
+    if (p.trace != nullptr) {                       // stage 3: slope slices in registers
+      float probe = 0.f;
+#pragma unroll
+      for (int j = 0; j < KPL; ++j) probe += sv[j][0];
+      if (probe == 1.2345e-30f) sh_part[0] = probe;   // keeps the loads ahead of the stamp
+      trace_stamp(p, f, 3);
+    }
+
+    // (c) LDS rows in groups of 8, then 4, 2, 1 (no duplicated rows)
+    {
+      int r0 = 0;
+      for (; r0 + 8 <= L; r0 += 8)
+        lds_row_group<FMT, KPL, 8>(lds, ldq16, r0, col, sv, sh_part, wave, lane, max_rows);
+      if (r0 + 4 <= L) {
+        lds_row_group<FMT, KPL, 4>(lds, ldq16, r0, col, sv, sh_part, wave, lane, max_rows);
+        r0 += 4;
+      }
+      if (r0 + 2 <= L) {
+        lds_row_group<FMT, KPL, 2>(lds, ldq16, r0, col, sv, sh_part, wave, lane, max_rows);
+        r0 += 2;
+      }
+      if (r0 < L) lds_row_group<FMT, KPL, 1>(lds, ldq16, r0, col, sv, sh_part, wave, lane, max_rows);
+    }
+    // register rows
+    if (nreg > 0) {
+      float t[RR > 0 ? RR : 1];
+#pragma unroll
+      for (int i = 0; i < RR; ++i) t[i] = chunk_dot<FMT, KPL>(rr[i], sv);
+      wave_sum_rows<(RR > 0 ? RR : 1)>(t);
+#pragma unroll
+      for (int i = 0; i < RR; ++i)
+        if (lane == 0 && i < nreg) sh_part[wave * max_rows + L + i] = t[i];
+    }
+    // streamed rows
+    for (int r0 = stream_begin; r0 < nrows; r0 += RB) {
+      uint4 m[RB][KPL];
+#pragma unroll
+      for (int i = 0; i < RB; ++i) {
+        const int row = min(r0 + i, nrows - 1);
+#pragma unroll
+        for (int j = 0; j < KPL; ++j) m[i][j] = slab[(int64_t)row * ldq16 + col[j]];
+      }
+      float t[RB];
+#pragma unroll
+      for (int i = 0; i < RB; ++i) t[i] = chunk_dot<FMT, KPL>(m[i], sv);
+      wave_sum_rows<RB>(t);
+#pragma unroll
+      for (int i = 0; i < RB; ++i)
+        if (lane == 0 && r0 + i < nrows) sh_part[wave * max_rows + r0 + i] = t[i];
+    }
+    __syncthreads();
+    trace_stamp(p, f, 4);
+
+    // (d) integrate own rows
+    if (tid < nrows) {
+      float v = sh_part[tid];
+      for (int w = 1; w < W; ++w) v += sh_part[w * max_rows + tid];
+      if (a.scales != nullptr) v *= a.scales[row_begin + tid];
+      float c = fmaf(a.gain, v, a.leak * state);
+      c = fminf(fmaxf(c, a.cmd_min), a.cmd_max);
+      state = c;
+      a.cmd[(int64_t)f * a.n_act + row_begin + tid] = c;
+      if (a.recon != nullptr) a.recon[(int64_t)f * a.n_act + row_begin + tid] = v;
+    }
+    trace_stamp(p, f, 5);
+    if (p.ts != nullptr) {                         // last workgroup to finish frame f stamps its end
+      __syncthreads();
+      if (tid == 0) {
+        const uint32_t prev =
+            __hip_atomic_fetch_add(p.bar + kBarDone, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (prev == (uint32_t)(f + 1) * (uint32_t)G - 1) p.ts[2 * f + 1] = wall_clock64();
+      }
+    }
+  }
+  if (tid < nrows) a.state[row_begin + tid] = state;
 }
 
 // Sum of the k_split partial actuator vectors in a fixed 64-leaf pairwise tree
@@ -406,33 +799,44 @@ hipError_t launch_mvm_integrate(const MvmArgs &in, int32_t *used, hipStream_t st
   return hipGetLastError();
 }
 
-template <int W, int KPL, int RB>
+template <int FMT, int W, int KPL, int RB>
 static void launch_block_variant(const MvmArgs &a, int G, int max_rows, hipStream_t st) {
-  mvm_block_kernel<W, KPL, RB><<<G, W * 64, (size_t)W * max_rows * sizeof(float), st>>>(a, max_rows);
+  mvm_block_kernel<FMT, W, KPL, RB><<<G, W * 64, (size_t)W * max_rows * sizeof(float), st>>>(a, max_rows);
 }
 
-template <int W>
+// Register budget: RB x KPL chunks in flight per lane stays small; the
+// requested rows per batch is lowered to the nearest instantiated value.
+template <int FMT, int W>
 static hipError_t launch_block_w(const MvmArgs &a, int G, int max_rows, int kpl, int rb, hipStream_t st) {
-  // register budget: RB x KPL 16-byte loads in flight per lane stays <= 16
   if (kpl <= 1) {
-    if (rb >= 8) launch_block_variant<W, 1, 8>(a, G, max_rows, st);
-    else launch_block_variant<W, 1, 4>(a, G, max_rows, st);
+    if (rb >= 4) launch_block_variant<FMT, W, 1, 4>(a, G, max_rows, st);
+    else if (rb >= 2) launch_block_variant<FMT, W, 1, 2>(a, G, max_rows, st);
+    else launch_block_variant<FMT, W, 1, 1>(a, G, max_rows, st);
   } else if (kpl <= 2) {
-    if (rb >= 8) launch_block_variant<W, 2, 8>(a, G, max_rows, st);
-    else launch_block_variant<W, 2, 4>(a, G, max_rows, st);
+    if (rb >= 4) launch_block_variant<FMT, W, 2, 4>(a, G, max_rows, st);
+    else if (rb >= 2) launch_block_variant<FMT, W, 2, 2>(a, G, max_rows, st);
+    else launch_block_variant<FMT, W, 2, 1>(a, G, max_rows, st);
   } else if (kpl <= 4) {
-    if (rb >= 4) launch_block_variant<W, 4, 4>(a, G, max_rows, st);
-    else launch_block_variant<W, 4, 2>(a, G, max_rows, st);
+    if (rb >= 2) launch_block_variant<FMT, W, 4, 2>(a, G, max_rows, st);
+    else launch_block_variant<FMT, W, 4, 1>(a, G, max_rows, st);
   } else if (kpl <= 8) {
-    if (rb >= 2) launch_block_variant<W, 8, 2>(a, G, max_rows, st);
-    else launch_block_variant<W, 8, 1>(a, G, max_rows, st);
+    launch_block_variant<FMT, W, 8, 1>(a, G, max_rows, st);
   } else {
     return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
+template <int FMT>
+static hipError_t launch_block_fmt(const MvmArgs &a, int G, int max_rows, int waves, int kpl, int rb,
+                                   hipStream_t st) {
+  return waves == 8 ? launch_block_w<FMT, 8>(a, G, max_rows, kpl, rb, st)
+                    : launch_block_w<FMT, 16>(a, G, max_rows, kpl, rb, st);
+}
+
 int mvm_block_max_kpl() { return 8; }
+
+int format_elems_per_chunk(int fmt) { return fmt == 0 ? 4 : (fmt == 3 ? 16 : 8); }
 
 hipError_t launch_mvm_block(const MvmArgs &a, int blocks, int waves, int rows_per_batch, hipStream_t st) {
   if (waves != 8 && waves != 16) return hipErrorInvalidValue;
@@ -444,11 +848,82 @@ hipError_t launch_mvm_block(const MvmArgs &a, int blocks, int waves, int rows_pe
     G = (a.n_act + lds_rows - 1) / lds_rows;
     max_rows = (a.n_act + G - 1) / G;
   }
-  const int kc = (a.n_s4 + waves - 1) / waves;
-  const int kpl = (kc + 63) / 64;
+  const int kpl = slice_chunks(a.n_chunks, waves) / 64;
   if (kpl > mvm_block_max_kpl()) return hipErrorInvalidValue;
-  return waves == 8 ? launch_block_w<8>(a, G, max_rows, kpl, rows_per_batch, st)
-                    : launch_block_w<16>(a, G, max_rows, kpl, rows_per_batch, st);
+  switch (a.fmt) {
+    case 0: return launch_block_fmt<0>(a, G, max_rows, waves, kpl, rows_per_batch, st);
+    case 1: return launch_block_fmt<1>(a, G, max_rows, waves, kpl, rows_per_batch, st);
+    case 2: return launch_block_fmt<2>(a, G, max_rows, waves, kpl, rows_per_batch, st);
+    case 3: return launch_block_fmt<3>(a, G, max_rows, waves, kpl, rows_per_batch, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int FMT, int KPL, int GS>
+static hipError_t launch_frames_variant(const PersistArgs &p, int G, int max_rows, hipStream_t st) {
+  constexpr int W = 8;
+  constexpr int RR = 16 / KPL;                      // register rows: 64 VGPRs of codes per lane
+  auto kern = frames_kernel<FMT, KPL, RR, GS>;
+  int dev = 0, ncu = 0, lds_max = 0;
+  hipError_t e;
+  if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+  if ((e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+  if ((e = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev)) != hipSuccess) return e;
+  const int64_t part_bytes = (int64_t)W * max_rows * sizeof(float);
+  const int64_t static_bytes = 64;                 // sh_abort and alignment slack
+  int64_t avail = (int64_t)lds_max - part_bytes - static_bytes;
+  int lds_rows = avail > 0 ? (int)(avail / p.mvm.ldq_bytes) : 0;
+  if (lds_rows > max_rows) lds_rows = max_rows;
+  const size_t lds = (size_t)lds_rows * p.mvm.ldq_bytes + (size_t)part_bytes;
+  if ((e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)lds)) != hipSuccess)
+    return e;
+  int per_cu = 0;
+  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, W * 64, lds)) != hipSuccess) return e;
+  if (per_cu * ncu < G) return hipErrorCooperativeLaunchTooLarge;
+  PersistArgs pa = p;
+  int32_t mr = max_rows, lr = lds_rows;
+  void *args[] = {&pa, &mr, &lr};
+  e = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(kern), dim3(G), dim3(W * 64), args, lds, st);
+  if (e != hipSuccess) return e;
+  return hipGetLastError();
+}
+
+template <int FMT, int KPL>
+static hipError_t launch_frames_gs(const PersistArgs &p, int G, int max_rows, hipStream_t st) {
+  const int n = p.cal.n_pix;
+  if (n <= 8) return launch_frames_variant<FMT, KPL, 8>(p, G, max_rows, st);
+  if (n <= 16) return launch_frames_variant<FMT, KPL, 16>(p, G, max_rows, st);
+  return launch_frames_variant<FMT, KPL, 32>(p, G, max_rows, st);
+}
+
+template <int FMT>
+static hipError_t launch_frames_fmt(const PersistArgs &p, int G, int max_rows, int kpl, hipStream_t st) {
+  if (kpl <= 1) return launch_frames_gs<FMT, 1>(p, G, max_rows, st);
+  if (kpl <= 2) return launch_frames_gs<FMT, 2>(p, G, max_rows, st);
+  if (kpl <= 4) return launch_frames_gs<FMT, 4>(p, G, max_rows, st);
+  if (kpl <= 8) return launch_frames_gs<FMT, 8>(p, G, max_rows, st);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_frames(const PersistArgs &p, int blocks, int rows_per_batch, hipStream_t st) {
+  (void)rows_per_batch;
+  constexpr int W = 8;
+  if (p.n_frames <= 0) return hipSuccess;
+  if (p.cal.n_pix < 1 || p.cal.n_pix > 32) return hipErrorInvalidValue;
+  int G = blocks < 1 ? 1 : blocks;
+  if (G > p.mvm.n_act) G = p.mvm.n_act;
+  const int max_rows = (p.mvm.n_act + G - 1) / G;
+  if (max_rows > W * 64) return hipErrorInvalidValue;      // one integrator row per thread
+  const int kpl = slice_chunks(p.mvm.n_chunks, W) / 64;
+  if (kpl > mvm_block_max_kpl()) return hipErrorInvalidValue;
+  switch (p.mvm.fmt) {
+    case 0: return launch_frames_fmt<0>(p, G, max_rows, kpl, st);
+    case 1: return launch_frames_fmt<1>(p, G, max_rows, kpl, st);
+    case 2: return launch_frames_fmt<2>(p, G, max_rows, kpl, st);
+    case 3: return launch_frames_fmt<3>(p, G, max_rows, kpl, st);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 bool mvm_variant_supported(int rows_per_wave, int unroll) {

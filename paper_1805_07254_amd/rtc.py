@@ -22,6 +22,7 @@ RTC_OK, RTC_E_ARG, RTC_E_STATE, RTC_E_NOMEM, RTC_E_DEVICE, RTC_E_NONFINITE, RTC_
     0, -1, -2, -3, -4, -5, -6
 RTC_THR_SUBTRACT, RTC_THR_ZERO = 1, 2
 RTC_CM_F32, RTC_CM_F16, RTC_CM_BF16, RTC_CM_FP8E4M3 = 0, 1, 2, 3
+CM_DTYPES = {"f32": RTC_CM_F32, "f16": RTC_CM_F16, "bf16": RTC_CM_BF16, "fp8e4m3": RTC_CM_FP8E4M3}
 STATUS_NAMES = {0: "RTC_OK", -1: "RTC_E_ARG", -2: "RTC_E_STATE", -3: "RTC_E_NOMEM",
                 -4: "RTC_E_DEVICE", -5: "RTC_E_NONFINITE", -6: "RTC_E_UNSUPPORTED"}
 
@@ -41,6 +42,7 @@ class rtc_config(ctypes.Structure):
 
 
 RTC_MVM_ROWBLOCK, RTC_MVM_STREAMED = 0, 1
+RTC_FRAMES_PER_LAUNCH, RTC_FRAMES_PERSISTENT = 0, 1
 
 
 class rtc_mvm_tuning(ctypes.Structure):
@@ -53,12 +55,16 @@ _SIGNATURES = {
     "rtc_init": (_i32, [ctypes.POINTER(rtc_config), ctypes.POINTER(_vp)]),
     "rtc_load_calib": (_i32, [_vp, _vp, _vp, _f32, _vp]),
     "rtc_load_cmat": (_i32, [_vp, _vp, _i32, _i32, _i64]),
+    "rtc_encode_cmat": (_i32, [_i32, _vp, _i32, _i32, _i64, _vp, _vp]),
     "rtc_frame": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "rtc_frame_batch": (_i32, [_vp, _i32, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp]),
     "rtc_calibrate_centroid": (_i32, [_vp, _vp, _vp, _vp, _vp]),
     "rtc_reconstruct_integrate": (_i32, [_vp, _vp, _vp, _vp, _vp]),
     "rtc_set_mvm_tuning": (_i32, [_vp, ctypes.POINTER(rtc_mvm_tuning)]),
     "rtc_get_mvm_tuning": (_i32, [_vp, ctypes.POINTER(rtc_mvm_tuning)]),
+    "rtc_set_frame_mode": (_i32, [_vp, _i32, _i32]),
+    "rtc_sync_check": (_i32, [_vp]),
+    "rtc_set_trace": (_i32, [_vp, _vp, _i32]),
     "rtc_reset": (_i32, [_vp]),
     "rtc_get_state": (_i32, [_vp, _vp]),
     "rtc_set_state": (_i32, [_vp, _vp]),
@@ -172,10 +178,12 @@ def _stream_ptr(stream) -> Optional[int]:
 
 # --------------------------------------------------------------------------- API
 def rtc_init(subap_mask: np.ndarray, n_pix: int, n_act: int, thr_mode: int = RTC_THR_SUBTRACT,
-             cm_dtype: int = RTC_CM_F32, gain: float = 0.4, leak: float = 1.0,
+             cm_dtype=RTC_CM_F32, gain: float = 0.4, leak: float = 1.0,
              cmd_min: float = -math.inf, cmd_max: float = math.inf, device: int = 0,
              abi_version: int = RTC_ABI_VERSION) -> RtcContext:
     lib = load_library()
+    if isinstance(cm_dtype, str):
+        cm_dtype = CM_DTYPES[cm_dtype]
     mask = np.ascontiguousarray(subap_mask, dtype=np.uint8)
     if mask.ndim != 2:
         raise ValueError("subap_mask must be 2-D [n_sub_y, n_sub_x]")
@@ -186,7 +194,7 @@ def rtc_init(subap_mask: np.ndarray, n_pix: int, n_act: int, thr_mode: int = RTC
     st = lib.rtc_init(ctypes.byref(cfg), ctypes.byref(out))
     _check(st, None)
     return RtcContext(out.value, {"n_sub_x": mask.shape[1], "n_sub_y": mask.shape[0], "n_pix": n_pix,
-                                  "n_act": n_act, "device": device, "thr_mode": thr_mode,
+                                  "n_act": n_act, "device": device, "thr_mode": thr_mode, "cm_dtype": cm_dtype,
                                   "gain": gain, "leak": leak})
 
 
@@ -209,6 +217,18 @@ def rtc_load_cmat(ctx: RtcContext, R: np.ndarray, n_slopes: Optional[int] = None
         raise ValueError("R must be 2-D [n_act, ld]")
     ns = m.shape[1] if n_slopes is None else int(n_slopes)
     _check(load_library().rtc_load_cmat(ctx.handle, mp, m.shape[0], ns, m.shape[1]), ctx)
+
+
+def rtc_encode_cmat(cm_dtype: int, R: np.ndarray):
+    """(codes, scales) of a float32 matrix in a reduced storage format (host only)."""
+    m, mp = _host_ptr(R, np.float32)
+    if m.ndim != 2:
+        raise ValueError("R must be 2-D")
+    codes = np.empty(m.shape, dtype=np.uint8 if cm_dtype == RTC_CM_FP8E4M3 else np.uint16)
+    scales = np.empty(m.shape[0], dtype=np.float32)
+    _check(load_library().rtc_encode_cmat(cm_dtype, mp, m.shape[0], m.shape[1], m.shape[1],
+                                          codes.ctypes.data, scales.ctypes.data), None)
+    return codes, scales
 
 
 def rtc_frame(ctx: RtcContext, pixels, cmd, slopes=None, recon=None, counts=None, stream=None) -> None:
@@ -271,6 +291,20 @@ def rtc_get_mvm_tuning(ctx: RtcContext) -> dict:
     t = rtc_mvm_tuning()
     _check(load_library().rtc_get_mvm_tuning(ctx.handle, ctypes.byref(t)), ctx)
     return {name: getattr(t, name) for name, _ in rtc_mvm_tuning._fields_}
+
+
+def rtc_set_frame_mode(ctx: RtcContext, mode: int, spin_limit: int = 0) -> None:
+    _check(load_library().rtc_set_frame_mode(ctx.handle, mode, spin_limit), ctx)
+
+
+def rtc_set_trace(ctx: RtcContext, trace=None, max_frames: int = 0) -> None:
+    """Stage stamps of persistent batches into a device tensor [max_frames, 8] (int64/uint64)."""
+    ptr = _dev_ptr(trace, ("uint64", "int64"), 8 * max_frames, "trace", ctx, False) if max_frames else None
+    _check(load_library().rtc_set_trace(ctx.handle, ptr, max_frames), ctx)
+
+
+def rtc_sync_check(ctx: RtcContext) -> None:
+    _check(load_library().rtc_sync_check(ctx.handle), ctx)
 
 
 def rtc_reset(ctx: RtcContext) -> None:

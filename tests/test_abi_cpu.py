@@ -54,7 +54,7 @@ def _cfg(**kw):
     (dict(n_act=0), rtc.RTC_E_ARG, "n_act"),
     (dict(thr_mode=0), rtc.RTC_E_ARG, "thr_mode"),
     (dict(cm_dtype=7), rtc.RTC_E_ARG, "cm_dtype"),
-    (dict(cm_dtype=2), rtc.RTC_E_UNSUPPORTED, "RTC_CM_F32"),
+    (dict(cm_dtype=2, n_pix=1, mask=np.ones((200, 200), np.uint8)), rtc.RTC_E_UNSUPPORTED, "too long"),
     (dict(gain=math.nan), rtc.RTC_E_NONFINITE, "gain"),
     (dict(leak=math.inf), rtc.RTC_E_NONFINITE, "gain"),
     (dict(cmd_min=1.0, cmd_max=-1.0), rtc.RTC_E_ARG, "cmd_min"),

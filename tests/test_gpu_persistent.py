@@ -1,0 +1,120 @@
+"""Persistent frame batches (one cooperative launch, one grid barrier per frame)."""
+import numpy as np
+import pytest
+
+from _closedloop import oracle_closed_loop
+from _gpu_helpers import _ctx_for, _dev, _gpu_batch, check_parity
+from aosim import ELT, TINY, Scenario, geometry
+
+torch = pytest.importorskip("torch")
+from paper_1805_07254_amd import rtc  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    rtc.load_library()
+
+
+@pytest.fixture(scope="module")
+def tiny_loop():
+    sc = Scenario(TINY)
+    return (sc,) + oracle_closed_loop(sc, 300)
+
+
+@pytest.fixture(scope="module")
+def elt_loop():
+    sc = Scenario(ELT)
+    return (sc,) + oracle_closed_loop(sc, 5)
+
+
+def _both_modes(sc, frames, fmt):
+    with _ctx_for(sc, cm_dtype=fmt) as ctx:
+        per = _gpu_batch(ctx, frames, ts=True)
+        rtc.rtc_reset(ctx)
+        rtc.rtc_set_frame_mode(ctx, rtc.RTC_FRAMES_PERSISTENT)
+        pers = _gpu_batch(ctx, frames, ts=True)
+        rtc.rtc_sync_check(ctx)
+        state = rtc.rtc_get_state(ctx)
+    return per, pers, state
+
+
+@pytest.mark.parametrize("fmt", ["f32", "f16", "bf16", "fp8e4m3"])
+@pytest.mark.parametrize("which", ["tiny", "elt"])
+def test_persistent_batch_is_bitwise_identical_to_per_launch(which, fmt, request):
+    sc, frames, ref = request.getfixturevalue(f"{which}_loop")
+    per, pers, state = _both_modes(sc, frames, fmt)
+    for key in ("counts", "slopes", "recon", "cmd"):
+        assert np.array_equal(per[key], pers[key]), f"{which} {fmt}: {key} differs"
+    assert np.array_equal(state, pers["cmd"][-1])
+    ts = pers["ts"]
+    # frame f+1's calibration may start while other workgroups still finish frame f,
+    # so only starts, ends and each frame's own span are ordered
+    assert np.all(ts[:, 1] > ts[:, 0])
+    assert np.all(ts[1:, 0] >= ts[:-1, 0]) and np.all(ts[1:, 1] >= ts[:-1, 1])
+    if fmt == "f32":
+        check_parity(pers, ref, sc.cfg.gain, sc.cfg.leak, what=f"{which} persistent")
+
+
+def test_persistent_batch_continues_from_state_and_chunks_compose(tiny_loop):
+    sc, frames, ref = tiny_loop
+    with _ctx_for(sc) as ctx:
+        rtc.rtc_set_frame_mode(ctx, rtc.RTC_FRAMES_PERSISTENT)
+        whole = _gpu_batch(ctx, frames[:40])
+        rtc.rtc_reset(ctx)
+        a = _gpu_batch(ctx, frames[:17])
+        b = _gpu_batch(ctx, frames[17:40])
+        rtc.rtc_sync_check(ctx)
+    assert np.array_equal(np.concatenate([a["cmd"], b["cmd"]]), whole["cmd"])
+
+
+def test_expired_barrier_wait_is_reported_and_cleared(tiny_loop):
+    # A spin limit of one poll makes the kernel's own bounded waits give up; the
+    # batch winds down normally and the host is told.
+    sc, frames, ref = tiny_loop
+    with _ctx_for(sc) as ctx:
+        rtc.rtc_set_frame_mode(ctx, rtc.RTC_FRAMES_PERSISTENT, spin_limit=1)
+        _gpu_batch(ctx, np.concatenate([frames] * 2))
+        with pytest.raises(rtc.RtcError) as ei:
+            rtc.rtc_sync_check(ctx)
+        assert ei.value.status == rtc.RTC_E_DEVICE and "barrier" in str(ei.value)
+        rtc.rtc_sync_check(ctx)                     # cleared
+        rtc.rtc_set_frame_mode(ctx, rtc.RTC_FRAMES_PERSISTENT)
+        rtc.rtc_reset(ctx)
+        good = _gpu_batch(ctx, frames[:20])
+        rtc.rtc_sync_check(ctx)
+    check_parity(good, {k: v[:20] for k, v in ref.items()}, sc.cfg.gain, sc.cfg.leak, what="after abort")
+
+
+def test_unsupported_persistent_shape_runs_per_launch():
+    # 19,000+ float32 slopes exceed the persistent kernel's register slices
+    rng = np.random.default_rng(8)
+    mask = geometry.subaperture_mask(110, 0.0)
+    nv = int(mask.sum())
+    H = 110
+    frames = rng.integers(95, 200, size=(2, H, H)).astype(np.uint16)
+    dark = np.full((H, H), 100.0, np.float32)
+    flat = np.ones((H, H), np.float32)
+    R = (rng.standard_normal((40, 2 * nv)) / 100).astype(np.float32)
+    out = []
+    for mode in (rtc.RTC_FRAMES_PER_LAUNCH, rtc.RTC_FRAMES_PERSISTENT):
+        with rtc.rtc_init(mask, 1, 40) as ctx:
+            rtc.rtc_load_calib(ctx, dark, flat, 3.0)
+            rtc.rtc_load_cmat(ctx, R)
+            rtc.rtc_set_frame_mode(ctx, mode)
+            out.append(_gpu_batch(ctx, frames))
+            rtc.rtc_sync_check(ctx)
+    assert 2 * nv > 16384
+    for key in out[0]:
+        assert np.array_equal(out[0][key], out[1][key])
+
+
+def test_frame_mode_validation():
+    with rtc.rtc_init(np.ones((2, 2), np.uint8), 2, 3) as ctx:
+        for bad in [(2, 0), (-1, 0), (1, -5)]:
+            with pytest.raises(rtc.RtcError) as ei:
+                rtc.rtc_set_frame_mode(ctx, *bad)
+            assert ei.value.status == rtc.RTC_E_ARG

@@ -234,12 +234,16 @@ typedef enum { RTC_FRAMES_PER_LAUNCH = 0, RTC_FRAMES_PERSISTENT = 1 } rtc_frame_
 rtc_status rtc_set_frame_mode(rtc_ctx *c, int32_t mode, int32_t spin_limit);
 
 /* Stage tracing of persistent batches: when set, each persistent batch writes
- * for its frames f < max_frames the device wall-clock stamps of workgroup 0 at
- * d_trace[f][0..5] = frame start, own slopes published, frame barrier passed,
- * slope slices loaded, partial sums done, commands written ([6], [7] unused).
- * d_trace is a caller-owned device buffer of max_frames * 8 uint64 that must
- * stay valid while batches run; max_frames = 0 turns tracing off. */
-rtc_status rtc_set_trace(rtc_ctx *c, uint64_t *d_trace, int32_t max_frames);
+ * for its frames f < max_frames and its workgroups g < n_groups the device
+ * wall-clock stamps (rtc_wall_clock_khz ticks) at
+ * d_trace[f][g][0..7] = frame start, own slopes issued, frame barrier
+ * passed, slope slices loaded, partial sums done, commands written, own
+ * stores complete (barrier entry), own arrival counted.  Entries of
+ * workgroups the batch does not launch stay untouched.
+ * d_trace is a caller-owned device buffer of max_frames * n_groups * 8
+ * uint64 that must stay valid while batches run; max_frames = 0 turns
+ * tracing off; n_groups must be in [1, 4096] when max_frames > 0. */
+rtc_status rtc_set_trace(rtc_ctx *c, uint64_t *d_trace, int32_t max_frames, int32_t n_groups);
 
 /* Synchronises the device and reports RTC_E_DEVICE if a persistent batch gave
  * up at a barrier since the last check (the flag is then cleared). */

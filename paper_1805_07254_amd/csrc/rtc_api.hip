@@ -49,11 +49,12 @@ struct rtc_ctx {
   float *d_state = nullptr;
   float *d_part = nullptr;
   float *d_sbuf = nullptr;   // [2][s_len] slope vectors of consecutive frames (persistent batches)
-  uint32_t *d_sync = nullptr;  // [0] stamp counter, [1] abort, [2] sticky abort, [64, 384) persistent barrier
+  uint32_t *d_sync = nullptr;  // rtck::sync_layout words: stamp counter, abort flags, persistent barrier
   int32_t frame_mode = RTC_FRAMES_PER_LAUNCH;
   int32_t spin_limit = 1 << 22;
-  uint64_t *d_trace = nullptr;  // caller-owned [trace_frames][8] stage stamps (persistent batches)
+  uint64_t *d_trace = nullptr;  // caller-owned [trace_frames][trace_groups][8] stage stamps
   int32_t trace_frames = 0;
+  int32_t trace_groups = 0;
   bool calib_loaded = false;
   bool cmat_loaded = false;
 };
@@ -101,8 +102,7 @@ bool dark_in_domain(float d) {
 // the largest chunk (16 elements), so every format's layout fits.
 int64_t xchg_len_of(int64_t n_slopes) { return (n_slopes + 1023) / 1024 * 1024; }
 
-constexpr int kSyncWords = 512;
-constexpr int kBarBase = 64, kBarWords = 320;
+constexpr int kSyncWords = rtck::sync_layout::kWords;
 
 int64_t round_up4(int64_t x) { return (x + 3) & ~int64_t(3); }
 int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
@@ -543,17 +543,15 @@ rtc_status rtc_frame_batch(rtc_ctx *c, int32_t n_frames, const uint16_t *d_pixel
     ma.leak = c->cfg.leak;
     ma.cmd_min = c->cfg.cmd_min;
     ma.cmd_max = c->cfg.cmd_max;
-    p.bar = c->d_sync + kBarBase;
-    p.abort_flag = c->d_sync + 1;
-    p.sticky = c->d_sync + 2;
+    p.bar = c->d_sync + rtck::sync_layout::kBarBase;
+    p.abort_flag = c->d_sync + rtck::sync_layout::kAbort;
+    p.sticky = c->d_sync + rtck::sync_layout::kSticky;
     p.spin_limit = c->spin_limit;
     p.ts = d_ts;
     p.trace = c->d_trace;
     p.trace_frames = c->trace_frames;
-    hipError_t e = hipMemsetAsync(c->d_sync + kBarBase, 0, kBarWords * sizeof(uint32_t), st);
-    if (e == hipSuccess) e = hipMemsetAsync(c->d_sync + 1, 0, sizeof(uint32_t), st);
-    if (e != hipSuccess) return hip_fail(c, e, "rtc_frame_batch: counter reset");
-    e = rtck::launch_frames(p, c->tuning.blocks > 0 ? c->tuning.blocks : c->n_cu, c->tuning.rows_per_wave, st);
+    p.trace_groups = c->trace_groups;
+    hipError_t e = rtck::launch_frames(p, c->tuning.blocks > 0 ? c->tuning.blocks : c->n_cu, c->tuning.rows_per_wave, st);
     if (e == hipSuccess) return RTC_OK;
     if (e != hipErrorInvalidValue && e != hipErrorCooperativeLaunchTooLarge)
       return hip_fail(c, e, "rtc_frame_batch: persistent launch");
@@ -674,12 +672,15 @@ rtc_status rtc_set_frame_mode(rtc_ctx *c, int32_t mode, int32_t spin_limit) {
   return RTC_OK;
 }
 
-rtc_status rtc_set_trace(rtc_ctx *c, uint64_t *d_trace, int32_t max_frames) {
+rtc_status rtc_set_trace(rtc_ctx *c, uint64_t *d_trace, int32_t max_frames, int32_t n_groups) {
   if (!c) return fail(nullptr, RTC_E_ARG, "rtc_set_trace: NULL context");
   if (max_frames < 0 || (max_frames > 0 && !d_trace))
     return fail(c, RTC_E_ARG, "rtc_set_trace: need a buffer for max_frames > 0");
+  if (max_frames > 0 && (n_groups < 1 || n_groups > 4096))
+    return fail(c, RTC_E_ARG, "rtc_set_trace: n_groups must be in [1, 4096]");
   c->d_trace = max_frames > 0 ? d_trace : nullptr;
   c->trace_frames = max_frames;
+  c->trace_groups = max_frames > 0 ? n_groups : 0;
   return RTC_OK;
 }
 
@@ -689,8 +690,9 @@ rtc_status rtc_sync_check(rtc_ctx *c) {
   hipError_t e = ds.status;
   uint32_t flag = 0;
   if (e == hipSuccess) e = hipDeviceSynchronize();
-  if (e == hipSuccess) e = hipMemcpy(&flag, c->d_sync + 2, sizeof(flag), hipMemcpyDeviceToHost);
-  if (e == hipSuccess && flag) e = hipMemset(c->d_sync + 2, 0, sizeof(uint32_t));
+  uint32_t *sticky = c->d_sync + rtck::sync_layout::kSticky;
+  if (e == hipSuccess) e = hipMemcpy(&flag, sticky, sizeof(flag), hipMemcpyDeviceToHost);
+  if (e == hipSuccess && flag) e = hipMemset(sticky, 0, sizeof(uint32_t));
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) return hip_fail(c, e, "rtc_sync_check");
   if (flag)

@@ -77,15 +77,34 @@ struct PersistArgs {
   float *sbuf;             // [2][s_len] slope vectors of consecutive frames in the exchange layout, zero-padded
   int32_t s_len;           // >= round_up(chunks, 64) * 16 floats
   MvmArgs mvm;             // cmd / recon = per-frame output bases [n_frames][n_act]
-  uint32_t *bar;           // [320] barrier, generation and frame-done words, zero at launch
-  uint32_t *abort_flag;    // raised when a bounded wait expires (zero at launch)
+  uint32_t *bar;           // sync words from sync_layout::kBarBase on (counters and mailboxes zeroed per launch)
+  uint32_t *abort_flag;    // raised when a bounded wait expires (zeroed per launch)
   uint32_t *sticky;        // raised with abort_flag; cleared only by the host
   int32_t spin_limit;      // spins (about 30-60 ns each) before a wait gives up
   uint64_t *ts;            // nullable [n_frames][2]
-  uint64_t *trace;         // nullable [trace_frames][kTraceStages] stage stamps of workgroup 0
+  uint64_t *trace;         // nullable [trace_frames][trace_groups][kTraceStages] stage stamps
   int32_t trace_frames;
+  int32_t trace_groups;
 };
 constexpr int kTraceStages = 8;
+
+// Synchronisation words of a context, in uint32 units.  Arrival counters sit
+// 4 KiB apart so that arrivals and polls at different counters do not queue at
+// one memory channel, and a barrier is released by writing the frame number
+// into one 64-byte mailbox per workgroup, so that every workgroup polls a line
+// of its own.  Offsets from kMailbox on are relative to kBarBase.
+namespace sync_layout {
+constexpr int kStampCounter = 0, kAbort = 1, kSticky = 2;
+constexpr int kBarBase = 1024;
+constexpr int kStride = 1024;
+constexpr int kGroups = 16;                       // group g arrival counter at kStride * g
+constexpr int kTop = kGroups * kStride;           // arrivals of whole groups
+constexpr int kDone = (kGroups + 1) * kStride;    // workgroups done with a batch (end stamp)
+constexpr int kMailbox = (kGroups + 2) * kStride; // + 16 * workgroup
+constexpr int kMaxGroups = 1024;
+constexpr int kEnds = kMailbox + 16 * kMaxGroups; // uint64 [2][kMaxGroups] per-workgroup frame end stamps
+constexpr int kWords = kBarBase + kEnds + 4 * kMaxGroups;
+}  // namespace sync_layout
 // Fails with hipErrorInvalidValue when the shape is unsupported (slab rows
 // beyond one per thread, LDS, register slices) and with the runtime's error
 // when the grid cannot be co-resident.

@@ -158,6 +158,84 @@ __device__ __forceinline__ float wave_sum(float v) {
   return (r0 + r1) + (r2 + r3);
 }
 
+// Sums of NR in {2, 4, 8} rows at once with the rows transposed across lanes:
+// at each of the first log2(NR) butterfly steps a lane keeps one half of its
+// values and sends the other half to its partner, so afterwards each lane
+// holds one row.  Lane l keeps row row_of_lane<NR>(l); the choice bits are
+// XORed with lane bit 2 so that lanes l and l^7 (half-row mirror partners)
+// hold the same rows.  Every row meets exactly the pair, quad, octet, 16-lane
+// and cross-row additions of wave_sum, and floating-point addition is
+// commutative, so each row's result is bitwise that of wave_sum.  On return
+// lanes 0..NR-1 (and their copies in every 8-lane group) hold row sums.
+template <int NR>
+__device__ __forceinline__ int row_of_lane(int lane) {
+  const int b0 = lane & 1, b1 = (lane >> 1) & 1, b2 = (lane >> 2) & 1;
+  if (NR == 2) return b0 ^ b2;
+  if (NR == 4) return 2 * (b1 ^ b2) + (b0 ^ b2);
+  return 4 * b2 + 2 * (b1 ^ b2) + (b0 ^ b2);
+}
+
+template <int NR>
+__device__ __forceinline__ float wave_sum_transposed(const float (&t)[NR], int lane) {
+  static_assert(NR == 2 || NR == 4 || NR == 8, "rows per transposed sum");
+  const bool b2 = (lane >> 2) & 1;
+  const bool s = ((lane & 1) != 0) != b2;          // keep the odd row of each pair
+  float u[NR / 2];
+#pragma unroll
+  for (int p = 0; p < NR / 2; ++p) {
+    const float keep = s ? t[2 * p + 1] : t[2 * p];
+    const float send = s ? t[2 * p] : t[2 * p + 1];
+    u[p] = keep + dpp_read<0xB1>(send);             // partner lane ^ 1
+  }
+  float x;
+  if constexpr (NR == 2) {
+    x = u[0] + dpp_read<0x4E>(u[0]);                // quad
+    x += dpp_read<0x141>(x);                        // octet
+  } else {
+    const bool c = (((lane >> 1) & 1) != 0) != b2;
+    float w[NR / 4];
+#pragma unroll
+    for (int q = 0; q < NR / 4; ++q) {
+      const float keep = c ? u[2 * q + 1] : u[2 * q];
+      const float send = c ? u[2 * q] : u[2 * q + 1];
+      w[q] = keep + dpp_read<0x4E>(send);           // partner lane ^ 2: quad sums
+    }
+    if constexpr (NR == 4) {
+      x = w[0] + dpp_read<0x141>(w[0]);             // octet
+    } else {
+      const float keep = b2 ? w[1] : w[0];
+      const float send = b2 ? w[0] : w[1];
+      x = keep + dpp_read<0x141>(send);             // partner lane ^ 7: octet
+    }
+  }
+  x += dpp_read<0x128>(x);                          // row_ror 8 (lane ^ 8): 16-lane row
+  x += __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(x), 0x401F));   // lane ^ 16
+  x += __int_as_float(__builtin_amdgcn_ds_bpermute((lane ^ 32) << 2, __float_as_int(x)));
+  return x;
+}
+
+// Wavefront sums of NR rows stored to out[0..min(NR, valid)-1].
+template <int NR>
+__device__ __forceinline__ void store_row_sums(float (&t)[NR], float *out, int valid, int lane) {
+  if constexpr (NR == 1) {
+    const float x = wave_sum(t[0]);
+    if (lane == 0 && valid > 0) out[0] = x;
+  } else if constexpr (NR <= 8) {
+    const float x = wave_sum_transposed<NR>(t, lane);
+    const int r = row_of_lane<NR>(lane);
+    if (lane < NR && r < valid) out[r] = x;
+  } else {
+    static_assert(NR % 8 == 0, "row groups of 8");
+#pragma unroll
+    for (int g = 0; g < NR / 8; ++g) {
+      float u[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) u[i] = t[8 * g + i];
+      store_row_sums<8>(u, out + 8 * g, valid - 8 * g, lane);
+    }
+  }
+}
+
 __device__ __forceinline__ float integrate_one(float *state, float *cmd, float *recon, int row,
                                                float a, float gain, float leak, float lo,
                                                float hi) {
@@ -383,6 +461,7 @@ __device__ __forceinline__ void slab_partials(const MvmArgs &a, const float *s, 
 #pragma unroll
       for (int j = 0; j < KPL; ++j) m[i][j] = rp[col[j]];
     }
+    float t[RB];
 #pragma unroll
     for (int i = 0; i < RB; ++i) {
       float acc[4] = {0.f, 0.f, 0.f, 0.f};
@@ -393,10 +472,9 @@ __device__ __forceinline__ void slab_partials(const MvmArgs &a, const float *s, 
 #pragma unroll
         for (int e = 0; e < EPC; ++e) acc[e & 3] = fmaf(v[e], sv[j][e], acc[e & 3]);
       }
-      float t = (acc[0] + acc[1]) + (acc[2] + acc[3]);
-      t = wave_sum(t);
-      if (lane == 0 && rb + i < nrows) sh_part[wave * max_rows + rb + i] = t;
+      t[i] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
     }
+    store_row_sums<RB>(t, sh_part + wave * max_rows + rb, nrows - rb, lane);
   }
 }
 
@@ -438,24 +516,27 @@ __global__ __launch_bounds__(W * 64) void mvm_block_kernel(MvmArgs a, int32_t ma
 // sums over LDS / register / streamed rows, integrate own rows (state stays in
 // registers).
 //
-// Frame barrier: 16 group counters, one top counter and a generation word.
-// The slopes bypass the non-coherent caches, so the barrier needs no cache
-// write-back or invalidation; each wavefront only waits until its own stores
-// have completed before its workgroup arrives.  Every wait is bounded: when
-// one exceeds the spin limit the abort flag is raised and the kernel winds
-// down, so every workgroup always exits.
+// Frame barrier.  Workgroups arrive at 16 group counters; the last arrival of
+// a group arrives at the top counter, and the last of those writes the frame
+// number into every workgroup's mailbox.  The slopes bypass the non-coherent
+// caches, so the barrier needs no cache write-back or invalidation; each
+// wavefront only waits until its own stores have completed before its
+// workgroup arrives.  Every wait is bounded: when one exceeds the spin limit
+// the abort flag is raised and the kernel winds down, so every workgroup
+// always exits.
 // ---------------------------------------------------------------------------
-constexpr int kBarTop = 0, kBarGen = 8, kBarDone = 4, kBarGroups = 16;   // offsets in PersistArgs::bar
+namespace sl = sync_layout;
 
-// Stage stamp of workgroup 0 (thread 0) for the first trace_frames frames.
+// Stage stamp of the first trace_groups workgroups (thread 0) for the first
+// trace_frames frames.
 __device__ __forceinline__ void trace_stamp(const PersistArgs &p, int f, int stage) {
-  if (p.trace != nullptr && f < p.trace_frames && blockIdx.x == 0 && threadIdx.x == 0)
-    p.trace[(int64_t)f * kTraceStages + stage] = wall_clock64();
+  if (p.trace != nullptr && f < p.trace_frames && (int)blockIdx.x < p.trace_groups && threadIdx.x == 0)
+    p.trace[((int64_t)f * p.trace_groups + blockIdx.x) * kTraceStages + stage] = wall_clock64();
 }
 
 __device__ __forceinline__ bool bounded_wait(const PersistArgs &p, const uint32_t *word, uint32_t target) {
   int32_t spins = 0;
-  while (__hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+  while ((int32_t)(__hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - target) < 0) {
     __builtin_amdgcn_s_sleep(1);
     if (++spins > p.spin_limit) {
       __hip_atomic_store(p.abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -466,24 +547,50 @@ __device__ __forceinline__ bool bounded_wait(const PersistArgs &p, const uint32_
   return true;
 }
 
-__device__ __forceinline__ void frame_barrier(const PersistArgs &p, uint32_t epoch) {
+__device__ __forceinline__ void frame_barrier(const PersistArgs &p, uint32_t epoch, int f) {
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // this wavefront's stores are complete
   __syncthreads();
-  if (threadIdx.x == 0) {
+  trace_stamp(p, f, 6);
+  if (threadIdx.x < 64) {
     const uint32_t G = gridDim.x;
-    const uint32_t grp = blockIdx.x % 16;
-    const uint32_t per = (G - grp + 15) / 16;          // workgroups in this group
-    const uint32_t ngrp = G < 16 ? G : 16;
-    const uint32_t prev =
-        __hip_atomic_fetch_add(p.bar + kBarGroups + 16 * grp, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (prev == epoch * per - 1) {
-      const uint32_t top = __hip_atomic_fetch_add(p.bar + kBarTop, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (top == epoch * ngrp - 1)
-        __hip_atomic_store(p.bar + kBarGen, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int release = 0;
+    if (threadIdx.x == 0) {
+      const uint32_t grp = blockIdx.x % sl::kGroups;
+      const uint32_t per = (G - grp + sl::kGroups - 1) / sl::kGroups;   // workgroups in this group
+      const uint32_t ngrp = G < (uint32_t)sl::kGroups ? G : (uint32_t)sl::kGroups;
+      const uint32_t prev = __hip_atomic_fetch_add(p.bar + sl::kStride * grp, 1u, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+      trace_stamp(p, f, 7);
+      if (prev == epoch * per - 1) {
+        const uint32_t top = __hip_atomic_fetch_add(p.bar + sl::kTop, 1u, __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_AGENT);
+        release = top == epoch * ngrp - 1;
+      }
     }
-    (void)bounded_wait(p, p.bar + kBarGen, epoch);
+    if (__builtin_amdgcn_readfirstlane(release)) {
+      for (uint32_t i = threadIdx.x; i < G; i += 64)
+        __hip_atomic_store(p.bar + sl::kMailbox + 16 * i, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (threadIdx.x == 0) (void)bounded_wait(p, p.bar + sl::kMailbox + 16 * blockIdx.x, epoch);
   }
   __syncthreads();
+}
+
+// End stamp of a frame: the latest of the per-workgroup end stamps, reduced by
+// wavefront 0 of one workgroup.
+__device__ __forceinline__ void reduce_end_stamp(const PersistArgs &p, int f) {
+  const uint64_t *ends = reinterpret_cast<const uint64_t *>(p.bar + sl::kEnds) + (f & 1) * sl::kMaxGroups;
+  uint64_t m = 0;
+  for (uint32_t i = threadIdx.x; i < gridDim.x; i += 64) {
+    const uint64_t v = __hip_atomic_load(ends + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    m = v > m ? v : m;
+  }
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    const uint64_t o = __shfl_xor(m, d);
+    m = o > m ? o : m;
+  }
+  if (threadIdx.x == 0) p.ts[2 * (int64_t)f + 1] = m;
 }
 
 template <int FMT, int KPL>
@@ -500,27 +607,6 @@ __device__ __forceinline__ float chunk_dot(const uint4 (&m)[KPL], const float (&
   return (acc[0] + acc[1]) + (acc[2] + acc[3]);
 }
 
-// Wavefront sums of NR rows at once, so the DPP latencies overlap.
-template <int NR>
-__device__ __forceinline__ void wave_sum_rows(float (&t)[NR]) {
-#pragma unroll
-  for (int r = 0; r < NR; ++r) t[r] += dpp_read<0xB1>(t[r]);
-#pragma unroll
-  for (int r = 0; r < NR; ++r) t[r] += dpp_read<0x4E>(t[r]);
-#pragma unroll
-  for (int r = 0; r < NR; ++r) t[r] += dpp_read<0x141>(t[r]);
-#pragma unroll
-  for (int r = 0; r < NR; ++r) t[r] += dpp_read<0x140>(t[r]);
-#pragma unroll
-  for (int r = 0; r < NR; ++r) {
-    const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(t[r]), 0));
-    const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(t[r]), 16));
-    const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(t[r]), 32));
-    const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(t[r]), 48));
-    t[r] = (r0 + r1) + (r2 + r3);
-  }
-}
-
 // NB slab rows held in LDS, starting at row r0: partial sums into sh_part.
 template <int FMT, int KPL, int NB>
 __device__ __forceinline__ void lds_row_group(const uint4 *lds, int ldq16, int r0, const int (&col)[KPL],
@@ -534,11 +620,7 @@ __device__ __forceinline__ void lds_row_group(const uint4 *lds, int ldq16, int r
     for (int j = 0; j < KPL; ++j) m[j] = lds[(int64_t)(r0 + i) * ldq16 + col[j]];
     t[i] = chunk_dot<FMT, KPL>(m, sv);
   }
-  wave_sum_rows<NB>(t);
-  if (lane == 0) {
-#pragma unroll
-    for (int i = 0; i < NB; ++i) sh_part[wave * max_rows + r0 + i] = t[i];
-  }
+  store_row_sums<NB>(t, sh_part + wave * max_rows + r0, NB, lane);
 }
 
 template <int FMT, int KPL, int RR, int GS>
@@ -592,6 +674,7 @@ __global__ __launch_bounds__(512) void frames_kernel(PersistArgs p, int32_t max_
   if (tid < nrows) state = a.state[row_begin + tid];
   __syncthreads();
 
+  int frames_done = 0;
   for (int f = 0; f < p.n_frames; ++f) {
     if (tid == 0) sh_abort = __hip_atomic_load(p.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
@@ -610,7 +693,7 @@ __global__ __launch_bounds__(512) void frames_kernel(PersistArgs p, int32_t max_
       calib_tile_row<GS, true>(ca, kk < k_end ? kk : p.cal.n_valid, tid & (GS - 1), p.vec);
     }
     trace_stamp(p, f, 1);
-    frame_barrier(p, (uint32_t)(f + 1));
+    frame_barrier(p, (uint32_t)(f + 1), f);
     trace_stamp(p, f, 2);
 
     // slope slices of this wavefront (device-coherent loads)
@@ -626,6 +709,9 @@ __global__ __launch_bounds__(512) void frames_kernel(PersistArgs p, int32_t max_
         sv[j][e] = okc[j] ? v : 0.f;
       }
     }
+    // end stamp of the previous frame, whose per-workgroup stamps the barrier
+    // has just made visible; the workgroups take turns
+    if (p.ts != nullptr && f > 0 && wave == 0 && b == (f - 1) % G) reduce_end_stamp(p, f - 1);
     if (p.trace != nullptr) {                       // stage 3: slope slices in registers
       float probe = 0.f;
 #pragma unroll
@@ -654,10 +740,7 @@ __global__ __launch_bounds__(512) void frames_kernel(PersistArgs p, int32_t max_
       float t[RR > 0 ? RR : 1];
 #pragma unroll
       for (int i = 0; i < RR; ++i) t[i] = chunk_dot<FMT, KPL>(rr[i], sv);
-      wave_sum_rows<(RR > 0 ? RR : 1)>(t);
-#pragma unroll
-      for (int i = 0; i < RR; ++i)
-        if (lane == 0 && i < nreg) sh_part[wave * max_rows + L + i] = t[i];
+      store_row_sums<(RR > 0 ? RR : 1)>(t, sh_part + wave * max_rows + L, nreg, lane);
     }
     // streamed rows
     for (int r0 = stream_begin; r0 < nrows; r0 += RB) {
@@ -671,10 +754,7 @@ __global__ __launch_bounds__(512) void frames_kernel(PersistArgs p, int32_t max_
       float t[RB];
 #pragma unroll
       for (int i = 0; i < RB; ++i) t[i] = chunk_dot<FMT, KPL>(m[i], sv);
-      wave_sum_rows<RB>(t);
-#pragma unroll
-      for (int i = 0; i < RB; ++i)
-        if (lane == 0 && r0 + i < nrows) sh_part[wave * max_rows + r0 + i] = t[i];
+      store_row_sums<RB>(t, sh_part + wave * max_rows + r0, nrows - r0, lane);
     }
     __syncthreads();
     trace_stamp(p, f, 4);
@@ -691,16 +771,27 @@ __global__ __launch_bounds__(512) void frames_kernel(PersistArgs p, int32_t max_
       if (a.recon != nullptr) a.recon[(int64_t)f * a.n_act + row_begin + tid] = v;
     }
     trace_stamp(p, f, 5);
-    if (p.ts != nullptr) {                         // last workgroup to finish frame f stamps its end
+    if (p.ts != nullptr) {                         // this workgroup's commands of frame f are issued
       __syncthreads();
-      if (tid == 0) {
-        const uint32_t prev =
-            __hip_atomic_fetch_add(p.bar + kBarDone, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (prev == (uint32_t)(f + 1) * (uint32_t)G - 1) p.ts[2 * f + 1] = wall_clock64();
-      }
+      if (tid == 0)
+        __hip_atomic_store(reinterpret_cast<uint64_t *>(p.bar + sl::kEnds) + (f & 1) * sl::kMaxGroups + b,
+                           wall_clock64(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
+    ++frames_done;
   }
   if (tid < nrows) a.state[row_begin + tid] = state;
+  // end stamp of the last frame: the last workgroup to finish reduces it
+  if (p.ts != nullptr && frames_done == p.n_frames) {
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    if (wave == 0) {
+      int last = 0;
+      if (tid == 0)
+        last = __hip_atomic_fetch_add(p.bar + sl::kDone, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+               (uint32_t)G - 1;
+      if (__builtin_amdgcn_readfirstlane(last)) reduce_end_stamp(p, p.n_frames - 1);
+    }
+  }
 }
 
 // Sum of the k_split partial actuator vectors in a fixed 64-leaf pairwise tree
@@ -859,6 +950,19 @@ hipError_t launch_mvm_block(const MvmArgs &a, int blocks, int waves, int rows_pe
   }
 }
 
+// Zeroes the arrival counters, the mailboxes of G workgroups and the abort flag
+// (stores, not a memset, so that the sequence can be captured in a graph).
+__global__ __launch_bounds__(kBlock) void persist_reset_kernel(uint32_t *bar, uint32_t *abort_flag, int G) {
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  uint32_t *w = nullptr;
+  if (t < sl::kGroups) w = bar + sl::kStride * t;
+  else if (t == sl::kGroups) w = bar + sl::kTop;
+  else if (t == sl::kGroups + 1) w = bar + sl::kDone;
+  else if (t == sl::kGroups + 2) w = abort_flag;
+  else if (t >= 64 && t < 64 + G) w = bar + sl::kMailbox + 16 * (t - 64);
+  if (w != nullptr) __hip_atomic_store(w, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 template <int FMT, int KPL, int GS>
 static hipError_t launch_frames_variant(const PersistArgs &p, int G, int max_rows, hipStream_t st) {
   constexpr int W = 8;
@@ -881,6 +985,8 @@ static hipError_t launch_frames_variant(const PersistArgs &p, int G, int max_row
   int per_cu = 0;
   if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, W * 64, lds)) != hipSuccess) return e;
   if (per_cu * ncu < G) return hipErrorCooperativeLaunchTooLarge;
+  persist_reset_kernel<<<(64 + G + kBlock - 1) / kBlock, kBlock, 0, st>>>(p.bar, p.abort_flag, G);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
   PersistArgs pa = p;
   int32_t mr = max_rows, lr = lds_rows;
   void *args[] = {&pa, &mr, &lr};
@@ -913,6 +1019,7 @@ hipError_t launch_frames(const PersistArgs &p, int blocks, int rows_per_batch, h
   if (p.cal.n_pix < 1 || p.cal.n_pix > 32) return hipErrorInvalidValue;
   int G = blocks < 1 ? 1 : blocks;
   if (G > p.mvm.n_act) G = p.mvm.n_act;
+  if (G > sl::kMaxGroups) return hipErrorInvalidValue;
   const int max_rows = (p.mvm.n_act + G - 1) / G;
   if (max_rows > W * 64) return hipErrorInvalidValue;      // one integrator row per thread
   const int kpl = slice_chunks(p.mvm.n_chunks, W) / 64;

@@ -64,7 +64,7 @@ _SIGNATURES = {
     "rtc_get_mvm_tuning": (_i32, [_vp, ctypes.POINTER(rtc_mvm_tuning)]),
     "rtc_set_frame_mode": (_i32, [_vp, _i32, _i32]),
     "rtc_sync_check": (_i32, [_vp]),
-    "rtc_set_trace": (_i32, [_vp, _vp, _i32]),
+    "rtc_set_trace": (_i32, [_vp, _vp, _i32, _i32]),
     "rtc_reset": (_i32, [_vp]),
     "rtc_get_state": (_i32, [_vp, _vp]),
     "rtc_set_state": (_i32, [_vp, _vp]),
@@ -297,10 +297,11 @@ def rtc_set_frame_mode(ctx: RtcContext, mode: int, spin_limit: int = 0) -> None:
     _check(load_library().rtc_set_frame_mode(ctx.handle, mode, spin_limit), ctx)
 
 
-def rtc_set_trace(ctx: RtcContext, trace=None, max_frames: int = 0) -> None:
-    """Stage stamps of persistent batches into a device tensor [max_frames, 8] (int64/uint64)."""
-    ptr = _dev_ptr(trace, ("uint64", "int64"), 8 * max_frames, "trace", ctx, False) if max_frames else None
-    _check(load_library().rtc_set_trace(ctx.handle, ptr, max_frames), ctx)
+def rtc_set_trace(ctx: RtcContext, trace=None, max_frames: int = 0, n_groups: int = 1) -> None:
+    """Stage stamps of persistent batches into a device tensor [max_frames, n_groups, 8] (int64/uint64)."""
+    ptr = (_dev_ptr(trace, ("uint64", "int64"), 8 * max_frames * n_groups, "trace", ctx, False)
+           if max_frames else None)
+    _check(load_library().rtc_set_trace(ctx.handle, ptr, max_frames, n_groups), ctx)
 
 
 def rtc_sync_check(ctx: RtcContext) -> None:

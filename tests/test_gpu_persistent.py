@@ -118,3 +118,43 @@ def test_frame_mode_validation():
             with pytest.raises(rtc.RtcError) as ei:
                 rtc.rtc_set_frame_mode(ctx, *bad)
             assert ei.value.status == rtc.RTC_E_ARG
+
+
+@pytest.mark.parametrize("fmt", ["f32", "bf16", "fp8e4m3"])
+@pytest.mark.parametrize("which", ["tiny", "elt"])
+def test_row_grouping_leaves_every_row_sum_bitwise_unchanged(which, fmt, request):
+    # rows_per_wave 1 reduces each row on its own; 2 and 4 reduce rows transposed
+    # across lanes.  Every row must see the same addition tree either way.
+    sc, frames, _ = request.getfixturevalue(f"{which}_loop")
+    frames = frames[:3]
+    outs = []
+    with _ctx_for(sc, cm_dtype=fmt) as ctx:
+        for rpw in (1, 2, 4):
+            rtc.rtc_reset(ctx)
+            outs.append(_gpu_batch(ctx, frames, tuning=dict(rows_per_wave=rpw)))
+    for o in outs[1:]:
+        assert np.array_equal(o["recon"], outs[0]["recon"]), f"{which} {fmt}: row sums depend on grouping"
+        assert np.array_equal(o["cmd"], outs[0]["cmd"])
+
+
+def test_stage_trace_of_every_traced_workgroup_is_ordered(tiny_loop):
+    sc, frames, _ = tiny_loop
+    F, NG = 6, 3
+    with _ctx_for(sc) as ctx:
+        rtc.rtc_set_frame_mode(ctx, rtc.RTC_FRAMES_PERSISTENT)
+        tr = torch.zeros(F * NG * 8, dtype=torch.int64, device="cuda:0")
+        rtc.rtc_set_trace(ctx, tr, F, NG)
+        _gpu_batch(ctx, frames[:F + 2], ts=True)
+        rtc.rtc_sync_check(ctx)
+        t = tr.cpu().numpy().reshape(F, NG, 8)
+        rtc.rtc_set_trace(ctx, None, 0)
+        with pytest.raises(rtc.RtcError):
+            rtc.rtc_set_trace(ctx, tr, F, 0)
+    stages = t[:, :, :6]
+    assert np.all(stages > 0), "a traced workgroup left a stage unstamped"
+    assert np.all(np.diff(stages, axis=2) >= 0), "stages out of order"
+    assert np.all(np.diff(stages[:, :, 0], axis=0) > 0), "frame starts out of order"
+    # no workgroup passes frame f's barrier before every traced one has published
+    assert np.all(stages[:, :, 2].min(axis=1) >= stages[:, :, 1].max(axis=1))
+    assert np.all(t[:, :, 6] >= t[:, :, 1]) and np.all(t[:, :, 7] >= t[:, :, 6])
+    assert np.all(t[:, :, 2] >= t[:, :, 7])

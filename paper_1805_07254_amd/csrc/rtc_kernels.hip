@@ -220,19 +220,19 @@ __device__ __forceinline__ void store_row_sums(float (&t)[NR], float *out, int v
   if constexpr (NR == 1) {
     const float x = wave_sum(t[0]);
     if (lane == 0 && valid > 0) out[0] = x;
-  } else if constexpr (NR <= 8) {
+  } else if constexpr (NR == 2 || NR == 4 || NR == 8) {
     const float x = wave_sum_transposed<NR>(t, lane);
     const int r = row_of_lane<NR>(lane);
     if (lane < NR && r < valid) out[r] = x;
-  } else {
-    static_assert(NR % 8 == 0, "row groups of 8");
+  } else {                                          // leading 8, 4 or 2 rows, then the rest
+    constexpr int H = NR > 8 ? 8 : (NR > 4 ? 4 : 2);
+    float u[H], w[NR - H];
 #pragma unroll
-    for (int g = 0; g < NR / 8; ++g) {
-      float u[8];
+    for (int i = 0; i < H; ++i) u[i] = t[i];
 #pragma unroll
-      for (int i = 0; i < 8; ++i) u[i] = t[8 * g + i];
-      store_row_sums<8>(u, out + 8 * g, valid - 8 * g, lane);
-    }
+    for (int i = 0; i < NR - H; ++i) w[i] = t[H + i];
+    store_row_sums<H>(u, out, valid, lane);
+    store_row_sums<NR - H>(w, out + H, valid - H, lane);
   }
 }
 
@@ -676,6 +676,14 @@ __global__ __launch_bounds__(512) void frames_kernel(PersistArgs p, int32_t max_
 
   int frames_done = 0;
   for (int f = 0; f < p.n_frames; ++f) {
+    // The register rows are loop-invariant codes; this empty statement makes
+    // them opaque per frame, so they are decoded where used instead of being
+    // kept decoded (twice the registers) across the whole loop.
+#pragma unroll
+    for (int i = 0; i < RR; ++i)
+#pragma unroll
+      for (int j = 0; j < KPL; ++j)
+        asm volatile("" : "+v"(rr[i][j].x), "+v"(rr[i][j].y), "+v"(rr[i][j].z), "+v"(rr[i][j].w));
     if (tid == 0) sh_abort = __hip_atomic_load(p.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
     if (sh_abort) break;                            // a bounded wait expired somewhere: wind down
@@ -720,18 +728,24 @@ __global__ __launch_bounds__(512) void frames_kernel(PersistArgs p, int32_t max_
       trace_stamp(p, f, 3);
     }
 
-    // (c) LDS rows in groups of 8, then 4, 2, 1 (no duplicated rows)
+    // (c) LDS rows in groups of LG (at most 64 VGPRs of codes, fewer when the
+    // register rows hold 128), then halves down to 1 (no duplicated rows)
     {
+      constexpr int LG = (FMT == 0 ? 8 : 16) / KPL >= 8 ? 8 : ((FMT == 0 ? 8 : 16) / KPL >= 4 ? 4 : 2);
       int r0 = 0;
-      for (; r0 + 8 <= L; r0 += 8)
-        lds_row_group<FMT, KPL, 8>(lds, ldq16, r0, col, sv, sh_part, wave, lane, max_rows);
-      if (r0 + 4 <= L) {
-        lds_row_group<FMT, KPL, 4>(lds, ldq16, r0, col, sv, sh_part, wave, lane, max_rows);
-        r0 += 4;
+      for (; r0 + LG <= L; r0 += LG)
+        lds_row_group<FMT, KPL, LG>(lds, ldq16, r0, col, sv, sh_part, wave, lane, max_rows);
+      if constexpr (LG > 4) {
+        if (r0 + 4 <= L) {
+          lds_row_group<FMT, KPL, 4>(lds, ldq16, r0, col, sv, sh_part, wave, lane, max_rows);
+          r0 += 4;
+        }
       }
-      if (r0 + 2 <= L) {
-        lds_row_group<FMT, KPL, 2>(lds, ldq16, r0, col, sv, sh_part, wave, lane, max_rows);
-        r0 += 2;
+      if constexpr (LG > 2) {
+        if (r0 + 2 <= L) {
+          lds_row_group<FMT, KPL, 2>(lds, ldq16, r0, col, sv, sh_part, wave, lane, max_rows);
+          r0 += 2;
+        }
       }
       if (r0 < L) lds_row_group<FMT, KPL, 1>(lds, ldq16, r0, col, sv, sh_part, wave, lane, max_rows);
     }
@@ -966,7 +980,7 @@ __global__ __launch_bounds__(kBlock) void persist_reset_kernel(uint32_t *bar, ui
 template <int FMT, int KPL, int GS>
 static hipError_t launch_frames_variant(const PersistArgs &p, int G, int max_rows, hipStream_t st) {
   constexpr int W = 8;
-  constexpr int RR = 16 / KPL;                      // register rows: 64 VGPRs of codes per lane
+  constexpr int RR = (FMT == 0 ? 24 : 16) / KPL;    // register rows: 96 (f32) / 64 VGPRs of codes per lane
   auto kern = frames_kernel<FMT, KPL, RR, GS>;
   int dev = 0, ncu = 0, lds_max = 0;
   hipError_t e;

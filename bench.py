@@ -61,7 +61,7 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=10000)
     p.add_argument("--warmup", type=int, default=1000)
-    p.add_argument("--launch-frames", type=int, default=1000, help="frames per persistent launch")
+    p.add_argument("--launch-frames", type=int, default=10000, help="frames per persistent launch")
     p.add_argument("--ring", type=int, default=128, help="distinct raw frames (repeated through the buffer)")
     p.add_argument("--mvm-kernel", type=int, default=0, help="0 = row-block, 1 = streamed")
     p.add_argument("--k-split", type=int, default=1)
@@ -180,7 +180,9 @@ def main():
         start_us = ticks_to_us(st[:, 0] - st[0, 0], khz)
         end_us = ticks_to_us(st[:, 1] - st[0, 0], khz)
         period = np.diff(start_us)
-        return {"period": period, "span": end_us - start_us, "wall": wall,
+        inside = np.ones(len(period), bool)                   # periods that do not straddle a relaunch
+        inside[args.launch_frames - 1::args.launch_frames] = False
+        return {"period": period, "period_inside": period[inside], "span": end_us - start_us, "wall": wall,
                 "launch_ms": ev0.elapsed_time(ev1) / launches, "launches": launches}
 
     # --- headline: FP32 matrix, persistent kernel
@@ -272,6 +274,9 @@ def main():
             if (prof.get("kernel_source_sha256_16") == kernel_source_hash()
                     and prof.get("frames_per_launch") == args.launch_frames):
                 traffic = prof.get("hbm_bytes_per_launch")
+            elif prof.get("kernel_source_sha256_16") == kernel_source_hash():
+                log(f"traffic counters were taken at {prof.get('frames_per_launch')} frames per launch; "
+                    f"not reported for {args.launch_frames}")
         except Exception:
             traffic = None
 
@@ -304,6 +309,7 @@ def main():
         "frame_period_us": st_period,
         "frame_span_us": st_span,
         "frame_period_us_skip100": frame_stats(head["period"], skip=100) if len(head["period"]) > 200 else None,
+        "frame_period_us_within_launches": frame_stats(head["period_inside"]),
         "per_launch_mode": per_launch,
         "kernels_us": {"reconstruct_integrate": round(mvm_us, 3), "calibrate_centroid": round(cal_us, 3),
                        "frames_kernel_per_launch_ms": round(head["launch_ms"], 4)},

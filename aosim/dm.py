@@ -28,18 +28,31 @@ def interaction_matrix(boxes: np.ndarray, acts: np.ndarray, w: float) -> np.ndar
     """float64 ``[2 n_valid, n_act]``: x-slope rows first, then y-slope rows.
 
     Closed form of the mean gradient of ``exp(-r^2 / 2 w^2)`` over each box,
-    scaled by ``d / pi`` to pixels.
+    scaled by ``d / pi`` to pixels.  Each entry is a product of a factor of
+    (box x edges, actuator x) and a factor of (box y edges, actuator y); the
+    factors are evaluated once per distinct pair and gathered.
     """
-    x0, x1, y0, y1 = (boxes[:, i][:, None] for i in range(4))
-    xa = acts[:, 0][None, :]
-    ya = acts[:, 1][None, :]
     d = boxes[0, 1] - boxes[0, 0]
     s2w = math.sqrt(2.0) * w
     g = lambda u: np.exp(-(u * u) / (2.0 * w * w))
     # integral of the Gaussian over an interval, times 1
     gi = lambda a, b, c: w * math.sqrt(math.pi / 2.0) * (erf((b - c) / s2w) - erf((a - c) / s2w))
-    dx = (g(x1 - xa) - g(x0 - xa)) * gi(y0, y1, ya)
-    dy = (g(y1 - ya) - g(y0 - ya)) * gi(x0, x1, xa)
+
+    def tables(lo, hi, pos):
+        ul, il = np.unique(lo, return_inverse=True)
+        up, ip = np.unique(pos, return_inverse=True)
+        lo_u = ul[:, None]
+        hi_u = (ul + (hi[0] - lo[0]))[:, None] if np.all(hi - lo == hi[0] - lo[0]) else None
+        if hi_u is None:                                    # unequal boxes: one row per box
+            lo_u, hi_u, il = lo[:, None], hi[:, None], np.arange(len(lo))
+        p = up[None, :]
+        return g(hi_u - p) - g(lo_u - p), gi(lo_u, hi_u, p), il, ip
+
+    x0, x1, y0, y1 = (boxes[:, i] for i in range(4))
+    gx, ix_int, bx, ax = tables(x0, x1, acts[:, 0])
+    gy, iy_int, by, ay = tables(y0, y1, acts[:, 1])
+    dx = gx[bx[:, None], ax[None, :]] * iy_int[by[:, None], ay[None, :]]
+    dy = gy[by[:, None], ay[None, :]] * ix_int[bx[:, None], ax[None, :]]
     scale = 1.0 / (math.pi * d)   # (d / pi) * (1 / d^2)
     return np.concatenate([dx, dy], axis=0) * scale
 

@@ -115,6 +115,47 @@ typedef struct {
  * slopes), RTC_E_DEVICE (no such device), RTC_E_NOMEM. */
 rtc_status rtc_init(const rtc_config *cfg, rtc_ctx **out);
 
+/* Several wavefront sensors reconstructed together (the multi-WFS systems of
+ * the paper's outlook, Section 3.4.1): each sensor has its own grid, pixels
+ * per subaperture and mask; one control matrix maps the concatenated slope
+ * vector to n_act actuators.
+ *  - Frame set: the sensors' frames back to back, sensor w's H_w x W_w
+ *    uint16 frame (H_w = n_sub_y*n_pix, W_w = n_sub_x*n_pix, row-major)
+ *    starting at element F_w = sum over v < w of H_v*W_v; the frame set has
+ *    rtc_frame_elems() elements and must be < 2^31.  Every frame argument of
+ *    the frame calls points to such a set (frame_stride >= rtc_frame_elems).
+ *  - Subapertures are numbered sensor by sensor, row-major within a sensor.
+ *  - Slope vector: for each sensor in order, its x slopes then its y slopes
+ *    (each sensor laid out as Figure 3 (b)); 2*n_valid in total.
+ *  - Calibration maps and thresholds follow the same sensor order
+ *    (rtc_load_calib_multi).
+ * A single-sensor rtc_init is the n_wfs = 1 case of this. */
+typedef struct {
+  int32_t n_sub_x, n_sub_y;    /* subaperture grid, 1..4096 each */
+  int32_t n_pix;               /* pixels per subaperture side, 1..32 */
+  const uint8_t *subap_mask;   /* host [n_sub_y][n_sub_x], nonzero = active; copied */
+} rtc_wfs;
+
+typedef struct {
+  uint32_t abi_version;        /* must equal RTC_ABI_VERSION */
+  int32_t n_wfs;               /* 1..64 */
+  const rtc_wfs *wfs;          /* host [n_wfs]; copied */
+  int32_t n_act;               /* as in rtc_config */
+  int32_t thr_mode;
+  int32_t cm_dtype;
+  float gain, leak;
+  float cmd_min, cmd_max;
+  int32_t device;
+} rtc_multi_config;
+
+/* As rtc_init for several sensors.  Errors as rtc_init, plus RTC_E_ARG for
+ * n_wfs outside 1..64, a NULL sensor array or a frame set of 2^31 or more
+ * elements. */
+rtc_status rtc_init_multi(const rtc_multi_config *cfg, rtc_ctx **out);
+
+/* Elements of one frame set (sum of H_w*W_w; H*W for one sensor), -1 if c NULL. */
+int64_t rtc_frame_elems(const rtc_ctx *c);
+
 /* Loads the pixel calibration (Figure 3 (a)): host float32 dark and flat maps
  * [H][W] row-major (flat multiplies: it holds inverse pixel gains), threshold T
  * (finite, >= 0, ADU after flat-fielding), and optional reference slopes
@@ -124,8 +165,16 @@ rtc_status rtc_init(const rtc_config *cfg, rtc_ctx **out);
  * Replaces a previous calibration after synchronising the device.
  * Errors: RTC_E_ARG (NULL maps, T < 0, dark outside {0} U [2^-13, 2^24) in
  * magnitude), RTC_E_NONFINITE, RTC_E_DEVICE, RTC_E_NOMEM. */
+/* rtc_load_calib on a multi-sensor context applies the one threshold to every
+ * sensor; dark and flat are laid out as a frame set. */
 rtc_status rtc_load_calib(rtc_ctx *c, const float *dark, const float *flat, float threshold,
                           const float *ref_slopes);
+
+/* Multi-sensor calibration: dark and flat as frame sets (rtc_frame_elems
+ * floats each), thresholds [n_wfs] (one per sensor, each finite and >= 0),
+ * ref_slopes [2*n_valid] or NULL.  Same checks and errors as rtc_load_calib. */
+rtc_status rtc_load_calib_multi(rtc_ctx *c, const float *dark, const float *flat, const float *thresholds,
+                                const float *ref_slopes);
 
 /* Loads the control matrix R (Section 1.1.1; Figure 3 (c)): host float32,
  * row-major [n_act][ld], row r holds the weights of actuator r over the slope

@@ -8,5 +8,5 @@ exact rational arithmetic or brute force (see ``tests/test_oracle_pins.py``);
 none is "parity unpinned".
 """
 from .rtc_oracle import (FrameOracle, calibrate, centroids, integrate, reconstruct,  # noqa: F401
-                         rtc_frame, slope_vector, subaperture_tiles, threshold_excess,
-                         valid_subapertures)
+                         rtc_frame, rtc_frame_multi, sensor_slopes, slope_vector, subaperture_tiles,
+                         threshold_excess, valid_subapertures)

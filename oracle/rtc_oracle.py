@@ -165,6 +165,41 @@ def rtc_frame(frame: np.ndarray, mask: np.ndarray, n_pix: int, dark: np.ndarray,
     return {"counts": counts, "slopes": s, "recon": a, "cmd": c}
 
 
+def sensor_slopes(frame: np.ndarray, mask: np.ndarray, n_pix: int, dark: np.ndarray, flat: np.ndarray,
+                  T: float, mode: str = "subtract"):
+    """Steps (a)-(b) of one wavefront sensor: (slopes x block then y block, counts)."""
+    cells = valid_subapertures(mask)
+    v, counts = calibrate(subaperture_tiles(frame, cells, n_pix), subaperture_tiles(dark, cells, n_pix),
+                          subaperture_tiles(flat, cells, n_pix), T, mode)
+    cx, cy = centroids(v, counts)
+    return slope_vector(cx, cy), counts
+
+
+def rtc_frame_multi(frames, sensors, darks, flats, thresholds, R: np.ndarray, c_prev: np.ndarray, gain: float,
+                    leak: float = 1.0, mode: str = "subtract", ref: np.ndarray | None = None,
+                    cmd_min: float = -np.inf, cmd_max: float = np.inf) -> dict:
+    """One frame of several wavefront sensors reconstructed by one matrix.
+
+    The paper runs one sensor and names multi-sensor systems as its outlook
+    (Section 3.4.1) without fixing a layout; here each sensor's slope vector
+    (x block then y block, as in Figure 3 (b)) is concatenated in sensor
+    order, reference slopes are subtracted from the concatenation, and R is
+    [n_act][total slopes].  ``sensors`` is a sequence of (mask, n_pix);
+    frames, darks, flats and thresholds follow the same order.
+    """
+    parts, counts = [], []
+    for frame, (mask, n_pix), dark, flat, T in zip(frames, sensors, darks, flats, thresholds):
+        s_w, c_w = sensor_slopes(frame, mask, n_pix, dark, flat, T, mode)
+        parts.append(s_w)
+        counts.append(c_w)
+    s = np.concatenate(parts)
+    if ref is not None:
+        s = s - np.asarray(ref, dtype=np.float32).astype(np.float64)
+    a = reconstruct(R, s)
+    c = integrate(c_prev, a, gain, leak, cmd_min, cmd_max)
+    return {"counts": np.concatenate(counts), "slopes": s, "recon": a, "cmd": c}
+
+
 class FrameOracle:
     """The same frame with the tile extraction and matrix promotion done once.
 

@@ -2,8 +2,8 @@
 //
 // Validation happens on the host before any device state changes, so every
 // error leaves the context as it was.  Device buffers:
-//   tile_off [n_valid]            int32 element offset of each active tile
-//   calib    [n_valid][n][n]      float2 (dark, flat), active tiles only
+//   tiles    [n_valid]            TileDesc of each active subaperture (offsets, slope positions, threshold)
+//   calib    per tile [n][n]      float2 (dark, flat), active tiles only
 //   ref      [s_len]              float32 reference slopes, s_len = round_up(2 n_valid, 16), zero-padded
 //   R        [n_act][ldq]         codes of the storage format, ldq = round_up(2 n_valid, elements per
 //                                 16 bytes), zero-padded; float32 storage has ldq = round_up(2 n_valid, 4)
@@ -23,26 +23,37 @@
 #include "../../include/rtc.h"
 #include "rtc_kernels.h"
 
+// One wavefront sensor of a context.
+struct WfsInfo {
+  int32_t n_sub_x = 0, n_sub_y = 0, n_pix = 0, H = 0, W = 0;
+  int64_t frame_off = 0;   // first element of its frame in the frame set
+  int32_t tile_base = 0;   // its first subaperture
+  int32_t n_tiles = 0;
+};
+
 struct rtc_ctx {
-  rtc_config cfg{};
+  rtc_config cfg{};        // abi_version, n_act, thr_mode, cm_dtype, gain, leak, clamp, device
   int device = 0;
-  int32_t H = 0, W = 0, n_pix = 0, n_valid = 0, n_slopes = 0, n_s4 = 0, n_act = 0;
+  int32_t n_valid = 0, n_slopes = 0, n_s4 = 0, n_act = 0;
+  std::vector<WfsInfo> wfs;
+  int64_t frame_elems = 0;  // elements of one frame set
+  int32_t max_n = 0;        // largest pixels per side
+  int32_t pairs = 0;        // every tile row starts on an even element and has even width
+  int64_t calib_len = 0;    // float2 elements of the per-tile calibration blocks
   int64_t ldr = 0;        // float32 row length of the matrix (elements)
   int64_t s_len = 0;      // slope / reference buffer length (elements)
   int32_t fmt = 0;        // rtc_cm_dtype of the stored matrix
   int64_t ldq = 0;        // stored row length (elements)
   int32_t n_chunks = 0;   // 16-byte chunks per stored row
-  std::vector<uint8_t> mask;
-  std::vector<int32_t> tile_off_h;
+  std::vector<rtck::TileDesc> tiles_h;
   std::string err;
   rtc_mvm_tuning tuning{RTC_MVM_ROWBLOCK, 1, 2, 4, 0, 8};
   int32_t n_cu = 0;
   int64_t wall_khz = 0;
 
-  int32_t *d_tile_off = nullptr;
+  rtck::TileDesc *d_tiles = nullptr;
   float2 *d_calib = nullptr;
   float *d_ref = nullptr;
-  float thr = 0.f;
   void *d_R = nullptr;
   float *d_scales = nullptr;
   float *d_s = nullptr;
@@ -183,64 +194,94 @@ const char *rtc_error_string(const rtc_ctx *c) {
 int32_t rtc_n_valid(const rtc_ctx *c) { return c ? c->n_valid : -1; }
 int32_t rtc_n_act(const rtc_ctx *c) { return c ? c->n_act : -1; }
 
-rtc_status rtc_init(const rtc_config *cfg, rtc_ctx **out) {
-  if (!cfg || !out) return fail(nullptr, RTC_E_ARG, "rtc_init: NULL config or output pointer");
-  if (cfg->abi_version != RTC_ABI_VERSION)
-    return fail(nullptr, RTC_E_ARG, "rtc_init: abi_version does not match RTC_ABI_VERSION");
-  if (cfg->n_sub_x < 1 || cfg->n_sub_x > 4096 || cfg->n_sub_y < 1 || cfg->n_sub_y > 4096)
-    return fail(nullptr, RTC_E_ARG, "rtc_init: n_sub_x/n_sub_y must be in 1..4096");
-  if (cfg->n_pix < 1 || cfg->n_pix > 32)
-    return fail(nullptr, RTC_E_ARG, "rtc_init: n_pix must be in 1..32");
-  const int64_t H = (int64_t)cfg->n_sub_y * cfg->n_pix, W = (int64_t)cfg->n_sub_x * cfg->n_pix;
-  if (H * W >= (int64_t(1) << 31)) return fail(nullptr, RTC_E_ARG, "rtc_init: frame has 2^31 or more pixels");
-  if (!cfg->subap_mask) return fail(nullptr, RTC_E_ARG, "rtc_init: subap_mask is NULL");
-  if (cfg->n_act < 1 || cfg->n_act > (1 << 20))
-    return fail(nullptr, RTC_E_ARG, "rtc_init: n_act must be in 1..2^20");
+// Common initialisation of one or more sensors; cfg holds the non-sensor fields.
+static rtc_status init_impl(const rtc_config *cfg, const rtc_wfs *wfs, int32_t n_wfs, const char *who,
+                            rtc_ctx **out) {
+  auto err = [&](rtc_status st, const char *msg) { return fail(nullptr, st, std::string(who) + ": " + msg); };
+  if (cfg->abi_version != RTC_ABI_VERSION) return err(RTC_E_ARG, "abi_version does not match RTC_ABI_VERSION");
+  if (n_wfs < 1 || n_wfs > 64 || !wfs) return err(RTC_E_ARG, "n_wfs must be in 1..64 with a sensor array");
+  std::vector<WfsInfo> info((size_t)n_wfs);
+  std::vector<rtck::TileDesc> tiles;
+  int64_t frame_elems = 0, calib_len = 0;
+  int32_t max_n = 0;
+  bool pairs = true;
+  for (int32_t w = 0; w < n_wfs; ++w) {
+    const rtc_wfs &d = wfs[w];
+    if (d.n_sub_x < 1 || d.n_sub_x > 4096 || d.n_sub_y < 1 || d.n_sub_y > 4096)
+      return err(RTC_E_ARG, "n_sub_x/n_sub_y must be in 1..4096");
+    if (d.n_pix < 1 || d.n_pix > 32) return err(RTC_E_ARG, "n_pix must be in 1..32");
+    if (!d.subap_mask) return err(RTC_E_ARG, "subap_mask is NULL");
+    WfsInfo &wi = info[w];
+    wi.n_sub_x = d.n_sub_x;
+    wi.n_sub_y = d.n_sub_y;
+    wi.n_pix = d.n_pix;
+    wi.H = d.n_sub_y * d.n_pix;
+    wi.W = d.n_sub_x * d.n_pix;
+    wi.frame_off = frame_elems;
+    wi.tile_base = (int32_t)tiles.size();
+    frame_elems += (int64_t)wi.H * wi.W;
+    if (frame_elems >= (int64_t(1) << 31)) return err(RTC_E_ARG, "the frame set has 2^31 or more pixels");
+    max_n = std::max(max_n, d.n_pix);
+    if ((d.n_pix & 1) || (wi.W & 1) || (wi.frame_off & 1)) pairs = false;
+    // active subapertures row-major; slope positions are fixed once all sensors are known
+    for (int32_t sy = 0; sy < d.n_sub_y; ++sy)
+      for (int32_t sx = 0; sx < d.n_sub_x; ++sx)
+        if (d.subap_mask[(int64_t)sy * d.n_sub_x + sx]) {
+          rtck::TileDesc t{};
+          t.off = (int32_t)(wi.frame_off + (int64_t)sy * d.n_pix * wi.W + (int64_t)sx * d.n_pix);
+          t.calib_off = (int32_t)calib_len;
+          t.pitch = wi.W;
+          t.n = d.n_pix;
+          t.thr = 0.0f;
+          calib_len += (int64_t)d.n_pix * d.n_pix;
+          tiles.push_back(t);
+        }
+    wi.n_tiles = (int32_t)tiles.size() - wi.tile_base;
+    if (wi.n_tiles == 0) return err(RTC_E_ARG, "the mask has no active subaperture");
+  }
+  if (calib_len >= (int64_t(1) << 31)) return err(RTC_E_ARG, "calibration blocks too large");
+  const int32_t n_valid = (int32_t)tiles.size();
+  for (const WfsInfo &wi : info)                   // each sensor: its x block, then its y block
+    for (int32_t k = 0; k < wi.n_tiles; ++k) {
+      rtck::TileDesc &t = tiles[(size_t)wi.tile_base + k];
+      t.sx = 2 * wi.tile_base + k;
+      t.sy = 2 * wi.tile_base + wi.n_tiles + k;
+    }
+  if (cfg->n_act < 1 || cfg->n_act > (1 << 20)) return err(RTC_E_ARG, "n_act must be in 1..2^20");
   if (cfg->thr_mode != RTC_THR_SUBTRACT && cfg->thr_mode != RTC_THR_ZERO)
-    return fail(nullptr, RTC_E_ARG, "rtc_init: thr_mode must be RTC_THR_SUBTRACT or RTC_THR_ZERO");
-  if (cfg->cm_dtype < RTC_CM_F32 || cfg->cm_dtype > RTC_CM_FP8E4M3)
-    return fail(nullptr, RTC_E_ARG, "rtc_init: unknown cm_dtype");
+    return err(RTC_E_ARG, "thr_mode must be RTC_THR_SUBTRACT or RTC_THR_ZERO");
+  if (cfg->cm_dtype < RTC_CM_F32 || cfg->cm_dtype > RTC_CM_FP8E4M3) return err(RTC_E_ARG, "unknown cm_dtype");
   if (!std::isfinite(cfg->gain) || !std::isfinite(cfg->leak))
-    return fail(nullptr, RTC_E_NONFINITE, "rtc_init: gain and leak must be finite");
-  if (std::isnan(cfg->cmd_min) || std::isnan(cfg->cmd_max))
-    return fail(nullptr, RTC_E_NONFINITE, "rtc_init: cmd_min/cmd_max must not be NaN");
-  if (!(cfg->cmd_min <= cfg->cmd_max)) return fail(nullptr, RTC_E_ARG, "rtc_init: cmd_min > cmd_max");
-  if (cfg->device < 0) return fail(nullptr, RTC_E_ARG, "rtc_init: device must be >= 0");
-
-  // index map: active subapertures row-major
-  const int64_t ncell = (int64_t)cfg->n_sub_x * cfg->n_sub_y;
-  std::vector<uint8_t> mask(cfg->subap_mask, cfg->subap_mask + ncell);
-  std::vector<int32_t> off;
-  for (int32_t sy = 0; sy < cfg->n_sub_y; ++sy)
-    for (int32_t sx = 0; sx < cfg->n_sub_x; ++sx)
-      if (mask[(int64_t)sy * cfg->n_sub_x + sx])
-        off.push_back((int32_t)((int64_t)sy * cfg->n_pix * W + (int64_t)sx * cfg->n_pix));
-  if (off.empty()) return fail(nullptr, RTC_E_ARG, "rtc_init: the mask has no active subaperture");
+    return err(RTC_E_NONFINITE, "gain and leak must be finite");
+  if (std::isnan(cfg->cmd_min) || std::isnan(cfg->cmd_max)) return err(RTC_E_NONFINITE, "cmd_min/cmd_max must not be NaN");
+  if (!(cfg->cmd_min <= cfg->cmd_max)) return err(RTC_E_ARG, "cmd_min > cmd_max");
+  if (cfg->device < 0) return err(RTC_E_ARG, "device must be >= 0");
   if (cfg->cm_dtype != RTC_CM_F32) {
-    // reduced formats run on the row-block kernel only: 16 wavefronts' slices must fit registers
+    // reduced formats run on the row-block kernels: slices of 8 wavefronts in panels
     const int epc = rtck::format_elems_per_chunk(cfg->cm_dtype);
-    const int64_t chunks = round_up(2 * (int64_t)off.size(), epc) / epc;
-    if (chunks > (int64_t)1 << 24 || rtck::slice_chunks((int)chunks, 16) / 64 > rtck::mvm_block_max_kpl())
-      return fail(nullptr, RTC_E_UNSUPPORTED, "rtc_init: slope vector too long for a reduced-precision matrix");
+    const int64_t chunks = round_up(2 * (int64_t)n_valid, epc) / epc;
+    if (chunks > (int64_t)1 << 24) return err(RTC_E_UNSUPPORTED, "slope vector too long for a reduced-precision matrix");
   }
 
   int ndev = 0;
   hipError_t e = hipGetDeviceCount(&ndev);
   if (e != hipSuccess || ndev == 0)
-    return fail(nullptr, RTC_E_DEVICE, std::string("rtc_init: no HIP device available (") +
+    return fail(nullptr, RTC_E_DEVICE, std::string(who) + ": no HIP device available (" +
                                            (e != hipSuccess ? hipGetErrorName(e) : "count 0") + ")");
-  if (cfg->device >= ndev) return fail(nullptr, RTC_E_DEVICE, "rtc_init: device ordinal out of range");
+  if (cfg->device >= ndev) return err(RTC_E_DEVICE, "device ordinal out of range");
 
   rtc_ctx *c = new (std::nothrow) rtc_ctx();
-  if (!c) return fail(nullptr, RTC_E_NOMEM, "rtc_init: host allocation failed");
+  if (!c) return err(RTC_E_NOMEM, "host allocation failed");
   c->cfg = *cfg;
   c->cfg.subap_mask = nullptr;
   c->device = cfg->device;
-  c->H = (int32_t)H;
-  c->W = (int32_t)W;
-  c->n_pix = cfg->n_pix;
-  c->n_valid = (int32_t)off.size();
-  c->n_slopes = 2 * c->n_valid;
+  c->wfs = std::move(info);
+  c->frame_elems = frame_elems;
+  c->max_n = max_n;
+  c->pairs = pairs ? 1 : 0;
+  c->calib_len = calib_len;
+  c->n_valid = n_valid;
+  c->n_slopes = 2 * n_valid;
   c->ldr = round_up4(c->n_slopes);
   c->n_s4 = (int32_t)(c->ldr / 4);
   c->s_len = round_up(c->n_slopes, 16);
@@ -251,14 +292,13 @@ rtc_status rtc_init(const rtc_config *cfg, rtc_ctx **out) {
     c->n_chunks = (int32_t)(c->ldq / epc);
   }
   c->n_act = cfg->n_act;
-  c->mask = std::move(mask);
-  c->tile_off_h = std::move(off);
+  c->tiles_h = std::move(tiles);
 
   DeviceScope ds(c->device);
-  auto bail = [&](hipError_t err, const char *what) {
-    const rtc_status s = hip_fail(nullptr, err, what);
+  auto bail = [&](hipError_t err2, const char *what) {
+    const rtc_status st = hip_fail(nullptr, err2, what);
     rtc_destroy(c);
-    return s;
+    return st;
   };
   if (ds.status != hipSuccess) return bail(ds.status, "rtc_init: hipSetDevice");
   int khz = 0;
@@ -270,7 +310,8 @@ rtc_status rtc_init(const rtc_config *cfg, rtc_ctx **out) {
     return bail(e, "rtc_init: compute-unit count");
   c->n_cu = ncu;
   const size_t s_bytes = (size_t)c->s_len * sizeof(float);
-  if ((e = hipMalloc(&c->d_tile_off, c->n_valid * sizeof(int32_t))) != hipSuccess ||
+  const size_t t_bytes = (size_t)c->n_valid * sizeof(rtck::TileDesc);
+  if ((e = hipMalloc(&c->d_tiles, t_bytes)) != hipSuccess ||
       (e = hipMalloc(&c->d_ref, s_bytes)) != hipSuccess ||
       (e = hipMalloc(&c->d_s, s_bytes)) != hipSuccess ||
       (e = hipMalloc(&c->d_state, c->n_act * sizeof(float))) != hipSuccess ||
@@ -278,8 +319,7 @@ rtc_status rtc_init(const rtc_config *cfg, rtc_ctx **out) {
       (e = hipMalloc(&c->d_sbuf, 2 * xchg_len_of(c->n_slopes) * sizeof(float))) != hipSuccess ||
       (e = hipMalloc(&c->d_sync, kSyncWords * sizeof(uint32_t))) != hipSuccess)
     return bail(e, "rtc_init: hipMalloc");
-  if ((e = hipMemcpy(c->d_tile_off, c->tile_off_h.data(), c->n_valid * sizeof(int32_t),
-                     hipMemcpyHostToDevice)) != hipSuccess ||
+  if ((e = hipMemcpy(c->d_tiles, c->tiles_h.data(), t_bytes, hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemset(c->d_ref, 0, s_bytes)) != hipSuccess ||
       (e = hipMemset(c->d_s, 0, s_bytes)) != hipSuccess ||
       (e = hipMemset(c->d_state, 0, c->n_act * sizeof(float))) != hipSuccess ||
@@ -292,37 +332,70 @@ rtc_status rtc_init(const rtc_config *cfg, rtc_ctx **out) {
   return RTC_OK;
 }
 
-rtc_status rtc_load_calib(rtc_ctx *c, const float *dark, const float *flat, float threshold,
-                          const float *ref_slopes) {
-  if (!c) return fail(nullptr, RTC_E_ARG, "rtc_load_calib: NULL context");
-  if (!dark || !flat) return fail(c, RTC_E_ARG, "rtc_load_calib: NULL dark or flat map");
-  if (!std::isfinite(threshold)) return fail(c, RTC_E_NONFINITE, "rtc_load_calib: threshold not finite");
-  if (threshold < 0.0f) return fail(c, RTC_E_ARG, "rtc_load_calib: threshold must be >= 0");
-  const int n = c->n_pix;
-  std::vector<float2> cal;
-  try {
-    cal.resize((size_t)c->n_valid * n * n);
-  } catch (...) {
-    return fail(c, RTC_E_NOMEM, "rtc_load_calib: host allocation failed");
+rtc_status rtc_init(const rtc_config *cfg, rtc_ctx **out) {
+  if (!cfg || !out) return fail(nullptr, RTC_E_ARG, "rtc_init: NULL config or output pointer");
+  if (cfg->abi_version != RTC_ABI_VERSION)
+    return fail(nullptr, RTC_E_ARG, "rtc_init: abi_version does not match RTC_ABI_VERSION");
+  const rtc_wfs one{cfg->n_sub_x, cfg->n_sub_y, cfg->n_pix, cfg->subap_mask};
+  return init_impl(cfg, &one, 1, "rtc_init", out);
+}
+
+rtc_status rtc_init_multi(const rtc_multi_config *mc, rtc_ctx **out) {
+  if (!mc || !out) return fail(nullptr, RTC_E_ARG, "rtc_init_multi: NULL config or output pointer");
+  rtc_config cfg{};
+  cfg.abi_version = mc->abi_version;
+  cfg.n_act = mc->n_act;
+  cfg.thr_mode = mc->thr_mode;
+  cfg.cm_dtype = mc->cm_dtype;
+  cfg.gain = mc->gain;
+  cfg.leak = mc->leak;
+  cfg.cmd_min = mc->cmd_min;
+  cfg.cmd_max = mc->cmd_max;
+  cfg.device = mc->device;
+  return init_impl(&cfg, mc->wfs, mc->n_wfs, "rtc_init_multi", out);
+}
+
+int64_t rtc_frame_elems(const rtc_ctx *c) { return c ? c->frame_elems : -1; }
+
+// Validates and uploads dark, flat (frame-set layout), one threshold per sensor
+// and the reference slopes.
+static rtc_status load_calib_impl(rtc_ctx *c, const float *dark, const float *flat, const float *thr,
+                                  const float *ref_slopes, const char *who) {
+  auto err = [&](rtc_status st, const char *msg) { return fail(c, st, std::string(who) + ": " + msg); };
+  if (!dark || !flat) return err(RTC_E_ARG, "NULL dark or flat map");
+  for (size_t w = 0; w < c->wfs.size(); ++w) {
+    if (!std::isfinite(thr[w])) return err(RTC_E_NONFINITE, "threshold not finite");
+    if (thr[w] < 0.0f) return err(RTC_E_ARG, "threshold must be >= 0");
   }
-  for (int32_t k = 0; k < c->n_valid; ++k) {
-    for (int i = 0; i < n; ++i) {
-      const int64_t base = (int64_t)c->tile_off_h[k] + (int64_t)i * c->W;
-      for (int j = 0; j < n; ++j) {
-        const float d = dark[base + j], f = flat[base + j];
-        if (!std::isfinite(d) || !std::isfinite(f))
-          return fail(c, RTC_E_NONFINITE, "rtc_load_calib: non-finite dark or flat value in an active subaperture");
-        if (!dark_in_domain(d))
-          return fail(c, RTC_E_ARG, "rtc_load_calib: dark values must be 0 or of magnitude in [2^-13, 2^24)");
-        cal[((size_t)k * n + i) * n + j] = make_float2(d, f);
+  std::vector<float2> cal;
+  std::vector<rtck::TileDesc> tiles = c->tiles_h;
+  try {
+    cal.resize((size_t)c->calib_len);
+  } catch (...) {
+    return err(RTC_E_NOMEM, "host allocation failed");
+  }
+  for (size_t w = 0; w < c->wfs.size(); ++w) {
+    const WfsInfo &wi = c->wfs[w];
+    for (int32_t k = wi.tile_base; k < wi.tile_base + wi.n_tiles; ++k) {
+      rtck::TileDesc &t = tiles[(size_t)k];
+      t.thr = thr[w];
+      const int n = t.n;
+      for (int i = 0; i < n; ++i) {
+        const int64_t base = (int64_t)t.off + (int64_t)i * t.pitch;
+        for (int j = 0; j < n; ++j) {
+          const float d = dark[base + j], f = flat[base + j];
+          if (!std::isfinite(d) || !std::isfinite(f))
+            return err(RTC_E_NONFINITE, "non-finite dark or flat value in an active subaperture");
+          if (!dark_in_domain(d)) return err(RTC_E_ARG, "dark values must be 0 or of magnitude in [2^-13, 2^24)");
+          cal[(size_t)t.calib_off + (size_t)i * n + j] = make_float2(d, f);
+        }
       }
     }
   }
   std::vector<float> ref((size_t)c->s_len, 0.0f);
   if (ref_slopes) {
     for (int32_t i = 0; i < c->n_slopes; ++i) {
-      if (!std::isfinite(ref_slopes[i]))
-        return fail(c, RTC_E_NONFINITE, "rtc_load_calib: non-finite reference slope");
+      if (!std::isfinite(ref_slopes[i])) return err(RTC_E_NONFINITE, "non-finite reference slope");
       ref[i] = ref_slopes[i];
     }
   }
@@ -334,15 +407,31 @@ rtc_status rtc_load_calib(rtc_ctx *c, const float *dark, const float *flat, floa
   // frames already queued keep using the old buffers until the device is idle
   if ((e = hipDeviceSynchronize()) != hipSuccess ||
       (e = hipMemcpy(d_cal, cal.data(), cal.size() * sizeof(float2), hipMemcpyHostToDevice)) != hipSuccess ||
-      (e = hipMemcpy(c->d_ref, ref.data(), ref.size() * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess) {
+      (e = hipMemcpy(c->d_ref, ref.data(), ref.size() * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(c->d_tiles, tiles.data(), tiles.size() * sizeof(rtck::TileDesc), hipMemcpyHostToDevice)) !=
+          hipSuccess) {
     (void)hipFree(d_cal);
     return hip_fail(c, e, "rtc_load_calib: upload");
   }
   dfree(c->d_calib);
   c->d_calib = d_cal;
-  c->thr = threshold;
+  c->tiles_h = std::move(tiles);
   c->calib_loaded = true;
   return RTC_OK;
+}
+
+rtc_status rtc_load_calib(rtc_ctx *c, const float *dark, const float *flat, float threshold,
+                          const float *ref_slopes) {
+  if (!c) return fail(nullptr, RTC_E_ARG, "rtc_load_calib: NULL context");
+  std::vector<float> thr(c->wfs.size(), threshold);
+  return load_calib_impl(c, dark, flat, thr.data(), ref_slopes, "rtc_load_calib");
+}
+
+rtc_status rtc_load_calib_multi(rtc_ctx *c, const float *dark, const float *flat, const float *thresholds,
+                                const float *ref_slopes) {
+  if (!c) return fail(nullptr, RTC_E_ARG, "rtc_load_calib_multi: NULL context");
+  if (!thresholds) return fail(c, RTC_E_ARG, "rtc_load_calib_multi: NULL thresholds");
+  return load_calib_impl(c, dark, flat, thresholds, ref_slopes, "rtc_load_calib_multi");
 }
 
 rtc_status rtc_load_cmat(rtc_ctx *c, const float *R, int32_t n_act, int32_t n_slopes, int64_t ld) {
@@ -429,32 +518,33 @@ static hipError_t launch_reconstruction(const rtc_ctx *c, rtck::MvmArgs ma, hipS
   ma.fmt = c->fmt;
   ma.n_chunks = c->n_chunks;
   if (t.kernel == RTC_MVM_ROWBLOCK || c->fmt != RTC_CM_F32) {
-    const int kpl = rtck::slice_chunks(c->n_chunks, t.waves) / 64;
-    if (kpl <= rtck::mvm_block_max_kpl() || c->fmt != RTC_CM_F32) {
-      ma.k_split = 1;
-      // reduced formats always fit 16 waves (checked at init); widen if 8 do not
-      const int waves = kpl <= rtck::mvm_block_max_kpl() ? t.waves : 16;
-      return rtck::launch_mvm_block(ma, t.blocks > 0 ? t.blocks : c->n_cu, waves, t.rows_per_wave, st);
-    }
     ma.k_split = 1;
-    ma.rows_per_wave = 2;
-    ma.unroll = 4;
+    const int G = t.blocks > 0 ? t.blocks : c->n_cu;
+    // slope vectors beyond 8 wavefronts' register slices: slope panels, sliced
+    // as the persistent kernel slices them
+    if (rtck::slice_chunks(c->n_chunks, 8) / 64 > rtck::mvm_block_max_kpl()) return rtck::launch_mvm_panel(ma, G, st);
+    return rtck::launch_mvm_block(ma, G, t.waves, t.rows_per_wave, st);
   }
   return rtck::launch_mvm_integrate(ma, nullptr, st);
 }
 
-static rtc_status enqueue_frame(rtc_ctx *c, const uint16_t *pix, float *cmd, float *slopes, float *recon,
-                                int32_t *counts, uint64_t *ts, hipStream_t st, const char *who) {
+// Calibration arguments of one frame set (outputs left for the caller to set).
+static rtck::CalibArgs calib_args(const rtc_ctx *c, const uint16_t *pix) {
   rtck::CalibArgs ca{};
   ca.pix = pix;
-  ca.W = c->W;
-  ca.tile_off = c->d_tile_off;
+  ca.tiles = c->d_tiles;
   ca.calib = c->d_calib;
   ca.n_valid = c->n_valid;
-  ca.n_pix = c->n_pix;
-  ca.thr = c->thr;
+  ca.max_n = c->max_n;
+  ca.pairs = c->pairs;
   ca.mode = c->cfg.thr_mode;
   ca.ref = c->d_ref;
+  return ca;
+}
+
+static rtc_status enqueue_frame(rtc_ctx *c, const uint16_t *pix, float *cmd, float *slopes, float *recon,
+                                int32_t *counts, uint64_t *ts, hipStream_t st, const char *who) {
+  rtck::CalibArgs ca = calib_args(c, pix);
   ca.s_int = c->d_s;
   ca.s_user = slopes;
   ca.counts = counts;
@@ -504,28 +594,19 @@ rtc_status rtc_frame_batch(rtc_ctx *c, int32_t n_frames, const uint16_t *d_pixel
   if (n_frames < 0) return fail(c, RTC_E_ARG, "rtc_frame_batch: n_frames < 0");
   if (n_frames == 0) return RTC_OK;
   if (!d_pixels || !d_cmd) return fail(c, RTC_E_ARG, "rtc_frame_batch: NULL pixels or cmd");
-  if (frame_stride < (int64_t)c->H * c->W)
+  if (frame_stride < c->frame_elems)
     return fail(c, RTC_E_ARG, "rtc_frame_batch: frame_stride shorter than a frame");
   DeviceScope ds(c->device);
   if (ds.status != hipSuccess) return hip_fail(c, ds.status, "rtc_frame_batch: hipSetDevice");
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   if (c->frame_mode == RTC_FRAMES_PERSISTENT) {
     rtck::PersistArgs p{};
-    p.cal.pix = d_pixels;
-    p.cal.W = c->W;
-    p.cal.tile_off = c->d_tile_off;
-    p.cal.calib = c->d_calib;
-    p.cal.n_valid = c->n_valid;
-    p.cal.n_pix = c->n_pix;
-    p.cal.thr = c->thr;
-    p.cal.mode = c->cfg.thr_mode;
-    p.cal.ref = c->d_ref;
+    p.cal = calib_args(c, d_pixels);
     p.cal.s_user = d_slopes;
     p.cal.counts = d_counts;
     p.frame_stride = frame_stride;
     p.n_frames = n_frames;
-    p.vec = ((c->n_pix & 1) == 0 && (c->W & 1) == 0 && (frame_stride & 1) == 0 &&
-             (reinterpret_cast<uintptr_t>(d_pixels) & 3) == 0) ? 1 : 0;
+    p.vec = (c->pairs && (frame_stride & 1) == 0 && (reinterpret_cast<uintptr_t>(d_pixels) & 3) == 0) ? 1 : 0;
     p.sbuf = c->d_sbuf;
     p.s_len = (int32_t)xchg_len_of(c->n_slopes);
     p.cal.xchg_epc = rtck::format_elems_per_chunk(c->fmt);
@@ -575,16 +656,7 @@ rtc_status rtc_calibrate_centroid(rtc_ctx *c, const uint16_t *d_pixels, float *d
   if (!d_pixels || !d_slopes) return fail(c, RTC_E_ARG, "rtc_calibrate_centroid: NULL pixels or slopes");
   DeviceScope ds(c->device);
   if (ds.status != hipSuccess) return hip_fail(c, ds.status, "rtc_calibrate_centroid: hipSetDevice");
-  rtck::CalibArgs ca{};
-  ca.pix = d_pixels;
-  ca.W = c->W;
-  ca.tile_off = c->d_tile_off;
-  ca.calib = c->d_calib;
-  ca.n_valid = c->n_valid;
-  ca.n_pix = c->n_pix;
-  ca.thr = c->thr;
-  ca.mode = c->cfg.thr_mode;
-  ca.ref = c->d_ref;
+  rtck::CalibArgs ca = calib_args(c, d_pixels);
   ca.s_int = d_slopes;     // the caller's vector is the only output
   ca.s_user = nullptr;
   ca.counts = d_counts;
@@ -764,7 +836,7 @@ void rtc_destroy(rtc_ctx *c) {
   if (!c) return;
   DeviceScope ds(c->device);
   if (ds.status == hipSuccess) (void)hipDeviceSynchronize();
-  dfree(c->d_tile_off);
+  dfree(c->d_tiles);
   dfree(c->d_calib);
   dfree(c->d_ref);
   dfree(c->d_R);

@@ -6,18 +6,29 @@
 
 namespace rtck {
 
+// One active subaperture (32 bytes): where its pixels and calibration are,
+// where its slopes go, and its sensor's geometry and threshold.
+struct TileDesc {
+  int32_t off;             // element offset of its top-left pixel in the frame set
+  int32_t calib_off;       // float2 offset of its [n][n] (dark, flat) block
+  int32_t sx, sy;          // positions of its x and y slopes in the slope vector
+  int32_t pitch;           // row length of its sensor's frame (elements)
+  int32_t n;               // pixels per side, 1..32
+  float thr;               // its sensor's threshold
+  int32_t reserved;
+};
+
 // Steps (a)-(b): calibration + centre of gravity of every active subaperture.
 struct CalibArgs {
-  const uint16_t *pix;     // [H][W] frame
-  int32_t W;               // frame row length (elements)
-  const int32_t *tile_off; // [n_valid] element offset of each tile's top-left pixel
-  const float2 *calib;     // [n_valid][n_pix][n_pix] (dark, flat)
+  const uint16_t *pix;     // frame set
+  const TileDesc *tiles;   // [n_valid]
+  const float2 *calib;     // per-tile (dark, flat) blocks
   int32_t n_valid;
-  int32_t n_pix;
-  float thr;
+  int32_t max_n;           // largest tile side (lanes per tile)
+  int32_t pairs;           // every tile row starts on an even element and has even width
   int32_t mode;            // 1 = subtract, 2 = zero
-  const float *ref;        // [2 n_valid] reference slopes
-  float *s_int;            // [>= 2 n_valid] library slope buffer
+  const float *ref;        // [n_slopes] reference slopes (by slope position)
+  float *s_int;            // [>= n_slopes] library slope buffer
   float *s_user;           // nullable copy
   int32_t *counts;         // nullable [n_valid]
   uint64_t *ts_start;      // nullable: written by block 0 on entry
@@ -65,6 +76,10 @@ __host__ __device__ inline int slice_chunks(int n_chunks, int waves) {
 // more than mvm_block_max_kpl() 16-byte vectors per lane.
 hipError_t launch_mvm_block(const MvmArgs &a, int blocks, int waves, int rows_per_batch, hipStream_t st);
 int mvm_block_max_kpl();
+// Row-block reconstruction over slope panels (8 wavefronts, any slope-vector
+// length): used when 8 wavefronts' slices would exceed mvm_block_max_kpl()
+// vectors per lane, with the slicing of the persistent kernel's panels.
+hipError_t launch_mvm_panel(const MvmArgs &a, int blocks, hipStream_t st);
 // Elements per 16-byte chunk of a storage format (4, 8, 8, 16).
 int format_elems_per_chunk(int fmt);
 

@@ -41,13 +41,15 @@ __device__ __forceinline__ int64_t xchg_pos(int64_t k, int epc) {
 // workgroups of the same launch); otherwise with ordinary stores.
 template <int GS, bool COH = false>
 __device__ __forceinline__ void calib_tile_row(const CalibArgs &a, int k, int i, int vec) {
-  const int n = a.n_pix;
+  TileDesc t{};
+  if (k < a.n_valid) t = a.tiles[k];
+  const int n = t.n;
   const double half = 0.5 * (double)(n - 1);
   double S = 0.0, Sx = 0.0;
   int cnt = 0;
   if (k < a.n_valid && i < n) {
-    const uint16_t *prow = a.pix + (int64_t)a.tile_off[k] + (int64_t)i * a.W;
-    const float2 *crow = a.calib + ((int64_t)k * n + i) * n;
+    const uint16_t *prow = a.pix + (int64_t)t.off + (int64_t)i * t.pitch;
+    const float2 *crow = a.calib + (int64_t)t.calib_off + (int64_t)i * n;
     uint32_t raw[GS];
     float2 cf[GS];
     if (vec) {
@@ -73,7 +75,7 @@ __device__ __forceinline__ void calib_tile_row(const CalibArgs &a, int k, int i,
         }
       }
     }
-    const double T = (double)a.thr;
+    const double T = (double)t.thr;
     const bool subtract = (a.mode == 1);
 #pragma unroll
     for (int j = 0; j < GS; ++j) {
@@ -105,19 +107,18 @@ __device__ __forceinline__ void calib_tile_row(const CalibArgs &a, int k, int i,
       cx = Sx / S;
       cy = Sy / S;
     }
-    const float sx = (float)(cx - (double)a.ref[k]);
-    const float sy = (float)(cy - (double)a.ref[a.n_valid + k]);
+    const float sx = (float)(cx - (double)a.ref[t.sx]);
+    const float sy = (float)(cy - (double)a.ref[t.sy]);
     if (COH) {
-      __hip_atomic_store(a.s_int + xchg_pos(k, a.xchg_epc), sx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(a.s_int + xchg_pos(a.n_valid + k, a.xchg_epc), sy, __ATOMIC_RELAXED,
-                         __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(a.s_int + xchg_pos(t.sx, a.xchg_epc), sx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(a.s_int + xchg_pos(t.sy, a.xchg_epc), sy, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     } else {
-      a.s_int[k] = sx;
-      a.s_int[a.n_valid + k] = sy;
+      a.s_int[t.sx] = sx;
+      a.s_int[t.sy] = sy;
     }
     if (a.s_user != nullptr) {
-      a.s_user[k] = sx;
-      a.s_user[a.n_valid + k] = sy;
+      a.s_user[t.sx] = sx;
+      a.s_user[t.sy] = sy;
     }
     if (a.counts != nullptr) a.counts[k] = cnt;
   }
@@ -214,16 +215,17 @@ __device__ __forceinline__ float wave_sum_transposed(const float (&t)[NR], int l
   return x;
 }
 
-// Wavefront sums of NR rows stored to out[0..min(NR, valid)-1].
+// Wavefront sums of NR rows stored to out[0..min(NR, valid)-1], or added to
+// what is there when acc is set (slope panels after the first).
 template <int NR>
-__device__ __forceinline__ void store_row_sums(float (&t)[NR], float *out, int valid, int lane) {
+__device__ __forceinline__ void store_row_sums(float (&t)[NR], float *out, int valid, int lane, bool acc = false) {
   if constexpr (NR == 1) {
     const float x = wave_sum(t[0]);
-    if (lane == 0 && valid > 0) out[0] = x;
+    if (lane == 0 && valid > 0) out[0] = acc ? out[0] + x : x;
   } else if constexpr (NR == 2 || NR == 4 || NR == 8) {
     const float x = wave_sum_transposed<NR>(t, lane);
     const int r = row_of_lane<NR>(lane);
-    if (lane < NR && r < valid) out[r] = x;
+    if (lane < NR && r < valid) out[r] = acc ? out[r] + x : x;
   } else {                                          // leading 8, 4 or 2 rows, then the rest
     constexpr int H = NR > 8 ? 8 : (NR > 4 ? 4 : 2);
     float u[H], w[NR - H];
@@ -231,8 +233,8 @@ __device__ __forceinline__ void store_row_sums(float (&t)[NR], float *out, int v
     for (int i = 0; i < H; ++i) u[i] = t[i];
 #pragma unroll
     for (int i = 0; i < NR - H; ++i) w[i] = t[H + i];
-    store_row_sums<H>(u, out, valid, lane);
-    store_row_sums<NR - H>(w, out + H, valid - H, lane);
+    store_row_sums<H>(u, out, valid, lane, acc);
+    store_row_sums<NR - H>(w, out + H, valid - H, lane, acc);
   }
 }
 
@@ -504,6 +506,103 @@ __global__ __launch_bounds__(W * 64) void mvm_block_kernel(MvmArgs a, int32_t ma
   if (a.ts_end != nullptr) completion_stamp(a.sync, a.ts_end);
 }
 
+// Dot product of a lane's KPL code chunks with its slope values, four
+// accumulators added pairwise (the order of the per-launch row-block kernel).
+template <int FMT, int KPL>
+__device__ __forceinline__ float chunk_dot(const uint4 (&m)[KPL], const float (&sv)[KPL][Codec<FMT>::EPC]) {
+  constexpr int EPC = Codec<FMT>::EPC;
+  float acc[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int j = 0; j < KPL; ++j) {
+    float v[EPC];
+    Codec<FMT>::decode(m[j], v);
+#pragma unroll
+    for (int e = 0; e < EPC; ++e) acc[e & 3] = fmaf(v[e], sv[j][e], acc[e & 3]);
+  }
+  return (acc[0] + acc[1]) + (acc[2] + acc[3]);
+}
+
+// ---------------------------------------------------------------------------
+// Slope panels: slope vectors longer than 8 wavefronts' register slices are
+// processed in panels of 8 x 64 x KPLP 16-byte chunks (16384 slopes in every
+// format).  In panel p, lane l of wavefront w holds chunks
+// (p 8 + w) 64 KPLP + j 64 + l, j < KPLP, and every row of the slab is
+// streamed against them; a row's wavefront sums are added over panels in
+// panel order in LDS.  With one panel this is the slicing of slab_partials.
+template <int FMT> struct PanelShape;
+template <> struct PanelShape<0> { static constexpr int KPLP = 8, RB = 2; };
+template <> struct PanelShape<1> { static constexpr int KPLP = 4, RB = 4; };
+template <> struct PanelShape<2> { static constexpr int KPLP = 4, RB = 4; };
+template <> struct PanelShape<3> { static constexpr int KPLP = 2, RB = 4; };
+constexpr int kPanelWaves = 8;
+
+__host__ __device__ inline int panel_count(int n_chunks, int kplp) {
+  const int per = kPanelWaves * 64 * kplp;
+  return (n_chunks + per - 1) / per;
+}
+
+// Rows [0, nrows) of the slab starting at row_begin against one panel's slope
+// values sv (chunks col[]), stored (panel 0) or added into sh_part.
+template <int FMT, int KPLP, int RB>
+__device__ __forceinline__ void panel_rows(const MvmArgs &a, int row_begin, int nrows, const int (&col)[KPLP],
+                                           const float (&sv)[KPLP][Codec<FMT>::EPC], float *sh_part_w,
+                                           int lane, bool acc) {
+  const char *base = static_cast<const char *>(a.Rq);
+  for (int rb = 0; rb < nrows; rb += RB) {
+    uint4 m[RB][KPLP];
+#pragma unroll
+    for (int i = 0; i < RB; ++i) {
+      const int row = row_begin + min(rb + i, nrows - 1);
+      const uint4 *rp = reinterpret_cast<const uint4 *>(base + (int64_t)row * a.ldq_bytes);
+#pragma unroll
+      for (int j = 0; j < KPLP; ++j) m[i][j] = rp[col[j]];
+    }
+    float t[RB];
+#pragma unroll
+    for (int i = 0; i < RB; ++i) t[i] = chunk_dot<FMT, KPLP>(m[i], sv);
+    store_row_sums<RB>(t, sh_part_w + rb, nrows - rb, lane, acc);
+  }
+}
+
+template <int FMT>
+__global__ __launch_bounds__(kPanelWaves * 64) void mvm_panel_kernel(MvmArgs a, int32_t max_rows) {
+  using PS = PanelShape<FMT>;
+  constexpr int KPLP = PS::KPLP, EPC = Codec<FMT>::EPC;
+  extern __shared__ float sh_part[];               // [8][max_rows]
+  const int G = gridDim.x;
+  const int row_begin = (int)(((int64_t)blockIdx.x * a.n_act) / G);
+  const int nrows = (int)(((int64_t)(blockIdx.x + 1) * a.n_act) / G) - row_begin;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const float4 *s4 = reinterpret_cast<const float4 *>(a.s);
+  const int np = panel_count(a.n_chunks, KPLP);
+  for (int pn = 0; pn < np; ++pn) {
+    int col[KPLP];
+    float sv[KPLP][EPC];
+#pragma unroll
+    for (int j = 0; j < KPLP; ++j) {
+      const int c = (pn * kPanelWaves + wave) * 64 * KPLP + j * 64 + lane;
+      const bool ok = c < a.n_chunks;
+      col[j] = ok ? c : 0;
+#pragma unroll
+      for (int q = 0; q < EPC / 4; ++q) {
+        const float4 v = s4[col[j] * (EPC / 4) + q];
+        sv[j][4 * q] = ok ? v.x : 0.f;
+        sv[j][4 * q + 1] = ok ? v.y : 0.f;
+        sv[j][4 * q + 2] = ok ? v.z : 0.f;
+        sv[j][4 * q + 3] = ok ? v.w : 0.f;
+      }
+    }
+    panel_rows<FMT, KPLP, PS::RB>(a, row_begin, nrows, col, sv, sh_part + wave * max_rows, lane, pn > 0);
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < nrows; t += kPanelWaves * 64) {
+    float v = slab_row_sum<kPanelWaves>(a, sh_part, max_rows, t);
+    if (a.scales != nullptr) v *= a.scales[row_begin + t];
+    integrate_one(a.state, a.cmd, a.recon, row_begin + t, v, a.gain, a.leak, a.cmd_min, a.cmd_max);
+  }
+  if (a.ts_end != nullptr) completion_stamp(a.sync, a.ts_end);
+}
+
 // ---------------------------------------------------------------------------
 // Persistent frames: one cooperative launch processes frames f = 0..n-1, one
 // workgroup per compute unit.  Workgroup b owns a share of the subapertures
@@ -593,19 +692,6 @@ __device__ __forceinline__ void reduce_end_stamp(const PersistArgs &p, int f) {
   if (threadIdx.x == 0) p.ts[2 * (int64_t)f + 1] = m;
 }
 
-template <int FMT, int KPL>
-__device__ __forceinline__ float chunk_dot(const uint4 (&m)[KPL], const float (&sv)[KPL][Codec<FMT>::EPC]) {
-  constexpr int EPC = Codec<FMT>::EPC;
-  float acc[4] = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-  for (int j = 0; j < KPL; ++j) {
-    float v[EPC];
-    Codec<FMT>::decode(m[j], v);
-#pragma unroll
-    for (int e = 0; e < EPC; ++e) acc[e & 3] = fmaf(v[e], sv[j][e], acc[e & 3]);
-  }
-  return (acc[0] + acc[1]) + (acc[2] + acc[3]);
-}
 
 // NB slab rows held in LDS, starting at row r0: partial sums into sh_part.
 template <int FMT, int KPL, int NB>
@@ -623,7 +709,7 @@ __device__ __forceinline__ void lds_row_group(const uint4 *lds, int ldq16, int r
   store_row_sums<NB>(t, sh_part + wave * max_rows + r0, NB, lane);
 }
 
-template <int FMT, int KPL, int RR, int GS>
+template <int FMT, int KPL, int RR, int GS, bool PANELS>
 __global__ __launch_bounds__(512) void frames_kernel(PersistArgs p, int32_t max_rows, int32_t lds_rows) {
   constexpr int W = 8;
   constexpr int EPC = Codec<FMT>::EPC;
@@ -704,71 +790,96 @@ __global__ __launch_bounds__(512) void frames_kernel(PersistArgs p, int32_t max_
     frame_barrier(p, (uint32_t)(f + 1), f);
     trace_stamp(p, f, 2);
 
-    // slope slices of this wavefront (device-coherent loads)
-    float sv[KPL][EPC];
-#pragma unroll
-    for (int j = 0; j < KPL; ++j) {
-      // this lane's chunk group; lanes past the slice read group 0 (in bounds) and zero it
-      const int64_t g = okc[j] ? (int64_t)((k_lo >> 6) + j) : 0;
-      const float *grp = ca.s_int + g * (64 * EPC) + lane;
-#pragma unroll
-      for (int e = 0; e < EPC; ++e) {
-        const float v = __hip_atomic_load(grp + e * 64, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        sv[j][e] = okc[j] ? v : 0.f;
-      }
-    }
-    // end stamp of the previous frame, whose per-workgroup stamps the barrier
-    // has just made visible; the workgroups take turns
-    if (p.ts != nullptr && f > 0 && wave == 0 && b == (f - 1) % G) reduce_end_stamp(p, f - 1);
-    if (p.trace != nullptr) {                       // stage 3: slope slices in registers
-      float probe = 0.f;
-#pragma unroll
-      for (int j = 0; j < KPL; ++j) probe += sv[j][0];
-      if (probe == 1.2345e-30f) sh_part[0] = probe;   // keeps the loads ahead of the stamp
+    if constexpr (PANELS) {
+      // long slope vectors: panels of the slope vector, every row streamed per panel
+      if (p.ts != nullptr && f > 0 && wave == 0 && b == (f - 1) % G) reduce_end_stamp(p, f - 1);
       trace_stamp(p, f, 3);
-    }
+      const int np = panel_count(a.n_chunks, KPL);
+      for (int pn = 0; pn < np; ++pn) {
+        int pcol[KPL];
+        float sv[KPL][EPC];
+#pragma unroll
+        for (int j = 0; j < KPL; ++j) {
+          const int c = (pn * W + wave) * 64 * KPL + j * 64 + lane;
+          const bool ok = c < a.n_chunks;
+          pcol[j] = ok ? c : 0;
+          const float *grp = ca.s_int + (int64_t)(ok ? (c >> 6) : 0) * (64 * EPC) + lane;
+#pragma unroll
+          for (int e = 0; e < EPC; ++e) {
+            const float v = __hip_atomic_load(grp + e * 64, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            sv[j][e] = ok ? v : 0.f;
+          }
+        }
+        panel_rows<FMT, KPL, PanelShape<FMT>::RB>(a, row_begin, nrows, pcol, sv, sh_part + wave * max_rows, lane,
+                                                  pn > 0);
+      }
+    } else {
+      // slope slices of this wavefront (device-coherent loads)
+      float sv[KPL][EPC];
+  #pragma unroll
+      for (int j = 0; j < KPL; ++j) {
+        // this lane's chunk group; lanes past the slice read group 0 (in bounds) and zero it
+        const int64_t g = okc[j] ? (int64_t)((k_lo >> 6) + j) : 0;
+        const float *grp = ca.s_int + g * (64 * EPC) + lane;
+  #pragma unroll
+        for (int e = 0; e < EPC; ++e) {
+          const float v = __hip_atomic_load(grp + e * 64, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          sv[j][e] = okc[j] ? v : 0.f;
+        }
+      }
+      // end stamp of the previous frame, whose per-workgroup stamps the barrier
+      // has just made visible; the workgroups take turns
+      if (p.ts != nullptr && f > 0 && wave == 0 && b == (f - 1) % G) reduce_end_stamp(p, f - 1);
+      if (p.trace != nullptr) {                       // stage 3: slope slices in registers
+        float probe = 0.f;
+  #pragma unroll
+        for (int j = 0; j < KPL; ++j) probe += sv[j][0];
+        if (probe == 1.2345e-30f) sh_part[0] = probe;   // keeps the loads ahead of the stamp
+        trace_stamp(p, f, 3);
+      }
 
-    // (c) LDS rows in groups of LG (at most 64 VGPRs of codes, fewer when the
-    // register rows hold 128), then halves down to 1 (no duplicated rows)
-    {
-      constexpr int LG = (FMT == 0 ? 8 : 16) / KPL >= 8 ? 8 : ((FMT == 0 ? 8 : 16) / KPL >= 4 ? 4 : 2);
-      int r0 = 0;
-      for (; r0 + LG <= L; r0 += LG)
-        lds_row_group<FMT, KPL, LG>(lds, ldq16, r0, col, sv, sh_part, wave, lane, max_rows);
-      if constexpr (LG > 4) {
-        if (r0 + 4 <= L) {
-          lds_row_group<FMT, KPL, 4>(lds, ldq16, r0, col, sv, sh_part, wave, lane, max_rows);
-          r0 += 4;
+      // (c) LDS rows in groups of LG (at most 64 VGPRs of codes, fewer when the
+      // register rows hold 128), then halves down to 1 (no duplicated rows)
+      {
+        constexpr int LG = (FMT == 0 ? 8 : 16) / KPL >= 8 ? 8 : ((FMT == 0 ? 8 : 16) / KPL >= 4 ? 4 : 2);
+        int r0 = 0;
+        for (; r0 + LG <= L; r0 += LG)
+          lds_row_group<FMT, KPL, LG>(lds, ldq16, r0, col, sv, sh_part, wave, lane, max_rows);
+        if constexpr (LG > 4) {
+          if (r0 + 4 <= L) {
+            lds_row_group<FMT, KPL, 4>(lds, ldq16, r0, col, sv, sh_part, wave, lane, max_rows);
+            r0 += 4;
+          }
         }
-      }
-      if constexpr (LG > 2) {
-        if (r0 + 2 <= L) {
-          lds_row_group<FMT, KPL, 2>(lds, ldq16, r0, col, sv, sh_part, wave, lane, max_rows);
-          r0 += 2;
+        if constexpr (LG > 2) {
+          if (r0 + 2 <= L) {
+            lds_row_group<FMT, KPL, 2>(lds, ldq16, r0, col, sv, sh_part, wave, lane, max_rows);
+            r0 += 2;
+          }
         }
+        if (r0 < L) lds_row_group<FMT, KPL, 1>(lds, ldq16, r0, col, sv, sh_part, wave, lane, max_rows);
       }
-      if (r0 < L) lds_row_group<FMT, KPL, 1>(lds, ldq16, r0, col, sv, sh_part, wave, lane, max_rows);
-    }
-    // register rows
-    if (nreg > 0) {
-      float t[RR > 0 ? RR : 1];
-#pragma unroll
-      for (int i = 0; i < RR; ++i) t[i] = chunk_dot<FMT, KPL>(rr[i], sv);
-      store_row_sums<(RR > 0 ? RR : 1)>(t, sh_part + wave * max_rows + L, nreg, lane);
-    }
-    // streamed rows
-    for (int r0 = stream_begin; r0 < nrows; r0 += RB) {
-      uint4 m[RB][KPL];
-#pragma unroll
-      for (int i = 0; i < RB; ++i) {
-        const int row = min(r0 + i, nrows - 1);
-#pragma unroll
-        for (int j = 0; j < KPL; ++j) m[i][j] = slab[(int64_t)row * ldq16 + col[j]];
+      // register rows
+      if (nreg > 0) {
+        float t[RR > 0 ? RR : 1];
+  #pragma unroll
+        for (int i = 0; i < RR; ++i) t[i] = chunk_dot<FMT, KPL>(rr[i], sv);
+        store_row_sums<(RR > 0 ? RR : 1)>(t, sh_part + wave * max_rows + L, nreg, lane);
       }
-      float t[RB];
-#pragma unroll
-      for (int i = 0; i < RB; ++i) t[i] = chunk_dot<FMT, KPL>(m[i], sv);
-      store_row_sums<RB>(t, sh_part + wave * max_rows + r0, nrows - r0, lane);
+      // streamed rows
+      for (int r0 = stream_begin; r0 < nrows; r0 += RB) {
+        uint4 m[RB][KPL];
+  #pragma unroll
+        for (int i = 0; i < RB; ++i) {
+          const int row = min(r0 + i, nrows - 1);
+  #pragma unroll
+          for (int j = 0; j < KPL; ++j) m[i][j] = slab[(int64_t)row * ldq16 + col[j]];
+        }
+        float t[RB];
+  #pragma unroll
+        for (int i = 0; i < RB; ++i) t[i] = chunk_dot<FMT, KPL>(m[i], sv);
+        store_row_sums<RB>(t, sh_part + wave * max_rows + r0, nrows - r0, lane);
+      }
     }
     __syncthreads();
     trace_stamp(p, f, 4);
@@ -851,13 +962,13 @@ __global__ __launch_bounds__(kBlock) void probe_read_kernel(const float4 *__rest
 }  // namespace
 
 hipError_t launch_calib_cog(const CalibArgs &a, hipStream_t st) {
-  if (a.n_pix < 1 || a.n_pix > 32) return hipErrorInvalidValue;
+  if (a.max_n < 1 || a.max_n > 32) return hipErrorInvalidValue;
   if (a.n_valid == 0) return hipSuccess;
-  const int gs = a.n_pix <= 8 ? 8 : (a.n_pix <= 16 ? 16 : 32);
+  const int gs = a.max_n <= 8 ? 8 : (a.max_n <= 16 ? 16 : 32);
   const int64_t lanes = (int64_t)a.n_valid * gs;
   const unsigned blocks = (unsigned)((lanes + kBlock - 1) / kBlock);
-  // 4-byte pixel pairs need an even row length and a 4-byte aligned frame
-  const int vec = ((a.n_pix & 1) == 0 && (a.W & 1) == 0 && (reinterpret_cast<uintptr_t>(a.pix) & 3) == 0) ? 1 : 0;
+  // 4-byte pixel pairs need even tile rows and a 4-byte aligned frame set
+  const int vec = (a.pairs && (reinterpret_cast<uintptr_t>(a.pix) & 3) == 0) ? 1 : 0;
   if (gs == 8)
     calib_cog_kernel<8><<<blocks, kBlock, 0, st>>>(a, vec);
   else if (gs == 16)
@@ -939,6 +1050,22 @@ static hipError_t launch_block_fmt(const MvmArgs &a, int G, int max_rows, int wa
                     : launch_block_w<FMT, 16>(a, G, max_rows, kpl, rb, st);
 }
 
+hipError_t launch_mvm_panel(const MvmArgs &a, int blocks, hipStream_t st) {
+  int G = blocks < 1 ? 1 : blocks;
+  if (G > a.n_act) G = a.n_act;
+  const int max_rows = (a.n_act + G - 1) / G;
+  const size_t lds = (size_t)kPanelWaves * max_rows * sizeof(float);
+  if (lds > 65536) return hipErrorInvalidValue;
+  switch (a.fmt) {
+    case 0: mvm_panel_kernel<0><<<G, kPanelWaves * 64, lds, st>>>(a, max_rows); break;
+    case 1: mvm_panel_kernel<1><<<G, kPanelWaves * 64, lds, st>>>(a, max_rows); break;
+    case 2: mvm_panel_kernel<2><<<G, kPanelWaves * 64, lds, st>>>(a, max_rows); break;
+    case 3: mvm_panel_kernel<3><<<G, kPanelWaves * 64, lds, st>>>(a, max_rows); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 int mvm_block_max_kpl() { return 8; }
 
 int format_elems_per_chunk(int fmt) { return fmt == 0 ? 4 : (fmt == 3 ? 16 : 8); }
@@ -977,11 +1104,12 @@ __global__ __launch_bounds__(kBlock) void persist_reset_kernel(uint32_t *bar, ui
   if (w != nullptr) __hip_atomic_store(w, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-template <int FMT, int KPL, int GS>
+template <int FMT, int KPL, int GS, bool PANELS>
 static hipError_t launch_frames_variant(const PersistArgs &p, int G, int max_rows, hipStream_t st) {
   constexpr int W = 8;
-  constexpr int RR = (FMT == 0 ? 24 : 16) / KPL;    // register rows: 96 (f32) / 64 VGPRs of codes per lane
-  auto kern = frames_kernel<FMT, KPL, RR, GS>;
+  // register rows: 96 (f32) / 64 VGPRs of codes per lane; none when panels stream every row
+  constexpr int RR = PANELS ? 0 : (FMT == 0 ? 24 : 16) / KPL;
+  auto kern = frames_kernel<FMT, KPL, RR, GS, PANELS>;
   int dev = 0, ncu = 0, lds_max = 0;
   hipError_t e;
   if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
@@ -990,7 +1118,7 @@ static hipError_t launch_frames_variant(const PersistArgs &p, int G, int max_row
   const int64_t part_bytes = (int64_t)W * max_rows * sizeof(float);
   const int64_t static_bytes = 64;                 // sh_abort and alignment slack
   int64_t avail = (int64_t)lds_max - part_bytes - static_bytes;
-  int lds_rows = avail > 0 ? (int)(avail / p.mvm.ldq_bytes) : 0;
+  int lds_rows = (avail > 0 && !PANELS) ? (int)(avail / p.mvm.ldq_bytes) : 0;
   if (lds_rows > max_rows) lds_rows = max_rows;
   const size_t lds = (size_t)lds_rows * p.mvm.ldq_bytes + (size_t)part_bytes;
   if ((e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -1009,35 +1137,34 @@ static hipError_t launch_frames_variant(const PersistArgs &p, int G, int max_row
   return hipGetLastError();
 }
 
-template <int FMT, int KPL>
+template <int FMT, int KPL, bool PANELS>
 static hipError_t launch_frames_gs(const PersistArgs &p, int G, int max_rows, hipStream_t st) {
-  const int n = p.cal.n_pix;
-  if (n <= 8) return launch_frames_variant<FMT, KPL, 8>(p, G, max_rows, st);
-  if (n <= 16) return launch_frames_variant<FMT, KPL, 16>(p, G, max_rows, st);
-  return launch_frames_variant<FMT, KPL, 32>(p, G, max_rows, st);
+  const int n = p.cal.max_n;
+  if (n <= 8) return launch_frames_variant<FMT, KPL, 8, PANELS>(p, G, max_rows, st);
+  if (n <= 16) return launch_frames_variant<FMT, KPL, 16, PANELS>(p, G, max_rows, st);
+  return launch_frames_variant<FMT, KPL, 32, PANELS>(p, G, max_rows, st);
 }
 
 template <int FMT>
 static hipError_t launch_frames_fmt(const PersistArgs &p, int G, int max_rows, int kpl, hipStream_t st) {
-  if (kpl <= 1) return launch_frames_gs<FMT, 1>(p, G, max_rows, st);
-  if (kpl <= 2) return launch_frames_gs<FMT, 2>(p, G, max_rows, st);
-  if (kpl <= 4) return launch_frames_gs<FMT, 4>(p, G, max_rows, st);
-  if (kpl <= 8) return launch_frames_gs<FMT, 8>(p, G, max_rows, st);
-  return hipErrorInvalidValue;
+  if (kpl <= 1) return launch_frames_gs<FMT, 1, false>(p, G, max_rows, st);
+  if (kpl <= 2) return launch_frames_gs<FMT, 2, false>(p, G, max_rows, st);
+  if (kpl <= 4) return launch_frames_gs<FMT, 4, false>(p, G, max_rows, st);
+  if (kpl <= 8) return launch_frames_gs<FMT, 8, false>(p, G, max_rows, st);
+  return launch_frames_gs<FMT, PanelShape<FMT>::KPLP, true>(p, G, max_rows, st);
 }
 
 hipError_t launch_frames(const PersistArgs &p, int blocks, int rows_per_batch, hipStream_t st) {
   (void)rows_per_batch;
   constexpr int W = 8;
   if (p.n_frames <= 0) return hipSuccess;
-  if (p.cal.n_pix < 1 || p.cal.n_pix > 32) return hipErrorInvalidValue;
+  if (p.cal.max_n < 1 || p.cal.max_n > 32) return hipErrorInvalidValue;
   int G = blocks < 1 ? 1 : blocks;
   if (G > p.mvm.n_act) G = p.mvm.n_act;
   if (G > sl::kMaxGroups) return hipErrorInvalidValue;
   const int max_rows = (p.mvm.n_act + G - 1) / G;
   if (max_rows > W * 64) return hipErrorInvalidValue;      // one integrator row per thread
-  const int kpl = slice_chunks(p.mvm.n_chunks, W) / 64;
-  if (kpl > mvm_block_max_kpl()) return hipErrorInvalidValue;
+  const int kpl = slice_chunks(p.mvm.n_chunks, W) / 64;   // above mvm_block_max_kpl(): slope panels
   switch (p.mvm.fmt) {
     case 0: return launch_frames_fmt<0>(p, G, max_rows, kpl, st);
     case 1: return launch_frames_fmt<1>(p, G, max_rows, kpl, st);

@@ -41,6 +41,18 @@ class rtc_config(ctypes.Structure):
                 ("cmd_max", ctypes.c_float), ("device", ctypes.c_int32)]
 
 
+class rtc_wfs(ctypes.Structure):
+    _fields_ = [("n_sub_x", ctypes.c_int32), ("n_sub_y", ctypes.c_int32), ("n_pix", ctypes.c_int32),
+                ("subap_mask", ctypes.POINTER(ctypes.c_uint8))]
+
+
+class rtc_multi_config(ctypes.Structure):
+    _fields_ = [("abi_version", ctypes.c_uint32), ("n_wfs", ctypes.c_int32), ("wfs", ctypes.POINTER(rtc_wfs)),
+                ("n_act", ctypes.c_int32), ("thr_mode", ctypes.c_int32), ("cm_dtype", ctypes.c_int32),
+                ("gain", ctypes.c_float), ("leak", ctypes.c_float), ("cmd_min", ctypes.c_float),
+                ("cmd_max", ctypes.c_float), ("device", ctypes.c_int32)]
+
+
 RTC_MVM_ROWBLOCK, RTC_MVM_STREAMED = 0, 1
 RTC_FRAMES_PER_LAUNCH, RTC_FRAMES_PERSISTENT = 0, 1
 
@@ -53,7 +65,10 @@ class rtc_mvm_tuning(ctypes.Structure):
 _vp, _i32, _i64, _f32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_float
 _SIGNATURES = {
     "rtc_init": (_i32, [ctypes.POINTER(rtc_config), ctypes.POINTER(_vp)]),
+    "rtc_init_multi": (_i32, [ctypes.POINTER(rtc_multi_config), ctypes.POINTER(_vp)]),
+    "rtc_frame_elems": (_i64, [_vp]),
     "rtc_load_calib": (_i32, [_vp, _vp, _vp, _f32, _vp]),
+    "rtc_load_calib_multi": (_i32, [_vp, _vp, _vp, _vp, _vp]),
     "rtc_load_cmat": (_i32, [_vp, _vp, _i32, _i32, _i64]),
     "rtc_encode_cmat": (_i32, [_i32, _vp, _i32, _i32, _i64, _vp, _vp]),
     "rtc_frame": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
@@ -108,8 +123,8 @@ class RtcContext:
         self.n_valid = lib.rtc_n_valid(self.handle)
         self.n_act = lib.rtc_n_act(self.handle)
         self.n_slopes = 2 * self.n_valid
-        self.H = cfg["n_sub_y"] * cfg["n_pix"]
-        self.W = cfg["n_sub_x"] * cfg["n_pix"]
+        self.frame_elems = int(lib.rtc_frame_elems(self.handle))   # elements of one frame (set)
+        self.n_wfs = len(cfg.get("wfs", [None]))
 
     def close(self):
         if self.handle is not None and self.handle.value:
@@ -198,12 +213,50 @@ def rtc_init(subap_mask: np.ndarray, n_pix: int, n_act: int, thr_mode: int = RTC
                                   "gain": gain, "leak": leak})
 
 
+def rtc_init_multi(sensors, n_act: int, thr_mode: int = RTC_THR_SUBTRACT, cm_dtype=RTC_CM_F32,
+                   gain: float = 0.4, leak: float = 1.0, cmd_min: float = -math.inf, cmd_max: float = math.inf,
+                   device: int = 0, abi_version: int = RTC_ABI_VERSION) -> RtcContext:
+    """sensors: sequence of (subap_mask [n_sub_y, n_sub_x], n_pix) in frame-set order."""
+    lib = load_library()
+    if isinstance(cm_dtype, str):
+        cm_dtype = CM_DTYPES[cm_dtype]
+    masks = [np.ascontiguousarray(m, dtype=np.uint8) for m, _ in sensors]
+    if any(m.ndim != 2 for m in masks):
+        raise ValueError("every subap_mask must be 2-D [n_sub_y, n_sub_x]")
+    arr = (rtc_wfs * max(len(masks), 1))()
+    for w, (m, (_, n_pix)) in enumerate(zip(masks, sensors)):
+        arr[w] = rtc_wfs(m.shape[1], m.shape[0], int(n_pix), m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)))
+    cfg = rtc_multi_config(abi_version, len(masks), arr, n_act, thr_mode, cm_dtype, gain, leak, cmd_min, cmd_max,
+                           device)
+    out = ctypes.c_void_p()
+    _check(lib.rtc_init_multi(ctypes.byref(cfg), ctypes.byref(out)), None)
+    return RtcContext(out.value, {"wfs": [(m.shape[1], m.shape[0], int(n)) for m, (_, n) in zip(masks, sensors)],
+                                  "n_act": n_act, "device": device, "thr_mode": thr_mode, "cm_dtype": cm_dtype,
+                                  "gain": gain, "leak": leak})
+
+
+def rtc_load_calib_multi(ctx: RtcContext, dark: np.ndarray, flat: np.ndarray, thresholds,
+                         ref_slopes: Optional[np.ndarray] = None) -> None:
+    """dark / flat: the sensors' maps concatenated as a frame set; thresholds: one per sensor."""
+    d, dp = _host_ptr(dark, np.float32)
+    f, fp = _host_ptr(flat, np.float32)
+    if d.size != ctx.frame_elems or f.size != ctx.frame_elems:
+        raise ValueError(f"dark/flat must have {ctx.frame_elems} elements")
+    t, tp = _host_ptr(np.asarray(thresholds, dtype=np.float32).ravel(), np.float32)
+    if t.size != ctx.n_wfs:
+        raise ValueError(f"need {ctx.n_wfs} thresholds")
+    r, rp = _host_ptr(ref_slopes, np.float32)
+    if r is not None and r.size != ctx.n_slopes:
+        raise ValueError(f"ref_slopes must have {ctx.n_slopes} elements")
+    _check(load_library().rtc_load_calib_multi(ctx.handle, dp, fp, tp, rp), ctx)
+
+
 def rtc_load_calib(ctx: RtcContext, dark: np.ndarray, flat: np.ndarray, threshold: float,
                    ref_slopes: Optional[np.ndarray] = None) -> None:
     d, dp = _host_ptr(dark, np.float32)
     f, fp = _host_ptr(flat, np.float32)
-    if d.size != ctx.H * ctx.W or f.size != ctx.H * ctx.W:
-        raise ValueError(f"dark/flat must have {ctx.H}x{ctx.W} elements")
+    if d.size != ctx.frame_elems or f.size != ctx.frame_elems:
+        raise ValueError(f"dark/flat must have {ctx.frame_elems} elements")
     r, rp = _host_ptr(ref_slopes, np.float32)
     if r is not None and r.size != ctx.n_slopes:
         raise ValueError(f"ref_slopes must have {ctx.n_slopes} elements")
@@ -234,7 +287,7 @@ def rtc_encode_cmat(cm_dtype: int, R: np.ndarray):
 def rtc_frame(ctx: RtcContext, pixels, cmd, slopes=None, recon=None, counts=None, stream=None) -> None:
     lib = load_library()
     _check(lib.rtc_frame(ctx.handle,
-                         _dev_ptr(pixels, "uint16", ctx.H * ctx.W, "pixels", ctx),
+                         _dev_ptr(pixels, "uint16", ctx.frame_elems, "pixels", ctx),
                          _dev_ptr(cmd, "float32", ctx.n_act, "cmd", ctx),
                          _dev_ptr(slopes, "float32", ctx.n_slopes, "slopes", ctx, False),
                          _dev_ptr(recon, "float32", ctx.n_act, "recon", ctx, False),
@@ -244,8 +297,8 @@ def rtc_frame(ctx: RtcContext, pixels, cmd, slopes=None, recon=None, counts=None
 
 def rtc_frame_batch(ctx: RtcContext, n_frames: int, pixels, cmd, slopes=None, recon=None, counts=None,
                     ts=None, frame_stride: Optional[int] = None, stream=None) -> None:
-    stride = ctx.H * ctx.W if frame_stride is None else frame_stride
-    need = 0 if n_frames == 0 else (n_frames - 1) * stride + ctx.H * ctx.W
+    stride = ctx.frame_elems if frame_stride is None else frame_stride
+    need = 0 if n_frames == 0 else (n_frames - 1) * stride + ctx.frame_elems
     _check(load_library().rtc_frame_batch(
         ctx.handle, n_frames,
         _dev_ptr(pixels, "uint16", need, "pixels", ctx),
@@ -260,7 +313,7 @@ def rtc_frame_batch(ctx: RtcContext, n_frames: int, pixels, cmd, slopes=None, re
 
 def rtc_calibrate_centroid(ctx: RtcContext, pixels, slopes, counts=None, stream=None) -> None:
     _check(load_library().rtc_calibrate_centroid(
-        ctx.handle, _dev_ptr(pixels, "uint16", ctx.H * ctx.W, "pixels", ctx),
+        ctx.handle, _dev_ptr(pixels, "uint16", ctx.frame_elems, "pixels", ctx),
         _dev_ptr(slopes, "float32", ctx.n_slopes, "slopes", ctx),
         _dev_ptr(counts, "int32", ctx.n_valid, "counts", ctx, False), _stream_ptr(stream)), ctx)
 

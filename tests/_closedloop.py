@@ -27,3 +27,21 @@ def oracle_closed_loop(sc, n_frames: int, k0: int = 0):
         for key in rec:
             rec[key].append(out[key])
     return frames, {key: np.stack(v) for key, v in rec.items()}
+
+
+def oracle_closed_loop_multi(sc, n_frames: int, R=None, k0: int = 0):
+    """Closed loop of a multi-sensor scenario; frame sets [n_frames, elements] and the oracle's record."""
+    cfg = sc.cfg
+    R = sc.control_matrix if R is None else R
+    sets, rec = [], {"counts": [], "slopes": [], "recon": [], "cmd": []}
+    c = np.zeros(sc.n_act)
+    for i in range(n_frames):
+        k = k0 + i
+        frames = sc.frames(k, sc.residual_slopes(k, c if i > 0 else None))
+        out = oracle.rtc_frame_multi(frames, sc.sensors, sc.darks, sc.flats, sc.thresholds, R, c, cfg.gain,
+                                     cfg.leak)
+        c = out["cmd"]
+        sets.append(np.concatenate([f.ravel() for f in frames]))
+        for key in rec:
+            rec[key].append(out[key])
+    return np.stack(sets), {key: np.stack(v) for key, v in rec.items()}

@@ -54,7 +54,6 @@ def _cfg(**kw):
     (dict(n_act=0), rtc.RTC_E_ARG, "n_act"),
     (dict(thr_mode=0), rtc.RTC_E_ARG, "thr_mode"),
     (dict(cm_dtype=7), rtc.RTC_E_ARG, "cm_dtype"),
-    (dict(cm_dtype=2, n_pix=1, mask=np.ones((200, 200), np.uint8)), rtc.RTC_E_UNSUPPORTED, "too long"),
     (dict(gain=math.nan), rtc.RTC_E_NONFINITE, "gain"),
     (dict(leak=math.inf), rtc.RTC_E_NONFINITE, "gain"),
     (dict(cmd_min=1.0, cmd_max=-1.0), rtc.RTC_E_ARG, "cmd_min"),
@@ -96,3 +95,46 @@ def test_valid_config_without_gpu_reports_device_error():
     with pytest.raises(rtc.RtcError) as ei:
         rtc.rtc_init(np.ones((2, 2), np.uint8), 4, 3)
     assert ei.value.status == rtc.RTC_E_DEVICE
+
+
+def _multi(sensors, **kw):
+    base = dict(abi_version=rtc.RTC_ABI_VERSION, n_act=5, thr_mode=1, cm_dtype=0, gain=0.4, leak=1.0,
+                cmd_min=-math.inf, cmd_max=math.inf, device=0)
+    base.update(kw)
+    keep = [np.ascontiguousarray(m, np.uint8) for m, _ in sensors]
+    arr = (rtc.rtc_wfs * max(len(keep), 1))()
+    for w, (m, (_, n)) in enumerate(zip(keep, sensors)):
+        arr[w] = rtc.rtc_wfs(m.shape[1], m.shape[0], n, m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)))
+    cfg = rtc.rtc_multi_config(base["abi_version"], kw.get("n_wfs", len(keep)), arr, base["n_act"],
+                               base["thr_mode"], base["cm_dtype"], base["gain"], base["leak"], base["cmd_min"],
+                               base["cmd_max"], base["device"])
+    return cfg, (keep, arr)
+
+
+@pytest.mark.parametrize("sensors,kw,status,text", [
+    ([(np.ones((4, 4)), 4)], dict(n_wfs=0), rtc.RTC_E_ARG, "n_wfs"),
+    ([(np.ones((4, 4)), 4)], dict(n_wfs=65), rtc.RTC_E_ARG, "n_wfs"),
+    ([(np.ones((4, 4)), 4), (np.zeros((3, 3)), 6)], {}, rtc.RTC_E_ARG, "no active"),
+    ([(np.ones((4, 4)), 4), (np.ones((2, 2)), 33)], {}, rtc.RTC_E_ARG, "n_pix"),
+    ([(np.ones((4096, 4096)), 16), (np.ones((4, 4)), 4)], {}, rtc.RTC_E_ARG, "2^31"),
+    ([(np.ones((4, 4)), 4), (np.ones((2, 2)), 6)], dict(abi_version=7), rtc.RTC_E_ARG, "abi_version"),
+    ([(np.ones((4, 4)), 4), (np.ones((2, 2)), 6)], dict(thr_mode=9), rtc.RTC_E_ARG, "thr_mode"),
+])
+def test_init_multi_rejects_invalid_config_without_a_device(sensors, kw, status, text):
+    lib = rtc.load_library()
+    cfg, _keep = _multi(sensors, **kw)
+    out = ctypes.c_void_p(12345)
+    assert lib.rtc_init_multi(ctypes.byref(cfg), ctypes.byref(out)) == status
+    assert text in lib.rtc_error_string(None).decode()
+    assert out.value == 12345
+    assert lib.rtc_init_multi(None, ctypes.byref(out)) == rtc.RTC_E_ARG
+
+
+def test_valid_multi_config_without_gpu_reports_device_error():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(rtc.RtcError) as ei:
+        rtc.rtc_init_multi([(np.ones((4, 4)), 4), (np.ones((2, 2)), 6)], 9)
+    assert ei.value.status == rtc.RTC_E_DEVICE
+    assert rtc.load_library().rtc_frame_elems(None) == -1

@@ -89,25 +89,50 @@ def test_expired_barrier_wait_is_reported_and_cleared(tiny_loop):
     check_parity(good, {k: v[:20] for k, v in ref.items()}, sc.cfg.gain, sc.cfg.leak, what="after abort")
 
 
-def test_unsupported_persistent_shape_runs_per_launch():
-    # 19,000+ float32 slopes exceed the persistent kernel's register slices
+@pytest.mark.parametrize("fmt", ["f32", "bf16"])
+def test_long_slope_vectors_run_in_panels_identically_in_both_modes(fmt):
+    # 19,000+ slopes exceed 8 wavefronts' register slices: two slope panels
     rng = np.random.default_rng(8)
     mask = geometry.subaperture_mask(110, 0.0)
     nv = int(mask.sum())
     H = 110
-    frames = rng.integers(95, 200, size=(2, H, H)).astype(np.uint16)
+    frames = rng.integers(95, 200, size=(3, H, H)).astype(np.uint16)
     dark = np.full((H, H), 100.0, np.float32)
     flat = np.ones((H, H), np.float32)
-    R = (rng.standard_normal((40, 2 * nv)) / 100).astype(np.float32)
+    R = (rng.standard_normal((300, 2 * nv)) / 100).astype(np.float32)
     out = []
     for mode in (rtc.RTC_FRAMES_PER_LAUNCH, rtc.RTC_FRAMES_PERSISTENT):
-        with rtc.rtc_init(mask, 1, 40) as ctx:
+        with rtc.rtc_init(mask, 1, 300, cm_dtype=fmt) as ctx:
             rtc.rtc_load_calib(ctx, dark, flat, 3.0)
             rtc.rtc_load_cmat(ctx, R)
             rtc.rtc_set_frame_mode(ctx, mode)
             out.append(_gpu_batch(ctx, frames))
             rtc.rtc_sync_check(ctx)
     assert 2 * nv > 16384
+    for key in out[0]:
+        assert np.array_equal(out[0][key], out[1][key]), key
+    # against the float64 product with the matrix as stored
+    from oracle import quant
+    Rq = R.astype(np.float64) if fmt == "f32" else quant.dequantize(*quant.encode(R, fmt), fmt)
+    a_ref = out[0]["slopes"].astype(np.float64) @ Rq.T
+    assert np.abs(out[0]["recon"] - a_ref).max() <= 1e-5 * np.abs(a_ref).max()
+
+
+def test_unsupported_persistent_shape_runs_per_launch():
+    # more than 512 actuator rows per compute unit: one launch pair per frame
+    rng = np.random.default_rng(9)
+    mask = np.ones((2, 2), np.uint8)
+    n_act = 131_073 * 2
+    frames = rng.integers(95, 200, size=(2, 8, 8)).astype(np.uint16)
+    R = (rng.standard_normal((n_act, 8)) / 10).astype(np.float32)
+    out = []
+    for mode in (rtc.RTC_FRAMES_PER_LAUNCH, rtc.RTC_FRAMES_PERSISTENT):
+        with rtc.rtc_init(mask, 4, n_act) as ctx:
+            rtc.rtc_load_calib(ctx, np.full((8, 8), 100.0, np.float32), np.ones((8, 8), np.float32), 3.0)
+            rtc.rtc_load_cmat(ctx, R)
+            rtc.rtc_set_frame_mode(ctx, mode)
+            out.append(_gpu_batch(ctx, frames))
+            rtc.rtc_sync_check(ctx)
     for key in out[0]:
         assert np.array_equal(out[0][key], out[1][key])
 

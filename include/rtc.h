@@ -281,6 +281,8 @@ rtc_status rtc_get_mvm_tuning(const rtc_ctx *c, rtc_mvm_tuning *t);
 typedef enum { RTC_FRAMES_PER_LAUNCH = 0, RTC_FRAMES_PERSISTENT = 1 } rtc_frame_mode;
 
 rtc_status rtc_set_frame_mode(rtc_ctx *c, int32_t mode, int32_t spin_limit);
+/* Current frame mode into *mode. */
+rtc_status rtc_get_frame_mode(const rtc_ctx *c, int32_t *mode);
 
 /* Stage tracing of persistent batches: when set, each persistent batch writes
  * for its frames f < max_frames and its workgroups g < n_groups the device
@@ -293,6 +295,42 @@ rtc_status rtc_set_frame_mode(rtc_ctx *c, int32_t mode, int32_t spin_limit);
  * uint64 that must stay valid while batches run; max_frames = 0 turns
  * tracing off; n_groups must be in [1, 4096] when max_frames > 0. */
 rtc_status rtc_set_trace(rtc_ctx *c, uint64_t *d_trace, int32_t max_frames, int32_t n_groups);
+
+/* Graph replay: records rtc_frame_batch with these arguments, in the
+ * context's current frame mode and tuning, into a HIP graph held by the
+ * context (replacing a previous one; the recording itself runs nothing), and
+ * rtc_graph_launch replays it on hip_stream.  Every replay processes the same
+ * frames into the same buffers, continuing from the integrator state that
+ * the previous replay or frame call left, exactly as the recorded call
+ * would.  The buffers must stay valid while the graph exists (until the next
+ * capture or rtc_destroy).  Counters are cleared by kernels, so the graph
+ * holds no memset nodes.  Errors: as rtc_frame_batch; RTC_E_UNSUPPORTED when
+ * the runtime cannot record the frame mode's launches (nothing is recorded);
+ * rtc_graph_launch without a graph: RTC_E_STATE. */
+rtc_status rtc_graph_capture(rtc_ctx *c, int32_t n_frames, const uint16_t *d_pixels, int64_t frame_stride,
+                             float *d_cmd, float *d_slopes, float *d_recon, int32_t *d_counts, uint64_t *d_ts);
+rtc_status rtc_graph_launch(rtc_ctx *c, void *hip_stream);
+
+/* Autotuner: one timed candidate of rtc_autotune. */
+typedef struct {
+  int32_t frame_mode;          /* rtc_frame_mode */
+  rtc_mvm_tuning tuning;
+  float us_per_frame;          /* mean over the timed frames (HIP events); < 0: the candidate failed */
+} rtc_tune_result;
+
+/* Times n_frames frames (after n_frames/4 + 1 untimed ones) of d_pixels
+ * (frame_stride apart; outputs to d_cmd, n_frames * n_act floats) on
+ * hip_stream for every candidate: persistent with 1x and 3/4x the compute
+ * units; per launch with the row-block kernel (8 and 16 wavefronts, 1, 2 and
+ * 4 rows per batch, 1x and 2x the compute units) and, for float32 matrices,
+ * the streamed kernel with 1, 2 and 4 slope partitions.  Sets the fastest
+ * frame mode and tuning on the context and restores the integrator state it
+ * found.  Up to max_results results go to results (may be NULL); *n_results
+ * (may be NULL) gets the number of candidates.  Synchronous.  Errors: as
+ * rtc_frame_batch, RTC_E_ARG for n_frames < 1. */
+rtc_status rtc_autotune(rtc_ctx *c, int32_t n_frames, const uint16_t *d_pixels, int64_t frame_stride,
+                        float *d_cmd, rtc_tune_result *results, int32_t max_results, int32_t *n_results,
+                        void *hip_stream);
 
 /* Synchronises the device and reports RTC_E_DEVICE if a persistent batch gave
  * up at a barrier since the last check (the flag is then cleared). */

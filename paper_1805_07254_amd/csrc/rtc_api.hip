@@ -66,6 +66,7 @@ struct rtc_ctx {
   uint64_t *d_trace = nullptr;  // caller-owned [trace_frames][trace_groups][8] stage stamps
   int32_t trace_frames = 0;
   int32_t trace_groups = 0;
+  hipGraphExec_t graph = nullptr;  // recorded frame batch (rtc_graph_capture)
   bool calib_loaded = false;
   bool cmat_loaded = false;
 };
@@ -649,6 +650,133 @@ rtc_status rtc_frame_batch(rtc_ctx *c, int32_t n_frames, const uint16_t *d_pixel
   return RTC_OK;
 }
 
+rtc_status rtc_graph_capture(rtc_ctx *c, int32_t n_frames, const uint16_t *d_pixels, int64_t frame_stride,
+                             float *d_cmd, float *d_slopes, float *d_recon, int32_t *d_counts, uint64_t *d_ts) {
+  if (!c) return fail(nullptr, RTC_E_ARG, "rtc_graph_capture: NULL context");
+  if (n_frames < 1) return fail(c, RTC_E_ARG, "rtc_graph_capture: n_frames must be >= 1");
+  DeviceScope ds(c->device);
+  if (ds.status != hipSuccess) return hip_fail(c, ds.status, "rtc_graph_capture: hipSetDevice");
+  hipStream_t s = nullptr;
+  hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+  if (e != hipSuccess) return hip_fail(c, e, "rtc_graph_capture: stream");
+  if ((e = hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed)) != hipSuccess) {
+    (void)hipStreamDestroy(s);
+    return hip_fail(c, e, "rtc_graph_capture: begin capture");
+  }
+  const rtc_status st = rtc_frame_batch(c, n_frames, d_pixels, frame_stride, d_cmd, d_slopes, d_recon, d_counts,
+                                        d_ts, s);
+  hipGraph_t g = nullptr;
+  const hipError_t e_end = hipStreamEndCapture(s, &g);
+  hipGraphExec_t ex = nullptr;
+  hipError_t e_inst = hipSuccess;
+  if (st == RTC_OK && e_end == hipSuccess && g) e_inst = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  if (g) (void)hipGraphDestroy(g);
+  (void)hipStreamDestroy(s);
+  (void)hipGetLastError();
+  if (st == RTC_E_ARG || st == RTC_E_STATE) return st;      // the call itself was invalid (message set)
+  if (st != RTC_OK || e_end != hipSuccess || e_inst != hipSuccess || !ex) {
+    if (ex) (void)hipGraphExecDestroy(ex);
+    const hipError_t why = e_end != hipSuccess ? e_end : e_inst;
+    return fail(c, RTC_E_UNSUPPORTED, std::string("rtc_graph_capture: the runtime did not record this frame mode (") +
+                                           (st != RTC_OK ? c->err : std::string(hipGetErrorName(why))) + ")");
+  }
+  if (c->graph) (void)hipGraphExecDestroy(c->graph);
+  c->graph = ex;
+  return RTC_OK;
+}
+
+rtc_status rtc_graph_launch(rtc_ctx *c, void *hip_stream) {
+  if (!c) return fail(nullptr, RTC_E_ARG, "rtc_graph_launch: NULL context");
+  if (!c->graph) return fail(c, RTC_E_STATE, "rtc_graph_launch: no recorded graph");
+  DeviceScope ds(c->device);
+  if (ds.status != hipSuccess) return hip_fail(c, ds.status, "rtc_graph_launch: hipSetDevice");
+  const hipError_t e = hipGraphLaunch(c->graph, static_cast<hipStream_t>(hip_stream));
+  return e == hipSuccess ? RTC_OK : hip_fail(c, e, "rtc_graph_launch");
+}
+
+rtc_status rtc_autotune(rtc_ctx *c, int32_t n_frames, const uint16_t *d_pixels, int64_t frame_stride,
+                        float *d_cmd, rtc_tune_result *results, int32_t max_results, int32_t *n_results,
+                        void *hip_stream) {
+  if (!c) return fail(nullptr, RTC_E_ARG, "rtc_autotune: NULL context");
+  if (n_frames < 1) return fail(c, RTC_E_ARG, "rtc_autotune: n_frames must be >= 1");
+  if (!c->calib_loaded || !c->cmat_loaded)
+    return fail(c, RTC_E_STATE, "rtc_autotune: load the calibration and the control matrix first");
+  if (!d_pixels || !d_cmd) return fail(c, RTC_E_ARG, "rtc_autotune: NULL pixels or cmd");
+  if (frame_stride < c->frame_elems) return fail(c, RTC_E_ARG, "rtc_autotune: frame_stride shorter than a frame");
+  DeviceScope ds(c->device);
+  if (ds.status != hipSuccess) return hip_fail(c, ds.status, "rtc_autotune: hipSetDevice");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  std::vector<rtc_tune_result> cand;
+  const int ncu = c->n_cu;
+  auto add = [&](int mode, int kernel, int ks, int rpw, int unroll, int blocks, int waves) {
+    rtc_tune_result r{};
+    r.frame_mode = mode;
+    r.tuning = rtc_mvm_tuning{kernel, ks, rpw, unroll, blocks, waves};
+    r.us_per_frame = -1.0f;
+    cand.push_back(r);
+  };
+  add(RTC_FRAMES_PERSISTENT, RTC_MVM_ROWBLOCK, 1, 2, 4, ncu, 8);
+  add(RTC_FRAMES_PERSISTENT, RTC_MVM_ROWBLOCK, 1, 2, 4, ncu * 3 / 4, 8);
+  for (int waves : {8, 16})
+    for (int rb : {1, 2, 4})
+      for (int mul : {1, 2}) add(RTC_FRAMES_PER_LAUNCH, RTC_MVM_ROWBLOCK, 1, rb, 4, ncu * mul, waves);
+  if (c->fmt == RTC_CM_F32)
+    for (int ks : {1, 2, 4}) add(RTC_FRAMES_PER_LAUNCH, RTC_MVM_STREAMED, ks, 2, 4, 0, 8);
+
+  std::vector<float> saved((size_t)c->n_act);
+  rtc_status s = rtc_get_state(c, saved.data());
+  if (s != RTC_OK) return s;
+  const int32_t mode0 = c->frame_mode;
+  const rtc_mvm_tuning tune0 = c->tuning;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return hip_fail(c, e, "rtc_autotune: events");
+  }
+  const int32_t warm = n_frames / 4 + 1;
+  int best = -1;
+  for (size_t i = 0; i < cand.size(); ++i) {
+    rtc_tune_result &r = cand[i];
+    c->frame_mode = r.frame_mode;
+    c->tuning = r.tuning;
+    bool ok = rtc_frame_batch(c, std::min(warm, n_frames), d_pixels, frame_stride, d_cmd, nullptr, nullptr,
+                              nullptr, nullptr, st) == RTC_OK;
+    ok = ok && hipEventRecord(e0, st) == hipSuccess;
+    ok = ok && rtc_frame_batch(c, n_frames, d_pixels, frame_stride, d_cmd, nullptr, nullptr, nullptr, nullptr,
+                               st) == RTC_OK;
+    ok = ok && hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
+    float ms = 0.0f;
+    ok = ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+    uint32_t aborted = 0;
+    ok = ok && hipMemcpy(&aborted, c->d_sync + rtck::sync_layout::kSticky, sizeof(aborted),
+                         hipMemcpyDeviceToHost) == hipSuccess;
+    if (aborted) (void)hipMemset(c->d_sync + rtck::sync_layout::kSticky, 0, sizeof(uint32_t));
+    ok = ok && aborted == 0;
+    if (ok) {
+      r.us_per_frame = ms * 1000.0f / (float)n_frames;
+      if (best < 0 || r.us_per_frame < cand[(size_t)best].us_per_frame) best = (int)i;
+    }
+    (void)hipGetLastError();
+    (void)hipDeviceSynchronize();
+    if ((s = rtc_set_state(c, saved.data())) != RTC_OK) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (s != RTC_OK || best < 0) {
+    c->frame_mode = mode0;
+    c->tuning = tune0;
+    return s != RTC_OK ? s : fail(c, RTC_E_DEVICE, "rtc_autotune: no candidate ran");
+  }
+  c->frame_mode = cand[(size_t)best].frame_mode;
+  c->tuning = cand[(size_t)best].tuning;
+  if (results)
+    for (int32_t i = 0; i < max_results && (size_t)i < cand.size(); ++i) results[i] = cand[(size_t)i];
+  if (n_results) *n_results = (int32_t)cand.size();
+  return RTC_OK;
+}
+
 rtc_status rtc_calibrate_centroid(rtc_ctx *c, const uint16_t *d_pixels, float *d_slopes, int32_t *d_counts,
                                   void *hip_stream) {
   if (!c) return fail(nullptr, RTC_E_ARG, "rtc_calibrate_centroid: NULL context");
@@ -741,6 +869,12 @@ rtc_status rtc_set_frame_mode(rtc_ctx *c, int32_t mode, int32_t spin_limit) {
   if (spin_limit < 0) return fail(c, RTC_E_ARG, "rtc_set_frame_mode: spin_limit must be >= 0");
   c->frame_mode = mode;
   c->spin_limit = spin_limit > 0 ? spin_limit : (1 << 22);
+  return RTC_OK;
+}
+
+rtc_status rtc_get_frame_mode(const rtc_ctx *c, int32_t *mode) {
+  if (!c || !mode) return fail(nullptr, RTC_E_ARG, "rtc_get_frame_mode: NULL argument");
+  *mode = c->frame_mode;
   return RTC_OK;
 }
 
@@ -846,6 +980,7 @@ void rtc_destroy(rtc_ctx *c) {
   dfree(c->d_part);
   dfree(c->d_sbuf);
   dfree(c->d_sync);
+  if (c->graph) (void)hipGraphExecDestroy(c->graph);
   delete c;
 }
 

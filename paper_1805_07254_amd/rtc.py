@@ -62,6 +62,10 @@ class rtc_mvm_tuning(ctypes.Structure):
                 ("unroll", ctypes.c_int32), ("blocks", ctypes.c_int32), ("waves", ctypes.c_int32)]
 
 
+class rtc_tune_result(ctypes.Structure):
+    _fields_ = [("frame_mode", ctypes.c_int32), ("tuning", rtc_mvm_tuning), ("us_per_frame", ctypes.c_float)]
+
+
 _vp, _i32, _i64, _f32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_float
 _SIGNATURES = {
     "rtc_init": (_i32, [ctypes.POINTER(rtc_config), ctypes.POINTER(_vp)]),
@@ -69,6 +73,10 @@ _SIGNATURES = {
     "rtc_frame_elems": (_i64, [_vp]),
     "rtc_load_calib": (_i32, [_vp, _vp, _vp, _f32, _vp]),
     "rtc_load_calib_multi": (_i32, [_vp, _vp, _vp, _vp, _vp]),
+    "rtc_graph_capture": (_i32, [_vp, _i32, _vp, _i64, _vp, _vp, _vp, _vp, _vp]),
+    "rtc_graph_launch": (_i32, [_vp, _vp]),
+    "rtc_get_frame_mode": (_i32, [_vp, ctypes.POINTER(_i32)]),
+    "rtc_autotune": (_i32, [_vp, _i32, _vp, _i64, _vp, _vp, _i32, ctypes.POINTER(_i32), _vp]),
     "rtc_load_cmat": (_i32, [_vp, _vp, _i32, _i32, _i64]),
     "rtc_encode_cmat": (_i32, [_i32, _vp, _i32, _i32, _i64, _vp, _vp]),
     "rtc_frame": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
@@ -413,3 +421,44 @@ def rtc_abi_version() -> int:
 
 def rtc_destroy(ctx: RtcContext) -> None:
     ctx.close()
+
+
+def rtc_graph_capture(ctx: RtcContext, n_frames: int, pixels, cmd, slopes=None, recon=None, counts=None, ts=None,
+                      frame_stride: Optional[int] = None) -> None:
+    """Records rtc_frame_batch with these buffers into the context's graph."""
+    stride = ctx.frame_elems if frame_stride is None else frame_stride
+    need = 0 if n_frames == 0 else (n_frames - 1) * stride + ctx.frame_elems
+    _check(load_library().rtc_graph_capture(
+        ctx.handle, n_frames, _dev_ptr(pixels, "uint16", need, "pixels", ctx), stride,
+        _dev_ptr(cmd, "float32", n_frames * ctx.n_act, "cmd", ctx),
+        _dev_ptr(slopes, "float32", n_frames * ctx.n_slopes, "slopes", ctx, False),
+        _dev_ptr(recon, "float32", n_frames * ctx.n_act, "recon", ctx, False),
+        _dev_ptr(counts, "int32", n_frames * ctx.n_valid, "counts", ctx, False),
+        _dev_ptr(ts, ("uint64", "int64"), 2 * n_frames, "ts", ctx, False)), ctx)
+
+
+def rtc_graph_launch(ctx: RtcContext, stream=None) -> None:
+    _check(load_library().rtc_graph_launch(ctx.handle, _stream_ptr(stream)), ctx)
+
+
+def rtc_autotune(ctx: RtcContext, n_frames: int, pixels, cmd, frame_stride: Optional[int] = None,
+                 stream=None) -> list:
+    """Times the candidate frame modes / launch shapes, keeps the fastest; returns every candidate's result."""
+    stride = ctx.frame_elems if frame_stride is None else frame_stride
+    need = (n_frames - 1) * stride + ctx.frame_elems
+    res = (rtc_tune_result * 64)()
+    n = ctypes.c_int32(0)
+    _check(load_library().rtc_autotune(ctx.handle, n_frames, _dev_ptr(pixels, "uint16", need, "pixels", ctx), stride,
+                                       _dev_ptr(cmd, "float32", n_frames * ctx.n_act, "cmd", ctx), res, 64,
+                                       ctypes.byref(n), _stream_ptr(stream)), ctx)
+    out = []
+    for r in res[:min(n.value, 64)]:
+        out.append({"frame_mode": r.frame_mode, "us_per_frame": r.us_per_frame,
+                    "tuning": {name: getattr(r.tuning, name) for name, _ in rtc_mvm_tuning._fields_}})
+    return out
+
+
+def rtc_get_frame_mode(ctx: RtcContext) -> int:
+    m = ctypes.c_int32(-1)
+    _check(load_library().rtc_get_frame_mode(ctx.handle, ctypes.byref(m)), ctx)
+    return m.value

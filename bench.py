@@ -75,6 +75,12 @@ def parse():
     p.add_argument("--variants", default="f16,bf16,fp8e4m3",
                    help="reduced-precision matrix formats also timed (comma list, empty = none)")
     p.add_argument("--variant-steps", type=int, default=2000)
+    p.add_argument("--workload", default="elt-scao", choices=["elt-scao", "elt-multi"],
+                   help="elt-scao: the single-sensor ELT frame (default); elt-multi: six 74x74 and three 16x16 "
+                        "sensors reconstructed by one BF16 matrix")
+    p.add_argument("--multi-steps", type=int, default=5000)
+    p.add_argument("--multi-ring", type=int, default=4, help="distinct multi-sensor frame sets")
+    p.add_argument("--multi-dtype", default="bf16")
     return p.parse_args()
 
 
@@ -106,11 +112,124 @@ def cpu_baseline(sc, ring_host, seconds: float) -> dict:
                       f"{t.mean():.0f} us, p99 {np.percentile(t, 99):.0f} us"}
 
 
+def run_multi(args):
+    """Several sensors in one persistent launch: autotuned, timed, and replayed from a graph."""
+    import torch
+    from aosim.multi import ELT_MULTI, MultiScenario
+    from paper_1805_07254_amd import rtc
+    from paper_1805_07254_amd.stats import frame_stats, ticks_to_us
+
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    rtc.load_library()
+    t0 = time.time()
+    sc = MultiScenario(ELT_MULTI)
+    cfg = sc.cfg
+    log(f"workload {cfg.name}: {len(cfg.sensors)} sensors, {sum(sc.n_valid)} subapertures, {sc.n_slopes} slopes, "
+        f"{sc.n_act} actuators")
+    R = sc.control_matrix
+    log(f"control matrix {R.shape} built at {time.time() - t0:.0f}s")
+    ring = np.stack([sc.frame_set(k, sc.all_turbulence_slopes(k)) for k in range(args.multi_ring)])
+    log(f"{args.multi_ring} frame sets of {ring.shape[1]} pixels generated at {time.time() - t0:.0f}s")
+    ctx = rtc.rtc_init_multi(sc.sensors, sc.n_act, cm_dtype=args.multi_dtype, gain=cfg.gain, leak=cfg.leak)
+    rtc.rtc_load_calib_multi(ctx, sc.dark_set, sc.flat_set, sc.thresholds)
+    rtc.rtc_load_cmat(ctx, R)
+    khz = rtc.rtc_wall_clock_khz(ctx)
+    stream = torch.cuda.current_stream()
+    ring16 = torch.from_numpy(ring.view(np.int16)).to("cuda:0")
+    n_buf = max(args.warmup + args.multi_steps, 1000)
+    frames = ring16[torch.arange(n_buf, device="cuda:0") % args.multi_ring].contiguous().view(torch.uint16)
+    launch = min(args.launch_frames, args.multi_steps)
+    cmd = torch.empty(max(launch, 1000) * sc.n_act, dtype=torch.float32, device="cuda:0")
+
+    tune = rtc.rtc_autotune(ctx, 64, frames, cmd, stream=stream)
+    mode = rtc.rtc_get_frame_mode(ctx)
+    best = min((r for r in tune if r["us_per_frame"] > 0), key=lambda r: r["us_per_frame"])
+    log(f"autotuned: frame mode {mode}, {best['tuning']}, {best['us_per_frame']:.2f} us/frame over 64 frames")
+
+    def run(first, n, ts=None):
+        done, launches = 0, 0
+        while done < n:
+            m = min(launch, n - done)
+            rtc.rtc_frame_batch(ctx, m, frames[first + done:], cmd, ts=None if ts is None else ts[2 * done:],
+                                stream=stream)
+            done += m
+            launches += 1
+        return launches
+
+    run(0, args.warmup)
+    torch.cuda.synchronize()
+    ts = torch.zeros(2 * args.multi_steps, dtype=torch.int64, device="cuda:0")
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t1 = time.perf_counter()
+    ev0.record(stream)
+    launches = run(args.warmup, args.multi_steps, ts)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t1
+    rtc.rtc_sync_check(ctx)
+    st = ts.cpu().numpy().reshape(-1, 2)
+    period = np.diff(ticks_to_us(st[:, 0] - st[0, 0], khz))
+    span = ticks_to_us(st[:, 1] - st[:, 0], khz)
+    st_period, st_span = frame_stats(period), frame_stats(span)
+    launch_ms = ev0.elapsed_time(ev1) / launches
+    log(f"frame period p50 {st_period['p50_us']:.2f} us p99 {st_period['p99_us']:.2f} us, "
+        f"{launch_ms:.3f} ms per launch of {launch}")
+
+    # graph replay: one recorded batch of 1000 frames replayed
+    gts = torch.zeros(2 * 1000, dtype=torch.int64, device="cuda:0")
+    graph = {"recorded": False}
+    try:
+        rtc.rtc_graph_capture(ctx, 1000, frames, cmd, ts=gts)
+        graph["recorded"] = True
+    except rtc.RtcError as err:
+        graph["error"] = str(err)
+    if graph["recorded"]:
+        periods = []
+        reps = max(1, args.multi_steps // 1000)
+        for _ in range(reps):
+            rtc.rtc_graph_launch(ctx, stream)
+            torch.cuda.synchronize()
+            g = gts.cpu().numpy().reshape(-1, 2)
+            periods.append(np.diff(ticks_to_us(g[:, 0] - g[0, 0], khz)))
+        rtc.rtc_sync_check(ctx)
+        graph["replays"] = reps
+        graph["frame_period_us"] = frame_stats(np.concatenate(periods))
+        log(f"graph replay: frame period p50 {graph['frame_period_us']['p50_us']:.2f} us")
+    rtc.rtc_destroy(ctx)
+
+    esz = {"f32": 4, "f16": 2, "bf16": 2, "fp8e4m3": 1}[args.multi_dtype]
+    npx = sum(n * s.n_pix * s.n_pix for n, s in zip(sc.n_valid, cfg.sensors))
+    fb = sc.n_act * sc.n_slopes * esz + (0 if esz == 4 else 4 * sc.n_act) + npx * 10 + 8 * sc.n_slopes + 8 * sc.n_act
+    achieved = fb * launch / (launch_ms * 1e6) if args.multi_steps % launch == 0 else fb / (wall * 1e6 / args.multi_steps) / 1e3
+    result = {
+        "metric": METRIC, "value": round(st_period["p50_us"], 3), "unit": "us", "n_gpus": 1,
+        "steps": args.multi_steps, "warmup": args.warmup, "ms_per_step": round(wall * 1e3 / args.multi_steps, 6),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": args.multi_dtype,
+        "data": "synthetic",
+        "config": {"workload": f"{cfg.name}: 6 x 74x74 SH (10x10 px) + 3 x 16x16 SH (6x6 px), obscuration 0.28, "
+                               f"{sc.n_slopes} slopes, {sc.n_act} actuators on two DMs, "
+                               f"{args.multi_dtype} control matrix {sc.n_act * sc.n_slopes * esz / 1e6:.1f} MB",
+                   "frames_per_launch": launch, "distinct_frame_sets": args.multi_ring,
+                   "frame_mode": "persistent" if mode == 1 else "per-launch", "tuning": best["tuning"]},
+        "frame_period_us": st_period, "frame_span_us": st_span,
+        "graph_replay": graph, "autotune": tune,
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None, "bytes_per_frame": fb,
+                     "kernel": "frames_kernel (persistent, slope panels)" if mode == 1 else
+                     "calib_cog_kernel + mvm_panel_kernel (per launch, slope panels)"},
+    }
+    print(json.dumps(result), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    if args.workload == "elt-multi":
+        run_multi(args)
+        return
     import torch
     from aosim import ELT, Scenario
     from paper_1805_07254_amd import rtc

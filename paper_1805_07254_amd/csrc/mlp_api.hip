@@ -1,0 +1,479 @@
+// C-ABI host side of the learned predictor (declared in include/rtc_mlp.h).
+//
+// Device buffers of a network (float32 unless noted), for max_batch rows:
+//   params  W1 [n_hid][n_in], b1 [n_hid], W2 [n_out][n_hid], b2 [n_out]; bfloat16 copies of W1, W2
+//   adam    first and second moments of every parameter
+//   grads   as the parameters
+//   work    Z1 [B][n_hid], H (bfloat16) [B][n_hid], Y [B][n_out], dY [B][n_out] (+ bfloat16),
+//           dH [B][n_hid], dZ1 [B][n_hid] (+ bfloat16), per-row squared errors [B]
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/rtc_mlp.h"
+#include "mlp_kernels.h"
+
+namespace {
+
+struct Tensor {
+  float *p = nullptr, *m = nullptr, *v = nullptr, *g = nullptr;
+  uint16_t *b = nullptr;   // bfloat16 copy (weights only)
+  int64_t n = 0;
+};
+
+thread_local std::string g_mlp_err = "no error";
+
+struct DevScope {
+  int prev = -1;
+  hipError_t status = hipSuccess;
+  explicit DevScope(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    status = hipSetDevice(dev);
+  }
+  ~DevScope() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+template <typename T>
+void dfree(T *&p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
+bool all_finite(const float *x, int64_t n) {
+  for (int64_t i = 0; i < n; ++i)
+    if (!std::isfinite(x[i])) return false;
+  return true;
+}
+
+}  // namespace
+
+struct rtc_mlp {
+  int32_t n_in = 0, n_hid = 0, n_out = 0, max_batch = 0, device = 0;
+  Tensor W1, b1, W2, b2;
+  float *Z1 = nullptr, *Y = nullptr, *dY = nullptr, *dH = nullptr, *dZ1 = nullptr, *row_sq = nullptr;
+  uint16_t *Hb = nullptr, *dYb = nullptr, *dZ1b = nullptr;
+  std::string err = "no error";
+};
+
+struct rtc_pred {
+  rtc_mlp *net = nullptr;
+  int32_t history = 0, n_modes = 0, n_slopes = 0, n_act = 0, pushes = 0;
+  float inv_gain = 1.0f;
+  float *P = nullptr, *PT = nullptr, *PD = nullptr, *mean = nullptr, *std_ = nullptr, *inv_std = nullptr;
+  float *hist = nullptr, *m = nullptr, *y = nullptr, *d = nullptr, *mhat = nullptr;
+  std::string err = "no error";
+};
+
+namespace {
+
+rtc_status mfail(rtc_mlp *m, rtc_status s, const std::string &msg) {
+  if (m) m->err = msg; else g_mlp_err = msg;
+  return s;
+}
+
+rtc_status hfail(rtc_mlp *m, hipError_t e, const char *what) {
+  return mfail(m, e == hipErrorOutOfMemory ? RTC_E_NOMEM : RTC_E_DEVICE,
+               std::string(what) + ": " + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ")");
+}
+
+hipError_t alloc_tensor(Tensor &t, int64_t n, bool with_bf16) {
+  t.n = n;
+  hipError_t e;
+  const size_t bytes = (size_t)n * sizeof(float);
+  if ((e = hipMalloc(&t.p, bytes)) != hipSuccess || (e = hipMalloc(&t.m, bytes)) != hipSuccess ||
+      (e = hipMalloc(&t.v, bytes)) != hipSuccess || (e = hipMalloc(&t.g, bytes)) != hipSuccess)
+    return e;
+  if (with_bf16 && (e = hipMalloc(&t.b, (size_t)n * sizeof(uint16_t))) != hipSuccess) return e;
+  if ((e = hipMemset(t.p, 0, bytes)) != hipSuccess || (e = hipMemset(t.m, 0, bytes)) != hipSuccess ||
+      (e = hipMemset(t.v, 0, bytes)) != hipSuccess || (e = hipMemset(t.g, 0, bytes)) != hipSuccess)
+    return e;
+  if (with_bf16 && (e = hipMemset(t.b, 0, (size_t)n * sizeof(uint16_t))) != hipSuccess) return e;
+  return hipSuccess;
+}
+
+void free_tensor(Tensor &t) {
+  dfree(t.p);
+  dfree(t.m);
+  dfree(t.v);
+  dfree(t.g);
+  dfree(t.b);
+}
+
+// Forward into m->Z1 / Hb / y (y has batch rows of n_out).
+hipError_t forward(rtc_mlp *m, int32_t B, const float *x, float *y, hipStream_t st) {
+  rtcm::GemmArgs g{};
+  g.M = B;
+  g.N = m->n_hid;
+  g.K = m->n_in;
+  g.a_f32 = x;
+  g.sam = m->n_in;
+  g.sak = 1;
+  g.b_bf16 = m->W1.b;
+  g.sbk = 1;
+  g.sbn = m->n_in;
+  g.alpha = 1.0f;
+  g.bias = m->b1.p;
+  g.gelu = 1;
+  g.ldc = m->n_hid;
+  g.c_pre = m->Z1;
+  g.c_bf16 = m->Hb;
+  hipError_t e = rtcm::launch_gemm(g, st);
+  if (e != hipSuccess) return e;
+  rtcm::GemmArgs h{};
+  h.M = B;
+  h.N = m->n_out;
+  h.K = m->n_hid;
+  h.a_bf16 = m->Hb;
+  h.sam = m->n_hid;
+  h.sak = 1;
+  h.b_bf16 = m->W2.b;
+  h.sbk = 1;
+  h.sbn = m->n_hid;
+  h.alpha = 1.0f;
+  h.bias = m->b2.p;
+  h.ldc = m->n_out;
+  h.c_f32 = y;
+  return rtcm::launch_gemm(h, st);
+}
+
+}  // namespace
+
+extern "C" {
+
+rtc_status rtc_mlp_create(int32_t n_in, int32_t n_hidden, int32_t n_out, int32_t max_batch, int32_t device,
+                          rtc_mlp **out) {
+  if (!out) return mfail(nullptr, RTC_E_ARG, "rtc_mlp_create: NULL output");
+  auto ok = [](int32_t v) { return v >= 1 && v <= (1 << 16); };
+  if (!ok(n_in) || !ok(n_hidden) || !ok(n_out) || !ok(max_batch) || device < 0)
+    return mfail(nullptr, RTC_E_ARG, "rtc_mlp_create: sizes must be in 1..65536 and device >= 0");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0)
+    return mfail(nullptr, RTC_E_DEVICE, "rtc_mlp_create: no HIP device available");
+  if (device >= ndev) return mfail(nullptr, RTC_E_DEVICE, "rtc_mlp_create: device ordinal out of range");
+  rtc_mlp *m = new (std::nothrow) rtc_mlp();
+  if (!m) return mfail(nullptr, RTC_E_NOMEM, "rtc_mlp_create: host allocation failed");
+  m->n_in = n_in;
+  m->n_hid = n_hidden;
+  m->n_out = n_out;
+  m->max_batch = max_batch;
+  m->device = device;
+  DevScope ds(device);
+  hipError_t e = ds.status;
+  const int64_t B = max_batch;
+  if (e == hipSuccess) e = alloc_tensor(m->W1, (int64_t)n_hidden * n_in, true);
+  if (e == hipSuccess) e = alloc_tensor(m->b1, n_hidden, false);
+  if (e == hipSuccess) e = alloc_tensor(m->W2, (int64_t)n_out * n_hidden, true);
+  if (e == hipSuccess) e = alloc_tensor(m->b2, n_out, false);
+  if (e == hipSuccess) e = hipMalloc(&m->Z1, (size_t)B * n_hidden * sizeof(float));
+  if (e == hipSuccess) e = hipMalloc(&m->Hb, (size_t)B * n_hidden * sizeof(uint16_t));
+  if (e == hipSuccess) e = hipMalloc(&m->Y, (size_t)B * n_out * sizeof(float));
+  if (e == hipSuccess) e = hipMalloc(&m->dY, (size_t)B * n_out * sizeof(float));
+  if (e == hipSuccess) e = hipMalloc(&m->dYb, (size_t)B * n_out * sizeof(uint16_t));
+  if (e == hipSuccess) e = hipMalloc(&m->dH, (size_t)B * n_hidden * sizeof(float));
+  if (e == hipSuccess) e = hipMalloc(&m->dZ1, (size_t)B * n_hidden * sizeof(float));
+  if (e == hipSuccess) e = hipMalloc(&m->dZ1b, (size_t)B * n_hidden * sizeof(uint16_t));
+  if (e == hipSuccess) e = hipMalloc(&m->row_sq, (size_t)B * sizeof(float));
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    const rtc_status s = hfail(nullptr, e, "rtc_mlp_create");
+    rtc_mlp_destroy(m);
+    return s;
+  }
+  *out = m;
+  return RTC_OK;
+}
+
+rtc_status rtc_mlp_set_params(rtc_mlp *m, const float *W1, const float *b1, const float *W2, const float *b2) {
+  if (!m) return mfail(nullptr, RTC_E_ARG, "rtc_mlp_set_params: NULL network");
+  if (!W1 || !b1 || !W2 || !b2) return mfail(m, RTC_E_ARG, "rtc_mlp_set_params: NULL parameter");
+  if (!all_finite(W1, m->W1.n) || !all_finite(b1, m->b1.n) || !all_finite(W2, m->W2.n) || !all_finite(b2, m->b2.n))
+    return mfail(m, RTC_E_NONFINITE, "rtc_mlp_set_params: non-finite parameter");
+  DevScope ds(m->device);
+  hipError_t e = ds.status;
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  const float *src[4] = {W1, b1, W2, b2};
+  Tensor *dst[4] = {&m->W1, &m->b1, &m->W2, &m->b2};
+  for (int i = 0; i < 4 && e == hipSuccess; ++i) {
+    Tensor &t = *dst[i];
+    const size_t bytes = (size_t)t.n * sizeof(float);
+    e = hipMemcpy(t.p, src[i], bytes, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(t.m, 0, bytes);
+    if (e == hipSuccess) e = hipMemset(t.v, 0, bytes);
+    if (e == hipSuccess && t.b) e = rtcm::launch_round_bf16(t.p, t.b, t.n, nullptr);
+  }
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  return e == hipSuccess ? RTC_OK : hfail(m, e, "rtc_mlp_set_params");
+}
+
+rtc_status rtc_mlp_get_params(rtc_mlp *m, float *W1, float *b1, float *W2, float *b2) {
+  if (!m) return mfail(nullptr, RTC_E_ARG, "rtc_mlp_get_params: NULL network");
+  if (!W1 || !b1 || !W2 || !b2) return mfail(m, RTC_E_ARG, "rtc_mlp_get_params: NULL output");
+  DevScope ds(m->device);
+  hipError_t e = ds.status;
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  float *dst[4] = {W1, b1, W2, b2};
+  const Tensor *src[4] = {&m->W1, &m->b1, &m->W2, &m->b2};
+  for (int i = 0; i < 4 && e == hipSuccess; ++i)
+    e = hipMemcpy(dst[i], src[i]->p, (size_t)src[i]->n * sizeof(float), hipMemcpyDeviceToHost);
+  return e == hipSuccess ? RTC_OK : hfail(m, e, "rtc_mlp_get_params");
+}
+
+rtc_status rtc_mlp_forward(rtc_mlp *m, int32_t batch, const float *d_x, float *d_y, void *hip_stream) {
+  if (!m) return mfail(nullptr, RTC_E_ARG, "rtc_mlp_forward: NULL network");
+  if (batch < 1 || batch > m->max_batch) return mfail(m, RTC_E_ARG, "rtc_mlp_forward: batch outside 1..max_batch");
+  if (!d_x || !d_y) return mfail(m, RTC_E_ARG, "rtc_mlp_forward: NULL input or output");
+  DevScope ds(m->device);
+  if (ds.status != hipSuccess) return hfail(m, ds.status, "rtc_mlp_forward: hipSetDevice");
+  const hipError_t e = forward(m, batch, d_x, d_y, static_cast<hipStream_t>(hip_stream));
+  return e == hipSuccess ? RTC_OK : hfail(m, e, "rtc_mlp_forward");
+}
+
+rtc_status rtc_mlp_loss_grad(rtc_mlp *m, int32_t B, const float *d_x, const float *d_t, float *d_loss,
+                             void *hip_stream) {
+  if (!m) return mfail(nullptr, RTC_E_ARG, "rtc_mlp_loss_grad: NULL network");
+  if (B < 1 || B > m->max_batch) return mfail(m, RTC_E_ARG, "rtc_mlp_loss_grad: batch outside 1..max_batch");
+  if (!d_x || !d_t || !d_loss) return mfail(m, RTC_E_ARG, "rtc_mlp_loss_grad: NULL argument");
+  DevScope ds(m->device);
+  if (ds.status != hipSuccess) return hfail(m, ds.status, "rtc_mlp_loss_grad: hipSetDevice");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  hipError_t e = forward(m, B, d_x, m->Y, st);
+  if (e == hipSuccess) e = rtcm::launch_loss_grad(m->Y, d_t, B, m->n_out, m->dY, m->dYb, m->row_sq, d_loss, st);
+  if (e == hipSuccess) {                            // dW2 = dY^T H
+    rtcm::GemmArgs g{};
+    g.M = m->n_out;
+    g.N = m->n_hid;
+    g.K = B;
+    g.a_bf16 = m->dYb;
+    g.sam = 1;
+    g.sak = m->n_out;
+    g.b_bf16 = m->Hb;
+    g.sbk = m->n_hid;
+    g.sbn = 1;
+    g.alpha = 1.0f;
+    g.ldc = m->n_hid;
+    g.c_f32 = m->W2.g;
+    e = rtcm::launch_gemm(g, st);
+  }
+  if (e == hipSuccess) e = rtcm::launch_col_sum(m->dY, B, m->n_out, m->b2.g, st);
+  if (e == hipSuccess) {                            // dH = dY W2
+    rtcm::GemmArgs g{};
+    g.M = B;
+    g.N = m->n_hid;
+    g.K = m->n_out;
+    g.a_bf16 = m->dYb;
+    g.sam = m->n_out;
+    g.sak = 1;
+    g.b_bf16 = m->W2.b;
+    g.sbk = m->n_hid;
+    g.sbn = 1;
+    g.alpha = 1.0f;
+    g.ldc = m->n_hid;
+    g.c_f32 = m->dH;
+    e = rtcm::launch_gemm(g, st);
+  }
+  if (e == hipSuccess) e = rtcm::launch_gelu_back(m->dH, m->Z1, m->dZ1, m->dZ1b, (int64_t)B * m->n_hid, st);
+  if (e == hipSuccess) {                            // dW1 = dZ1^T X
+    rtcm::GemmArgs g{};
+    g.M = m->n_hid;
+    g.N = m->n_in;
+    g.K = B;
+    g.a_bf16 = m->dZ1b;
+    g.sam = 1;
+    g.sak = m->n_hid;
+    g.b_f32 = d_x;
+    g.sbk = m->n_in;
+    g.sbn = 1;
+    g.alpha = 1.0f;
+    g.ldc = m->n_in;
+    g.c_f32 = m->W1.g;
+    e = rtcm::launch_gemm(g, st);
+  }
+  if (e == hipSuccess) e = rtcm::launch_col_sum(m->dZ1, B, m->n_hid, m->b1.g, st);
+  return e == hipSuccess ? RTC_OK : hfail(m, e, "rtc_mlp_loss_grad");
+}
+
+rtc_status rtc_mlp_get_grads(rtc_mlp *m, float *dW1, float *db1, float *dW2, float *db2) {
+  if (!m) return mfail(nullptr, RTC_E_ARG, "rtc_mlp_get_grads: NULL network");
+  if (!dW1 || !db1 || !dW2 || !db2) return mfail(m, RTC_E_ARG, "rtc_mlp_get_grads: NULL output");
+  DevScope ds(m->device);
+  hipError_t e = ds.status;
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  float *dst[4] = {dW1, db1, dW2, db2};
+  const Tensor *src[4] = {&m->W1, &m->b1, &m->W2, &m->b2};
+  for (int i = 0; i < 4 && e == hipSuccess; ++i)
+    e = hipMemcpy(dst[i], src[i]->g, (size_t)src[i]->n * sizeof(float), hipMemcpyDeviceToHost);
+  return e == hipSuccess ? RTC_OK : hfail(m, e, "rtc_mlp_get_grads");
+}
+
+rtc_status rtc_mlp_adam(rtc_mlp *m, float lr, float beta1, float beta2, float eps, int32_t step, void *hip_stream) {
+  if (!m) return mfail(nullptr, RTC_E_ARG, "rtc_mlp_adam: NULL network");
+  if (step < 1 || !std::isfinite(lr) || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) ||
+      !(eps > 0.0f))
+    return mfail(m, RTC_E_ARG, "rtc_mlp_adam: need step >= 1, finite lr, betas in [0, 1), eps > 0");
+  DevScope ds(m->device);
+  if (ds.status != hipSuccess) return hfail(m, ds.status, "rtc_mlp_adam: hipSetDevice");
+  const float c1 = (float)(1.0 - std::pow((double)beta1, (double)step));
+  const float c2 = (float)(1.0 - std::pow((double)beta2, (double)step));
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  hipError_t e = hipSuccess;
+  Tensor *ts[4] = {&m->W1, &m->b1, &m->W2, &m->b2};
+  for (int i = 0; i < 4 && e == hipSuccess; ++i)
+    e = rtcm::launch_adam(ts[i]->p, ts[i]->m, ts[i]->v, ts[i]->g, ts[i]->b, ts[i]->n, lr, beta1, beta2, eps, c1, c2,
+                          st);
+  return e == hipSuccess ? RTC_OK : hfail(m, e, "rtc_mlp_adam");
+}
+
+void rtc_mlp_destroy(rtc_mlp *m) {
+  if (!m) return;
+  DevScope ds(m->device);
+  if (ds.status == hipSuccess) (void)hipDeviceSynchronize();
+  free_tensor(m->W1);
+  free_tensor(m->b1);
+  free_tensor(m->W2);
+  free_tensor(m->b2);
+  dfree(m->Z1);
+  dfree(m->Hb);
+  dfree(m->Y);
+  dfree(m->dY);
+  dfree(m->dYb);
+  dfree(m->dH);
+  dfree(m->dZ1);
+  dfree(m->dZ1b);
+  dfree(m->row_sq);
+  delete m;
+}
+
+// ---------------------------------------------------------------------------
+// predictor
+static rtc_status pfail(rtc_pred *p, rtc_status s, const std::string &msg) {
+  if (p) p->err = msg; else g_mlp_err = msg;
+  return s;
+}
+
+void rtc_pred_destroy(rtc_pred *p);
+
+rtc_status rtc_pred_create(rtc_mlp *net, int32_t history, int32_t n_modes, int32_t n_slopes, int32_t n_act,
+                           const float *P, const float *PD, const float *mean, const float *std_, float gain,
+                           rtc_pred **out) {
+  if (!net || !out) return pfail(nullptr, RTC_E_ARG, "rtc_pred_create: NULL network or output");
+  if (history < 1 || n_modes < 1 || n_slopes < 1 || n_act < 1)
+    return pfail(nullptr, RTC_E_ARG, "rtc_pred_create: sizes must be >= 1");
+  if ((int64_t)history * n_modes != net->n_in || n_modes != net->n_out)
+    return pfail(nullptr, RTC_E_ARG, "rtc_pred_create: the network must map history * n_modes inputs to n_modes");
+  if (!P || !PD || !mean || !std_) return pfail(nullptr, RTC_E_ARG, "rtc_pred_create: NULL matrix");
+  if (!all_finite(P, (int64_t)n_modes * n_slopes) || !all_finite(PD, (int64_t)n_modes * n_act) ||
+      !all_finite(mean, n_modes) || !all_finite(std_, n_modes) || !std::isfinite(gain) || !(gain > 0.0f))
+    return pfail(nullptr, RTC_E_NONFINITE, "rtc_pred_create: non-finite input or non-positive gain");
+  std::vector<float> inv((size_t)n_modes), PT((size_t)n_slopes * n_modes);
+  for (int32_t j = 0; j < n_modes; ++j) {
+    if (!(std_[j] > 0.0f)) return pfail(nullptr, RTC_E_NONFINITE, "rtc_pred_create: std must be positive");
+    inv[(size_t)j] = 1.0f / std_[j];
+    for (int32_t i = 0; i < n_slopes; ++i) PT[(size_t)i * n_modes + j] = P[(size_t)j * n_slopes + i];
+  }
+  rtc_pred *p = new (std::nothrow) rtc_pred();
+  if (!p) return pfail(nullptr, RTC_E_NOMEM, "rtc_pred_create: host allocation failed");
+  p->net = net;
+  p->history = history;
+  p->n_modes = n_modes;
+  p->n_slopes = n_slopes;
+  p->n_act = n_act;
+  p->inv_gain = 1.0f / gain;
+  DevScope ds(net->device);
+  hipError_t e = ds.status;
+  const size_t fm = sizeof(float) * (size_t)n_modes;
+  if (e == hipSuccess) e = hipMalloc(&p->P, fm * n_slopes);
+  if (e == hipSuccess) e = hipMalloc(&p->PT, fm * n_slopes);
+  if (e == hipSuccess) e = hipMalloc(&p->PD, fm * n_act);
+  if (e == hipSuccess) e = hipMalloc(&p->mean, fm);
+  if (e == hipSuccess) e = hipMalloc(&p->std_, fm);
+  if (e == hipSuccess) e = hipMalloc(&p->inv_std, fm);
+  if (e == hipSuccess) e = hipMalloc(&p->hist, fm * history);
+  if (e == hipSuccess) e = hipMalloc(&p->m, fm);
+  if (e == hipSuccess) e = hipMalloc(&p->y, fm);
+  if (e == hipSuccess) e = hipMalloc(&p->d, fm);
+  if (e == hipSuccess) e = hipMalloc(&p->mhat, fm);
+  if (e == hipSuccess) e = hipMemcpy(p->P, P, fm * n_slopes, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(p->PT, PT.data(), fm * n_slopes, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(p->PD, PD, fm * n_act, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(p->mean, mean, fm, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(p->std_, std_, fm, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(p->inv_std, inv.data(), fm, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemset(p->hist, 0, fm * history);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    const rtc_status s = pfail(nullptr, e == hipErrorOutOfMemory ? RTC_E_NOMEM : RTC_E_DEVICE,
+                               std::string("rtc_pred_create: ") + hipGetErrorName(e));
+    rtc_pred_destroy(p);
+    return s;
+  }
+  *out = p;
+  return RTC_OK;
+}
+
+rtc_status rtc_pred_reset(rtc_pred *p) {
+  if (!p) return pfail(nullptr, RTC_E_ARG, "rtc_pred_reset: NULL predictor");
+  DevScope ds(p->net->device);
+  hipError_t e = ds.status;
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e == hipSuccess) e = hipMemset(p->hist, 0, sizeof(float) * (size_t)p->n_modes * p->history);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) return pfail(p, RTC_E_DEVICE, std::string("rtc_pred_reset: ") + hipGetErrorName(e));
+  p->pushes = 0;
+  return RTC_OK;
+}
+
+rtc_status rtc_pred_step(rtc_pred *p, const float *d_slopes, const float *d_cmd_prev, float *d_slopes_out,
+                         float *d_modes, void *hip_stream) {
+  if (!p) return pfail(nullptr, RTC_E_ARG, "rtc_pred_step: NULL predictor");
+  if (!d_slopes || !d_cmd_prev || !d_slopes_out) return pfail(p, RTC_E_ARG, "rtc_pred_step: NULL argument");
+  if (d_slopes_out == d_slopes || d_slopes_out == d_cmd_prev)
+    return pfail(p, RTC_E_ARG, "rtc_pred_step: d_slopes_out aliases an input");
+  DevScope ds(p->net->device);
+  if (ds.status != hipSuccess) return pfail(p, RTC_E_DEVICE, "rtc_pred_step: hipSetDevice");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const int nm = p->n_modes;
+  hipError_t e = rtcm::launch_gemv_f32(p->P, p->n_slopes, d_slopes, nm, p->n_slopes, 1.0f, 0.0f, p->m, st);
+  if (e == hipSuccess) e = rtcm::launch_gemv_f32(p->PD, p->n_act, d_cmd_prev, nm, p->n_act, 1.0f, 1.0f, p->m, st);
+  if (e == hipSuccess) e = rtcm::launch_history_push(p->hist, p->history, nm, p->m, p->mean, p->inv_std, st);
+  const bool full = p->pushes + 1 >= p->history;
+  if (e == hipSuccess && full) e = forward(p->net, 1, p->hist, p->y, st);
+  if (e == hipSuccess) e = rtcm::launch_denorm(full ? p->y : nullptr, p->m, p->std_, nm, p->d, p->mhat, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d_slopes_out, d_slopes, sizeof(float) * p->n_slopes, hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess)
+    e = rtcm::launch_gemv_f32(p->PT, nm, p->d, p->n_slopes, nm, p->inv_gain, 1.0f, d_slopes_out, st);
+  if (e == hipSuccess && d_modes) e = hipMemcpyAsync(d_modes, p->m, sizeof(float) * nm, hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess && d_modes)
+    e = hipMemcpyAsync(d_modes + nm, p->mhat, sizeof(float) * nm, hipMemcpyDeviceToDevice, st);
+  if (e != hipSuccess) return pfail(p, RTC_E_DEVICE, std::string("rtc_pred_step: ") + hipGetErrorName(e));
+  if (p->pushes < p->history) ++p->pushes;
+  return RTC_OK;
+}
+
+void rtc_pred_destroy(rtc_pred *p) {
+  if (!p) return;
+  DevScope ds(p->net ? p->net->device : 0);
+  if (ds.status == hipSuccess) (void)hipDeviceSynchronize();
+  dfree(p->P);
+  dfree(p->PT);
+  dfree(p->PD);
+  dfree(p->mean);
+  dfree(p->std_);
+  dfree(p->inv_std);
+  dfree(p->hist);
+  dfree(p->m);
+  dfree(p->y);
+  dfree(p->d);
+  dfree(p->mhat);
+  delete p;
+}
+
+const char *rtc_mlp_error_string(const rtc_mlp *m) { return m ? m->err.c_str() : g_mlp_err.c_str(); }
+const char *rtc_pred_error_string(const rtc_pred *p) { return p ? p->err.c_str() : g_mlp_err.c_str(); }
+
+}  // extern "C"

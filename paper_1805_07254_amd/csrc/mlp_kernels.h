@@ -1,0 +1,45 @@
+// Internal interface between the predictor's C-ABI host code and its gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rtcm {
+
+// C[m][n] = alpha sum_k A(m, k) B(k, n) (+ bias[n]), optional GELU; float32
+// accumulation on bfloat16 operands.  A(m, k) = a[m sam + k sak] and
+// B(k, n) = b[k sbk + n sbn], read from float32 (rounded to bfloat16 on load)
+// or bfloat16 storage (exactly one of the two pointers set per operand).
+struct GemmArgs {
+  int M, N, K;
+  const float *a_f32;
+  const uint16_t *a_bf16;
+  int64_t sam, sak;
+  const float *b_f32;
+  const uint16_t *b_bf16;
+  int64_t sbk, sbn;
+  float alpha;
+  const float *bias;   // nullable [N]
+  int gelu;            // apply GELU after the bias
+  int64_t ldc;
+  float *c_pre;        // nullable: value before the GELU
+  float *c_f32;        // nullable: result
+  uint16_t *c_bf16;    // nullable: result rounded to bfloat16
+};
+hipError_t launch_gemm(const GemmArgs &g, hipStream_t st);
+
+hipError_t launch_round_bf16(const float *x, uint16_t *y, int64_t n, hipStream_t st);
+hipError_t launch_loss_grad(const float *Y, const float *T, int B, int n, float *dY, uint16_t *dYb, float *row_sq,
+                            float *loss, hipStream_t st);
+hipError_t launch_gelu_back(const float *dH, const float *Z, float *dZ, uint16_t *dZb, int64_t n, hipStream_t st);
+hipError_t launch_col_sum(const float *dZ, int B, int n, float *db, hipStream_t st);
+hipError_t launch_adam(float *theta, float *m, float *v, const float *grad, uint16_t *theta_b, int64_t n, float lr,
+                       float b1, float b2, float eps, float c1, float c2, hipStream_t st);
+hipError_t launch_gemv_f32(const float *A, int64_t lda, const float *x, int rows, int cols, float alpha, float beta,
+                           float *y, hipStream_t st);
+hipError_t launch_history_push(float *hist, int history, int n_modes, const float *m, const float *mean,
+                               const float *inv_std, hipStream_t st);
+hipError_t launch_denorm(const float *y, const float *m_last, const float *std_, int n_modes, float *d, float *mhat,
+                         hipStream_t st);
+
+}  // namespace rtcm

@@ -76,6 +76,20 @@ _SIGNATURES = {
     "rtc_graph_capture": (_i32, [_vp, _i32, _vp, _i64, _vp, _vp, _vp, _vp, _vp]),
     "rtc_graph_launch": (_i32, [_vp, _vp]),
     "rtc_get_frame_mode": (_i32, [_vp, ctypes.POINTER(_i32)]),
+    "rtc_mlp_create": (_i32, [_i32, _i32, _i32, _i32, _i32, ctypes.POINTER(_vp)]),
+    "rtc_mlp_set_params": (_i32, [_vp, _vp, _vp, _vp, _vp]),
+    "rtc_mlp_get_params": (_i32, [_vp, _vp, _vp, _vp, _vp]),
+    "rtc_mlp_forward": (_i32, [_vp, _i32, _vp, _vp, _vp]),
+    "rtc_mlp_loss_grad": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp]),
+    "rtc_mlp_get_grads": (_i32, [_vp, _vp, _vp, _vp, _vp]),
+    "rtc_mlp_adam": (_i32, [_vp, _f32, _f32, _f32, _f32, _i32, _vp]),
+    "rtc_mlp_destroy": (None, [_vp]),
+    "rtc_mlp_error_string": (ctypes.c_char_p, [_vp]),
+    "rtc_pred_create": (_i32, [_vp, _i32, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _f32, ctypes.POINTER(_vp)]),
+    "rtc_pred_reset": (_i32, [_vp]),
+    "rtc_pred_step": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp]),
+    "rtc_pred_destroy": (None, [_vp]),
+    "rtc_pred_error_string": (ctypes.c_char_p, [_vp]),
     "rtc_autotune": (_i32, [_vp, _i32, _vp, _i64, _vp, _vp, _i32, ctypes.POINTER(_i32), _vp]),
     "rtc_load_cmat": (_i32, [_vp, _vp, _i32, _i32, _i64]),
     "rtc_encode_cmat": (_i32, [_i32, _vp, _i32, _i32, _i64, _vp, _vp]),
@@ -462,3 +476,124 @@ def rtc_get_frame_mode(ctx: RtcContext) -> int:
     m = ctypes.c_int32(-1)
     _check(load_library().rtc_get_frame_mode(ctx.handle, ctypes.byref(m)), ctx)
     return m.value
+
+
+# ---------------------------------------------------------------------------
+# learned predictor (include/rtc_mlp.h)
+def _mcheck(status: int, handle, err_fn: str):
+    if status != RTC_OK:
+        msg = getattr(load_library(), err_fn)(handle)
+        raise RtcError(status, msg.decode() if msg else "")
+
+
+class MlpNet:
+    """Owning handle of an ``rtc_mlp*`` (n_in -> n_hidden GELU -> n_out)."""
+
+    def __init__(self, n_in: int, n_hidden: int, n_out: int, max_batch: int, device: int = 0):
+        out = _vp()
+        _mcheck(load_library().rtc_mlp_create(n_in, n_hidden, n_out, max_batch, device, ctypes.byref(out)), None,
+                "rtc_mlp_error_string")
+        self.handle = out
+        self.n_in, self.n_hidden, self.n_out, self.max_batch, self.device = n_in, n_hidden, n_out, max_batch, device
+
+    def _chk(self, st):
+        _mcheck(st, self.handle, "rtc_mlp_error_string")
+
+    def _shapes(self):
+        return [(self.n_hidden, self.n_in), (self.n_hidden,), (self.n_out, self.n_hidden), (self.n_out,)]
+
+    def set_params(self, W1, b1, W2, b2) -> None:
+        arrs = [np.ascontiguousarray(a, dtype=np.float32) for a in (W1, b1, W2, b2)]
+        for a, shp in zip(arrs, self._shapes()):
+            if a.shape != shp:
+                raise ValueError(f"parameter shape {a.shape} != {shp}")
+        self._chk(load_library().rtc_mlp_set_params(self.handle, *[a.ctypes.data for a in arrs]))
+
+    def get_params(self):
+        arrs = [np.empty(shp, np.float32) for shp in self._shapes()]
+        self._chk(load_library().rtc_mlp_get_params(self.handle, *[a.ctypes.data for a in arrs]))
+        return arrs
+
+    def get_grads(self):
+        arrs = [np.empty(shp, np.float32) for shp in self._shapes()]
+        self._chk(load_library().rtc_mlp_get_grads(self.handle, *[a.ctypes.data for a in arrs]))
+        return arrs
+
+    def _dev(self, t, numel, what):
+        import torch
+        if t.dtype != torch.float32 or t.device.type != "cuda" or not t.is_contiguous() or t.numel() < numel:
+            raise ValueError(f"{what}: need a contiguous float32 device tensor of >= {numel} elements")
+        return t.data_ptr()
+
+    def forward(self, batch: int, x, y, stream=None) -> None:
+        self._chk(load_library().rtc_mlp_forward(self.handle, batch, self._dev(x, batch * self.n_in, "x"),
+                                                 self._dev(y, batch * self.n_out, "y"), _stream_ptr(stream)))
+
+    def loss_grad(self, batch: int, x, t, loss, stream=None) -> None:
+        self._chk(load_library().rtc_mlp_loss_grad(self.handle, batch, self._dev(x, batch * self.n_in, "x"),
+                                                   self._dev(t, batch * self.n_out, "t"), self._dev(loss, 1, "loss"),
+                                                   _stream_ptr(stream)))
+
+    def adam(self, lr: float, step: int, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8,
+             stream=None) -> None:
+        self._chk(load_library().rtc_mlp_adam(self.handle, lr, beta1, beta2, eps, step, _stream_ptr(stream)))
+
+    def close(self):
+        if self.handle is not None and self.handle.value:
+            load_library().rtc_mlp_destroy(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+class Predictor:
+    """Owning handle of an ``rtc_pred*`` (predictive feed-forward); keeps its network alive."""
+
+    def __init__(self, net: MlpNet, history: int, P, PD, mean, std, gain: float):
+        P, PD, mean, std = (np.ascontiguousarray(a, dtype=np.float32) for a in (P, PD, mean, std))
+        n_modes, n_slopes = P.shape
+        n_act = PD.shape[1]
+        if PD.shape != (n_modes, n_act) or mean.shape != (n_modes,) or std.shape != (n_modes,):
+            raise ValueError("P [n_modes, n_slopes], PD [n_modes, n_act], mean/std [n_modes]")
+        out = _vp()
+        _mcheck(load_library().rtc_pred_create(net.handle, history, n_modes, n_slopes, n_act, P.ctypes.data,
+                                               PD.ctypes.data, mean.ctypes.data, std.ctypes.data, gain,
+                                               ctypes.byref(out)), None, "rtc_pred_error_string")
+        self.handle, self.net = out, net
+        self.history, self.n_modes, self.n_slopes, self.n_act = history, n_modes, n_slopes, n_act
+
+    def _chk(self, st):
+        _mcheck(st, self.handle, "rtc_pred_error_string")
+
+    def reset(self) -> None:
+        self._chk(load_library().rtc_pred_reset(self.handle))
+
+    def step(self, slopes, cmd_prev, slopes_out, modes=None, stream=None) -> None:
+        """slopes_out = slopes + P^T (forecast change) / gain, to be fed to the integrator."""
+        ptr = lambda t, n, w: MlpNet._dev(self.net, t, n, w)
+        self._chk(load_library().rtc_pred_step(self.handle, ptr(slopes, self.n_slopes, "slopes"),
+                                               ptr(cmd_prev, self.n_act, "cmd_prev"),
+                                               ptr(slopes_out, self.n_slopes, "slopes_out"),
+                                               None if modes is None else ptr(modes, 2 * self.n_modes, "modes"),
+                                               _stream_ptr(stream)))
+
+    def close(self):
+        if self.handle is not None and self.handle.value:
+            load_library().rtc_pred_destroy(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

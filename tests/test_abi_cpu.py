@@ -11,13 +11,16 @@ import pytest
 from paper_1805_07254_amd import rtc
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "rtc.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in sorted(os.listdir(os.path.join(ROOT, "include")))
+           if h.endswith(".h")]
 
 
 def _declared():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(rtc_[a-z0-9_]+)\s*\(", text)))
+    names = set()
+    for h in HEADERS:
+        text = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"\b(rtc_[a-z0-9_]+)\s*\(", text))
+    return sorted(names)
 
 
 def test_library_exports_every_declared_symbol():
@@ -138,3 +141,18 @@ def test_valid_multi_config_without_gpu_reports_device_error():
         rtc.rtc_init_multi([(np.ones((4, 4)), 4), (np.ones((2, 2)), 6)], 9)
     assert ei.value.status == rtc.RTC_E_DEVICE
     assert rtc.load_library().rtc_frame_elems(None) == -1
+
+
+def test_mlp_create_rejects_bad_sizes_and_reports_no_device():
+    lib = rtc.load_library()
+    out = ctypes.c_void_p(777)
+    assert lib.rtc_mlp_create(0, 4, 4, 8, 0, ctypes.byref(out)) == rtc.RTC_E_ARG
+    assert b"sizes" in lib.rtc_mlp_error_string(None)
+    assert lib.rtc_mlp_create(4, 4, 4, 1 << 17, 0, ctypes.byref(out)) == rtc.RTC_E_ARG
+    assert out.value == 777
+    import torch
+    if not torch.cuda.is_available():
+        assert lib.rtc_mlp_create(4, 4, 4, 8, 0, ctypes.byref(out)) == rtc.RTC_E_DEVICE
+    assert lib.rtc_pred_create(None, 1, 1, 1, 1, None, None, None, None, 0.4, ctypes.byref(out)) == rtc.RTC_E_ARG
+    lib.rtc_mlp_destroy(None)
+    lib.rtc_pred_destroy(None)

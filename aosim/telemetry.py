@@ -25,7 +25,6 @@ from dataclasses import dataclass
 import numpy as np
 import torch
 
-from .turbulence import von_karman_psd
 from .scenario import ROOT_SEED
 
 SEED_KEY = 7           # spawn-key component of telemetry screens
@@ -44,18 +43,24 @@ class Layers:
 
 
 def screen(ny: int, nx: int, delta: float, r0: float, L0: float, seed: tuple, device) -> torch.Tensor:
-    """float32 periodic von Karman screen [ny, nx] (rad), seeded by a spawn key."""
-    g = torch.Generator(device="cpu")
+    """float32 periodic von Karman screen [ny, nx] (rad), seeded by a spawn key.
+
+    The Gaussian draws come from a generator on ``device`` (seeded from the
+    spawn key), so they are reproducible for a given device type and torch
+    build."""
+    device = torch.device(device)
+    g = torch.Generator(device=device)
     g.manual_seed(int(np.random.SeedSequence(ROOT_SEED, spawn_key=seed).generate_state(1)[0]))
-    fy = torch.fft.fftfreq(ny, d=delta, dtype=torch.float64)
-    fx = torch.fft.fftfreq(nx, d=delta, dtype=torch.float64)
-    f = torch.sqrt(fy[:, None] ** 2 + fx[None, :] ** 2)
-    psd = torch.from_numpy(von_karman_psd(f.numpy(), r0, L0))
+    fy = torch.fft.fftfreq(ny, d=delta, dtype=torch.float64, device=device)
+    fx = torch.fft.fftfreq(nx, d=delta, dtype=torch.float64, device=device)
+    f2 = fy[:, None] ** 2 + fx[None, :] ** 2
+    # von Karman phase PSD (as aosim.turbulence.von_karman_psd), evaluated on the device
+    psd = 0.023 * r0 ** (-5.0 / 3.0) * (f2 + 1.0 / (L0 * L0)) ** (-11.0 / 6.0)
     psd[0, 0] = 0.0
     amp = torch.sqrt(psd) * math.sqrt(1.0 / (ny * delta) * 1.0 / (nx * delta))
-    re = torch.randn((ny, nx), generator=g, dtype=torch.float64)
-    im = torch.randn((ny, nx), generator=g, dtype=torch.float64)
-    c = torch.complex(re * amp, im * amp).to(device)
+    re = torch.randn((ny, nx), generator=g, dtype=torch.float64, device=device)
+    im = torch.randn((ny, nx), generator=g, dtype=torch.float64, device=device)
+    c = torch.complex(re * amp, im * amp)
     return (torch.fft.ifft2(c) * (ny * nx)).real.to(torch.float32)
 
 
@@ -123,10 +128,11 @@ class Telemetry:
         return out
 
     def noise(self, seg: int, n_frames: int, n_slopes: int) -> torch.Tensor:
-        g = torch.Generator(device="cpu")
+        """float32 [n_frames, n_slopes] Gaussian slope noise of segment `seg` (device generator)."""
+        g = torch.Generator(device=self.device)
         g.manual_seed(int(np.random.SeedSequence(ROOT_SEED, spawn_key=(self.config_index, SEED_KEY + 1, seg))
                           .generate_state(1)[0]))
-        return (torch.randn((n_frames, n_slopes), generator=g) * self.layers.noise_px).to(self.device)
+        return torch.randn((n_frames, n_slopes), generator=g, device=self.device) * self.layers.noise_px
 
 
 def kl_basis(samples: torch.Tensor, n_modes: int) -> torch.Tensor:

@@ -75,12 +75,18 @@ def parse():
     p.add_argument("--variants", default="f16,bf16,fp8e4m3",
                    help="reduced-precision matrix formats also timed (comma list, empty = none)")
     p.add_argument("--variant-steps", type=int, default=2000)
-    p.add_argument("--workload", default="elt-scao", choices=["elt-scao", "elt-multi"],
+    p.add_argument("--workload", default="elt-scao", choices=["elt-scao", "elt-multi", "elt-predict"],
                    help="elt-scao: the single-sensor ELT frame (default); elt-multi: six 74x74 and three 16x16 "
                         "sensors reconstructed by one BF16 matrix")
     p.add_argument("--multi-steps", type=int, default=5000)
     p.add_argument("--multi-ring", type=int, default=4, help="distinct multi-sensor frame sets")
     p.add_argument("--multi-dtype", default="bf16")
+    p.add_argument("--pred-frames", type=int, default=200000, help="closed-loop training frames (elt-predict)")
+    p.add_argument("--pred-modes", type=int, default=500)
+    p.add_argument("--pred-hidden", type=int, default=1024)
+    p.add_argument("--pred-history", type=int, default=5)
+    p.add_argument("--pred-epochs", type=int, default=6)
+    p.add_argument("--pred-batch", type=int, default=512)
     return p.parse_args()
 
 
@@ -222,6 +228,127 @@ def run_multi(args):
     print(json.dumps(result), flush=True)
 
 
+def run_predict(args):
+    """Learned predictor at the ELT size: closed-loop telemetry of the integrator, training with the
+    library's kernels, closed-loop judgement against the integrator, and per-frame cost."""
+    import torch
+    from aosim import ELT, Scenario
+    from aosim.telemetry import Telemetry, kl_basis
+    from paper_1805_07254_amd import predict, rtc
+
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    rtc.load_library()
+    t0 = time.time()
+    dev = torch.device("cuda:0")
+    sc = Scenario(ELT)
+    cfg = sc.cfg
+    ns, na, nm, H = 2 * sc.n_valid, sc.n_act, args.pred_modes, args.pred_history
+    D = torch.from_numpy(sc.interaction.astype(np.float32)).to(dev)
+    R = sc.control_matrix
+    log(f"{cfg.name}: D and R built at {time.time() - t0:.0f}s")
+    tel = Telemetry(sc.mask, cfg.pitch, config_index=cfg.index, device=dev)
+    seg_len = 2000
+    n_train = max(1, args.pred_frames // seg_len)
+    ol = torch.cat([tel.segment(k, seg_len)[::8] for k in range(min(n_train, 12))])
+    P = kl_basis(ol, nm).to(dev)
+    PD = P @ D
+    del ol
+    log(f"{nm} KL modes at {time.time() - t0:.0f}s")
+    ctx = predict.make_context(sc, R, gain=cfg.gain)
+    zs = []
+    for seg in range(n_train + 1):                       # last one: validation
+        s = tel.segment(seg, seg_len)
+        out = predict.run_loop(D, s, tel.noise(seg, seg_len, ns), ctx)
+        zs.append(predict.pol_modes(out["residual"], out["cmd_prev"], P, PD))
+        if (seg + 1) % 10 == 0:
+            log(f"telemetry: {(seg + 1) * seg_len} closed-loop frames at {time.time() - t0:.0f}s")
+    mean, std = predict.change_stats(torch.cat(zs[:n_train]))
+    xs, ys = zip(*[predict.windows(z, H, mean, std) for z in zs[:n_train]])
+    x, y = torch.cat(xs), torch.cat(ys)
+    del xs, ys
+    xv, yv = predict.windows(zs[n_train], H, mean, std)
+    net = rtc.MlpNet(H * nm, args.pred_hidden, nm, args.pred_batch)
+    net.set_params(*predict.init_params(H * nm, args.pred_hidden, nm, seed=5))
+    persist = float(((xv[:, -nm:] - yv) ** 2).mean().item())     # forecast = the last change again
+    t1 = time.time()
+    hist = predict.train(net, x, y, epochs=args.pred_epochs, batch=args.pred_batch, lr=1e-3, seed=6, x_val=xv,
+                         y_val=yv, log=log)
+    train_s = time.time() - t1
+    steps = args.pred_epochs * (x.shape[0] // args.pred_batch)
+
+    # one training step's device time (HIP events on the launch stream)
+    stream = torch.cuda.current_stream()
+    loss = torch.zeros(1, device=dev)
+    xb, yb = x[:args.pred_batch].contiguous(), y[:args.pred_batch].contiguous()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(50):
+        net.loss_grad(args.pred_batch, xb, yb, loss, stream=stream)
+    ev1.record(stream)
+    ev1.synchronize()
+    step_ms = ev0.elapsed_time(ev1) / 50
+    n_in, nh = H * nm, args.pred_hidden
+    flops = 2 * args.pred_batch * (2 * n_in * nh + 3 * nh * nm)   # forward 2 products, backward 3
+    log(f"training: {steps} steps in {train_s:.1f}s; forward+backward {step_ms:.3f} ms "
+        f"({flops / step_ms / 1e9:.1f} TFLOP/s)")
+
+    # judge on held-out segments
+    pred = rtc.Predictor(net, H, P.cpu().numpy(), PD.cpu().numpy(), mean.cpu().numpy(), std.cpu().numpy(), cfg.gain)
+    judged = []
+    for seg in (n_train + 1, n_train + 2):
+        s = tel.segment(seg, seg_len)
+        nz = tel.noise(seg, seg_len, ns)
+        base = predict.run_loop(D, s, nz, ctx)
+        withp = predict.run_loop(D, s, nz, ctx, pred)
+        judged.append({"segment": seg, "open_loop": predict.residual_rms(s + nz, 100),
+                       "integrator": predict.residual_rms(base["residual"], 100),
+                       "predictive": predict.residual_rms(withp["residual"], 100)})
+        log(f"segment {seg}: {judged[-1]}")
+
+    # per-frame cost on slopes: integrator alone vs predictor step + integrator
+    r = torch.zeros((ns + 15) // 16 * 16, device=dev)
+    r[:ns] = s[500] + nz[500]
+    r2 = torch.empty_like(r)
+    c0 = torch.zeros(na, device=dev)
+    c1 = torch.empty(na, device=dev)
+    st_ptr = stream.cuda_stream
+
+    def timed(fn, reps=2000):
+        for _ in range(50):
+            fn()
+        ev0.record(stream)
+        for _ in range(reps):
+            fn()
+        ev1.record(stream)
+        ev1.synchronize()
+        return ev0.elapsed_time(ev1) * 1e3 / reps
+    t_int = timed(lambda: rtc.rtc_reconstruct_integrate(ctx, r, c1, stream=st_ptr))
+    t_pred = timed(lambda: (pred.step(r, c0, r2, stream=st_ptr), rtc.rtc_reconstruct_integrate(ctx, r2, c1,
+                                                                                                  stream=st_ptr)))
+    pred.close()
+    res_i = float(np.mean([j["integrator"] for j in judged]))
+    res_p = float(np.mean([j["predictive"] for j in judged]))
+    result = {
+        "metric": "closed-loop residual slope RMS, learned predictor vs integrator (px)",
+        "value": round(res_p, 5), "unit": "px", "n_gpus": 1, "steps": steps, "warmup": 0,
+        "ms_per_step": round(step_ms, 4), "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": f"{cfg.name}: {sc.n_valid} subapertures, {na} actuators, two frozen-flow layers "
+                               f"(8 and 20 m/s, 1 kHz, 0.05 px noise), {nm} KL modes, network "
+                               f"{H}x{nm} -> {args.pred_hidden} (GELU) -> {nm}, {n_train * seg_len} training frames",
+                   "epochs": args.pred_epochs, "batch": args.pred_batch},
+        "integrator_residual_px": round(res_i, 5), "predictive_residual_px": round(res_p, 5),
+        "gain_percent": round(100 * (1 - res_p / res_i), 2), "judged_segments": judged,
+        "validation_mse": {"last_change": persist, "zero_change": float((yv ** 2).mean().item()),
+                           "trained": hist[-1].get("val_loss")}, "training": hist,
+        "frame_cost_us": {"integrator": round(t_int, 3), "predictor_step_plus_integrator": round(t_pred, 3)},
+        "training_step": {"ms": round(step_ms, 4), "tflops": round(flops / step_ms / 1e9, 2),
+                          "peak_bf16_tflops": 2500.0},
+    }
+    print(json.dumps(result), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -229,6 +356,9 @@ def main():
         sys.exit(2)
     if args.workload == "elt-multi":
         run_multi(args)
+        return
+    if args.workload == "elt-predict":
+        run_predict(args)
         return
     import torch
     from aosim import ELT, Scenario

@@ -64,12 +64,13 @@ void rtc_mlp_destroy(rtc_mlp *m);
  * n_in = history * n_modes and n_out = n_modes.  Per frame k, with measured
  * slopes r_k and the command c_{k-1} the mirror held while they were taken:
  *   m_k = P r_k + PD c_{k-1}                 pseudo-open-loop modes [n_modes]
- *   window <- last `history` frames of (m - mean) / std
- *   d_k = network(window) * std              forecast change m_{k+1} - m_k
- *                                            (0 until the window is full)
+ *   window <- last `history` changes (m_k - m_{k-1} - mean) / std
+ *   d_k = network(window) * std + mean       forecast change m_{k+1} - m_k
+ *                                            (0 until history + 1 frames)
  *   r'_k = r_k + P^T d_k / gain              slopes handed to the integrator
  * where P [n_modes][n_slopes] has orthonormal rows (modes of the slope
- * space) and PD = P D [n_modes][n_act] maps commands to their modal slopes.
+ * space), PD = P D [n_modes][n_act] maps commands to their modal slopes, and
+ * mean / std normalise the per-frame changes of the modes.
  * The integrator c_k = c_{k-1} + gain R r'_k (rtc_reconstruct_integrate with
  * the same gain) then adds R P^T d_k to its command: the forecast change of the
  * leading modes is applied in the frame it happens instead of one frame

@@ -92,24 +92,26 @@ def adam(theta, m, v, g, lr, b1, b2, eps, t):
     return theta, m, v
 
 
-def predictor_step(params, window, r, c_prev, P, PD, mean, std, history, gain, rounding=True):
+def predictor_step(params, state, r, c_prev, P, PD, mean, std, history, gain, rounding=True):
     """One frame of the predictive feed-forward.
 
-    m = P r + PD c_prev; the window (oldest first, ``history`` rows of
-    normalised modes) gains (m - mean) / std; when full, the forecast change
-    is d = network(window) * std (the network forecasts the normalised
-    change), otherwise d = 0; the slopes handed to the integrator are
-    r' = r + P^T d / gain.  Returns (r', m, m + d, new window).
+    m = P r + PD c_prev; from the second frame on the window (oldest first,
+    ``history`` rows) gains the normalised change (m - m_prev - mean) / std;
+    when it holds ``history`` changes the forecast change is
+    d = network(window) * std + mean, otherwise d = 0; the slopes handed to
+    the integrator are r' = r + P^T d / gain.  ``state`` is a dict with
+    "window" (list) and "m_prev" (None at start).  Returns (r', m, m + d, state).
     """
     P, PD = np.asarray(P, dtype=np.float64), np.asarray(PD, dtype=np.float64)
     mean, std = np.asarray(mean, np.float64), np.asarray(std, np.float64)
     r = np.asarray(r, np.float64)
     m = P @ r + PD @ np.asarray(c_prev, np.float64)
-    z = (m - mean) / std
-    window = (list(window) + [z])[-history:]
+    window = list(state.get("window", []))
+    if state.get("m_prev") is not None:
+        window = (window + [(m - state["m_prev"] - mean) / std])[-history:]
     if len(window) == history:
-        d = forward(params, np.concatenate(window)[None, :], rounding)["Y"][0] * std
+        d = forward(params, np.concatenate(window)[None, :], rounding)["Y"][0] * std + mean
     else:
         d = np.zeros_like(m)
     r_out = r + P.T @ d / float(np.float32(gain))
-    return r_out, m, m + d, window
+    return r_out, m, m + d, {"window": window, "m_prev": m}

@@ -62,10 +62,10 @@ struct rtc_mlp {
 
 struct rtc_pred {
   rtc_mlp *net = nullptr;
-  int32_t history = 0, n_modes = 0, n_slopes = 0, n_act = 0, pushes = 0;
+  int32_t history = 0, n_modes = 0, n_slopes = 0, n_act = 0, frames = 0;   // frames seen, up to history
   float inv_gain = 1.0f;
   float *P = nullptr, *PT = nullptr, *PD = nullptr, *mean = nullptr, *std_ = nullptr, *inv_std = nullptr;
-  float *hist = nullptr, *m = nullptr, *y = nullptr, *d = nullptr, *mhat = nullptr;
+  float *hist = nullptr, *m = nullptr, *m_prev = nullptr, *y = nullptr, *d = nullptr, *mhat = nullptr;
   std::string err = "no error";
 };
 
@@ -139,6 +139,15 @@ hipError_t forward(rtc_mlp *m, int32_t B, const float *x, float *y, hipStream_t 
   h.ldc = m->n_out;
   h.c_f32 = y;
   return rtcm::launch_gemm(h, st);
+}
+
+// Batch-1 forward for the predictor step: two bfloat16 GEMV layers with the
+// rounding points of the batched forward.
+hipError_t forward_one(rtc_mlp *m, const float *x, float *y, hipStream_t st) {
+  hipError_t e = rtcm::launch_gemv_bf16(m->W1.b, x, m->b1.p, m->n_hid, m->n_in, 1, m->Z1, m->Hb, st);
+  if (e != hipSuccess) return e;
+  // the second layer rounds the float32 activations to bfloat16 as it reads them
+  return rtcm::launch_gemv_bf16(m->W2.b, m->Z1, m->b2.p, m->n_out, m->n_hid, 0, y, nullptr, st);
 }
 
 }  // namespace
@@ -394,6 +403,7 @@ rtc_status rtc_pred_create(rtc_mlp *net, int32_t history, int32_t n_modes, int32
   if (e == hipSuccess) e = hipMalloc(&p->inv_std, fm);
   if (e == hipSuccess) e = hipMalloc(&p->hist, fm * history);
   if (e == hipSuccess) e = hipMalloc(&p->m, fm);
+  if (e == hipSuccess) e = hipMalloc(&p->m_prev, fm);
   if (e == hipSuccess) e = hipMalloc(&p->y, fm);
   if (e == hipSuccess) e = hipMalloc(&p->d, fm);
   if (e == hipSuccess) e = hipMalloc(&p->mhat, fm);
@@ -423,7 +433,7 @@ rtc_status rtc_pred_reset(rtc_pred *p) {
   if (e == hipSuccess) e = hipMemset(p->hist, 0, sizeof(float) * (size_t)p->n_modes * p->history);
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) return pfail(p, RTC_E_DEVICE, std::string("rtc_pred_reset: ") + hipGetErrorName(e));
-  p->pushes = 0;
+  p->frames = 0;
   return RTC_OK;
 }
 
@@ -439,10 +449,12 @@ rtc_status rtc_pred_step(rtc_pred *p, const float *d_slopes, const float *d_cmd_
   const int nm = p->n_modes;
   hipError_t e = rtcm::launch_gemv_f32(p->P, p->n_slopes, d_slopes, nm, p->n_slopes, 1.0f, 0.0f, p->m, st);
   if (e == hipSuccess) e = rtcm::launch_gemv_f32(p->PD, p->n_act, d_cmd_prev, nm, p->n_act, 1.0f, 1.0f, p->m, st);
-  if (e == hipSuccess) e = rtcm::launch_history_push(p->hist, p->history, nm, p->m, p->mean, p->inv_std, st);
-  const bool full = p->pushes + 1 >= p->history;
-  if (e == hipSuccess && full) e = forward(p->net, 1, p->hist, p->y, st);
-  if (e == hipSuccess) e = rtcm::launch_denorm(full ? p->y : nullptr, p->m, p->std_, nm, p->d, p->mhat, st);
+  if (e == hipSuccess)
+    e = rtcm::launch_history_push(p->hist, p->history, nm, p->m, p->m_prev, p->mean, p->inv_std, p->frames > 0, st);
+  const bool full = p->frames >= p->history;        // `history` changes need history + 1 frames
+  if (e == hipSuccess && full) e = forward_one(p->net, p->hist, p->y, st);
+  if (e == hipSuccess)
+    e = rtcm::launch_denorm(full ? p->y : nullptr, p->m, p->mean, p->std_, nm, p->d, p->mhat, st);
   if (e == hipSuccess)
     e = hipMemcpyAsync(d_slopes_out, d_slopes, sizeof(float) * p->n_slopes, hipMemcpyDeviceToDevice, st);
   if (e == hipSuccess)
@@ -451,7 +463,7 @@ rtc_status rtc_pred_step(rtc_pred *p, const float *d_slopes, const float *d_cmd_
   if (e == hipSuccess && d_modes)
     e = hipMemcpyAsync(d_modes + nm, p->mhat, sizeof(float) * nm, hipMemcpyDeviceToDevice, st);
   if (e != hipSuccess) return pfail(p, RTC_E_DEVICE, std::string("rtc_pred_step: ") + hipGetErrorName(e));
-  if (p->pushes < p->history) ++p->pushes;
+  if (p->frames < p->history) ++p->frames;
   return RTC_OK;
 }
 
@@ -467,6 +479,7 @@ void rtc_pred_destroy(rtc_pred *p) {
   dfree(p->inv_std);
   dfree(p->hist);
   dfree(p->m);
+  dfree(p->m_prev);
   dfree(p->y);
   dfree(p->d);
   dfree(p->mhat);

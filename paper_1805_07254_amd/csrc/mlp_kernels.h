@@ -37,9 +37,11 @@ hipError_t launch_adam(float *theta, float *m, float *v, const float *grad, uint
                        float b1, float b2, float eps, float c1, float c2, hipStream_t st);
 hipError_t launch_gemv_f32(const float *A, int64_t lda, const float *x, int rows, int cols, float alpha, float beta,
                            float *y, hipStream_t st);
-hipError_t launch_history_push(float *hist, int history, int n_modes, const float *m, const float *mean,
-                               const float *inv_std, hipStream_t st);
-hipError_t launch_denorm(const float *y, const float *m_last, const float *std_, int n_modes, float *d, float *mhat,
-                         hipStream_t st);
+hipError_t launch_gemv_bf16(const uint16_t *W, const float *x, const float *b, int rows, int cols, int gelu_on,
+                            float *out_f32, uint16_t *out_bf16, hipStream_t st);
+hipError_t launch_history_push(float *hist, int history, int n_modes, const float *m, float *m_prev,
+                               const float *mean, const float *inv_std, int push, hipStream_t st);
+hipError_t launch_denorm(const float *y, const float *m_last, const float *mean, const float *std_, int n_modes,
+                         float *d, float *mhat, hipStream_t st);
 
 }  // namespace rtcm

@@ -180,40 +180,78 @@ __global__ __launch_bounds__(256) void adam_kernel(float *theta, float *m, float
   }
 }
 
-// y[r] = alpha sum_j A[r][j] x[j] + beta y[r]: one wavefront per row, lanes
-// stride the row, four accumulators, butterfly sum (fixed order).
-__global__ __launch_bounds__(256) void gemv_f32_kernel(const float *A, int64_t lda, const float *x, int rows,
-                                                       int cols, float alpha, float beta, float *y) {
-  const int lane = threadIdx.x & 63;
-  const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (r >= rows) return;                              // wave-uniform
-  const float *row = A + (int64_t)r * lda;
-  float acc[4] = {0.f, 0.f, 0.f, 0.f};
-  int j = lane, q = 0;
-  for (; j < cols; j += 64, q = (q + 1) & 3) acc[q] = fmaf(row[j], x[j], acc[q]);
-  float s = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+// Fixed-order sum of one value per thread of a 256-thread workgroup
+// (butterfly within each wavefront, then the four wavefronts in order).
+__device__ __forceinline__ float block_sum(float s, float *sh) {
   for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-  if (lane == 0) y[r] = alpha * s + (beta == 0.0f ? 0.0f : beta * y[r]);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+  __syncthreads();
+  const float t = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+  __syncthreads();
+  return t;
 }
 
-// Predictor history: shift the window by one frame and append the normalised
-// modes (m - mean) / std; mark the window full after `history` pushes.
-__global__ __launch_bounds__(256) void history_push_kernel(float *hist, int history, int n_modes, const float *m,
-                                                           const float *mean, const float *inv_std) {
-  const int j = blockIdx.x * 256 + threadIdx.x;
-  if (j < n_modes) {
-    for (int h = 0; h + 1 < history; ++h) hist[(int64_t)h * n_modes + j] = hist[(int64_t)(h + 1) * n_modes + j];
-    hist[(int64_t)(history - 1) * n_modes + j] = (m[j] - mean[j]) * inv_std[j];
+// y[r] = alpha sum_j A[r][j] x[j] + beta y[r]: one workgroup per row, threads
+// stride the row, two accumulators, fixed-order block sum.
+__global__ __launch_bounds__(256) void gemv_f32_kernel(const float *A, int64_t lda, const float *x, int rows,
+                                                       int cols, float alpha, float beta, float *y) {
+  __shared__ float sh[4];
+  const int r = blockIdx.x;
+  const float *row = A + (int64_t)r * lda;
+  float a0 = 0.f, a1 = 0.f;
+  int j = threadIdx.x;
+  for (; j + 256 < cols; j += 512) {
+    a0 = fmaf(row[j], x[j], a0);
+    a1 = fmaf(row[j + 256], x[j + 256], a1);
+  }
+  if (j < cols) a0 = fmaf(row[j], x[j], a0);
+  const float s = block_sum(a0 + a1, sh);
+  if (threadIdx.x == 0) y[r] = alpha * s + (beta == 0.0f ? 0.0f : beta * y[r]);
+}
+
+// Batch-1 layer of the network: z[r] = sum_k bf16(x[k]) W[r][k] + b[r] with
+// bfloat16 weights and float32 accumulation (the rounding points of the
+// training products); out_f32 = GELU(z) or z, out_bf16 its bfloat16 rounding.
+__global__ __launch_bounds__(256) void gemv_bf16_kernel(const uint16_t *W, const float *x, const float *b, int rows,
+                                                        int cols, int gelu_on, float *out_f32, uint16_t *out_bf16) {
+  __shared__ float sh[4];
+  const int r = blockIdx.x;
+  const uint16_t *row = W + (int64_t)r * cols;
+  float a0 = 0.f;
+  for (int j = threadIdx.x; j < cols; j += 256)
+    a0 = fmaf(__uint_as_float((uint32_t)row[j] << 16), __uint_as_float((uint32_t)bf16_bits(x[j]) << 16), a0);
+  const float s = block_sum(a0, sh);
+  if (threadIdx.x == 0) {
+    const float z = s + (b ? b[r] : 0.0f);
+    const float y = gelu_on ? gelu(z) : z;
+    if (out_f32) out_f32[r] = y;
+    if (out_bf16) out_bf16[r] = bf16_bits(y);
   }
 }
 
-// Forecast change in physical units: d = y * std (0 without a forecast,
-// y == nullptr) and the forecast modes m_last + d.
-__global__ __launch_bounds__(256) void denorm_kernel(const float *y, const float *m_last, const float *std_,
-                                                     int n_modes, float *d, float *mhat) {
+// Predictor history: with a previous frame (push != 0), shift the window by
+// one frame and append the normalised change (m - m_prev - mean) / std; then
+// m_prev = m.
+__global__ __launch_bounds__(256) void history_push_kernel(float *hist, int history, int n_modes, const float *m,
+                                                           float *m_prev, const float *mean, const float *inv_std,
+                                                           int push) {
   const int j = blockIdx.x * 256 + threadIdx.x;
   if (j < n_modes) {
-    const float dj = y ? y[j] * std_[j] : 0.0f;
+    if (push) {
+      for (int h = 0; h + 1 < history; ++h) hist[(int64_t)h * n_modes + j] = hist[(int64_t)(h + 1) * n_modes + j];
+      hist[(int64_t)(history - 1) * n_modes + j] = (m[j] - m_prev[j] - mean[j]) * inv_std[j];
+    }
+    m_prev[j] = m[j];
+  }
+}
+
+// Forecast change in physical units: d = y * std + mean (0 without a
+// forecast, y == nullptr) and the forecast modes m_last + d.
+__global__ __launch_bounds__(256) void denorm_kernel(const float *y, const float *m_last, const float *mean,
+                                                     const float *std_, int n_modes, float *d, float *mhat) {
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j < n_modes) {
+    const float dj = y ? fmaf(y[j], std_[j], mean[j]) : 0.0f;
     d[j] = dj;
     mhat[j] = m_last[j] + dj;
   }
@@ -267,19 +305,27 @@ hipError_t launch_adam(float *theta, float *m, float *v, const float *grad, uint
 hipError_t launch_gemv_f32(const float *A, int64_t lda, const float *x, int rows, int cols, float alpha, float beta,
                            float *y, hipStream_t st) {
   if (rows <= 0) return hipSuccess;
-  gemv_f32_kernel<<<(rows + 3) / 4, 256, 0, st>>>(A, lda, x, rows, cols, alpha, beta, y);
+  gemv_f32_kernel<<<rows, 256, 0, st>>>(A, lda, x, rows, cols, alpha, beta, y);
   return hipGetLastError();
 }
 
-hipError_t launch_history_push(float *hist, int history, int n_modes, const float *m, const float *mean,
-                               const float *inv_std, hipStream_t st) {
-  history_push_kernel<<<(n_modes + 255) / 256, 256, 0, st>>>(hist, history, n_modes, m, mean, inv_std);
+hipError_t launch_gemv_bf16(const uint16_t *W, const float *x, const float *b, int rows, int cols, int gelu_on,
+                            float *out_f32, uint16_t *out_bf16, hipStream_t st) {
+  if (rows <= 0) return hipSuccess;
+  gemv_bf16_kernel<<<rows, 256, 0, st>>>(W, x, b, rows, cols, gelu_on, out_f32, out_bf16);
   return hipGetLastError();
 }
 
-hipError_t launch_denorm(const float *y, const float *m_last, const float *std_, int n_modes, float *d, float *mhat,
-                         hipStream_t st) {
-  denorm_kernel<<<(n_modes + 255) / 256, 256, 0, st>>>(y, m_last, std_, n_modes, d, mhat);
+hipError_t launch_history_push(float *hist, int history, int n_modes, const float *m, float *m_prev,
+                               const float *mean, const float *inv_std, int push, hipStream_t st) {
+  history_push_kernel<<<(n_modes + 255) / 256, 256, 0, st>>>(hist, history, n_modes, m, m_prev, mean, inv_std,
+                                                              push);
+  return hipGetLastError();
+}
+
+hipError_t launch_denorm(const float *y, const float *m_last, const float *mean, const float *std_, int n_modes,
+                         float *d, float *mhat, hipStream_t st) {
+  denorm_kernel<<<(n_modes + 255) / 256, 256, 0, st>>>(y, m_last, mean, std_, n_modes, d, mhat);
   return hipGetLastError();
 }
 

@@ -17,9 +17,9 @@ the telescope.
 
 Data flow of one frame k (slopes r_k measured with commands c_{k-1} applied):
     integrator:  c_k = c_{k-1} + g R r_k
-    predictive:  m_k = P r_k + (P D) c_{k-1}                    (POL modes)
-                 d_k = std network(last frames' normalised m)   (forecast m_{k+1} - m_k)
-                 c_k = c_{k-1} + g R (r_k + P^T d_k / g)        (the same integrator)
+    predictive:  m_k = P r_k + (P D) c_{k-1}                      (POL modes)
+                 d_k = network(last normalised changes of m)      (forecast m_{k+1} - m_k)
+                 c_k = c_{k-1} + g R (r_k + P^T d_k / g)          (the same integrator)
 A zero forecast leaves the plain integrator, which is therefore the fallback.
 """
 from __future__ import annotations
@@ -90,14 +90,22 @@ def pol_modes(residual: torch.Tensor, cmd_prev: torch.Tensor, P: torch.Tensor, P
     return residual @ P.T + cmd_prev @ PD.T
 
 
-def windows(z: torch.Tensor, history: int):
-    """Inputs [F - history, history n_modes] (oldest first) and targets [F - history, n_modes]:
-    the change of the normalised modes from the window's last frame to the next frame."""
-    F, nm = z.shape
-    idx = torch.arange(F - history, device=z.device)[:, None] + torch.arange(history, device=z.device)[None, :]
-    x = z[idx].reshape(F - history, history * nm)
-    y = z[history:] - z[history - 1:F - 1]
-    return x.contiguous(), y.contiguous()
+def change_stats(m: torch.Tensor):
+    """Mean and std of the per-frame changes of the modes [F, n_modes]."""
+    dm = m[1:] - m[:-1]
+    return dm.mean(dim=0), dm.std(dim=0)
+
+
+def windows(m: torch.Tensor, history: int, mean: torch.Tensor, std: torch.Tensor):
+    """Training pairs from one segment of modes m [F, n_modes]: inputs [F - 1 - history,
+    history n_modes] (the last ``history`` normalised changes, oldest first) and
+    targets (the next normalised change)."""
+    z = ((m[1:] - m[:-1] - mean) / std).contiguous()
+    F1, nm = z.shape
+    n = F1 - history
+    idx = torch.arange(n, device=z.device)[:, None] + torch.arange(history, device=z.device)[None, :]
+    x = z[idx].reshape(n, history * nm)
+    return x.contiguous(), z[history:].contiguous()
 
 
 def init_params(n_in: int, n_hidden: int, n_out: int, seed: int):

@@ -112,26 +112,32 @@ def test_predictor_step_matches_oracle():
     with rtc.MlpNet(hist * nm, hid, nm, 4) as net:
         net.set_params(*params)
         pred = rtc.Predictor(net, hist, P, PD, mean, std, gain)
-        window = []
+        state = {}
+        m_prev_err = None
         r_out = torch.empty(ns, device="cuda:0")
         modes = torch.empty(2 * nm, device="cuda:0")
-        for k in range(6):
+        for k in range(7):
             r = rng.standard_normal(ns).astype(np.float32)
             c_prev = (rng.standard_normal(na) * 0.3).astype(np.float32)
             pred.step(_d(r), _d(c_prev), r_out, modes)
             torch.cuda.synchronize()
-            r_ref, m_ref, mhat_ref, window = pr.predictor_step(params, window, r, c_prev, P, PD, mean, std, hist,
-                                                               gain)
+            r_ref, m_ref, mhat_ref, state = pr.predictor_step(params, state, r, c_prev, P, PD, mean, std, hist,
+                                                              gain)
+            window = state["window"]
             got_m = modes.cpu().numpy()[:nm].astype(np.float64)
             got_mhat = modes.cpu().numpy()[nm:].astype(np.float64)
             em = 1.5 * (ns + na) * U * (np.abs(P) @ np.abs(r) + np.abs(PD) @ np.abs(c_prev)) + U * np.abs(m_ref)
             assert np.all(np.abs(got_m - m_ref) <= em)
+            em_max = em if m_prev_err is None else np.maximum(em, m_prev_err)
+            m_prev_err = em
             d_ref = mhat_ref - m_ref
             if len(window) < hist:
                 ed = np.zeros(nm)
-            else:                                            # network on the normalised window
+            else:                                            # network on the normalised changes
                 X = np.concatenate(window)[None, :]
-                eX = np.concatenate([em / std] * hist)[None, :] * 2 + 4 * U * np.abs(X)
+                # a change carries the errors of two projections; earlier frames' errors are
+                # bounded by the largest seen (inputs of the same scale)
+                eX = np.concatenate([2 * em_max / std] * hist)[None, :] * 2 + 4 * U * np.abs(X)
                 f, e = forward_bounds(params, X, eX)
                 ed = e["Y"][0] * std + 2 * U * np.abs(d_ref)
             assert np.all(np.abs(got_mhat - mhat_ref) <= em + ed + U * np.abs(mhat_ref)), k

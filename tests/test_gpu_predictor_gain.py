@@ -47,24 +47,22 @@ def test_trained_predictor_beats_the_integrator():
         ol.append(s[::10])
     P = kl_basis(torch.cat(ol[:N_TRAIN]), N_MODES).to(dev)
     PD = P @ D
-    z_all = [predict.pol_modes(r, c, P, PD) for r, c in zip(res, cprev)]
-    ztrain = torch.cat(z_all[:N_TRAIN])
-    mean, std = ztrain.mean(dim=0), ztrain.std(dim=0)
-    norm = lambda z: ((z - mean) / std).contiguous()
-    xs, ys = zip(*[predict.windows(norm(z), HISTORY) for z in z_all[:N_TRAIN]])
+    m_all = [predict.pol_modes(r, c, P, PD) for r, c in zip(res, cprev)]
+    mean, std = predict.change_stats(torch.cat(m_all[:N_TRAIN]))
+    xs, ys = zip(*[predict.windows(m, HISTORY, mean, std) for m in m_all[:N_TRAIN]])
     x, y = torch.cat(xs), torch.cat(ys)
-    xv, yv = predict.windows(norm(z_all[N_TRAIN]), HISTORY)
+    xv, yv = predict.windows(m_all[N_TRAIN], HISTORY, mean, std)
 
     net = rtc.MlpNet(HISTORY * N_MODES, HIDDEN, N_MODES, 256)
     net.set_params(*predict.init_params(HISTORY * N_MODES, HIDDEN, N_MODES, seed=5))
     before = predict.evaluate(net, xv, yv, 256)
-    persist = float((yv ** 2).mean().item())          # forecast = last frame (zero change)
+    persist = float(((xv[:, -N_MODES:] - yv) ** 2).mean().item())   # forecast = the last change again
     hist = predict.train(net, x, y, epochs=8, batch=256, lr=2e-3, seed=6, x_val=xv, y_val=yv)
     after = hist[-1]["val_loss"]
-    print(f"validation MSE (normalised modes): untrained {before:.4f}, last-frame {persist:.4f}, "
+    print(f"validation MSE (normalised changes): untrained {before:.4f}, last change {persist:.4f}, "
           f"trained {after:.4f}", flush=True)
     # the network starts near "no change" (small output layer); training must beat
-    # both that and the last-frame forecast
+    # both that and repeating the last change
     assert after < before and after < 0.9 * persist
 
     # judge on a held-out segment

@@ -88,16 +88,20 @@ def test_predictor_step_warm_up_and_forecast():
     nm, ns, na, hist, gain = 3, 8, 5, 2, 0.5
     P = np.linalg.qr(rng.standard_normal((ns, nm)))[0].T             # orthonormal rows
     PD = rng.standard_normal((nm, na))
-    mean, std = rng.standard_normal(nm), 1.0 + rng.random(nm)
+    mean, std = rng.standard_normal(nm) * 0.1, 1.0 + rng.random(nm)
     params = [np.zeros((4, hist * nm)), np.zeros(4), np.zeros((nm, 4)), np.full(nm, 0.5)]
-    r, c0 = rng.standard_normal(ns), rng.standard_normal(na)
-    r2, m, mhat, w = pr.predictor_step(params, [], r, c0, P, PD, mean, std, hist, gain, rounding=False)
-    assert np.allclose(m, P @ r + PD @ c0) and np.array_equal(mhat, m)   # window not full: no change
-    assert np.array_equal(r2, r)                                          # the plain integrator's slopes
-    r2, m2, mhat, w = pr.predictor_step(params, w, r, c0, P, PD, mean, std, hist, gain, rounding=False)
-    # zero weights: the network outputs b2 = 0.5, so the forecast change is 0.5 std
-    d = 0.5 * std
-    assert np.allclose(mhat, m2 + d) and len(w) == hist
-    assert np.allclose(w[-1], (m2 - mean) / std)
+    st = {}
+    ms = []
+    for k in range(hist + 1):                      # history changes need history + 1 frames
+        r, c0 = rng.standard_normal(ns), rng.standard_normal(na)
+        r2, m, mhat, st = pr.predictor_step(params, st, r, c0, P, PD, mean, std, hist, gain, rounding=False)
+        ms.append(m)
+        assert np.allclose(m, P @ r + PD @ c0)
+        if k < hist:                                # warm-up: no forecast, the plain integrator's slopes
+            assert np.array_equal(mhat, m) and np.array_equal(r2, r)
+    # zero weights: the network outputs b2 = 0.5, so the forecast change is 0.5 std + mean
+    d = 0.5 * std + mean
+    assert np.allclose(mhat, ms[-1] + d) and len(st["window"]) == hist
+    assert np.allclose(st["window"][-1], (ms[-1] - ms[-2] - mean) / std)
     # the integrator's extra command for these slopes is g R P^T d / g = R P^T d
     assert np.allclose(P @ (r2 - r), d / gain)

@@ -332,6 +332,95 @@ rtc_status rtc_autotune(rtc_ctx *c, int32_t n_frames, const uint16_t *d_pixels, 
                         float *d_cmd, rtc_tune_result *results, int32_t max_results, int32_t *n_results,
                         void *hip_stream);
 
+/* ---- Pixel-stream processing (Section 2.3.6 and Figure 6; the latency
+ * measurements of Section 3.2, Figures 11 and 12) ----
+ *
+ * The frame is processed while its pixels arrive.  A camera emulator inside
+ * the launch lands the rows of each frame in a two-slot ring held by the
+ * context: rows of frame f land uniformly over readout_us from the frame's
+ * scheduled start f * frame_period_us (after a short lead), in packets of
+ * rows_per_packet rows, each packet followed by a landed-row count.  The
+ * other workgroups are workers (the paper's processing threads, horizontal
+ * strategy): worker b owns a contiguous run of subapertures in arrival
+ * order, and as soon as the rows a group of them needs have landed it
+ * calibrates and centroids them and multiplies their slopes into the matching
+ * columns of the control matrix, accumulating a partial actuator vector.  The
+ * P partial vectors are summed per actuator in a fixed order (blocks of 64
+ * workers, each a wavefront tree: the parallel vector addition of Section
+ * 2.3.5 and Figure 5), block by block as soon as a block has published, and
+ * the integrator is applied.  Latency, as in the paper, is the time from the
+ * last pixel of a frame landing to its last command being written.
+ *
+ * Subaperture allocation: counts decrease linearly from the first worker to
+ * the last with first / last = alloc_ratio (1 = equal shares, Figure 6 (c);
+ * > 1 = unequal, Figure 6 (d)), so workers whose pixels arrive last have the
+ * least to do after the last pixel.  full_frame = 1 makes every subaperture
+ * wait for the whole frame (no pixel-stream processing) for comparison.
+ *
+ * Tail: the subapertures of the last tail_rows subaperture rows (at most 64)
+ * are left out of the allocation; instead every worker calibrates them itself
+ * once their rows land and multiplies their slopes into its own actuator rows
+ * (a row split of those columns, from LDS), so that after the last pixel no
+ * partial vector has to travel between workgroups.
+ * Results do not depend on the allocation or the tail beyond float32
+ * rounding order. */
+typedef struct {
+  int32_t n_workers;           /* worker workgroups, 0 = compute units - 1; one more runs the camera */
+  int32_t full_frame;          /* 0 or 1 */
+  double alloc_ratio;          /* subapertures of the first worker / of the last, in [1, 1000] */
+  double frame_period_us;      /* camera frame period, (0, 1e6] */
+  double readout_us;           /* (0, frame_period_us] */
+  int32_t rows_per_packet;     /* >= 1 */
+  int32_t wait_limit_us;       /* a wait gives up after this long; 0 = 2 frame periods + 50 ms */
+  int32_t tail_rows;           /* subaperture rows at the bottom of the frame taken by every worker, 0..n_sub_y */
+  int32_t reserved;            /* 0 */
+} rtc_pipe_config;
+
+/* Linearly decreasing allocation (host only, no device): counts[b] for b <
+ * n_workers, summing to n_subaps.  Target shares are proportional to
+ * w_b = ratio + (1 - ratio) b / (n_workers - 1) (w = 1 for one worker); each
+ * count is the floor of its share, and the remaining subapertures go one each
+ * to the largest fractional parts (ties to the lower index).  Errors:
+ * RTC_E_ARG for n_subaps < 0, n_workers < 1, ratio outside [1, 1000] or NaN,
+ * NULL counts. */
+rtc_status rtc_pipe_allocation(int32_t n_subaps, int32_t n_workers, double ratio, int32_t *counts);
+
+/* Prepares pixel-stream processing of a single-sensor context: copies the
+ * stored control matrix column-major (x and y columns of each subaperture
+ * adjacent, any storage format), the allocation and the rows each
+ * subaperture needs (its last pixel row + 1, or every row with full_frame),
+ * and allocates the ring, partial vectors and counters.  Call after
+ * rtc_load_cmat, and again after each new matrix.  Synchronous.  Errors:
+ * RTC_E_STATE without a matrix; RTC_E_ARG for a config out of range;
+ * RTC_E_UNSUPPORTED for several sensors, n_act > 8192, more than 64 actuator
+ * rows per worker, more than 64 tail subapertures or an odd frame size;
+ * RTC_E_NOMEM / RTC_E_DEVICE. */
+rtc_status rtc_pipe_setup(rtc_ctx *c, const rtc_pipe_config *cfg);
+
+/* Shape chosen by rtc_pipe_setup (any pointer may be NULL): workers, matrix
+ * columns per worker kept in LDS, image rows, most subapertures of a worker,
+ * tail subapertures. */
+rtc_status rtc_pipe_info(const rtc_ctx *c, int32_t *n_workers, int32_t *lds_cols, int32_t *image_rows,
+                         int32_t *max_subaps, int32_t *n_tail);
+
+/* Runs n_frames frames through the camera emulator and the workers in one
+ * launch on hip_stream (asynchronous).  d_frames: n_frames source frames,
+ * frame_stride (even, >= rtc_frame_elems) elements apart, 4-byte aligned;
+ * they are copied row by row into the ring as they "arrive".  Outputs as
+ * rtc_frame_batch (d_cmd [n_frames][n_act]; d_slopes, d_recon, d_counts
+ * nullable).  Time stamps (device wall clock, rtc_wall_clock_khz ticks,
+ * nullable): d_cam_ts [n_frames][4] = scheduled frame start, first packet
+ * landed, last packet landed (the last pixel), largest delay of a packet
+ * behind its schedule; d_worker_ts [n_frames][n_workers][2] = worker's
+ * partial vector published, its actuator rows integrated.  The integrator
+ * state carries across calls and frame modes.  A wait that exceeds
+ * wait_limit_us gives up, and the batch stops early; rtc_sync_check reports
+ * it.  Errors: RTC_E_STATE before rtc_pipe_setup or after a new
+ * matrix; RTC_E_ARG for bad arguments; RTC_E_DEVICE when the launch fails. */
+rtc_status rtc_pipe_run(rtc_ctx *c, int32_t n_frames, const uint16_t *d_frames, int64_t frame_stride,
+                        float *d_cmd, float *d_slopes, float *d_recon, int32_t *d_counts, uint64_t *d_cam_ts,
+                        uint64_t *d_worker_ts, void *hip_stream);
+
 /* Synchronises the device and reports RTC_E_DEVICE if a persistent batch gave
  * up at a barrier since the last check (the flag is then cleared). */
 rtc_status rtc_sync_check(rtc_ctx *c);

@@ -23,86 +23,11 @@
 #include "../../include/rtc.h"
 #include "rtc_kernels.h"
 
-// One wavefront sensor of a context.
-struct WfsInfo {
-  int32_t n_sub_x = 0, n_sub_y = 0, n_pix = 0, H = 0, W = 0;
-  int64_t frame_off = 0;   // first element of its frame in the frame set
-  int32_t tile_base = 0;   // its first subaperture
-  int32_t n_tiles = 0;
-};
+#include "rtc_ctx.h"
 
-struct rtc_ctx {
-  rtc_config cfg{};        // abi_version, n_act, thr_mode, cm_dtype, gain, leak, clamp, device
-  int device = 0;
-  int32_t n_valid = 0, n_slopes = 0, n_s4 = 0, n_act = 0;
-  std::vector<WfsInfo> wfs;
-  int64_t frame_elems = 0;  // elements of one frame set
-  int32_t max_n = 0;        // largest pixels per side
-  int32_t pairs = 0;        // every tile row starts on an even element and has even width
-  int64_t calib_len = 0;    // float2 elements of the per-tile calibration blocks
-  int64_t ldr = 0;        // float32 row length of the matrix (elements)
-  int64_t s_len = 0;      // slope / reference buffer length (elements)
-  int32_t fmt = 0;        // rtc_cm_dtype of the stored matrix
-  int64_t ldq = 0;        // stored row length (elements)
-  int32_t n_chunks = 0;   // 16-byte chunks per stored row
-  std::vector<rtck::TileDesc> tiles_h;
-  std::string err;
-  rtc_mvm_tuning tuning{RTC_MVM_ROWBLOCK, 1, 2, 4, 0, 8};
-  int32_t n_cu = 0;
-  int64_t wall_khz = 0;
-
-  rtck::TileDesc *d_tiles = nullptr;
-  float2 *d_calib = nullptr;
-  float *d_ref = nullptr;
-  void *d_R = nullptr;
-  float *d_scales = nullptr;
-  float *d_s = nullptr;
-  float *d_state = nullptr;
-  float *d_part = nullptr;
-  float *d_sbuf = nullptr;   // [2][s_len] slope vectors of consecutive frames (persistent batches)
-  uint32_t *d_sync = nullptr;  // rtck::sync_layout words: stamp counter, abort flags, persistent barrier
-  int32_t frame_mode = RTC_FRAMES_PER_LAUNCH;
-  int32_t spin_limit = 1 << 22;
-  uint64_t *d_trace = nullptr;  // caller-owned [trace_frames][trace_groups][8] stage stamps
-  int32_t trace_frames = 0;
-  int32_t trace_groups = 0;
-  hipGraphExec_t graph = nullptr;  // recorded frame batch (rtc_graph_capture)
-  bool calib_loaded = false;
-  bool cmat_loaded = false;
-};
+using namespace rtcx;
 
 namespace {
-
-thread_local std::string g_init_err = "no error";
-
-rtc_status fail(rtc_ctx *c, rtc_status s, const std::string &msg) {
-  if (c) c->err = msg; else g_init_err = msg;
-  return s;
-}
-
-rtc_status hip_fail(rtc_ctx *c, hipError_t e, const char *what) {
-  std::string m = std::string(what) + ": " + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ")";
-  return fail(c, e == hipErrorOutOfMemory ? RTC_E_NOMEM : RTC_E_DEVICE, m);
-}
-
-// Makes the context's device current for the scope and restores the caller's.
-struct DeviceScope {
-  int prev = -1;
-  hipError_t status = hipSuccess;
-  explicit DeviceScope(int dev) {
-    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-    status = hipSetDevice(dev);
-  }
-  ~DeviceScope() {
-    if (prev >= 0) (void)hipSetDevice(prev);
-  }
-};
-
-template <typename T>
-void dfree(T *&p) {
-  if (p) (void)hipFree(p);
-  p = nullptr;
-}
 
 bool dark_in_domain(float d) {
   // raw - dark is exact in float64 for every raw in [0, 65535] iff this holds.
@@ -491,6 +416,7 @@ rtc_status rtc_load_cmat(rtc_ctx *c, const float *R, int32_t n_act, int32_t n_sl
   c->d_R = d_R;
   c->d_scales = d_sc;
   c->cmat_loaded = true;
+  ++c->cmat_gen;
   return RTC_OK;
 }
 
@@ -902,8 +828,8 @@ rtc_status rtc_sync_check(rtc_ctx *c) {
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) return hip_fail(c, e, "rtc_sync_check");
   if (flag)
-    return fail(c, RTC_E_DEVICE, "rtc_sync_check: a persistent batch gave up at a frame barrier "
-                                 "(bounded wait expired); its later frames were not processed");
+    return fail(c, RTC_E_DEVICE, "rtc_sync_check: a persistent or pixel-stream batch gave up at a bounded "
+                                 "wait; its later frames were not processed");
   return RTC_OK;
 }
 
@@ -980,6 +906,12 @@ void rtc_destroy(rtc_ctx *c) {
   dfree(c->d_part);
   dfree(c->d_sbuf);
   dfree(c->d_sync);
+  dfree(c->d_packed);
+  dfree(c->d_ppart);
+  dfree(c->d_ring);
+  dfree(c->d_psync);
+  dfree(c->d_first);
+  dfree(c->d_need);
   if (c->graph) (void)hipGraphExecDestroy(c->graph);
   delete c;
 }

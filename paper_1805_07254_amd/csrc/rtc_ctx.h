@@ -1,0 +1,109 @@
+// Internal: the context object behind rtc_ctx* and the host helpers shared by
+// the C-ABI source files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/rtc.h"
+#include "rtc_kernels.h"
+
+// One wavefront sensor of a context.
+struct WfsInfo {
+  int32_t n_sub_x = 0, n_sub_y = 0, n_pix = 0, H = 0, W = 0;
+  int64_t frame_off = 0;   // first element of its frame in the frame set
+  int32_t tile_base = 0;   // its first subaperture
+  int32_t n_tiles = 0;
+};
+
+struct rtc_ctx {
+  rtc_config cfg{};        // abi_version, n_act, thr_mode, cm_dtype, gain, leak, clamp, device
+  int device = 0;
+  int32_t n_valid = 0, n_slopes = 0, n_s4 = 0, n_act = 0;
+  std::vector<WfsInfo> wfs;
+  int64_t frame_elems = 0;  // elements of one frame set
+  int32_t max_n = 0;        // largest pixels per side
+  int32_t pairs = 0;        // every tile row starts on an even element and has even width
+  int64_t calib_len = 0;    // float2 elements of the per-tile calibration blocks
+  int64_t ldr = 0;        // float32 row length of the matrix (elements)
+  int64_t s_len = 0;      // slope / reference buffer length (elements)
+  int32_t fmt = 0;        // rtc_cm_dtype of the stored matrix
+  int64_t ldq = 0;        // stored row length (elements)
+  int32_t n_chunks = 0;   // 16-byte chunks per stored row
+  std::vector<rtck::TileDesc> tiles_h;
+  std::string err;
+  rtc_mvm_tuning tuning{RTC_MVM_ROWBLOCK, 1, 2, 4, 0, 8};
+  int32_t n_cu = 0;
+  int64_t wall_khz = 0;
+
+  rtck::TileDesc *d_tiles = nullptr;
+  float2 *d_calib = nullptr;
+  float *d_ref = nullptr;
+  void *d_R = nullptr;
+  float *d_scales = nullptr;
+  float *d_s = nullptr;
+  float *d_state = nullptr;
+  float *d_part = nullptr;
+  float *d_sbuf = nullptr;   // [2][s_len] slope vectors of consecutive frames (persistent batches)
+  uint32_t *d_sync = nullptr;  // rtck::sync_layout words: stamp counter, abort flags, persistent barrier
+  int32_t frame_mode = RTC_FRAMES_PER_LAUNCH;
+  int32_t spin_limit = 1 << 22;
+  uint64_t *d_trace = nullptr;  // caller-owned [trace_frames][trace_groups][8] stage stamps
+  int32_t trace_frames = 0;
+  int32_t trace_groups = 0;
+  hipGraphExec_t graph = nullptr;  // recorded frame batch (rtc_graph_capture)
+  bool calib_loaded = false;
+  bool cmat_loaded = false;
+  uint64_t cmat_gen = 0;           // bumped by every rtc_load_cmat
+
+  // pixel-stream processing (rtc_pipe_setup)
+  uint64_t pipe_gen = 0;           // cmat_gen the packed columns were made from; 0 = not set up
+  rtc_pipe_config pipe_cfg{};
+  int32_t pipe_workers = 0, pipe_lds_cols = 0, pipe_max_nb = 0, pipe_H = 0, pipe_W = 0;
+  int32_t pipe_n_tail = 0, pipe_own_max = 0;
+  int64_t pipe_ldp = 0, pipe_ring_stride = 0;
+  size_t pipe_lds = 0;
+  void *d_packed = nullptr;        // [2 n_valid][ldp] codes
+  float *d_ppart = nullptr;        // [2][workers][ldp]
+  uint16_t *d_ring = nullptr;      // [2][ring_stride]
+  uint32_t *d_psync = nullptr;     // rtck::pipe_layout words
+  int32_t *d_first = nullptr;      // [workers + 1]
+  int32_t *d_need = nullptr;       // [n_valid]
+};
+
+namespace rtcx {
+
+inline thread_local std::string g_init_err = "no error";
+
+inline rtc_status fail(rtc_ctx *c, rtc_status s, const std::string &msg) {
+  if (c) c->err = msg; else g_init_err = msg;
+  return s;
+}
+
+inline rtc_status hip_fail(rtc_ctx *c, hipError_t e, const char *what) {
+  std::string m = std::string(what) + ": " + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ")";
+  return fail(c, e == hipErrorOutOfMemory ? RTC_E_NOMEM : RTC_E_DEVICE, m);
+}
+
+// Makes the context's device current for the scope and restores the caller's.
+struct DeviceScope {
+  int prev = -1;
+  hipError_t status = hipSuccess;
+  explicit DeviceScope(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    status = hipSetDevice(dev);
+  }
+  ~DeviceScope() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+template <typename T>
+inline void dfree(T *&p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
+}  // namespace rtcx

@@ -125,6 +125,82 @@ constexpr int kWords = kBarBase + kEnds + 4 * kMaxGroups;
 // when the grid cannot be co-resident.
 hipError_t launch_frames(const PersistArgs &p, int blocks, int rows_per_batch, hipStream_t st);
 
+// Pixel-stream frames: a camera workgroup lands the rows of each frame in a
+// two-slot ring on a schedule (rows of frame f land uniformly over the readout
+// time from f * frame period on) and publishes a landed-row counter; every
+// other workgroup (a worker) owns a contiguous run of subapertures in arrival
+// order and, as soon as their rows have landed, calibrates them, centroids
+// them and multiplies their slopes into the matching columns of the control
+// matrix (a partial actuator vector).  Worker b also owns actuator rows
+// [b n_act / P, (b+1) n_act / P): it sums the P partial vectors of those rows
+// (fixed order) and applies the integrator.
+namespace pipe_layout {
+constexpr int kStride = 1024;                     // 4 KiB between counters
+constexpr int kRowCopies = 16;                    // landed-row counter copies, worker b polls copy b % 16
+constexpr int kFlags = kRowCopies * kStride;      // + 16 * worker: frames whose partial vector is published
+constexpr int kMaxWorkers = 1024;
+constexpr int kOwnDone = kFlags + 16 * kMaxWorkers;   // workers done with a frame (all their rows integrated)
+constexpr int kWords = kOwnDone + kStride;
+constexpr int kMaxQuadsPerThread = 4;             // packed column length <= 4 * 4 * 512 codes
+constexpr int kCamStamps = 4;                     // per frame: scheduled start, first rows, last rows, worst slip
+}  // namespace pipe_layout
+
+struct PipeArgs {
+  const TileDesc *tiles;   // [n_valid] (one sensor: off is relative to the frame start)
+  const float2 *calib;
+  const float *ref;
+  int32_t n_valid;
+  int32_t max_n;
+  int32_t mode;            // 1 = subtract, 2 = zero
+  int32_t fmt;             // storage format of the packed columns
+  // camera
+  const uint16_t *src;     // [n_frames] frames, src_stride elements apart, 4-byte aligned
+  int64_t src_stride;
+  uint16_t *ring;          // [2][ring_stride] landing slots
+  int64_t ring_stride;     // elements, multiple of 128
+  int64_t frame_elems;     // even
+  int32_t H, W;            // image rows and row length (elements)
+  int32_t rows_per_packet;
+  int32_t n_frames;
+  double t_frame, t_row;   // wall-clock ticks
+  int64_t lead;            // ticks from the camera's start to frame 0
+  int64_t wait_ticks;      // a wait gives up after this long
+  // workers
+  const int32_t *first;    // [P + 1] first subaperture of each worker
+  const int32_t *need;     // [n_valid] image rows a subaperture needs
+  const void *packed;      // [2 n_valid][ldp] codes: column 2k = x slope of subaperture k, 2k + 1 = y slope
+  int64_t ldp;             // codes per packed column, multiple of 64
+  int32_t lds_cols;        // trailing columns of a worker kept in LDS
+  int32_t max_nb;          // most subapertures of a worker
+  int32_t n_tail;          // subapertures [n_valid - n_tail, n_valid): every worker processes them for its own rows
+  int32_t own_max;         // most actuator rows of a worker
+  int32_t n_act;
+  const float *scales;     // nullable [n_act]
+  float *state;            // [n_act]
+  float *cmd;              // [n_frames][n_act]
+  float *recon;            // nullable [n_frames][n_act]
+  float gain, leak, cmd_min, cmd_max;
+  float *part;             // [2][P][ldp] partial actuator vectors
+  float *s_user;           // nullable [n_frames][2 n_valid]
+  int32_t *counts;         // nullable [n_frames][n_valid]
+  uint32_t *sync;          // pipe_layout words (zeroed per launch)
+  uint32_t *abort_flag;    // zeroed per launch
+  uint32_t *sticky;
+  uint64_t *cam_ts;        // nullable [n_frames][kCamStamps]
+  uint64_t *wk_ts;         // nullable [n_frames][P][2]: partial published, rows integrated
+};
+// G = P + 1 workgroups of 512 threads; lds_bytes of dynamic LDS per workgroup.
+hipError_t launch_pipe(const PipeArgs &p, int G, size_t lds_bytes, hipStream_t st);
+// LDS bytes a worker needs besides its columns.
+size_t pipe_lds_fixed(int max_nb, int n_tail, int own_max);
+constexpr int kPipeMaxTail = 64;                   // tail subapertures (two slope columns per lane)
+// Bytes per code of a storage format (4, 2, 2, 1).
+int format_code_bytes(int fmt);
+// packed[(2k + h) ldp + r] = code of row r, slope column (h ? tiles[k].sy : tiles[k].sx); rows
+// n_act..ldp-1 zero.
+hipError_t launch_pack_columns(const void *Rq, int64_t ldq_bytes, int fmt, const TileDesc *tiles, int n_valid,
+                               int n_act, void *packed, int64_t ldp, hipStream_t st);
+
 // Roofline probes.
 hipError_t launch_probe_copy(const void *src, void *dst, int64_t n_bytes, hipStream_t st);
 hipError_t launch_probe_read(const void *src, int64_t n_bytes, float *out, hipStream_t st);

@@ -66,6 +66,13 @@ class rtc_tune_result(ctypes.Structure):
     _fields_ = [("frame_mode", ctypes.c_int32), ("tuning", rtc_mvm_tuning), ("us_per_frame", ctypes.c_float)]
 
 
+class rtc_pipe_config(ctypes.Structure):
+    _fields_ = [("n_workers", ctypes.c_int32), ("full_frame", ctypes.c_int32), ("alloc_ratio", ctypes.c_double),
+                ("frame_period_us", ctypes.c_double), ("readout_us", ctypes.c_double),
+                ("rows_per_packet", ctypes.c_int32), ("wait_limit_us", ctypes.c_int32),
+                ("tail_rows", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
 _vp, _i32, _i64, _f32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_float
 _SIGNATURES = {
     "rtc_init": (_i32, [ctypes.POINTER(rtc_config), ctypes.POINTER(_vp)]),
@@ -91,6 +98,10 @@ _SIGNATURES = {
     "rtc_pred_destroy": (None, [_vp]),
     "rtc_pred_error_string": (ctypes.c_char_p, [_vp]),
     "rtc_autotune": (_i32, [_vp, _i32, _vp, _i64, _vp, _vp, _i32, ctypes.POINTER(_i32), _vp]),
+    "rtc_pipe_allocation": (_i32, [_i32, _i32, ctypes.c_double, _vp]),
+    "rtc_pipe_setup": (_i32, [_vp, ctypes.POINTER(rtc_pipe_config)]),
+    "rtc_pipe_info": (_i32, [_vp] + [ctypes.POINTER(_i32)] * 5),
+    "rtc_pipe_run": (_i32, [_vp, _i32, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "rtc_load_cmat": (_i32, [_vp, _vp, _i32, _i32, _i64]),
     "rtc_encode_cmat": (_i32, [_i32, _vp, _i32, _i32, _i64, _vp, _vp]),
     "rtc_frame": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
@@ -470,6 +481,49 @@ def rtc_autotune(ctx: RtcContext, n_frames: int, pixels, cmd, frame_stride: Opti
         out.append({"frame_mode": r.frame_mode, "us_per_frame": r.us_per_frame,
                     "tuning": {name: getattr(r.tuning, name) for name, _ in rtc_mvm_tuning._fields_}})
     return out
+
+
+def rtc_pipe_allocation(n_subaps: int, n_workers: int, ratio: float) -> np.ndarray:
+    """Linearly decreasing subaperture counts per worker (host only)."""
+    counts = np.zeros(max(n_workers, 1), dtype=np.int32)
+    _check(load_library().rtc_pipe_allocation(n_subaps, n_workers, float(ratio), counts.ctypes.data), None)
+    return counts
+
+
+def rtc_pipe_setup(ctx: RtcContext, n_workers: int = 0, full_frame: bool = False, alloc_ratio: float = 1.0,
+                   frame_period_us: float = 1000.0, readout_us: Optional[float] = None,
+                   rows_per_packet: int = 2, wait_limit_us: int = 0, tail_rows: int = 0) -> None:
+    cfg = rtc_pipe_config(n_workers=n_workers, full_frame=1 if full_frame else 0, alloc_ratio=float(alloc_ratio),
+                          frame_period_us=float(frame_period_us),
+                          readout_us=float(frame_period_us if readout_us is None else readout_us),
+                          rows_per_packet=rows_per_packet, wait_limit_us=wait_limit_us, tail_rows=tail_rows,
+                          reserved=0)
+    _check(load_library().rtc_pipe_setup(ctx.handle, ctypes.byref(cfg)), ctx)
+
+
+def rtc_pipe_info(ctx: RtcContext) -> dict:
+    v = [ctypes.c_int32(0) for _ in range(5)]
+    _check(load_library().rtc_pipe_info(ctx.handle, *[ctypes.byref(x) for x in v]), ctx)
+    return {"n_workers": v[0].value, "lds_cols": v[1].value, "image_rows": v[2].value, "max_subaps": v[3].value,
+            "n_tail": v[4].value}
+
+
+def rtc_pipe_run(ctx: RtcContext, n_frames: int, frames, cmd, slopes=None, recon=None, counts=None, cam_ts=None,
+                 worker_ts=None, frame_stride: Optional[int] = None, stream=None) -> None:
+    stride = ctx.frame_elems if frame_stride is None else frame_stride
+    need = 0 if n_frames == 0 else (n_frames - 1) * stride + ctx.frame_elems
+    n_workers = rtc_pipe_info(ctx)["n_workers"] if worker_ts is not None else 0
+    _check(load_library().rtc_pipe_run(
+        ctx.handle, n_frames,
+        _dev_ptr(frames, "uint16", need, "frames", ctx),
+        stride,
+        _dev_ptr(cmd, "float32", n_frames * ctx.n_act, "cmd", ctx),
+        _dev_ptr(slopes, "float32", n_frames * ctx.n_slopes, "slopes", ctx, False),
+        _dev_ptr(recon, "float32", n_frames * ctx.n_act, "recon", ctx, False),
+        _dev_ptr(counts, "int32", n_frames * ctx.n_valid, "counts", ctx, False),
+        _dev_ptr(cam_ts, ("uint64", "int64"), 4 * n_frames, "cam_ts", ctx, False),
+        _dev_ptr(worker_ts, ("uint64", "int64"), 2 * n_frames * n_workers, "worker_ts", ctx, False),
+        _stream_ptr(stream)), ctx)
 
 
 def rtc_get_frame_mode(ctx: RtcContext) -> int:

@@ -75,12 +75,15 @@ def parse():
     p.add_argument("--variants", default="f16,bf16,fp8e4m3",
                    help="reduced-precision matrix formats also timed (comma list, empty = none)")
     p.add_argument("--variant-steps", type=int, default=2000)
-    p.add_argument("--workload", default="elt-scao", choices=["elt-scao", "elt-multi", "elt-predict"],
+    p.add_argument("--workload", default="elt-scao", choices=["elt-scao", "elt-multi", "elt-predict", "elt-pipe"],
                    help="elt-scao: the single-sensor ELT frame (default); elt-multi: six 74x74 and three 16x16 "
                         "sensors reconstructed by one BF16 matrix")
     p.add_argument("--multi-steps", type=int, default=5000)
     p.add_argument("--multi-ring", type=int, default=4, help="distinct multi-sensor frame sets")
     p.add_argument("--multi-dtype", default="bf16")
+    p.add_argument("--pipe-frames", type=int, default=1000, help="camera frames per pixel-stream mode (elt-pipe)")
+    p.add_argument("--pipe-period-us", type=float, default=1000.0, help="camera frame period (elt-pipe)")
+    p.add_argument("--pipe-readout-us", type=float, default=1000.0, help="camera readout time (elt-pipe)")
     p.add_argument("--pred-frames", type=int, default=200000, help="closed-loop training frames (elt-predict)")
     p.add_argument("--pred-modes", type=int, default=500)
     p.add_argument("--pred-hidden", type=int, default=1024)
@@ -228,6 +231,118 @@ def run_multi(args):
     print(json.dumps(result), flush=True)
 
 
+def run_pipe(args):
+    """Pixel-stream processing at the ELT size: last-pixel -> last-command latency of a camera
+    emulated inside the launch, for full-frame processing, pixel-stream processing with equal
+    and linearly decreasing subaperture allocation, and with the tail band on every workgroup;
+    per-worker end of computation relative to the last pixel; and, for context, the
+    whole-frame time of the persistent kernel with the frame already in memory."""
+    import torch
+    from aosim import ELT, Scenario
+    from paper_1805_07254_amd import rtc
+    from paper_1805_07254_amd.stats import frame_stats, ticks_to_us
+
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    rtc.load_library()
+    t0 = time.time()
+    sc = Scenario(ELT)
+    cfg = sc.cfg
+    R = sc.control_matrix
+    n_ring = 16
+    ring = np.stack([sc.frame(k, sc.turbulence_slopes(k)) for k in range(n_ring)])
+    log(f"{cfg.name}: matrix and {n_ring} frames at {time.time() - t0:.0f}s")
+    ctx = rtc.rtc_init(sc.mask, cfg.n_pix, sc.n_act, gain=cfg.gain, leak=cfg.leak)
+    rtc.rtc_load_calib(ctx, sc.dark, sc.flat, cfg.threshold)
+    rtc.rtc_load_cmat(ctx, R)
+    khz = rtc.rtc_wall_clock_khz(ctx)
+    F = args.pipe_frames
+    ring16 = torch.from_numpy(ring.reshape(n_ring, -1).view(np.int16)).to("cuda:0")
+    frames = ring16[torch.arange(F, device="cuda:0") % n_ring].contiguous().view(torch.uint16)
+    cmd = torch.empty(F * sc.n_act, dtype=torch.float32, device="cuda:0")
+    skip = min(10, F // 10)
+
+    def mode(name, **kw):
+        rtc.rtc_reset(ctx)
+        rtc.rtc_pipe_setup(ctx, frame_period_us=args.pipe_period_us, readout_us=args.pipe_readout_us,
+                           rows_per_packet=2, **kw)
+        info = rtc.rtc_pipe_info(ctx)
+        P = info["n_workers"]
+        cam = torch.zeros(4 * F, dtype=torch.int64, device="cuda:0")
+        wk = torch.zeros(2 * F * P, dtype=torch.int64, device="cuda:0")
+        rtc.rtc_pipe_run(ctx, F, frames, cmd, cam_ts=cam, worker_ts=wk)
+        torch.cuda.synchronize()
+        rtc.rtc_sync_check(ctx)
+        cam = cam.cpu().numpy().reshape(F, 4)[skip:]
+        wk = wk.cpu().numpy().reshape(F, P, 2)[skip:]
+        last = cam[:, 2:3]
+        lat = ticks_to_us(wk[:, :, 1].max(axis=1) - cam[:, 2], khz)
+        part = ticks_to_us(wk[:, :, 0] - last, khz).mean(axis=0)          # per worker: partial published
+        done = ticks_to_us(wk[:, :info["n_owners"], 1] - last, khz).mean(axis=0)   # per owner: rows stored
+        st = frame_stats(lat)
+        rec = {"mode": name, **kw, "workers": P, "owners": info["n_owners"], "lds_cols": info["lds_cols"],
+               "tail_subaps": info["n_tail"],
+               "max_subaps_per_worker": info["max_subaps"], "latency_us": st,
+               "worker_partial_vs_last_pixel_us": {"last_worker": round(float(part[-1]), 2),
+                                                   "max": round(float(part.max()), 2),
+                                                   "median": round(float(np.median(part)), 2),
+                                                   "profile": [round(float(x), 1) for x in part]},
+               "owner_done_vs_last_pixel_us": {"max": round(float(done.max()), 2),
+                                                "min": round(float(done.min()), 2)},
+               "camera_slip_us": frame_stats(ticks_to_us(cam[:, 3], khz)),
+               "readout_us": frame_stats(ticks_to_us(cam[:, 2] - cam[:, 0], khz))}
+        log(f"{name}: latency p50 {st['p50_us']:.2f} us p99 {st['p99_us']:.2f} us rms {st['rms_jitter_us']:.2f} us; "
+            f"last worker's partial {part[-1]:+.1f} us vs last pixel; camera slip p99 "
+            f"{rec['camera_slip_us']['p99_us']:.1f} us")
+        return rec
+
+    modes = [mode("full frame, equal allocation", full_frame=True, alloc_ratio=1.0),
+             mode("pixel stream, equal allocation", alloc_ratio=1.0),
+             mode("pixel stream, linearly decreasing allocation", alloc_ratio=8.0),
+             mode("pixel stream, linearly decreasing allocation, tail band on every workgroup", alloc_ratio=8.0,
+                  tail_rows=1)]
+    sweep = []
+    keep = F
+    F = min(F, 300)
+    for ratio in (2.0, 4.0, 16.0):
+        r = mode(f"pixel stream, ratio {ratio:g}", alloc_ratio=ratio)
+        sweep.append({"alloc_ratio": ratio, "p50_us": r["latency_us"]["p50_us"], "p99_us": r["latency_us"]["p99_us"]})
+    for tail in (2, 3):
+        r = mode(f"pixel stream, ratio 8, tail {tail}", alloc_ratio=8.0, tail_rows=tail)
+        sweep.append({"alloc_ratio": 8.0, "tail_rows": tail, "p50_us": r["latency_us"]["p50_us"],
+                      "p99_us": r["latency_us"]["p99_us"]})
+    F = keep
+
+    # whole frame already in memory: the persistent kernel's frame span (start -> last command)
+    rtc.rtc_reset(ctx)
+    rtc.rtc_set_frame_mode(ctx, rtc.RTC_FRAMES_PERSISTENT)
+    ts = torch.zeros(2 * F, dtype=torch.int64, device="cuda:0")
+    rtc.rtc_frame_batch(ctx, F, frames, cmd, ts=ts)
+    torch.cuda.synchronize()
+    rtc.rtc_sync_check(ctx)
+    st = ts.cpu().numpy().reshape(F, 2)[skip:]
+    whole = frame_stats(ticks_to_us(st[:, 1] - st[:, 0], khz))
+    rtc.rtc_destroy(ctx)
+    best = modes[-1]["latency_us"]
+    result = {
+        "metric": "ELT-SCAO last pixel -> DM command latency with pixel-stream processing (us)",
+        "value": round(best["p50_us"], 3), "unit": "us", "n_gpus": 1, "steps": args.pipe_frames, "warmup": skip,
+        "ms_per_step": args.pipe_period_us / 1e3, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{cfg.name}: {sc.n_valid} subapertures (10x10 px, 740x740 frame), {sc.n_act} "
+                               f"actuators, f32 matrix; camera emulated in the launch: {args.pipe_period_us:g} us "
+                               f"frame period, rows landing uniformly over {args.pipe_readout_us:g} us, 2-row packets",
+                   "distinct_frames": n_ring},
+        "p99_us": round(best["p99_us"], 3), "rms_jitter_us": round(best["rms_jitter_us"], 3),
+        "modes": modes, "sweep": sweep,
+        "whole_frame_in_memory_persistent_span_us": whole,
+        "paper_context": {"equal_allocation_latency_ms": 0.84, "unequal_allocation_latency_ms": 0.64,
+                          "camera_hz": 500, "hardware": "Xeon Phi KNL + GigE camera"},
+        "roofline": None,
+    }
+    print(json.dumps(result), flush=True)
+
+
 def run_predict(args):
     """Learned predictor at the ELT size: closed-loop telemetry of the integrator, training with the
     library's kernels, closed-loop judgement against the integrator, and per-frame cost."""
@@ -359,6 +474,9 @@ def main():
         return
     if args.workload == "elt-predict":
         run_predict(args)
+        return
+    if args.workload == "elt-pipe":
+        run_pipe(args)
         return
     import torch
     from aosim import ELT, Scenario

@@ -345,9 +345,10 @@ rtc_status rtc_autotune(rtc_ctx *c, int32_t n_frames, const uint16_t *d_pixels, 
  * order, and as soon as the rows a group of them needs have landed it
  * calibrates and centroids them and multiplies their slopes into the matching
  * columns of the control matrix, accumulating a partial actuator vector.  The
- * P partial vectors are summed per actuator in a fixed order (blocks of 64
- * workers, each a wavefront tree: the parallel vector addition of Section
- * 2.3.5 and Figure 5), block by block as soon as a block has published, and
+ * P partial vectors are added per actuator in worker order by the owners --
+ * the first half of the workers, whose own subapertures land early -- each
+ * vector as soon as it is published (the vector addition of Section 2.3.5
+ * and Figure 5 becomes a running sum that keeps pace with the arrivals), and
  * the integrator is applied.  Latency, as in the paper, is the time from the
  * last pixel of a frame landing to its last command being written.
  *
@@ -358,7 +359,7 @@ rtc_status rtc_autotune(rtc_ctx *c, int32_t n_frames, const uint16_t *d_pixels, 
  * wait for the whole frame (no pixel-stream processing) for comparison.
  *
  * Tail: the subapertures of the last tail_rows subaperture rows (at most 64)
- * are left out of the allocation; instead every worker calibrates them itself
+ * are left out of the allocation; instead every owner calibrates them itself
  * once their rows land and multiplies their slopes into its own actuator rows
  * (a row split of those columns, from LDS), so that after the last pixel no
  * partial vector has to travel between workgroups.
@@ -399,9 +400,9 @@ rtc_status rtc_pipe_setup(rtc_ctx *c, const rtc_pipe_config *cfg);
 
 /* Shape chosen by rtc_pipe_setup (any pointer may be NULL): workers, matrix
  * columns per worker kept in LDS, image rows, most subapertures of a worker,
- * tail subapertures. */
+ * tail subapertures, owners (workers 0..n_owners-1 hold the actuator rows). */
 rtc_status rtc_pipe_info(const rtc_ctx *c, int32_t *n_workers, int32_t *lds_cols, int32_t *image_rows,
-                         int32_t *max_subaps, int32_t *n_tail);
+                         int32_t *max_subaps, int32_t *n_tail, int32_t *n_owners);
 
 /* Runs n_frames frames through the camera emulator and the workers in one
  * launch on hip_stream (asynchronous).  d_frames: n_frames source frames,
@@ -412,7 +413,8 @@ rtc_status rtc_pipe_info(const rtc_ctx *c, int32_t *n_workers, int32_t *lds_cols
  * nullable): d_cam_ts [n_frames][4] = scheduled frame start, first packet
  * landed, last packet landed (the last pixel), largest delay of a packet
  * behind its schedule; d_worker_ts [n_frames][n_workers][2] = worker's
- * partial vector published, its actuator rows integrated.  The integrator
+ * partial vector published, worker done with the frame (an owner: its
+ * actuator rows integrated and stored).  The integrator
  * state carries across calls and frame modes.  A wait that exceeds
  * wait_limit_us gives up, and the batch stops early; rtc_sync_check reports
  * it.  Errors: RTC_E_STATE before rtc_pipe_setup or after a new

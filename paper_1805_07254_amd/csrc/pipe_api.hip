@@ -86,7 +86,9 @@ rtc_status rtc_pipe_setup(rtc_ctx *c, const rtc_pipe_config *cfg) {
   while (n_main > 0 && c->tiles_h[n_main - 1].off / c->tiles_h[n_main - 1].pitch >= tail_top) --n_main;
   const int32_t n_tail = n - n_main;
   if (n_tail > rtck::kPipeMaxTail) return fail(c, RTC_E_UNSUPPORTED, "rtc_pipe_setup: more than 64 tail subapertures");
-  const int32_t own_max = (c->n_act + P - 1) / P;
+  // owners: the first half of the workers (at least enough for 64 rows each)
+  const int32_t n_own = std::min(P, std::max((c->n_act + 63) / 64, (P + 1) / 2));
+  const int32_t own_max = (c->n_act + n_own - 1) / n_own;
   std::vector<int32_t> counts(P), first(P + 1, 0), need(n);
   linear_allocation(n_main, P, cfg->alloc_ratio, counts.data());
   int32_t max_nb = 1;
@@ -108,7 +110,7 @@ rtc_status rtc_pipe_setup(rtc_ctx *c, const rtc_pipe_config *cfg) {
   const int64_t ldp = (c->n_act + 63) / 64 * 64;
   const int64_t col_bytes = ldp * code_bytes;
   const size_t fixed = rtck::pipe_lds_fixed(max_nb, n_tail, own_max);
-  const int64_t avail = (int64_t)lds_max - (int64_t)fixed - 64;   // 64: static shared words
+  const int64_t avail = (int64_t)lds_max - (int64_t)fixed - rtck::kPipeStaticLds;
   if (avail < 0) return fail(c, RTC_E_UNSUPPORTED, "rtc_pipe_setup: too many subapertures per worker for LDS");
   const int32_t lds_cols = (int32_t)std::min<int64_t>(2 * (int64_t)max_nb, avail / col_bytes);
   const size_t lds = (size_t)lds_cols * col_bytes + fixed;
@@ -168,6 +170,7 @@ rtc_status rtc_pipe_setup(rtc_ctx *c, const rtc_pipe_config *cfg) {
   c->pipe_max_nb = max_nb;
   c->pipe_n_tail = n_tail;
   c->pipe_own_max = own_max;
+  c->pipe_n_own = n_own;
   c->pipe_H = wi.H;
   c->pipe_W = wi.W;
   c->pipe_ldp = ldp;
@@ -178,7 +181,7 @@ rtc_status rtc_pipe_setup(rtc_ctx *c, const rtc_pipe_config *cfg) {
 }
 
 rtc_status rtc_pipe_info(const rtc_ctx *c, int32_t *n_workers, int32_t *lds_cols, int32_t *image_rows,
-                         int32_t *max_subaps, int32_t *n_tail) {
+                         int32_t *max_subaps, int32_t *n_tail, int32_t *n_owners) {
   if (!c) return fail(nullptr, RTC_E_ARG, "rtc_pipe_info: NULL context");
   if (c->pipe_gen == 0) return fail(const_cast<rtc_ctx *>(c), RTC_E_STATE, "rtc_pipe_info: call rtc_pipe_setup first");
   if (n_workers) *n_workers = c->pipe_workers;
@@ -186,6 +189,7 @@ rtc_status rtc_pipe_info(const rtc_ctx *c, int32_t *n_workers, int32_t *lds_cols
   if (image_rows) *image_rows = c->pipe_H;
   if (max_subaps) *max_subaps = c->pipe_max_nb;
   if (n_tail) *n_tail = c->pipe_n_tail;
+  if (n_owners) *n_owners = c->pipe_n_own;
   return RTC_OK;
 }
 
@@ -240,6 +244,7 @@ rtc_status rtc_pipe_run(rtc_ctx *c, int32_t n_frames, const uint16_t *d_frames, 
   p.max_nb = c->pipe_max_nb;
   p.n_tail = c->pipe_n_tail;
   p.own_max = c->pipe_own_max;
+  p.n_own = c->pipe_n_own;
   p.n_act = c->n_act;
   p.scales = c->d_scales;
   p.state = c->d_state;

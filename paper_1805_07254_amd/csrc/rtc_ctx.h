@@ -62,7 +62,7 @@ struct rtc_ctx {
   uint64_t pipe_gen = 0;           // cmat_gen the packed columns were made from; 0 = not set up
   rtc_pipe_config pipe_cfg{};
   int32_t pipe_workers = 0, pipe_lds_cols = 0, pipe_max_nb = 0, pipe_H = 0, pipe_W = 0;
-  int32_t pipe_n_tail = 0, pipe_own_max = 0;
+  int32_t pipe_n_tail = 0, pipe_own_max = 0, pipe_n_own = 0;
   int64_t pipe_ldp = 0, pipe_ring_stride = 0;
   size_t pipe_lds = 0;
   void *d_packed = nullptr;        // [2 n_valid][ldp] codes

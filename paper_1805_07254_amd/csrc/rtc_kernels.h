@@ -131,9 +131,10 @@ hipError_t launch_frames(const PersistArgs &p, int blocks, int rows_per_batch, h
 // other workgroup (a worker) owns a contiguous run of subapertures in arrival
 // order and, as soon as their rows have landed, calibrates them, centroids
 // them and multiplies their slopes into the matching columns of the control
-// matrix (a partial actuator vector).  Worker b also owns actuator rows
-// [b n_act / P, (b+1) n_act / P): it sums the P partial vectors of those rows
-// (fixed order) and applies the integrator.
+// matrix (a partial actuator vector).  The first n_own workers also own
+// actuator rows (owner b: [b n_act / n_own, (b+1) n_act / n_own)): each sums
+// the P partial vectors of its rows in worker order and applies the
+// integrator.
 namespace pipe_layout {
 constexpr int kStride = 1024;                     // 4 KiB between counters
 constexpr int kRowCopies = 16;                    // landed-row counter copies, worker b polls copy b % 16
@@ -172,8 +173,9 @@ struct PipeArgs {
   int64_t ldp;             // codes per packed column, multiple of 64
   int32_t lds_cols;        // trailing columns of a worker kept in LDS
   int32_t max_nb;          // most subapertures of a worker
-  int32_t n_tail;          // subapertures [n_valid - n_tail, n_valid): every worker processes them for its own rows
-  int32_t own_max;         // most actuator rows of a worker
+  int32_t n_tail;          // subapertures [n_valid - n_tail, n_valid): every owner processes them for its own rows
+  int32_t n_own;           // owners: workers [0, n_own) hold the actuator rows
+  int32_t own_max;         // most actuator rows of an owner (<= 64)
   int32_t n_act;
   const float *scales;     // nullable [n_act]
   float *state;            // [n_act]
@@ -194,6 +196,7 @@ hipError_t launch_pipe(const PipeArgs &p, int G, size_t lds_bytes, hipStream_t s
 // LDS bytes a worker needs besides its columns.
 size_t pipe_lds_fixed(int max_nb, int n_tail, int own_max);
 constexpr int kPipeMaxTail = 64;                   // tail subapertures (two slope columns per lane)
+constexpr int kPipeStaticLds = 4096;               // static shared memory of the pipe kernel (upper bound)
 // Bytes per code of a storage format (4, 2, 2, 1).
 int format_code_bytes(int fmt);
 // packed[(2k + h) ldp + r] = code of row r, slope column (h ? tiles[k].sy : tiles[k].sx); rows

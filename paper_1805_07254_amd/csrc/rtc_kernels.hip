@@ -955,11 +955,15 @@ __global__ __launch_bounds__(512) void frames_kernel(PersistArgs p, int32_t max_
 // columns (column-major, thread t handles quads of 4 consecutive rows); the
 // worker's trailing lds_cols columns -- the ones whose slopes arrive last --
 // are copied to LDS once per launch.  The partial actuator vector is then
-// published, and the worker sums its own actuator rows over the P partial
-// vectors (64-worker blocks in order, each a wavefront tree) as soon as each
-// block has published: the blocks of early workers are summed while the last
-// pixels are still arriving.  Every wait is bounded in time and gives up when
-// another workgroup has raised the abort flag, so every workgroup exits.
+// published.  The actuator rows belong to the first n_own workers (owners),
+// whose own subapertures land early: an owner adds the P partial vectors of
+// its rows in worker order, each as soon as it is published, so only the last
+// workers' vectors remain after the last pixel.  The tail subapertures (the
+// last rows of the frame) are not allocated to workers: every owner
+// calibrates them itself and applies their columns (kept in LDS) to its own
+// rows, so after the last pixel nothing travels between workgroups.  Every
+// wait is bounded in time and gives up when another workgroup has raised the
+// abort flag, so every workgroup exits.
 // ---------------------------------------------------------------------------
 namespace pl = pipe_layout;
 constexpr int kPipeQ = pl::kMaxQuadsPerThread;
@@ -1027,43 +1031,6 @@ __device__ bool pipe_wait(const PipeArgs &p, const uint32_t *word, uint32_t targ
 // The whole workgroup waits (thread 0 polls); uniform result.
 __device__ bool pipe_block_wait(const PipeArgs &p, const uint32_t *word, uint32_t target, uint32_t *sh) {
   if (threadIdx.x == 0) *sh = pipe_wait(p, word, target) ? 1u : 0u;
-  __syncthreads();
-  const bool ok = *sh != 0;
-  __syncthreads();
-  return ok;
-}
-
-// Wavefront 0 waits until workers [w0, min(w0 + 64, P)) have published frame
-// target - 1; uniform result for the workgroup.
-__device__ bool pipe_flags_wait(const PipeArgs &p, int w0, int P, uint32_t target, uint32_t *sh) {
-  if (threadIdx.x < 64) {
-    const int w = w0 + (int)threadIdx.x;
-    const uint32_t *fl = p.sync + pl::kFlags + 16 * (w < P ? w : 0);
-    const uint64_t t0 = wall_clock64();
-    bool ok = true;
-    for (uint32_t spins = 0;; ++spins) {
-      const bool ready =
-          w >= P || (int32_t)(__hip_atomic_load(fl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - target) >= 0;
-      if (__ballot(!ready) == 0) break;
-      __builtin_amdgcn_s_sleep(1);
-      if ((spins & 31) == 31) {
-        int stop = 0;
-        if (threadIdx.x == 0) {
-          if (__hip_atomic_load(p.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
-            stop = 1;
-          } else if (wall_clock64() - t0 > (uint64_t)p.wait_ticks) {
-            pipe_raise_abort(p);
-            stop = 1;
-          }
-        }
-        if (__builtin_amdgcn_readfirstlane(stop)) {
-          ok = false;
-          break;
-        }
-      }
-    }
-    if (threadIdx.x == 0) *sh = ok ? 1u : 0u;
-  }
   __syncthreads();
   const bool ok = *sh != 0;
   __syncthreads();
@@ -1263,8 +1230,6 @@ __device__ __forceinline__ float decode_one(const void *packed, int64_t idx) {
   }
 }
 
-constexpr int kOwnPerWave = 8;                     // owned actuator rows per wavefront (64 per worker)
-
 // Calibration passes over local subapertures [j0, j1) of the run starting at
 // k0 (need[] local to the run), each pass starting when its rows have landed;
 // after each pass, `after(j, j2)` runs with the pass's slopes in sh_s.
@@ -1293,10 +1258,12 @@ template <int FMT, int GS>
 __global__ __launch_bounds__(512) void pipe_kernel(PipeArgs p) {
   using QT = typename Quad<FMT>::T;
   // LDS: [lds_cols][nq] codes, sh_s [2 max_nb], sh_need [max_nb], tail need [n_tail],
-  // tail slopes [2 n_tail], tail matrix block [own_max][2 n_tail] floats
+  // tail slopes [2 n_tail], tail matrix block [2 n_tail][own_max] floats
   extern __shared__ uint4 pipe_lds[];
   __shared__ uint32_t sh_abort, sh_wait;
   __shared__ uint64_t sh_t0;
+  __shared__ float sh_red[8 * 64];                 // per-wavefront partial-vector sums of the owned rows
+  __shared__ uint32_t sh_ok[8];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int P = (int)gridDim.x - 1;
@@ -1318,26 +1285,23 @@ __global__ __launch_bounds__(512) void pipe_kernel(PipeArgs p) {
   const int kt = p.n_valid - p.n_tail;             // first tail subaperture
   const int Lc = min(ncol, p.lds_cols), lfirst = ncol - Lc;
   const QT *gcols = reinterpret_cast<const QT *>(p.packed) + (int64_t)2 * k0 * nq;
-  // owned actuator rows [ob, ob + nown): row ob + wave + 8 q in wavefront `wave`
-  const int ob = (int)(((int64_t)b * p.n_act) / P);
-  const int nown = (int)(((int64_t)(b + 1) * p.n_act) / P) - ob;
+  // owners are the first n_own workers (their own subapertures land first); owner b
+  // holds actuator rows [ob, ob + nown), row ob + r in lane r of wavefront 0
+  const bool owner = b < p.n_own;
+  const int ob = owner ? (int)(((int64_t)b * p.n_act) / p.n_own) : 0;
+  const int nown = owner ? (int)(((int64_t)(b + 1) * p.n_act) / p.n_own) - ob : 0;
   for (int64_t x = tid; x < (int64_t)Lc * nq; x += 512) lds_cols[x] = gcols[(int64_t)lfirst * nq + x];
   for (int j = tid; j < nb; j += 512) sh_need[j] = p.need[k0 + j];
   for (int j = tid; j < p.n_tail; j += 512) sh_tneed[j] = p.need[kt + j];
-  for (int x = tid; x < nown * nt2; x += 512) {
-    const int jr = x / nt2, col = x - jr * nt2;
-    sh_tR[x] = decode_one<FMT>(p.packed, (int64_t)(2 * kt + col) * p.ldp + ob + jr);
+  for (int x = tid; x < nt2 * p.own_max; x += 512) {
+    const int c = x / p.own_max, r = x - c * p.own_max;
+    sh_tR[x] = r < nown ? decode_one<FMT>(p.packed, (int64_t)(2 * kt + c) * p.ldp + ob + r) : 0.f;
   }
-  float st[kOwnPerWave];
-#pragma unroll
-  for (int q = 0; q < kOwnPerWave; ++q) {
-    const int jr = wave + 8 * q;
-    st[q] = jr < nown ? p.state[ob + jr] : 0.f;
-  }
+  float st = (wave == 0 && lane < nown) ? p.state[ob + lane] : 0.f;
   __syncthreads();
   const uint32_t *rows_ctr = p.sync + (b % pl::kRowCopies) * pl::kStride;
   const uint32_t *ring_w = reinterpret_cast<const uint32_t *>(p.ring);
-  const int nblk = (P + 63) / 64;
+  const uint32_t *flags = p.sync + pl::kFlags;
 
   for (int f = 0; f < p.n_frames; ++f) {
     if (tid == 0) sh_abort = __hip_atomic_load(p.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1345,8 +1309,8 @@ __global__ __launch_bounds__(512) void pipe_kernel(PipeArgs p) {
     const bool aborted = sh_abort != 0;
     __syncthreads();
     if (aborted) break;
-    // partial slot f & 1 held frame f - 2: every worker is done with it once this
-    // worker has all partial vectors of frame f - 1, so this wait returns at once
+    // partial slot f & 1 held frame f - 2, consumed by every owner before it counted
+    // frame f - 2 done; by now that has long happened, so this wait returns at once
     if (f >= 2 && !pipe_block_wait(p, p.sync + pl::kOwnDone, (uint32_t)(P * (f - 1)), &sh_wait)) break;
     const uint32_t *slot = ring_w + (int64_t)(f & 1) * (p.ring_stride / 2);
     float4 acc[kPipeQ];
@@ -1384,82 +1348,101 @@ __global__ __launch_bounds__(512) void pipe_kernel(PipeArgs p) {
       __hip_atomic_store(p.sync + pl::kFlags + 16 * b, (uint32_t)(f + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 
-    // (c) own rows: sum of the P partial vectors, blocks of 64 workers in order
-    float tot[kOwnPerWave];
+    if (owner) {
+      // (c) own rows: the P partial vectors, each added as soon as it is published.
+      // Wavefront k adds workers k, k + 8, k + 16, ... in order (lanes = rows); the 8
+      // sums are then added in wavefront order, so the order never depends on timing.
+      float tot = 0.f, tail = 0.f;
+      {
+        float part_sum = 0.f;
+        bool ok = true;
+        const float *prow = part_f + ob + lane;
+        uint64_t t_progress = wall_clock64();
+        for (int w = wave, spins = 0; w < P;) {
+          const int wl = w + 8 * lane;
+          const bool ready = wl < P && (int32_t)(__hip_atomic_load(flags + 16 * wl, __ATOMIC_RELAXED,
+                                                                   __HIP_MEMORY_SCOPE_AGENT) - (uint32_t)(f + 1)) >= 0;
+          const uint64_t waiting = ~__ballot(ready);
+          const int m = waiting == 0 ? 64 : (int)__builtin_ctzll(waiting);   // published run from w on
+          if (m == 0) {
+            __builtin_amdgcn_s_sleep(1);
+            if ((++spins & 31) == 0) {
+              int stop = 0;
+              if (lane == 0) {
+                if (__hip_atomic_load(p.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                  stop = 1;
+                } else if (wall_clock64() - t_progress > (uint64_t)p.wait_ticks) {
+                  pipe_raise_abort(p);
+                  stop = 1;
+                }
+              }
+              if (__builtin_amdgcn_readfirstlane(stop)) {
+                ok = false;
+                break;
+              }
+            }
+            continue;
+          }
+          for (int i = 0; i < m; i += 16) {
+            float v[16];
 #pragma unroll
-    for (int q = 0; q < kOwnPerWave; ++q) tot[q] = 0.f;
-    bool ok = true;
-    for (int blk = 0; blk < nblk; ++blk) {
-      if (!pipe_flags_wait(p, 64 * blk, P, (uint32_t)(f + 1), &sh_wait)) {
-        ok = false;
-        break;
-      }
-      const int w = 64 * blk + lane;
-      float v[kOwnPerWave];
+            for (int u = 0; u < 16; ++u)
+              v[u] = (i + u < m && lane < nown)
+                         ? __hip_atomic_load(prow + (int64_t)(w + 8 * (i + u)) * p.ldp, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT)
+                         : 0.f;
 #pragma unroll
-      for (int q = 0; q < kOwnPerWave; ++q) {
-        const int jr = wave + 8 * q;
-        v[q] = (jr < nown && w < P)
-                   ? __hip_atomic_load(part_f + (int64_t)w * p.ldp + ob + jr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                   : 0.f;
-      }
-#pragma unroll
-      for (int q = 0; q < kOwnPerWave; ++q) {
-        if (wave + 8 * q < nown) {
-          const float s = wave_sum(v[q]);
-          tot[q] = blk == 0 ? s : tot[q] + s;
+            for (int u = 0; u < 16; ++u)
+              if (i + u < m) part_sum += v[u];
+          }
+          w += 8 * m;
+          spins = 0;
+          t_progress = wall_clock64();
         }
+        sh_red[wave * 64 + lane] = part_sum;
+        if (lane == 0) sh_ok[wave] = ok ? 1u : 0u;
       }
-    }
-    if (!ok) break;
-
-    // (a)-(c) tail subapertures: every worker, for its own rows (row split)
-    if (p.n_tail > 0) {
-      const bool ok_tail = pipe_passes<GS>(p, f, slot, rows_ctr, kt, 0, p.n_tail, sh_tneed, sh_ts, b == 0,
-                                           &sh_wait, [&](int, int) {});
-      if (!ok_tail) break;
+      __syncthreads();
+      bool ok_sum = true;
 #pragma unroll
-      for (int q = 0; q < kOwnPerWave; ++q) {
-        const int jr = wave + 8 * q;
-        if (jr < nown) {
-          float v = 0.f;
-          for (int c = lane; c < nt2; c += 64) v = fmaf(sh_tR[jr * nt2 + c], sh_ts[c], v);
-          tot[q] += wave_sum(v);
-        }
+      for (int k = 0; k < 8; ++k) ok_sum = ok_sum && sh_ok[k] != 0;
+      if (wave == 0)
+#pragma unroll
+        for (int k = 0; k < 8; ++k) tot += sh_red[k * 64 + lane];
+      __syncthreads();
+      if (!ok_sum) break;
+
+      // (a)-(c) tail subapertures: every owner calibrates them and applies their columns
+      // to its own rows, pass by pass
+      if (p.n_tail > 0) {
+        const bool ok_tail = pipe_passes<GS>(p, f, slot, rows_ctr, kt, 0, p.n_tail, sh_tneed, sh_ts, b == 0,
+                                             &sh_wait, [&](int j, int j2) {
+          if (wave == 0 && lane < nown)
+            for (int c = 2 * j; c < 2 * j2; ++c) tail = fmaf(sh_tR[c * p.own_max + lane], sh_ts[c], tail);
+        });
+        if (!ok_tail) break;
       }
-    }
 
-    // (d) integrator of the owned rows
-#pragma unroll
-    for (int q = 0; q < kOwnPerWave; ++q) {
-      const int jr = wave + 8 * q;
-      if (jr < nown) {
-        const int row = ob + jr;
-        float a = tot[q];
+      // (d) integrator of the owned rows
+      if (wave == 0 && lane < nown) {
+        const int row = ob + lane;
+        float a = tot + tail;
         if (p.scales != nullptr) a *= p.scales[row];
-        float c = fmaf(p.gain, a, p.leak * st[q]);
+        float c = fmaf(p.gain, a, p.leak * st);
         c = fminf(fmaxf(c, p.cmd_min), p.cmd_max);
-        st[q] = c;
-        if (lane == 0) {
-          p.cmd[(int64_t)f * p.n_act + row] = c;
-          if (p.recon != nullptr) p.recon[(int64_t)f * p.n_act + row] = a;
-        }
+        st = c;
+        p.cmd[(int64_t)f * p.n_act + row] = c;
+        if (p.recon != nullptr) p.recon[(int64_t)f * p.n_act + row] = a;
       }
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      __syncthreads();
     }
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-    __syncthreads();
     if (tid == 0) {
       if (p.wk_ts != nullptr) p.wk_ts[((int64_t)f * P + b) * 2 + 1] = wall_clock64();
       __hip_atomic_fetch_add(p.sync + pl::kOwnDone, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   }
-  if (lane == 0) {
-#pragma unroll
-    for (int q = 0; q < kOwnPerWave; ++q) {
-      const int jr = wave + 8 * q;
-      if (jr < nown) p.state[ob + jr] = st[q];
-    }
-  }
+  if (wave == 0 && lane < nown) p.state[ob + lane] = st;
 }
 
 // Zeroes the landed-row counters, the flags of P workers, the done counter and
@@ -1796,7 +1779,8 @@ hipError_t launch_pipe(const PipeArgs &p, int G, size_t lds, hipStream_t st) {
   if (p.n_frames <= 0) return hipSuccess;
   if (p.max_n < 1 || p.max_n > 32 || G < 2 || G - 1 > pl::kMaxWorkers) return hipErrorInvalidValue;
   if (p.ldp % 64 != 0 || p.ldp / 4 > (int64_t)kPipeQ * 512) return hipErrorInvalidValue;
-  if ((p.n_act + G - 2) / (G - 1) > 8 * kOwnPerWave || p.own_max < (p.n_act + G - 2) / (G - 1)) return hipErrorInvalidValue;
+  if (p.n_own < 1 || p.n_own > G - 1 || p.own_max > 64 || p.own_max < (p.n_act + p.n_own - 1) / p.n_own)
+    return hipErrorInvalidValue;
   if (p.n_tail < 0 || p.n_tail > kPipeMaxTail || p.n_tail > p.n_valid) return hipErrorInvalidValue;
   if (p.frame_elems % 2 != 0 || p.src_stride % 2 != 0 || p.ring_stride % 128 != 0 || p.rows_per_packet < 1)
     return hipErrorInvalidValue;

@@ -100,7 +100,7 @@ _SIGNATURES = {
     "rtc_autotune": (_i32, [_vp, _i32, _vp, _i64, _vp, _vp, _i32, ctypes.POINTER(_i32), _vp]),
     "rtc_pipe_allocation": (_i32, [_i32, _i32, ctypes.c_double, _vp]),
     "rtc_pipe_setup": (_i32, [_vp, ctypes.POINTER(rtc_pipe_config)]),
-    "rtc_pipe_info": (_i32, [_vp] + [ctypes.POINTER(_i32)] * 5),
+    "rtc_pipe_info": (_i32, [_vp] + [ctypes.POINTER(_i32)] * 6),
     "rtc_pipe_run": (_i32, [_vp, _i32, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "rtc_load_cmat": (_i32, [_vp, _vp, _i32, _i32, _i64]),
     "rtc_encode_cmat": (_i32, [_i32, _vp, _i32, _i32, _i64, _vp, _vp]),
@@ -502,10 +502,10 @@ def rtc_pipe_setup(ctx: RtcContext, n_workers: int = 0, full_frame: bool = False
 
 
 def rtc_pipe_info(ctx: RtcContext) -> dict:
-    v = [ctypes.c_int32(0) for _ in range(5)]
+    v = [ctypes.c_int32(0) for _ in range(6)]
     _check(load_library().rtc_pipe_info(ctx.handle, *[ctypes.byref(x) for x in v]), ctx)
     return {"n_workers": v[0].value, "lds_cols": v[1].value, "image_rows": v[2].value, "max_subaps": v[3].value,
-            "n_tail": v[4].value}
+            "n_tail": v[4].value, "n_owners": v[5].value}
 
 
 def rtc_pipe_run(ctx: RtcContext, n_frames: int, frames, cmd, slopes=None, recon=None, counts=None, cam_ts=None,

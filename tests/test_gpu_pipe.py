@@ -83,8 +83,10 @@ def _check_arrival_order(sc, out, ratio, full, period_us, readout_us, khz, tail_
         assert np.all(wk[:, b, 0] >= earliest), f"worker {b} published before its rows landed"
     if full:
         assert np.all(wk[:, counts > 0, 0] >= cam[:, 2:3]), "a worker started before the whole frame landed"
-    # every command needs every partial vector, the last of which needs the last rows
-    assert np.all(wk[:, :, 1] >= cam[:, 2:3])
+    # every command needs every partial vector (and the tail), the last of which needs the last rows
+    n_own = out["info"]["n_owners"]
+    assert 1 <= n_own <= P and (sc.n_act + n_own - 1) // n_own <= 64
+    assert np.all(wk[:, :n_own, 1] >= cam[:, 2:3])
     assert np.all(wk[:, :, 1] >= wk[:, :, 0])
     lat_us = (wk[:, :, 1].max(axis=1) - cam[:, 2]) / tpu
     early = (wk[1:, 0, 0] - cam[1:, 2]) / tpu

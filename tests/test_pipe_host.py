@@ -56,7 +56,7 @@ def test_pipe_entry_points_reject_null_context():
                               readout_us=1000.0, rows_per_packet=2, wait_limit_us=0, tail_rows=0,
                               reserved=0)
     assert lib.rtc_pipe_setup(None, ctypes.byref(cfg)) == rtc.RTC_E_ARG
-    assert lib.rtc_pipe_info(None, None, None, None, None, None) == rtc.RTC_E_ARG
+    assert lib.rtc_pipe_info(None, None, None, None, None, None, None) == rtc.RTC_E_ARG
     assert lib.rtc_pipe_run(None, 1, None, 0, None, None, None, None, None, None, None) == rtc.RTC_E_ARG
     assert lib.rtc_pipe_allocation(4, 2, 1.0, None) == rtc.RTC_E_ARG
     assert ctypes.sizeof(rtc.rtc_pipe_config) == 48

@@ -34,7 +34,7 @@ sys.path.insert(0, ROOT)
 METRIC = ("ELT-SCAO frame latency p50/p99 + RMS jitter (µs); GEMV GB/s vs HBM/LLC peak")
 HBM_PEAK_GBPS = 8000.0
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "frames_elt_traffic.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_1805_07254_amd", "csrc", "rtc_kernels.hip")
+KERNEL_SRCS = [os.path.join(ROOT, "paper_1805_07254_amd", "csrc", f) for f in ("rtc_kernels.hip", "rtc_device.h")]
 FMT_BYTES = {"f32": 4, "f16": 2, "bf16": 2, "fp8e4m3": 1}
 
 
@@ -43,8 +43,12 @@ def log(msg):
 
 
 def kernel_source_hash() -> str:
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """sha256 prefix of the sources of the persistent frame kernel."""
+    h = hashlib.sha256()
+    for path in KERNEL_SRCS:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def frame_bytes(sc, fmt: str) -> int:

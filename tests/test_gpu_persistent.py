@@ -80,7 +80,7 @@ def test_expired_barrier_wait_is_reported_and_cleared(tiny_loop):
         _gpu_batch(ctx, np.concatenate([frames] * 2))
         with pytest.raises(rtc.RtcError) as ei:
             rtc.rtc_sync_check(ctx)
-        assert ei.value.status == rtc.RTC_E_DEVICE and "barrier" in str(ei.value)
+        assert ei.value.status == rtc.RTC_E_DEVICE and "bounded wait" in str(ei.value)
         rtc.rtc_sync_check(ctx)                     # cleared
         rtc.rtc_set_frame_mode(ctx, rtc.RTC_FRAMES_PERSISTENT)
         rtc.rtc_reset(ctx)

@@ -40,10 +40,15 @@ __device__ __forceinline__ int64_t xchg_pos(int64_t k, int epc) {
 // frame pointer allows it (vec != 0).
 // COH: slopes are written with device-coherent stores (read by other
 // workgroups of the same launch); otherwise with ordinary stores.
+// tl / rl (nullable): a copy of the tile descriptors and of the (x, y)
+// reference slopes of subapertures from some first one on (usually in LDS),
+// subaperture k at index kl.
 template <int GS, bool COH = false>
-__device__ __forceinline__ void calib_tile_row(const CalibArgs &a, int k, int i, int vec) {
+__device__ __forceinline__ void calib_tile_row(const CalibArgs &a, int k, int i, int vec,
+                                               const TileDesc *tl = nullptr, int kl = 0,
+                                               const float2 *rl = nullptr) {
   TileDesc t{};
-  if (k < a.n_valid) t = a.tiles[k];
+  if (k < a.n_valid) t = tl != nullptr ? tl[kl] : a.tiles[k];
   const int n = t.n;
   const double half = 0.5 * (double)(n - 1);
   double S = 0.0, Sx = 0.0;
@@ -81,8 +86,9 @@ __device__ __forceinline__ void calib_tile_row(const CalibArgs &a, int k, int i,
   double cx, cy;
   tile_centroid<GS>(S, Sx, cnt, i, half, cx, cy, cnt);
   if (i == 0 && k < a.n_valid) {
-    const float sx = (float)(cx - (double)a.ref[t.sx]);
-    const float sy = (float)(cy - (double)a.ref[t.sy]);
+    const float2 r = rl != nullptr ? rl[kl] : make_float2(a.ref[t.sx], a.ref[t.sy]);
+    const float sx = (float)(cx - (double)r.x);
+    const float sy = (float)(cy - (double)r.y);
     if (COH) {
       __hip_atomic_store(a.s_int + xchg_pos(t.sx, a.xchg_epc), sx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __hip_atomic_store(a.s_int + xchg_pos(t.sy, a.xchg_epc), sy, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -659,12 +665,28 @@ __device__ __forceinline__ void lds_row_group(const uint4 *lds, int ldq16, int r
   store_row_sums<NB>(t, sh_part + wave * max_rows + r0, NB, lane);
 }
 
-template <int FMT, int KPL, int RR, int GS, bool PANELS>
-__global__ __launch_bounds__(512) void frames_kernel(PersistArgs p, int32_t max_rows, int32_t lds_rows) {
-  constexpr int W = 8;
+// Persistent frames kernel.  The slope dimension is cut into W = 8 slices of
+// whole 64-chunk groups, as in the per-launch row-block kernel with 8
+// wavefronts; a workgroup has 8 / VW wavefronts and wavefront w handles the
+// slices w + (8 / VW) u, u < VW, each with its own partial row sums, so every
+// row's sum has the per-launch kernel's addition tree whatever VW is.  With
+// VW = 2 (256 threads, one wavefront per SIMD) a wavefront may use the whole
+// 512-entry register file: RR rows of the slab are kept in ordinary registers
+// and RA more in accumulation registers (AGPRs, which the matrix cores would
+// otherwise use), so more of the matrix stays on chip.
+template <int FMT, int KPL, int RR, int RA, int VW, int GS, bool PANELS>
+__global__ __launch_bounds__(512 / VW) void frames_kernel(PersistArgs p, int32_t max_rows, int32_t lds_rows,
+                                                          int32_t tile_cap) {
+  static_assert(!PANELS || (VW == 1 && RA == 0), "slope panels use 8 wavefronts");
+  constexpr int W = 8;                             // slope slices
+  constexpr int PW = W / VW;                       // wavefronts of the workgroup
+  constexpr int NT = PW * 64;
   constexpr int EPC = Codec<FMT>::EPC;
   constexpr int RB = KPL <= 2 ? 4 : 2;             // streamed rows per batch
-  extern __shared__ uint4 lds[];                   // [lds_rows][ldq16] slab, then [W][max_rows] floats
+  // LDS: [lds_rows][ldq16] slab, [W][max_rows] floats, then (tile_cap > 0) the
+  // workgroup's tile descriptors and reference slopes, which stay the same for
+  // every frame
+  extern __shared__ uint4 lds[];
   __shared__ uint32_t sh_abort;
   const MvmArgs &a = p.mvm;
   const int tid = threadIdx.x;
@@ -678,33 +700,58 @@ __global__ __launch_bounds__(512) void frames_kernel(PersistArgs p, int32_t max_
   const int nrows = (int)(((int64_t)(b + 1) * a.n_act) / G) - row_begin;
   const int k_begin = (int)(((int64_t)b * p.cal.n_valid) / G);
   const int k_end = (int)(((int64_t)(b + 1) * p.cal.n_valid) / G);
-  constexpr int SPP = W * 64 / GS;                 // subapertures per calibration pass
-  const int kc = slice_chunks(a.n_chunks, W);      // chunks per wavefront slice (whole 64-chunk groups)
-  const int k_lo = wave * kc;
-  const int k_hi = min(k_lo + kc, a.n_chunks);
+  constexpr int SPP = NT / GS;                     // subapertures per calibration pass
+  const int kc = slice_chunks(a.n_chunks, W);      // chunks per slice (whole 64-chunk groups)
   const uint4 *slab = reinterpret_cast<const uint4 *>(static_cast<const char *>(a.Rq) +
                                                       (int64_t)row_begin * a.ldq_bytes);
-
-  int col[KPL];
-  bool okc[KPL];
-#pragma unroll
-  for (int j = 0; j < KPL; ++j) {
-    const int c = k_lo + j * 64 + lane;
-    okc[j] = c < k_hi;
-    col[j] = okc[j] ? c : 0;
+  TileDesc *sh_tiles = reinterpret_cast<TileDesc *>(sh_part + W * max_rows);
+  float2 *sh_ref = reinterpret_cast<float2 *>(sh_tiles + tile_cap);
+  const bool cached = k_end - k_begin <= tile_cap;
+  if (cached) {
+    for (int k = k_begin + tid; k < k_end; k += NT) {
+      const TileDesc t = p.cal.tiles[k];
+      sh_tiles[k - k_begin] = t;
+      sh_ref[k - k_begin] = make_float2(p.cal.ref[t.sx], p.cal.ref[t.sy]);
+    }
   }
 
-  // on-chip slab: rows [0, L) in LDS, [L, L + nreg) in registers, the rest streamed
+  int col[VW][KPL];
+  bool okc[VW][KPL];
+#pragma unroll
+  for (int u = 0; u < VW; ++u) {
+    const int k_lo = (wave + PW * u) * kc;
+    const int k_hi = min(k_lo + kc, a.n_chunks);
+#pragma unroll
+    for (int j = 0; j < KPL; ++j) {
+      const int c = k_lo + j * 64 + lane;
+      okc[u][j] = c < k_hi;
+      col[u][j] = okc[u][j] ? c : 0;
+    }
+  }
+
+  // on-chip slab: rows [0, L) in LDS, [L, L + nreg) in registers, the next nacc in
+  // accumulation registers, the rest streamed
   const int L = min(lds_rows, nrows);
   const int nreg = min(RR, max(0, nrows - L));
-  const int stream_begin = L + nreg;
-  for (int64_t c = tid; c < (int64_t)L * ldq16; c += W * 64) lds[c] = slab[c];
-  uint4 rr[RR > 0 ? RR : 1][KPL];
+  const int nacc = min(RA, max(0, nrows - L - RR));
+  const int stream_begin = L + nreg + nacc;
+  for (int64_t c = tid; c < (int64_t)L * ldq16; c += NT) lds[c] = slab[c];
+  uint4 rr[VW][RR > 0 ? RR : 1][KPL];
+  uint4 ra[VW][RA > 0 ? RA : 1][KPL];
 #pragma unroll
-  for (int i = 0; i < RR; ++i) {
-    const int row = min(L + i, nrows - 1);
+  for (int u = 0; u < VW; ++u) {
 #pragma unroll
-    for (int j = 0; j < KPL; ++j) rr[i][j] = slab[(int64_t)row * ldq16 + col[j]];
+    for (int i = 0; i < RR; ++i) {
+      const int row = min(L + i, nrows - 1);
+#pragma unroll
+      for (int j = 0; j < KPL; ++j) rr[u][i][j] = slab[(int64_t)row * ldq16 + col[u][j]];
+    }
+#pragma unroll
+    for (int i = 0; i < RA; ++i) {
+      const int row = min(L + RR + i, nrows - 1);
+#pragma unroll
+      for (int j = 0; j < KPL; ++j) ra[u][i][j] = slab[(int64_t)row * ldq16 + col[u][j]];
+    }
   }
   float state = 0.f;
   if (tid < nrows) state = a.state[row_begin + tid];
@@ -714,12 +761,21 @@ __global__ __launch_bounds__(512) void frames_kernel(PersistArgs p, int32_t max_
   for (int f = 0; f < p.n_frames; ++f) {
     // The register rows are loop-invariant codes; this empty statement makes
     // them opaque per frame, so they are decoded where used instead of being
-    // kept decoded (twice the registers) across the whole loop.
+    // kept decoded (twice the registers) across the whole loop, and keeps the
+    // RA rows in accumulation registers.
 #pragma unroll
-    for (int i = 0; i < RR; ++i)
+    for (int u = 0; u < VW; ++u) {
 #pragma unroll
-      for (int j = 0; j < KPL; ++j)
-        asm volatile("" : "+v"(rr[i][j].x), "+v"(rr[i][j].y), "+v"(rr[i][j].z), "+v"(rr[i][j].w));
+      for (int i = 0; i < RR; ++i)
+#pragma unroll
+        for (int j = 0; j < KPL; ++j)
+          asm volatile("" : "+v"(rr[u][i][j].x), "+v"(rr[u][i][j].y), "+v"(rr[u][i][j].z), "+v"(rr[u][i][j].w));
+#pragma unroll
+      for (int i = 0; i < RA; ++i)
+#pragma unroll
+        for (int j = 0; j < KPL; ++j)
+          asm volatile("" : "+a"(ra[u][i][j].x), "+a"(ra[u][i][j].y), "+a"(ra[u][i][j].z), "+a"(ra[u][i][j].w));
+    }
     if (tid == 0) sh_abort = __hip_atomic_load(p.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
     if (sh_abort) break;                            // a bounded wait expired somewhere: wind down
@@ -734,7 +790,8 @@ __global__ __launch_bounds__(512) void frames_kernel(PersistArgs p, int32_t max_
     ca.counts = p.cal.counts ? p.cal.counts + (int64_t)f * p.cal.n_valid : nullptr;
     for (int k0 = k_begin; k0 < k_end; k0 += SPP) {
       const int kk = k0 + tid / GS;
-      calib_tile_row<GS, true>(ca, kk < k_end ? kk : p.cal.n_valid, tid & (GS - 1), p.vec);
+      calib_tile_row<GS, true>(ca, kk < k_end ? kk : p.cal.n_valid, tid & (GS - 1), p.vec,
+                               cached ? sh_tiles : nullptr, kk - k_begin, cached ? sh_ref : nullptr);
     }
     trace_stamp(p, f, 1);
     frame_barrier(p, (uint32_t)(f + 1), f);
@@ -765,16 +822,20 @@ __global__ __launch_bounds__(512) void frames_kernel(PersistArgs p, int32_t max_
       }
     } else {
       // slope slices of this wavefront (device-coherent loads)
-      float sv[KPL][EPC];
-  #pragma unroll
-      for (int j = 0; j < KPL; ++j) {
-        // this lane's chunk group; lanes past the slice read group 0 (in bounds) and zero it
-        const int64_t g = okc[j] ? (int64_t)((k_lo >> 6) + j) : 0;
-        const float *grp = ca.s_int + g * (64 * EPC) + lane;
-  #pragma unroll
-        for (int e = 0; e < EPC; ++e) {
-          const float v = __hip_atomic_load(grp + e * 64, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          sv[j][e] = okc[j] ? v : 0.f;
+      float sv[VW][KPL][EPC];
+#pragma unroll
+      for (int u = 0; u < VW; ++u) {
+        const int k_lo = (wave + PW * u) * kc;
+#pragma unroll
+        for (int j = 0; j < KPL; ++j) {
+          // this lane's chunk group; lanes past the slice read group 0 (in bounds) and zero it
+          const int64_t g = okc[u][j] ? (int64_t)((k_lo >> 6) + j) : 0;
+          const float *grp = ca.s_int + g * (64 * EPC) + lane;
+#pragma unroll
+          for (int e = 0; e < EPC; ++e) {
+            const float v = __hip_atomic_load(grp + e * 64, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            sv[u][j][e] = okc[u][j] ? v : 0.f;
+          }
         }
       }
       // end stamp of the previous frame, whose per-workgroup stamps the barrier
@@ -782,53 +843,82 @@ __global__ __launch_bounds__(512) void frames_kernel(PersistArgs p, int32_t max_
       if (p.ts != nullptr && f > 0 && wave == 0 && b == (f - 1) % G) reduce_end_stamp(p, f - 1);
       if (p.trace != nullptr) {                       // stage 3: slope slices in registers
         float probe = 0.f;
-  #pragma unroll
-        for (int j = 0; j < KPL; ++j) probe += sv[j][0];
+#pragma unroll
+        for (int u = 0; u < VW; ++u)
+#pragma unroll
+          for (int j = 0; j < KPL; ++j) probe += sv[u][j][0];
         if (probe == 1.2345e-30f) sh_part[0] = probe;   // keeps the loads ahead of the stamp
         trace_stamp(p, f, 3);
       }
 
-      // (c) LDS rows in groups of LG (at most 64 VGPRs of codes, fewer when the
-      // register rows hold 128), then halves down to 1 (no duplicated rows)
-      {
-        constexpr int LG = (FMT == 0 ? 8 : 16) / KPL >= 8 ? 8 : ((FMT == 0 ? 8 : 16) / KPL >= 4 ? 4 : 2);
-        int r0 = 0;
-        for (; r0 + LG <= L; r0 += LG)
-          lds_row_group<FMT, KPL, LG>(lds, ldq16, r0, col, sv, sh_part, wave, lane, max_rows);
-        if constexpr (LG > 4) {
-          if (r0 + 4 <= L) {
-            lds_row_group<FMT, KPL, 4>(lds, ldq16, r0, col, sv, sh_part, wave, lane, max_rows);
-            r0 += 4;
+#pragma unroll
+      for (int u = 0; u < VW; ++u) {
+        const int sl = wave + PW * u;                  // slice
+        // (c) LDS rows in groups of LG (at most 64 VGPRs of codes, fewer when the
+        // register rows hold 128), then halves down to 1 (no duplicated rows)
+        {
+          constexpr int LG = (FMT == 0 ? 8 : 16) / KPL >= 8 ? 8 : ((FMT == 0 ? 8 : 16) / KPL >= 4 ? 4 : 2);
+          int r0 = 0;
+          for (; r0 + LG <= L; r0 += LG)
+            lds_row_group<FMT, KPL, LG>(lds, ldq16, r0, col[u], sv[u], sh_part, sl, lane, max_rows);
+          if constexpr (LG > 4) {
+            if (r0 + 4 <= L) {
+              lds_row_group<FMT, KPL, 4>(lds, ldq16, r0, col[u], sv[u], sh_part, sl, lane, max_rows);
+              r0 += 4;
+            }
           }
-        }
-        if constexpr (LG > 2) {
-          if (r0 + 2 <= L) {
-            lds_row_group<FMT, KPL, 2>(lds, ldq16, r0, col, sv, sh_part, wave, lane, max_rows);
-            r0 += 2;
+          if constexpr (LG > 2) {
+            if (r0 + 2 <= L) {
+              lds_row_group<FMT, KPL, 2>(lds, ldq16, r0, col[u], sv[u], sh_part, sl, lane, max_rows);
+              r0 += 2;
+            }
           }
+          if (r0 < L) lds_row_group<FMT, KPL, 1>(lds, ldq16, r0, col[u], sv[u], sh_part, sl, lane, max_rows);
         }
-        if (r0 < L) lds_row_group<FMT, KPL, 1>(lds, ldq16, r0, col, sv, sh_part, wave, lane, max_rows);
+        // register rows
+        if (nreg > 0) {
+          float t[RR > 0 ? RR : 1];
+#pragma unroll
+          for (int i = 0; i < RR; ++i) t[i] = chunk_dot<FMT, KPL>(rr[u][i], sv[u]);
+          store_row_sums<(RR > 0 ? RR : 1)>(t, sh_part + sl * max_rows + L, nreg, lane);
+        }
+        // accumulation-register rows, copied to ordinary registers one row at a
+        // time where used (volatile, so the copies are not gathered ahead)
+        if (nacc > 0) {
+          float t[RA > 0 ? RA : 1];
+#pragma unroll
+          for (int i = 0; i < RA; ++i) {
+            uint4 m[KPL];
+#pragma unroll
+            for (int j = 0; j < KPL; ++j) {
+              asm volatile("v_accvgpr_read_b32 %0, %1" : "=v"(m[j].x) : "a"(ra[u][i][j].x));
+              asm volatile("v_accvgpr_read_b32 %0, %1" : "=v"(m[j].y) : "a"(ra[u][i][j].y));
+              asm volatile("v_accvgpr_read_b32 %0, %1" : "=v"(m[j].z) : "a"(ra[u][i][j].z));
+              asm volatile("v_accvgpr_read_b32 %0, %1" : "=v"(m[j].w) : "a"(ra[u][i][j].w));
+            }
+            t[i] = chunk_dot<FMT, KPL>(m, sv[u]);
+          }
+          store_row_sums<(RA > 0 ? RA : 1)>(t, sh_part + sl * max_rows + L + RR, nacc, lane);
+        }
       }
-      // register rows
-      if (nreg > 0) {
-        float t[RR > 0 ? RR : 1];
-  #pragma unroll
-        for (int i = 0; i < RR; ++i) t[i] = chunk_dot<FMT, KPL>(rr[i], sv);
-        store_row_sums<(RR > 0 ? RR : 1)>(t, sh_part + wave * max_rows + L, nreg, lane);
-      }
-      // streamed rows
+      // streamed rows: every slice's loads of a batch in flight together
       for (int r0 = stream_begin; r0 < nrows; r0 += RB) {
-        uint4 m[RB][KPL];
-  #pragma unroll
-        for (int i = 0; i < RB; ++i) {
-          const int row = min(r0 + i, nrows - 1);
-  #pragma unroll
-          for (int j = 0; j < KPL; ++j) m[i][j] = slab[(int64_t)row * ldq16 + col[j]];
+        uint4 m[VW][RB][KPL];
+#pragma unroll
+        for (int u = 0; u < VW; ++u)
+#pragma unroll
+          for (int i = 0; i < RB; ++i) {
+            const int row = min(r0 + i, nrows - 1);
+#pragma unroll
+            for (int j = 0; j < KPL; ++j) m[u][i][j] = slab[(int64_t)row * ldq16 + col[u][j]];
+          }
+#pragma unroll
+        for (int u = 0; u < VW; ++u) {
+          float t[RB];
+#pragma unroll
+          for (int i = 0; i < RB; ++i) t[i] = chunk_dot<FMT, KPL>(m[u][i], sv[u]);
+          store_row_sums<RB>(t, sh_part + (wave + PW * u) * max_rows + r0, nrows - r0, lane);
         }
-        float t[RB];
-  #pragma unroll
-        for (int i = 0; i < RB; ++i) t[i] = chunk_dot<FMT, KPL>(m[i], sv);
-        store_row_sums<RB>(t, sh_part + wave * max_rows + r0, nrows - r0, lane);
       }
     }
     __syncthreads();
@@ -1054,12 +1144,25 @@ __global__ __launch_bounds__(kBlock) void persist_reset_kernel(uint32_t *bar, ui
   if (w != nullptr) __hip_atomic_store(w, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-template <int FMT, int KPL, int GS, bool PANELS>
+constexpr int kTileCache = 128;                    // most subapertures per workgroup with LDS descriptors
+
+// Register rows per slice: FP32 slabs use 4 wavefronts of two slices each, one
+// row of ordinary registers and 256 accumulation registers of rows; the
+// reduced formats, whose slabs fit on chip, use 8 wavefronts and 64 ordinary
+// registers of codes; slope panels stream every row.
+template <int FMT, int KPL, bool PANELS, bool WIDE>
+struct FrameShape {
+  static constexpr int VW = (WIDE && FMT == 0 && !PANELS && KPL <= 4) ? 2 : 1;
+  static constexpr int RR = PANELS ? 0 : (VW == 2 ? 4 / KPL : (FMT == 0 ? 24 : 16) / KPL);
+  static constexpr int RA = VW == 2 ? 32 / KPL : 0;
+};
+
+template <int FMT, int KPL, int GS, bool PANELS, bool WIDE>
 static hipError_t launch_frames_variant(const PersistArgs &p, int G, int max_rows, hipStream_t st) {
   constexpr int W = 8;
-  // register rows: 96 (f32) / 64 VGPRs of codes per lane; none when panels stream every row
-  constexpr int RR = PANELS ? 0 : (FMT == 0 ? 24 : 16) / KPL;
-  auto kern = frames_kernel<FMT, KPL, RR, GS, PANELS>;
+  using FS = FrameShape<FMT, KPL, PANELS, WIDE>;
+  constexpr int NT = 512 / FS::VW;
+  auto kern = frames_kernel<FMT, KPL, FS::RR, FS::RA, FS::VW, GS, PANELS>;
   int dev = 0, ncu = 0, lds_max = 0;
   hipError_t e;
   if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
@@ -1067,41 +1170,53 @@ static hipError_t launch_frames_variant(const PersistArgs &p, int G, int max_row
   if ((e = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev)) != hipSuccess) return e;
   const int64_t part_bytes = (int64_t)W * max_rows * sizeof(float);
   const int64_t static_bytes = 64;                 // sh_abort and alignment slack
-  int64_t avail = (int64_t)lds_max - part_bytes - static_bytes;
+  // tile descriptors and reference slopes of a workgroup's subapertures, kept in LDS
+  const int per_wg = (p.cal.n_valid + G - 1) / G;
+  const int tile_cap = per_wg <= kTileCache ? per_wg : 0;
+  const int64_t tile_bytes = (int64_t)tile_cap * (sizeof(TileDesc) + sizeof(float2));
+  int64_t avail = (int64_t)lds_max - part_bytes - tile_bytes - static_bytes;
   int lds_rows = (avail > 0 && !PANELS) ? (int)(avail / p.mvm.ldq_bytes) : 0;
   if (lds_rows > max_rows) lds_rows = max_rows;
-  const size_t lds = (size_t)lds_rows * p.mvm.ldq_bytes + (size_t)part_bytes;
+  const size_t lds = (size_t)lds_rows * p.mvm.ldq_bytes + (size_t)part_bytes + (size_t)tile_bytes;
   if ((e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)lds)) != hipSuccess)
     return e;
   int per_cu = 0;
-  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, W * 64, lds)) != hipSuccess) return e;
+  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, NT, lds)) != hipSuccess) return e;
   if (per_cu * ncu < G) return hipErrorCooperativeLaunchTooLarge;
   persist_reset_kernel<<<(64 + G + kBlock - 1) / kBlock, kBlock, 0, st>>>(p.bar, p.abort_flag, G);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   PersistArgs pa = p;
-  int32_t mr = max_rows, lr = lds_rows;
-  void *args[] = {&pa, &mr, &lr};
-  e = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(kern), dim3(G), dim3(W * 64), args, lds, st);
+  int32_t mr = max_rows, lr = lds_rows, tc = tile_cap;
+  void *args[] = {&pa, &mr, &lr, &tc};
+  e = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(kern), dim3(G), dim3(NT), args, lds, st);
   if (e != hipSuccess) return e;
   return hipGetLastError();
 }
 
-template <int FMT, int KPL, bool PANELS>
+template <int FMT, int KPL, bool PANELS, bool WIDE>
 static hipError_t launch_frames_gs(const PersistArgs &p, int G, int max_rows, hipStream_t st) {
   const int n = p.cal.max_n;
-  if (n <= 8) return launch_frames_variant<FMT, KPL, 8, PANELS>(p, G, max_rows, st);
-  if (n <= 16) return launch_frames_variant<FMT, KPL, 16, PANELS>(p, G, max_rows, st);
-  return launch_frames_variant<FMT, KPL, 32, PANELS>(p, G, max_rows, st);
+  if (n <= 8) return launch_frames_variant<FMT, KPL, 8, PANELS, WIDE>(p, G, max_rows, st);
+  if (n <= 16) return launch_frames_variant<FMT, KPL, 16, PANELS, WIDE>(p, G, max_rows, st);
+  return launch_frames_variant<FMT, KPL, 32, PANELS, WIDE>(p, G, max_rows, st);
+}
+
+// FP32 slabs of at most 256 rows per workgroup use the 4-wavefront shape
+// (one integrator row per thread).
+template <int FMT, int KPL, bool PANELS>
+static hipError_t launch_frames_rows(const PersistArgs &p, int G, int max_rows, hipStream_t st) {
+  if (max_rows <= 256) return launch_frames_gs<FMT, KPL, PANELS, true>(p, G, max_rows, st);
+  return launch_frames_gs<FMT, KPL, PANELS, false>(p, G, max_rows, st);
 }
 
 template <int FMT>
 static hipError_t launch_frames_fmt(const PersistArgs &p, int G, int max_rows, int kpl, hipStream_t st) {
-  if (kpl <= 1) return launch_frames_gs<FMT, 1, false>(p, G, max_rows, st);
-  if (kpl <= 2) return launch_frames_gs<FMT, 2, false>(p, G, max_rows, st);
-  if (kpl <= 4) return launch_frames_gs<FMT, 4, false>(p, G, max_rows, st);
-  if (kpl <= 8) return launch_frames_gs<FMT, 8, false>(p, G, max_rows, st);
-  return launch_frames_gs<FMT, PanelShape<FMT>::KPLP, true>(p, G, max_rows, st);
+  if (kpl <= 1) return launch_frames_rows<FMT, 1, false>(p, G, max_rows, st);
+  if (kpl <= 2) return launch_frames_rows<FMT, 2, false>(p, G, max_rows, st);
+  if (kpl <= 4) return launch_frames_rows<FMT, 4, false>(p, G, max_rows, st);
+  if (kpl <= 8) return launch_frames_gs<FMT, 8, false, false>(p, G, max_rows, st);
+  return launch_frames_gs<FMT, PanelShape<FMT>::KPLP, true, false>(p, G, max_rows, st);
 }
 
 hipError_t launch_frames(const PersistArgs &p, int blocks, int rows_per_batch, hipStream_t st) {

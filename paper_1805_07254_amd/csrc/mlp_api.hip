@@ -8,6 +8,7 @@
 //           dH [B][n_hid], dZ1 [B][n_hid] (+ bfloat16), per-row squared errors [B]
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <new>
 #include <string>
@@ -57,6 +58,8 @@ struct rtc_mlp {
   Tensor W1, b1, W2, b2;
   float *Z1 = nullptr, *Y = nullptr, *dY = nullptr, *dH = nullptr, *dZ1 = nullptr, *row_sq = nullptr;
   uint16_t *Hb = nullptr, *dYb = nullptr, *dZ1b = nullptr;
+  float *ws = nullptr;     // split-K partial tiles of the training products
+  int64_t ws_len = 0;
   std::string err = "no error";
 };
 
@@ -107,6 +110,8 @@ void free_tensor(Tensor &t) {
 // Forward into m->Z1 / Hb / y (y has batch rows of n_out).
 hipError_t forward(rtc_mlp *m, int32_t B, const float *x, float *y, hipStream_t st) {
   rtcm::GemmArgs g{};
+  g.ws = m->ws;
+  g.ws_len = m->ws_len;
   g.M = B;
   g.N = m->n_hid;
   g.K = m->n_in;
@@ -125,6 +130,8 @@ hipError_t forward(rtc_mlp *m, int32_t B, const float *x, float *y, hipStream_t 
   hipError_t e = rtcm::launch_gemm(g, st);
   if (e != hipSuccess) return e;
   rtcm::GemmArgs h{};
+  h.ws = m->ws;
+  h.ws_len = m->ws_len;
   h.M = B;
   h.N = m->n_out;
   h.K = m->n_hid;
@@ -187,6 +194,13 @@ rtc_status rtc_mlp_create(int32_t n_in, int32_t n_hidden, int32_t n_out, int32_t
   if (e == hipSuccess) e = hipMalloc(&m->dZ1, (size_t)B * n_hidden * sizeof(float));
   if (e == hipSuccess) e = hipMalloc(&m->dZ1b, (size_t)B * n_hidden * sizeof(uint16_t));
   if (e == hipSuccess) e = hipMalloc(&m->row_sq, (size_t)B * sizeof(float));
+  {
+    // up to 8 splits of the largest product's output
+    const int64_t mn = std::max(std::max(B * n_hidden, B * (int64_t)n_out),
+                                std::max((int64_t)n_out * n_hidden, (int64_t)n_hidden * n_in));
+    m->ws_len = 8 * mn;
+    if (e == hipSuccess) e = hipMalloc(&m->ws, (size_t)m->ws_len * sizeof(float));
+  }
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
     const rtc_status s = hfail(nullptr, e, "rtc_mlp_create");
@@ -254,6 +268,8 @@ rtc_status rtc_mlp_loss_grad(rtc_mlp *m, int32_t B, const float *d_x, const floa
   if (e == hipSuccess) e = rtcm::launch_loss_grad(m->Y, d_t, B, m->n_out, m->dY, m->dYb, m->row_sq, d_loss, st);
   if (e == hipSuccess) {                            // dW2 = dY^T H
     rtcm::GemmArgs g{};
+    g.ws = m->ws;
+    g.ws_len = m->ws_len;
     g.M = m->n_out;
     g.N = m->n_hid;
     g.K = B;
@@ -271,6 +287,8 @@ rtc_status rtc_mlp_loss_grad(rtc_mlp *m, int32_t B, const float *d_x, const floa
   if (e == hipSuccess) e = rtcm::launch_col_sum(m->dY, B, m->n_out, m->b2.g, st);
   if (e == hipSuccess) {                            // dH = dY W2
     rtcm::GemmArgs g{};
+    g.ws = m->ws;
+    g.ws_len = m->ws_len;
     g.M = B;
     g.N = m->n_hid;
     g.K = m->n_out;
@@ -288,6 +306,8 @@ rtc_status rtc_mlp_loss_grad(rtc_mlp *m, int32_t B, const float *d_x, const floa
   if (e == hipSuccess) e = rtcm::launch_gelu_back(m->dH, m->Z1, m->dZ1, m->dZ1b, (int64_t)B * m->n_hid, st);
   if (e == hipSuccess) {                            // dW1 = dZ1^T X
     rtcm::GemmArgs g{};
+    g.ws = m->ws;
+    g.ws_len = m->ws_len;
     g.M = m->n_hid;
     g.N = m->n_in;
     g.K = B;
@@ -353,6 +373,7 @@ void rtc_mlp_destroy(rtc_mlp *m) {
   dfree(m->dH);
   dfree(m->dZ1);
   dfree(m->dZ1b);
+  dfree(m->ws);
   dfree(m->row_sq);
   delete m;
 }

@@ -25,6 +25,8 @@ struct GemmArgs {
   float *c_pre;        // nullable: value before the GELU
   float *c_f32;        // nullable: result
   uint16_t *c_bf16;    // nullable: result rounded to bfloat16
+  float *ws;           // nullable: split-K workspace of ws_len floats (no split without it)
+  int64_t ws_len;
 };
 hipError_t launch_gemm(const GemmArgs &g, hipStream_t st);
 

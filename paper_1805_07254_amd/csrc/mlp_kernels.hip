@@ -14,6 +14,8 @@
 // Every reduction has a fixed order: results are run-to-run deterministic.
 #include "mlp_kernels.h"
 
+#include <algorithm>
+
 namespace rtcm {
 namespace {
 
@@ -36,73 +38,211 @@ __device__ __forceinline__ float gelu_grad(float z) {
 }
 
 // ---------------------------------------------------------------------------
-// GEMM.  Workgroup = 4 wavefronts computing a 64 x 64 tile of C; wavefront w
-// owns the 32 x 32 sub-tile (w / 2, w % 2).  Per K step of 32 the A (64 x 32)
-// and B (32 x 64) tiles are staged in LDS as bfloat16 (zero outside the
-// matrices), then each wavefront issues two 32x32x16 matrix-core operations.
+// GEMM.  Workgroup = 4 wavefronts computing a BM x BN tile of C (64 x 64);
+// wavefront w owns rows [(w / 2) BM / 2, +BM / 2) and columns
+// [(w % 2) BN / 2, +BN / 2), that is (BM / 64) x (BN / 64) blocks of 32 x 32.  K is walked in tiles
+// of 64 through two LDS buffers: the next tile is loaded into registers while
+// the matrix cores work on the current one.  A tile is read in runs of 4
+// elements along the operand's contiguous dimension (k for X W^T, m or n for
+// the weight gradients), one 8- or 16-byte load per run where the rows are
+// aligned, element by element otherwise.  The K range may be split over
+// gridDim.z workgroups whose float32 partial tiles a second kernel adds in
+// split order.
 // Operand layout of the 32x32x16 operation: lane l supplies row (A) or column
 // (B) l % 32 and the eight consecutive k = 8 (l / 32) .. 8 (l / 32) + 7; its
 // 16 results are column l % 32, rows 8 (v / 4) + 4 (l / 32) + v % 4.
-constexpr int kTile = 64, kK = 32, kPad = 8;
+constexpr int kKT = 64, kKP = kKT + 8;
 
-__global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g) {
-  __shared__ uint16_t As[kTile][kK + kPad];        // [m][k]
-  __shared__ uint16_t Bs[kTile][kK + kPad];        // [n][k]
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int m0 = blockIdx.y * kTile, n0 = blockIdx.x * kTile;
-  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-  f32x16 acc;
-#pragma unroll
-  for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
+__device__ __forceinline__ void gemm_epilogue(const GemmArgs &g, int m, int n, float acc) {
+  float z = g.alpha * acc;
+  if (g.bias) z += g.bias[n];
+  const int64_t o = (int64_t)m * g.ldc + n;
+  if (g.c_pre) g.c_pre[o] = z;
+  const float y = g.gelu ? gelu(z) : z;
+  if (g.c_f32) g.c_f32[o] = y;
+  if (g.c_bf16) g.c_bf16[o] = bf16_bits(y);
+}
 
-  for (int k0 = 0; k0 < g.K; k0 += kK) {
-    // stage: 64 x 32 elements of each operand, 8 per thread
+// One operand of a tile: R rows (m of A or n of B) x kKT k.  Element (i, k) of
+// the operand matrix is at f32 / b16 + i si + k sk; `kc`: contiguous along k
+// (sk == 1) else along i (si == 1); `vec`: runs of 4 may be read as one load.
+struct Operand {
+  const float *f32;
+  const uint16_t *b16;
+  int64_t si, sk;
+  int rows;                                        // valid i (M or N)
+  bool kc, vec;
+};
+
+template <int R>
+struct TileRegs {
+  static constexpr int NV = R * kKT / 4 / 256;     // runs of 4 per thread
+  uint2 v[NV];                                     // 4 bfloat16 codes of a run, packed
+};
+
+__device__ __forceinline__ uint2 pack4(uint16_t a, uint16_t b, uint16_t c, uint16_t d) {
+  return make_uint2((uint32_t)a | ((uint32_t)b << 16), (uint32_t)c | ((uint32_t)d << 16));
+}
+__device__ __forceinline__ uint16_t unpack4(const uint2 &x, int e) {
+  const uint32_t w = e < 2 ? x.x : x.y;
+  return (uint16_t)((e & 1) ? (w >> 16) : (w & 0xffffu));
+}
+
+// Run r of this thread: first element (i, kk) and direction.
+template <int R>
+__device__ __forceinline__ void run_pos(const Operand &o, int r, int &i, int &kk) {
+  const int q = r * 256 + threadIdx.x;
+  if (o.kc) {
+    i = q / (kKT / 4);
+    kk = (q % (kKT / 4)) * 4;
+  } else {
+    kk = q / (R / 4);
+    i = (q % (R / 4)) * 4;
+  }
+}
+
+// VEC: every run is aligned and lies wholly inside or wholly outside the
+// matrix (all sizes multiples of 4), so there is no element-wise path.
+template <int R, bool VEC>
+__device__ __forceinline__ void load_tile(const Operand &o, int i0, int k0, int k_end, TileRegs<R> &t) {
 #pragma unroll
-    for (int r = 0; r < 8; ++r) {
-      const int e = r * 256 + tid;
-      const int i = e / kK, kk = e % kK;           // i: row of A / column of B within the tile
-      const int m = m0 + i, n = n0 + i, k = k0 + kk;
-      uint16_t a = 0, b = 0;
-      if (m < g.M && k < g.K) {
-        const int64_t off = (int64_t)m * g.sam + (int64_t)k * g.sak;
-        a = g.a_f32 ? bf16_bits(g.a_f32[off]) : g.a_bf16[off];
+  for (int r = 0; r < TileRegs<R>::NV; ++r) {
+    int i, kk;
+    run_pos<R>(o, r, i, kk);
+    const int gi = i0 + i, gk = k0 + kk;
+    const int64_t base = (int64_t)gi * o.si + (int64_t)gk * o.sk;
+    const bool whole = o.kc ? (gi < o.rows && gk + 3 < k_end) : (gi + 3 < o.rows && gk < k_end);
+    if (VEC) {
+      uint2 x = make_uint2(0u, 0u);
+      if (whole) {
+        if (o.f32) {
+          const float4 y = *reinterpret_cast<const float4 *>(o.f32 + base);
+          x = pack4(bf16_bits(y.x), bf16_bits(y.y), bf16_bits(y.z), bf16_bits(y.w));
+        } else {
+          x = *reinterpret_cast<const uint2 *>(o.b16 + base);
+        }
       }
-      if (n < g.N && k < g.K) {
-        const int64_t off = (int64_t)k * g.sbk + (int64_t)n * g.sbn;
-        b = g.b_f32 ? bf16_bits(g.b_f32[off]) : g.b_bf16[off];
+      t.v[r] = x;
+    } else if (o.vec && whole) {
+      if (o.f32) {
+        const float4 x = *reinterpret_cast<const float4 *>(o.f32 + base);
+        t.v[r] = pack4(bf16_bits(x.x), bf16_bits(x.y), bf16_bits(x.z), bf16_bits(x.w));
+      } else {
+        t.v[r] = *reinterpret_cast<const uint2 *>(o.b16 + base);
       }
-      As[i][kk] = a;
-      Bs[i][kk] = b;
+    } else {
+      uint16_t x[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int ei = gi + (o.kc ? 0 : e), ek = gk + (o.kc ? e : 0);
+        x[e] = 0;
+        if (ei < o.rows && ek < k_end) {
+          const int64_t off = (int64_t)ei * o.si + (int64_t)ek * o.sk;
+          x[e] = o.f32 ? bf16_bits(o.f32[off]) : o.b16[off];
+        }
+      }
+      t.v[r] = pack4(x[0], x[1], x[2], x[3]);
+    }
+  }
+}
+
+template <int R>
+__device__ __forceinline__ void store_tile(const Operand &o, const TileRegs<R> &t, uint16_t (*S)[kKP]) {
+#pragma unroll
+  for (int r = 0; r < TileRegs<R>::NV; ++r) {
+    int i, kk;
+    run_pos<R>(o, r, i, kk);
+    if (o.kc) {
+      *reinterpret_cast<uint2 *>(&S[i][kk]) = t.v[r];
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) S[i + e][kk] = unpack4(t.v[r], e);
+    }
+  }
+}
+
+template <int BM, int BN, bool VEC>
+__global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g, int k_chunk, int a_vec, int b_vec) {
+  constexpr int MB = BM / 64, NB = BN / 64;        // 32 x 32 blocks per wavefront along m and n
+  __shared__ __align__(16) uint16_t As[2][BM][kKP];   // [m][k]
+  __shared__ __align__(16) uint16_t Bs[2][BN][kKP];   // [n][k]
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  const int kb0 = blockIdx.z * k_chunk;
+  const int kb1 = min(g.K, kb0 + k_chunk);
+  const int wm = (wave >> 1) * (BM / 2), wn = (wave & 1) * (BN / 2);
+  const Operand A{g.a_f32, g.a_bf16, g.sam, g.sak, g.M, g.sak == 1, a_vec != 0};
+  const Operand B{g.b_f32, g.b_bf16, g.sbn, g.sbk, g.N, g.sbk == 1, b_vec != 0};
+  f32x16 acc[MB][NB];
+#pragma unroll
+  for (int b = 0; b < MB; ++b)
+#pragma unroll
+    for (int c = 0; c < NB; ++c)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[b][c][v] = 0.0f;
+
+  TileRegs<BM> ra;
+  TileRegs<BN> rb;
+  if (kb0 < kb1) {
+    load_tile<BM, VEC>(A, m0, kb0, kb1, ra);
+    load_tile<BN, VEC>(B, n0, kb0, kb1, rb);
+    store_tile<BM>(A, ra, As[0]);
+    store_tile<BN>(B, rb, Bs[0]);
+  }
+  __syncthreads();
+  int buf = 0;
+  for (int k0 = kb0; k0 < kb1; k0 += kKT) {
+    const bool more = k0 + kKT < kb1;
+    if (more) {                                     // in flight while the matrix cores work
+      load_tile<BM, VEC>(A, m0, k0 + kKT, kb1, ra);
+      load_tile<BN, VEC>(B, n0, k0 + kKT, kb1, rb);
+    }
+#pragma unroll
+    for (int ks = 0; ks < kKT; ks += 16) {
+      const int kq = ks + 8 * (lane >> 5);
+      bf16x8 bv[NB];
+#pragma unroll
+      for (int c = 0; c < NB; ++c)
+        bv[c] = *reinterpret_cast<const bf16x8 *>(&Bs[buf][wn + 32 * c + (lane & 31)][kq]);
+#pragma unroll
+      for (int b = 0; b < MB; ++b) {
+        const bf16x8 av = *reinterpret_cast<const bf16x8 *>(&As[buf][wm + 32 * b + (lane & 31)][kq]);
+#pragma unroll
+        for (int c = 0; c < NB; ++c) acc[b][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv[c], acc[b][c], 0, 0, 0);
+      }
+    }
+    if (more) {
+      store_tile<BM>(A, ra, As[buf ^ 1]);
+      store_tile<BN>(B, rb, Bs[buf ^ 1]);
     }
     __syncthreads();
-#pragma unroll
-    for (int ks = 0; ks < kK; ks += 16) {
-      bf16x8 av, bv;
-      const int kb = ks + 8 * (lane >> 5);
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        av[j] = __builtin_bit_cast(__bf16, As[wm + (lane & 31)][kb + j]);
-        bv[j] = __builtin_bit_cast(__bf16, Bs[wn + (lane & 31)][kb + j]);
-      }
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
-    }
-    __syncthreads();
+    buf ^= 1;
   }
 
-  const int n = n0 + wn + (lane & 31);
 #pragma unroll
-  for (int v = 0; v < 16; ++v) {
-    const int m = m0 + wm + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-    if (m < g.M && n < g.N) {
-      float z = g.alpha * acc[v];
-      if (g.bias) z += g.bias[n];
-      const int64_t o = (int64_t)m * g.ldc + n;
-      if (g.c_pre) g.c_pre[o] = z;
-      const float y = g.gelu ? gelu(z) : z;
-      if (g.c_f32) g.c_f32[o] = y;
-      if (g.c_bf16) g.c_bf16[o] = bf16_bits(y);
-    }
+  for (int c = 0; c < NB; ++c) {
+    const int n = n0 + wn + 32 * c + (lane & 31);
+#pragma unroll
+    for (int b = 0; b < MB; ++b)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int m = m0 + wm + 32 * b + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+        if (m < g.M && n < g.N) {
+          if (gridDim.z == 1) gemm_epilogue(g, m, n, acc[b][c][v]);
+          else g.ws[((int64_t)blockIdx.z * g.M + m) * g.N + n] = acc[b][c][v];
+        }
+      }
   }
+}
+
+// Sum of the split-K partial tiles in split order, then the epilogue.
+__global__ __launch_bounds__(256) void gemm_split_sum_kernel(GemmArgs g, int splits) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t mn = (int64_t)g.M * g.N;
+  if (t >= mn) return;
+  float s = g.ws[t];
+  for (int z = 1; z < splits; ++z) s += g.ws[(int64_t)z * mn + t];
+  gemm_epilogue(g, (int)(t / g.N), (int)(t % g.N), s);
 }
 
 // ---------------------------------------------------------------------------
@@ -136,12 +276,19 @@ __global__ __launch_bounds__(256) void loss_grad_kernel(const float *Y, const fl
 }
 
 // loss = sum of the row sums / (B n_out), in row order.
-__global__ void loss_total_kernel(const float *row_sq, int B, int n, float *loss) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    double s = 0.0;
-    for (int b = 0; b < B; ++b) s += (double)row_sq[b];
-    loss[0] = (float)(s / ((double)B * (double)n));
+// loss = sum of the row sums (float64; thread t adds rows t, t + 256, ... in
+// order, then a fixed pairwise tree) / (B n).
+__global__ __launch_bounds__(256) void loss_total_kernel(const float *row_sq, int B, int n, float *loss) {
+  __shared__ double part[256];
+  double s = 0.0;
+  for (int b = threadIdx.x; b < B; b += 256) s += (double)row_sq[b];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+    __syncthreads();
   }
+  if (threadIdx.x == 0) loss[0] = (float)(part[0] / ((double)B * (double)n));
 }
 
 // dZ = dH * gelu'(Z) (float32 and bfloat16).
@@ -154,14 +301,32 @@ __global__ __launch_bounds__(256) void gelu_back_kernel(const float *dH, const f
   }
 }
 
-// db[j] = sum over rows b of dZ[b][j], rows in order.
-__global__ __launch_bounds__(256) void col_sum_kernel(const float *dZ, int B, int n, float *db) {
-  const int j = blockIdx.x * 256 + threadIdx.x;
+// db[j] = sum over rows b of dZ[b][j]: a workgroup of 16 wavefronts takes 64
+// columns; wavefront r adds rows r, r + 16, ... in order (8 loads in flight),
+// then the 16 partial sums are added in a fixed pairwise tree.
+__global__ __launch_bounds__(1024) void col_sum_kernel(const float *dZ, int B, int n, float *db) {
+  __shared__ float part[16][64];
+  const int c = threadIdx.x & 63, r = threadIdx.x >> 6;
+  const int j = blockIdx.x * 64 + c;
+  float s = 0.0f;
   if (j < n) {
-    float s = 0.0f;
-    for (int b = 0; b < B; ++b) s += dZ[(int64_t)b * n + j];
-    db[j] = s;
+    int b = r;
+    for (; b + 16 * 7 < B; b += 16 * 8) {
+      float v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = dZ[(int64_t)(b + 16 * u) * n + j];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += v[u];
+    }
+    for (; b < B; b += 16) s += dZ[(int64_t)b * n + j];
   }
+  part[r][c] = s;
+  __syncthreads();
+  for (int w = 8; w > 0; w >>= 1) {
+    if (r < w) part[r][c] += part[r + w][c];
+    __syncthreads();
+  }
+  if (r == 0 && j < n) db[j] = part[0][c];
 }
 
 // Adam with bias correction; refreshes the bfloat16 copy of the parameters.
@@ -263,8 +428,38 @@ __global__ __launch_bounds__(256) void denorm_kernel(const float *y, const float
 hipError_t launch_gemm(const GemmArgs &g, hipStream_t st) {
   if (g.M <= 0 || g.N <= 0) return hipSuccess;
   if (g.K < 0) return hipErrorInvalidValue;
-  const dim3 grid((g.N + kTile - 1) / kTile, (g.M + kTile - 1) / kTile);
-  gemm_bf16_kernel<<<grid, 256, 0, st>>>(g);
+  // 64 x 64 tiles; the K range is split until about 512 workgroups run (two
+  // per compute unit), within the workspace
+  // the aligned-run kernels need every run wholly inside or outside the matrix
+  auto vec_ok = [](const void *p, int bytes, int64_t s_run, int64_t s_other) {
+    return s_run == 1 && s_other % 4 == 0 && (reinterpret_cast<uintptr_t>(p) % (4 * bytes)) == 0;
+  };
+  const void *pa = g.a_f32 ? (const void *)g.a_f32 : (const void *)g.a_bf16;
+  const void *pb = g.b_f32 ? (const void *)g.b_f32 : (const void *)g.b_bf16;
+  const int ab = g.a_f32 ? 4 : 2, bb = g.b_f32 ? 4 : 2;
+  const int a_vec = g.sak == 1 ? vec_ok(pa, ab, g.sak, g.sam) : vec_ok(pa, ab, g.sam, g.sak);
+  const int b_vec = g.sbk == 1 ? vec_ok(pb, bb, g.sbk, g.sbn) : vec_ok(pb, bb, g.sbn, g.sbk);
+  const bool all_vec = a_vec && b_vec && g.M % 4 == 0 && g.N % 4 == 0 && g.K % 4 == 0;
+  // (128 x 128 tiles measured slower at these sizes: the K range per workgroup
+  // is a few tiles, so the pipeline's start and end dominate)
+  constexpr int bm = 64, bn = 64;
+  const int tiles = ((g.M + bm - 1) / bm) * ((g.N + bn - 1) / bn);
+  const int k_tiles = (g.K + kKT - 1) / kKT;
+  const int target = 512;
+  int splits = (target + tiles - 1) / tiles;
+  splits = std::min(splits, std::max(1, k_tiles / 2));
+  if (g.ws == nullptr) splits = 1;
+  else splits = (int)std::min<int64_t>(splits, g.ws_len / ((int64_t)g.M * g.N));
+  if (splits < 1) splits = 1;
+  const int k_chunk = ((k_tiles + splits - 1) / splits) * kKT;
+  splits = std::max(1, (g.K + k_chunk - 1) / k_chunk);
+  const dim3 grid((g.N + bn - 1) / bn, (g.M + bm - 1) / bm, splits);
+  if (all_vec) gemm_bf16_kernel<64, 64, true><<<grid, 256, 0, st>>>(g, k_chunk, a_vec, b_vec);
+  else gemm_bf16_kernel<64, 64, false><<<grid, 256, 0, st>>>(g, k_chunk, a_vec, b_vec);
+  if (splits > 1) {
+    const int64_t mn = (int64_t)g.M * g.N;
+    gemm_split_sum_kernel<<<(unsigned)((mn + 255) / 256), 256, 0, st>>>(g, splits);
+  }
   return hipGetLastError();
 }
 
@@ -282,7 +477,7 @@ hipError_t launch_round_bf16(const float *x, uint16_t *y, int64_t n, hipStream_t
 hipError_t launch_loss_grad(const float *Y, const float *T, int B, int n, float *dY, uint16_t *dYb, float *row_sq,
                             float *loss, hipStream_t st) {
   loss_grad_kernel<<<B, 256, 0, st>>>(Y, T, B, n, dY, dYb, row_sq);
-  loss_total_kernel<<<1, 64, 0, st>>>(row_sq, B, n, loss);
+  loss_total_kernel<<<1, 256, 0, st>>>(row_sq, B, n, loss);
   return hipGetLastError();
 }
 
@@ -292,7 +487,7 @@ hipError_t launch_gelu_back(const float *dH, const float *Z, float *dZ, uint16_t
 }
 
 hipError_t launch_col_sum(const float *dZ, int B, int n, float *db, hipStream_t st) {
-  col_sum_kernel<<<(n + 255) / 256, 256, 0, st>>>(dZ, B, n, db);
+  col_sum_kernel<<<(n + 63) / 64, 1024, 0, st>>>(dZ, B, n, db);
   return hipGetLastError();
 }
 

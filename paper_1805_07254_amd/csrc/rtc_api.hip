@@ -14,7 +14,9 @@
 //   sync     [4]                  uint32 completion counter
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
+#include <cstdint>
 #include <cstring>
 #include <new>
 #include <string>
@@ -456,6 +458,22 @@ static hipError_t launch_reconstruction(const rtc_ctx *c, rtck::MvmArgs ma, hipS
 }
 
 // Calibration arguments of one frame set (outputs left for the caller to set).
+// Largest float2 count of one workgroup's (dark, flat) blocks when G
+// workgroups share the subapertures of a persistent launch (the blocks are
+// contiguous in subaperture order).
+static int32_t calib_span(const rtc_ctx *c, int G) {
+  int64_t span = 0;
+  const int64_t n = c->n_valid;
+  for (int b = 0; b < G; ++b) {
+    const int64_t k0 = (int64_t)b * n / G, k1 = (int64_t)(b + 1) * n / G;
+    if (k1 <= k0) continue;
+    const int64_t lo = c->tiles_h[(size_t)k0].calib_off;
+    const int64_t hi = k1 < n ? (int64_t)c->tiles_h[(size_t)k1].calib_off : c->calib_len;
+    span = std::max(span, hi - lo);
+  }
+  return span > INT32_MAX ? 0 : (int32_t)span;
+}
+
 static rtck::CalibArgs calib_args(const rtc_ctx *c, const uint16_t *pix) {
   rtck::CalibArgs ca{};
   ca.pix = pix;
@@ -559,7 +577,9 @@ rtc_status rtc_frame_batch(rtc_ctx *c, int32_t n_frames, const uint16_t *d_pixel
     p.trace = c->d_trace;
     p.trace_frames = c->trace_frames;
     p.trace_groups = c->trace_groups;
-    hipError_t e = rtck::launch_frames(p, c->tuning.blocks > 0 ? c->tuning.blocks : c->n_cu, c->tuning.rows_per_wave, st);
+    const int blocks = c->tuning.blocks > 0 ? c->tuning.blocks : c->n_cu;
+    p.calib_span = calib_span(c, rtck::frames_grid(blocks, c->n_act));
+    hipError_t e = rtck::launch_frames(p, blocks, c->tuning.rows_per_wave, st);
     if (e == hipSuccess) return RTC_OK;
     if (e != hipErrorInvalidValue && e != hipErrorCooperativeLaunchTooLarge)
       return hip_fail(c, e, "rtc_frame_batch: persistent launch");

@@ -100,6 +100,8 @@ struct PersistArgs {
   uint64_t *trace;         // nullable [trace_frames][trace_groups][kTraceStages] stage stamps
   int32_t trace_frames;
   int32_t trace_groups;
+  int32_t calib_span;      // largest float2 count of one workgroup's (dark, flat) blocks for the
+                           // grid of frames_grid(); 0 = not known (they are then read from memory)
 };
 constexpr int kTraceStages = 8;
 
@@ -124,6 +126,9 @@ constexpr int kWords = kBarBase + kEnds + 4 * kMaxGroups;
 // beyond one per thread, LDS, register slices) and with the runtime's error
 // when the grid cannot be co-resident.
 hipError_t launch_frames(const PersistArgs &p, int blocks, int rows_per_batch, hipStream_t st);
+// Workgroups of a persistent launch asked for `blocks` workgroups (workgroup b
+// owns subapertures [b n_valid / G, (b + 1) n_valid / G)).
+int frames_grid(int blocks, int n_act);
 
 // Pixel-stream frames: a camera workgroup lands the rows of each frame in a
 // two-slot ring on a schedule (rows of frame f land uniformly over the readout

@@ -43,10 +43,108 @@ __device__ __forceinline__ int64_t xchg_pos(int64_t k, int epc) {
 // tl / rl (nullable): a copy of the tile descriptors and of the (x, y)
 // reference slopes of subapertures from some first one on (usually in LDS),
 // subaperture k at index kl.
-template <int GS, bool COH = false>
-__device__ __forceinline__ void calib_tile_row(const CalibArgs &a, int k, int i, int vec,
-                                               const TileDesc *tl = nullptr, int kl = 0,
-                                               const float2 *rl = nullptr) {
+// Slopes of subaperture k from its centre of gravity (cx, cy) minus its
+// reference slopes, stored (device-coherent when COH), with the optional user
+// copy and pixel count.
+template <bool COH>
+__device__ __forceinline__ void tile_publish(const CalibArgs &a, const TileDesc &t, int k, double cx, double cy,
+                                             int cnt, float2 r) {
+  const float sx = (float)(cx - (double)r.x);
+  const float sy = (float)(cy - (double)r.y);
+  if (COH) {
+    __hip_atomic_store(a.s_int + xchg_pos(t.sx, a.xchg_epc), sx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(a.s_int + xchg_pos(t.sy, a.xchg_epc), sy, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  } else {
+    a.s_int[t.sx] = sx;
+    a.s_int[t.sy] = sy;
+  }
+  if (a.s_user != nullptr) {
+    a.s_user[t.sx] = sx;
+    a.s_user[t.sy] = sy;
+  }
+  if (a.counts != nullptr) a.counts[k] = cnt;
+}
+
+// TL: the descriptor and reference slopes come from the copies tl / rl
+// (indexed kl); VEC: 4-byte pixel pairs and 16-byte (dark, flat) pairs.
+// Both are compile-time choices, so that every access has a known address
+// space and no loaded value has to be merged across branches: either would
+// make the compiler wait for all outstanding loads.  For tiles of up to 16
+// pixels a side every load is unconditional (positions past the row repeat
+// its last one), so all of a lane's loads are in flight before the first use;
+// wider tiles load only their own pixels (fewer registers).
+template <int GS, bool COH, bool TL, bool VEC>
+__device__ __forceinline__ void calib_tile_row(const CalibArgs &a, int k, int i, const TileDesc *tl = nullptr,
+                                               int kl = 0, const float2 *rl = nullptr) {
+  TileDesc t{};
+  if (k < a.n_valid) t = TL ? tl[kl] : a.tiles[k];
+  const int n = t.n;
+  const double half = 0.5 * (double)(n - 1);
+  double S = 0.0, Sx = 0.0;
+  int cnt = 0;
+  if (k < a.n_valid && i < n) {
+    const uint16_t *prow = a.pix + (int64_t)t.off + (int64_t)i * t.pitch;
+    const float2 *crow = a.calib + (int64_t)t.calib_off + (int64_t)i * n;
+    uint32_t raw[GS];
+    float2 cf[GS];
+    if constexpr (VEC) {
+      const uint32_t *p2 = reinterpret_cast<const uint32_t *>(prow);
+      const float4 *c2 = reinterpret_cast<const float4 *>(crow);
+      if constexpr (GS <= 16) {
+        const int last = n / 2 - 1;                // rows have even width here
+        uint32_t w[GS / 2];
+        float4 c[GS / 2];
+#pragma unroll
+        for (int j = 0; j < GS / 2; ++j) {
+          const int jj = j < last ? j : last;
+          w[j] = p2[jj];
+          c[j] = c2[jj];
+        }
+#pragma unroll
+        for (int j = 0; j < GS / 2; ++j) {
+          raw[2 * j] = w[j] & 0xffffu;
+          raw[2 * j + 1] = w[j] >> 16;
+          cf[2 * j] = make_float2(c[j].x, c[j].y);
+          cf[2 * j + 1] = make_float2(c[j].z, c[j].w);
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < GS / 2; ++j) {
+          if (2 * j < n) {
+            const uint32_t w = p2[j];
+            const float4 c = c2[j];
+            raw[2 * j] = w & 0xffffu;
+            raw[2 * j + 1] = w >> 16;
+            cf[2 * j] = make_float2(c.x, c.y);
+            cf[2 * j + 1] = make_float2(c.z, c.w);
+          }
+        }
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < GS; ++j) {
+        if (GS <= 16 || j < n) {
+          const int jj = j < n - 1 ? j : n - 1;
+          raw[j] = prow[jj];
+          cf[j] = crow[jj];
+        }
+      }
+    }
+    tile_row_sums<GS>(raw, cf, n, t.thr, a.mode == 1, half, S, Sx, cnt);
+  }
+  double cx, cy;
+  tile_centroid<GS>(S, Sx, cnt, i, half, cx, cy, cnt);
+  if (i == 0 && k < a.n_valid)
+    tile_publish<COH>(a, t, k, cx, cy, cnt, TL ? rl[kl] : make_float2(a.ref[t.sx], a.ref[t.sy]));
+}
+
+// The same with the descriptor source and pixel-pair mode chosen at run time
+// (tl == nullptr: from memory), for tiles wider than 16 pixels in the
+// persistent kernel, where the specialised copies need more registers than
+// the on-chip matrix rows leave.
+template <int GS, bool COH>
+__device__ __forceinline__ void calib_tile_row_any(const CalibArgs &a, int k, int i, int vec, const TileDesc *tl,
+                                                   int kl, const float2 *rl) {
   TileDesc t{};
   if (k < a.n_valid) t = tl != nullptr ? tl[kl] : a.tiles[k];
   const int n = t.n;
@@ -85,31 +183,134 @@ __device__ __forceinline__ void calib_tile_row(const CalibArgs &a, int k, int i,
   }
   double cx, cy;
   tile_centroid<GS>(S, Sx, cnt, i, half, cx, cy, cnt);
-  if (i == 0 && k < a.n_valid) {
-    const float2 r = rl != nullptr ? rl[kl] : make_float2(a.ref[t.sx], a.ref[t.sy]);
-    const float sx = (float)(cx - (double)r.x);
-    const float sy = (float)(cy - (double)r.y);
-    if (COH) {
-      __hip_atomic_store(a.s_int + xchg_pos(t.sx, a.xchg_epc), sx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(a.s_int + xchg_pos(t.sy, a.xchg_epc), sy, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (i == 0 && k < a.n_valid)
+    tile_publish<COH>(a, t, k, cx, cy, cnt, rl != nullptr ? rl[kl] : make_float2(a.ref[t.sx], a.ref[t.sy]));
+}
+
+// Subapertures [k_begin, k_end) of a workgroup of NT threads, one pass of
+// NT / GS tiles at a time, slopes published with device-coherent stores; tl /
+// rl (nullable): the workgroup's copies of its descriptors and reference
+// slopes.
+template <int GS, int NT>
+__device__ __forceinline__ void wg_calibration(const CalibArgs &a, int k_begin, int k_end, int vec,
+                                               const TileDesc *tl, const float2 *rl) {
+  const int i = threadIdx.x & (GS - 1);
+  for (int k0 = k_begin; k0 < k_end; k0 += NT / GS) {
+    const int kk = k0 + (int)threadIdx.x / GS;
+    const int k = kk < k_end ? kk : a.n_valid;
+    if constexpr (GS > 16) {
+      calib_tile_row_any<GS, true>(a, k, i, vec, tl, kk - k_begin, rl);
+    } else if (tl != nullptr) {
+      if (vec)
+        calib_tile_row<GS, true, true, true>(a, k, i, tl, kk - k_begin, rl);
+      else
+        calib_tile_row<GS, true, true, false>(a, k, i, tl, kk - k_begin, rl);
     } else {
-      a.s_int[t.sx] = sx;
-      a.s_int[t.sy] = sy;
+      if (vec)
+        calib_tile_row<GS, true, false, true>(a, k, i);
+      else
+        calib_tile_row<GS, true, false, false>(a, k, i);
     }
-    if (a.s_user != nullptr) {
-      a.s_user[t.sx] = sx;
-      a.s_user[t.sy] = sy;
-    }
-    if (a.counts != nullptr) a.counts[k] = cnt;
   }
 }
 
-template <int GS>
-__global__ __launch_bounds__(kBlock) void calib_cog_kernel(CalibArgs a, int vec) {
+// Split form of calib_tile_row for workgroups with many subapertures (slope
+// panels) that keep their tile descriptors, reference slopes and (dark, flat)
+// blocks in LDS, so that the pixel loads of several passes are in flight
+// together: pixel_row_fetch issues the loads of one tile row (pairs packed in
+// words when VEC) for a descriptor read beforehand, pixel_row_finish reads the
+// (dark, flat) pairs from LDS (block of subaperture k at t.calib_off -
+// cl_base; descriptor and reference slopes at k - k_begin) and completes the
+// tile with the same arithmetic.  Every pointer has a known address space and,
+// for tiles of up to 16 pixels a side, every load is unconditional, so the
+// compiler's waits are partial.
+template <int GS, bool VEC>
+__device__ __forceinline__ void pixel_row_fetch(const CalibArgs &a, int k, int i, const TileDesc &t,
+                                                uint32_t (&w)[GS]) {
+  if (k < a.n_valid && i < t.n) {
+    const uint16_t *prow = a.pix + (int64_t)t.off + (int64_t)i * t.pitch;
+    if constexpr (VEC) {
+      const uint32_t *p2 = reinterpret_cast<const uint32_t *>(prow);
+      const int last = t.n / 2 - 1;
+#pragma unroll
+      for (int j = 0; j < GS / 2; ++j)
+        if (GS <= 16 || 2 * j < t.n) w[j] = p2[j < last ? j : last];
+    } else {
+#pragma unroll
+      for (int j = 0; j < GS; ++j)
+        if (GS <= 16 || j < t.n) w[j] = prow[j < t.n - 1 ? j : t.n - 1];
+    }
+  }
+}
+
+template <int GS, bool VEC>
+__device__ __forceinline__ void pixel_row_finish(const CalibArgs &a, int k, int i, const TileDesc &t,
+                                                 const uint32_t (&w)[GS], const float2 *cl, int32_t cl_base,
+                                                 const float2 *rl, int kl) {
+  const int n = t.n;
+  const double half = 0.5 * (double)(n - 1);
+  double S = 0.0, Sx = 0.0;
+  int cnt = 0;
+  if (k < a.n_valid && i < n) {
+    const float2 *crow = cl + (t.calib_off - cl_base) + (int64_t)i * n;
+    uint32_t raw[GS];
+    float2 cf[GS];
+    if constexpr (VEC) {
+#pragma unroll
+      for (int j = 0; j < GS / 2; ++j) {
+        raw[2 * j] = w[j] & 0xffffu;
+        raw[2 * j + 1] = w[j] >> 16;
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < GS; ++j) raw[j] = w[j];
+    }
+#pragma unroll
+    for (int j = 0; j < GS; ++j)
+      if (GS <= 16 || j < n) cf[j] = crow[j < n - 1 ? j : n - 1];
+    tile_row_sums<GS>(raw, cf, n, t.thr, a.mode == 1, half, S, Sx, cnt);
+  }
+  double cx, cy;
+  tile_centroid<GS>(S, Sx, cnt, i, half, cx, cy, cnt);
+  if (i == 0 && k < a.n_valid)
+    tile_publish<true>(a, t, k, cx, cy, cnt, rl[kl]);
+}
+
+// Subapertures [k_begin, k_end) of a workgroup of NT threads, GS lanes per
+// tile: descriptors of MP passes first, then all their pixel loads, then the
+// passes in order.  VEC: 4-byte pixel pairs (a compile-time choice too, so
+// that the loaded words need no copies that would wait for them).
+template <int GS, int NT, bool VEC>
+__device__ __forceinline__ void panel_calibration(const CalibArgs &a, int k_begin, int k_end, const TileDesc *tl,
+                                                  const float2 *rl, const float2 *cl, int32_t cl_base) {
+  constexpr int SPP = NT / GS;
+  constexpr int MP = GS <= 16 ? 4 : 1;
+  const int i = threadIdx.x & (GS - 1);
+  for (int k0 = k_begin; k0 < k_end; k0 += MP * SPP) {
+    int kq[MP];
+    TileDesc td[MP];
+    uint32_t pw[MP][GS];
+#pragma unroll
+    for (int q = 0; q < MP; ++q) {
+      const int kk = k0 + q * SPP + (int)threadIdx.x / GS;
+      kq[q] = kk < k_end ? kk : a.n_valid;
+      td[q] = TileDesc{};
+      if (kq[q] < a.n_valid) td[q] = tl[kq[q] - k_begin];
+    }
+#pragma unroll
+    for (int q = 0; q < MP; ++q) pixel_row_fetch<GS, VEC>(a, kq[q], i, td[q], pw[q]);
+#pragma unroll
+    for (int q = 0; q < MP; ++q)
+      pixel_row_finish<GS, VEC>(a, kq[q], i, td[q], pw[q], cl, cl_base, rl, kq[q] - k_begin);
+  }
+}
+
+template <int GS, bool VEC>
+__global__ __launch_bounds__(kBlock) void calib_cog_kernel(CalibArgs a) {
   const int tid = threadIdx.x;
   if (a.ts_start != nullptr && blockIdx.x == 0 && tid == 0) a.ts_start[0] = wall_clock64();
   const int k = (int)(((int64_t)blockIdx.x * kBlock + tid) / GS);   // subaperture
-  calib_tile_row<GS>(a, k, tid & (GS - 1), vec);
+  calib_tile_row<GS, false, false, VEC>(a, k, tid & (GS - 1));
 }
 
 // ---------------------------------------------------------------------------
@@ -676,7 +877,7 @@ __device__ __forceinline__ void lds_row_group(const uint4 *lds, int ldq16, int r
 // otherwise use), so more of the matrix stays on chip.
 template <int FMT, int KPL, int RR, int RA, int VW, int GS, bool PANELS>
 __global__ __launch_bounds__(512 / VW) void frames_kernel(PersistArgs p, int32_t max_rows, int32_t lds_rows,
-                                                          int32_t tile_cap) {
+                                                          int32_t tile_cap, int32_t calib_cap) {
   static_assert(!PANELS || (VW == 1 && RA == 0), "slope panels use 8 wavefronts");
   constexpr int W = 8;                             // slope slices
   constexpr int PW = W / VW;                       // wavefronts of the workgroup
@@ -684,7 +885,8 @@ __global__ __launch_bounds__(512 / VW) void frames_kernel(PersistArgs p, int32_t
   constexpr int EPC = Codec<FMT>::EPC;
   constexpr int RB = KPL <= 2 ? 4 : 2;             // streamed rows per batch
   // LDS: [lds_rows][ldq16] slab, [W][max_rows] floats, then (tile_cap > 0) the
-  // workgroup's tile descriptors and reference slopes, which stay the same for
+  // workgroup's tile descriptors and reference slopes, then (calib_cap > 0,
+  // slope panels only) its (dark, flat) blocks, which all stay the same for
   // every frame
   extern __shared__ uint4 lds[];
   __shared__ uint32_t sh_abort;
@@ -700,7 +902,6 @@ __global__ __launch_bounds__(512 / VW) void frames_kernel(PersistArgs p, int32_t
   const int nrows = (int)(((int64_t)(b + 1) * a.n_act) / G) - row_begin;
   const int k_begin = (int)(((int64_t)b * p.cal.n_valid) / G);
   const int k_end = (int)(((int64_t)(b + 1) * p.cal.n_valid) / G);
-  constexpr int SPP = NT / GS;                     // subapertures per calibration pass
   const int kc = slice_chunks(a.n_chunks, W);      // chunks per slice (whole 64-chunk groups)
   const uint4 *slab = reinterpret_cast<const uint4 *>(static_cast<const char *>(a.Rq) +
                                                       (int64_t)row_begin * a.ldq_bytes);
@@ -712,6 +913,21 @@ __global__ __launch_bounds__(512 / VW) void frames_kernel(PersistArgs p, int32_t
       const TileDesc t = p.cal.tiles[k];
       sh_tiles[k - k_begin] = t;
       sh_ref[k - k_begin] = make_float2(p.cal.ref[t.sx], p.cal.ref[t.sy]);
+    }
+  }
+  // slope panels (the slab is streamed, LDS is free): the workgroup's (dark,
+  // flat) blocks, contiguous in subaperture order, copied once per launch
+  float2 *sh_cal = reinterpret_cast<float2 *>(sh_ref + tile_cap);
+  int32_t cal_base = 0;
+  bool cal_lds = false;
+  if constexpr (PANELS) {
+    if (calib_cap > 0 && k_end > k_begin) {
+      const TileDesc t0 = p.cal.tiles[k_begin], t1 = p.cal.tiles[k_end - 1];
+      cal_base = t0.calib_off;
+      const int32_t len = t1.calib_off + t1.n * t1.n - cal_base;
+      cal_lds = len <= calib_cap;
+      if (cal_lds)
+        for (int c = tid; c < len; c += NT) sh_cal[c] = p.cal.calib[(int64_t)cal_base + c];
     }
   }
 
@@ -788,10 +1004,18 @@ __global__ __launch_bounds__(512 / VW) void frames_kernel(PersistArgs p, int32_t
     ca.s_int = p.sbuf + (int64_t)(f & 1) * p.s_len;
     ca.s_user = p.cal.s_user ? p.cal.s_user + (int64_t)f * 2 * p.cal.n_valid : nullptr;
     ca.counts = p.cal.counts ? p.cal.counts + (int64_t)f * p.cal.n_valid : nullptr;
-    for (int k0 = k_begin; k0 < k_end; k0 += SPP) {
-      const int kk = k0 + tid / GS;
-      calib_tile_row<GS, true>(ca, kk < k_end ? kk : p.cal.n_valid, tid & (GS - 1), p.vec,
-                               cached ? sh_tiles : nullptr, kk - k_begin, cached ? sh_ref : nullptr);
+    if constexpr (PANELS) {
+      // many subapertures per workgroup: pixel loads of several passes in flight
+      if (cached && cal_lds) {
+        if (p.vec)
+          panel_calibration<GS, NT, true>(ca, k_begin, k_end, sh_tiles, sh_ref, sh_cal, cal_base);
+        else
+          panel_calibration<GS, NT, false>(ca, k_begin, k_end, sh_tiles, sh_ref, sh_cal, cal_base);
+      } else {
+        wg_calibration<GS, NT>(ca, k_begin, k_end, p.vec, nullptr, nullptr);
+      }
+    } else {
+      wg_calibration<GS, NT>(ca, k_begin, k_end, p.vec, cached ? sh_tiles : nullptr, cached ? sh_ref : nullptr);
     }
     trace_stamp(p, f, 1);
     frame_barrier(p, (uint32_t)(f + 1), f);
@@ -1010,11 +1234,13 @@ hipError_t launch_calib_cog(const CalibArgs &a, hipStream_t st) {
   // 4-byte pixel pairs need even tile rows and a 4-byte aligned frame set
   const int vec = (a.pairs && (reinterpret_cast<uintptr_t>(a.pix) & 3) == 0) ? 1 : 0;
   if (gs == 8)
-    calib_cog_kernel<8><<<blocks, kBlock, 0, st>>>(a, vec);
+    vec ? calib_cog_kernel<8, true><<<blocks, kBlock, 0, st>>>(a) : calib_cog_kernel<8, false><<<blocks, kBlock, 0, st>>>(a);
   else if (gs == 16)
-    calib_cog_kernel<16><<<blocks, kBlock, 0, st>>>(a, vec);
+    vec ? calib_cog_kernel<16, true><<<blocks, kBlock, 0, st>>>(a)
+        : calib_cog_kernel<16, false><<<blocks, kBlock, 0, st>>>(a);
   else
-    calib_cog_kernel<32><<<blocks, kBlock, 0, st>>>(a, vec);
+    vec ? calib_cog_kernel<32, true><<<blocks, kBlock, 0, st>>>(a)
+        : calib_cog_kernel<32, false><<<blocks, kBlock, 0, st>>>(a);
   return hipGetLastError();
 }
 
@@ -1177,7 +1403,10 @@ static hipError_t launch_frames_variant(const PersistArgs &p, int G, int max_row
   int64_t avail = (int64_t)lds_max - part_bytes - tile_bytes - static_bytes;
   int lds_rows = (avail > 0 && !PANELS) ? (int)(avail / p.mvm.ldq_bytes) : 0;
   if (lds_rows > max_rows) lds_rows = max_rows;
-  const size_t lds = (size_t)lds_rows * p.mvm.ldq_bytes + (size_t)part_bytes + (size_t)tile_bytes;
+  // slope panels: the workgroups' (dark, flat) blocks when the largest fits
+  const int calib_cap = (PANELS && p.calib_span > 0 && (int64_t)p.calib_span * 8 <= avail) ? p.calib_span : 0;
+  const size_t lds = (size_t)lds_rows * p.mvm.ldq_bytes + (size_t)part_bytes + (size_t)tile_bytes +
+                     (size_t)calib_cap * sizeof(float2);
   if ((e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)lds)) != hipSuccess)
     return e;
@@ -1187,8 +1416,8 @@ static hipError_t launch_frames_variant(const PersistArgs &p, int G, int max_row
   persist_reset_kernel<<<(64 + G + kBlock - 1) / kBlock, kBlock, 0, st>>>(p.bar, p.abort_flag, G);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   PersistArgs pa = p;
-  int32_t mr = max_rows, lr = lds_rows, tc = tile_cap;
-  void *args[] = {&pa, &mr, &lr, &tc};
+  int32_t mr = max_rows, lr = lds_rows, tc = tile_cap, cc = calib_cap;
+  void *args[] = {&pa, &mr, &lr, &tc, &cc};
   e = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(kern), dim3(G), dim3(NT), args, lds, st);
   if (e != hipSuccess) return e;
   return hipGetLastError();
@@ -1219,13 +1448,17 @@ static hipError_t launch_frames_fmt(const PersistArgs &p, int G, int max_rows, i
   return launch_frames_gs<FMT, PanelShape<FMT>::KPLP, true, false>(p, G, max_rows, st);
 }
 
+int frames_grid(int blocks, int n_act) {
+  const int G = blocks < 1 ? 1 : blocks;
+  return G > n_act ? n_act : G;
+}
+
 hipError_t launch_frames(const PersistArgs &p, int blocks, int rows_per_batch, hipStream_t st) {
   (void)rows_per_batch;
   constexpr int W = 8;
   if (p.n_frames <= 0) return hipSuccess;
   if (p.cal.max_n < 1 || p.cal.max_n > 32) return hipErrorInvalidValue;
-  int G = blocks < 1 ? 1 : blocks;
-  if (G > p.mvm.n_act) G = p.mvm.n_act;
+  const int G = frames_grid(blocks, p.mvm.n_act);
   if (G > sl::kMaxGroups) return hipErrorInvalidValue;
   const int max_rows = (p.mvm.n_act + G - 1) / G;
   if (max_rows > W * 64) return hipErrorInvalidValue;      // one integrator row per thread

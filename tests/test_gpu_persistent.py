@@ -2,6 +2,7 @@
 import numpy as np
 import pytest
 
+import oracle
 from _closedloop import oracle_closed_loop
 from _gpu_helpers import _ctx_for, _dev, _gpu_batch, check_parity
 from aosim import ELT, TINY, Scenario, geometry
@@ -116,6 +117,38 @@ def test_long_slope_vectors_run_in_panels_identically_in_both_modes(fmt):
     Rq = R.astype(np.float64) if fmt == "f32" else quant.dequantize(*quant.encode(R, fmt), fmt)
     a_ref = out[0]["slopes"].astype(np.float64) @ Rq.T
     assert np.abs(out[0]["recon"] - a_ref).max() <= 1e-5 * np.abs(a_ref).max()
+
+
+@pytest.mark.parametrize("blocks", [0, 64, 32])
+def test_panel_calibration_blocks_in_lds_or_memory_match_per_launch(blocks):
+    # slope panels with 10 x 10 pixel tiles: with the default grid a workgroup's
+    # (dark, flat) blocks sit in LDS and its pixel loads of four passes are in
+    # flight together; 64 workgroups keep the blocks in LDS without the tile
+    # descriptor copy, 32 workgroups have more blocks than LDS holds and read
+    # them from memory
+    rng = np.random.default_rng(12)
+    mask = geometry.subaperture_mask(110, 0.0)
+    nv = int(mask.sum())
+    n = 10
+    H = 110 * n
+    frames = rng.integers(95, 200, size=(3, H, H)).astype(np.uint16)
+    dark = rng.uniform(95.0, 105.0, size=(H, H)).astype(np.float32)
+    flat = rng.normal(1.0, 0.02, size=(H, H)).astype(np.float32)
+    R = (rng.standard_normal((300, 2 * nv)) / 100).astype(np.float32)
+    out = []
+    for mode, tuning in ((rtc.RTC_FRAMES_PER_LAUNCH, None), (rtc.RTC_FRAMES_PERSISTENT, {"blocks": blocks})):
+        with rtc.rtc_init(mask, n, 300, cm_dtype="bf16") as ctx:
+            rtc.rtc_load_calib(ctx, dark, flat, 20.0)
+            rtc.rtc_load_cmat(ctx, R)
+            rtc.rtc_set_frame_mode(ctx, mode)
+            out.append(_gpu_batch(ctx, frames, tuning=tuning))
+            rtc.rtc_sync_check(ctx)
+    assert 2 * nv > 16384
+    for key in out[0]:
+        assert np.array_equal(out[0][key], out[1][key]), key
+    ref = oracle.rtc_frame(frames[0], mask, n, dark, flat, 20.0, np.zeros((300, 2 * nv)), np.zeros(300), 0.4)
+    assert np.array_equal(out[0]["counts"][0].astype(np.int64), ref["counts"])
+    assert np.abs(out[0]["slopes"][0] - ref["slopes"]).max() <= 1e-5 * max(np.abs(ref["slopes"]).max(), 0.1)
 
 
 def test_unsupported_persistent_shape_runs_per_launch():

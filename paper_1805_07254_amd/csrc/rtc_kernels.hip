@@ -1372,21 +1372,22 @@ __global__ __launch_bounds__(kBlock) void persist_reset_kernel(uint32_t *bar, ui
 
 constexpr int kTileCache = 128;                    // most subapertures per workgroup with LDS descriptors
 
-// Register rows per slice: FP32 slabs use 4 wavefronts of two slices each, one
-// row of ordinary registers and 256 accumulation registers of rows; the
-// reduced formats, whose slabs fit on chip, use 8 wavefronts and 64 ordinary
+// Register rows per slice: FP32 slabs use 4 wavefronts of two slices each, 64
+// ordinary registers of rows (32 for tiles wider than 16 pixels, whose
+// calibration needs more) and 256 accumulation registers of rows; the reduced
+// formats, whose slabs fit on chip, use 8 wavefronts and 64 ordinary
 // registers of codes; slope panels stream every row.
-template <int FMT, int KPL, bool PANELS, bool WIDE>
+template <int FMT, int KPL, bool PANELS, bool WIDE, int GS>
 struct FrameShape {
   static constexpr int VW = (WIDE && FMT == 0 && !PANELS && KPL <= 4) ? 2 : 1;
-  static constexpr int RR = PANELS ? 0 : (VW == 2 ? 4 / KPL : (FMT == 0 ? 24 : 16) / KPL);
+  static constexpr int RR = PANELS ? 0 : (VW == 2 ? (GS <= 16 ? 8 : 4) / KPL : (FMT == 0 ? 24 : 16) / KPL);
   static constexpr int RA = VW == 2 ? 32 / KPL : 0;
 };
 
 template <int FMT, int KPL, int GS, bool PANELS, bool WIDE>
 static hipError_t launch_frames_variant(const PersistArgs &p, int G, int max_rows, hipStream_t st) {
   constexpr int W = 8;
-  using FS = FrameShape<FMT, KPL, PANELS, WIDE>;
+  using FS = FrameShape<FMT, KPL, PANELS, WIDE, GS>;
   constexpr int NT = 512 / FS::VW;
   auto kern = frames_kernel<FMT, KPL, FS::RR, FS::RA, FS::VW, GS, PANELS>;
   int dev = 0, ncu = 0, lds_max = 0;

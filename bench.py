@@ -159,6 +159,11 @@ def run_multi(args):
     mode = rtc.rtc_get_frame_mode(ctx)
     best = min((r for r in tune if r["us_per_frame"] > 0), key=lambda r: r["us_per_frame"])
     log(f"autotuned: frame mode {mode}, {best['tuning']}, {best['us_per_frame']:.2f} us/frame over 64 frames")
+    balance = None
+    if mode == rtc.RTC_FRAMES_PERSISTENT:
+        balance = rtc.rtc_balance_rows(ctx, 64, frames, cmd, stream=stream)
+        log(f"row split: equal {balance['us_equal']:.2f} us/frame, measured {balance['us_split']:.2f} us/frame, "
+            f"kept {balance['kept']}")
 
     def run(first, n, ts=None):
         done, launches = 0, 0
@@ -224,7 +229,8 @@ def run_multi(args):
                                f"{sc.n_slopes} slopes, {sc.n_act} actuators on two DMs, "
                                f"{args.multi_dtype} control matrix {sc.n_act * sc.n_slopes * esz / 1e6:.1f} MB",
                    "frames_per_launch": launch, "distinct_frame_sets": args.multi_ring,
-                   "frame_mode": "persistent" if mode == 1 else "per-launch", "tuning": best["tuning"]},
+                   "frame_mode": "persistent" if mode == 1 else "per-launch", "tuning": best["tuning"],
+                   "row_split": balance},
         "frame_period_us": st_period, "frame_span_us": st_span,
         "graph_replay": graph, "autotune": tune,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",

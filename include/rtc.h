@@ -332,6 +332,43 @@ rtc_status rtc_autotune(rtc_ctx *c, int32_t n_frames, const uint16_t *d_pixels, 
                         float *d_cmd, rtc_tune_result *results, int32_t max_results, int32_t *n_results,
                         void *hip_stream);
 
+/* Row split of persistent batches (an unequal allocation of the
+ * reconstruction's rows to workgroups, in the spirit of the unequal
+ * allocation of Section 2.3.6: equal shares finish at different times when
+ * the workers are not equally fast).  With row_start set, workgroup b of a
+ * persistent launch of G workgroups owns the contiguous actuator rows
+ * [row_start[b], row_start[b+1]) instead of [b n_act / G, (b+1) n_act / G).
+ * row_start: host array of G + 1 int32 with row_start[0] = 0,
+ * row_start[G] = n_act, every share >= 1 and <= 512 rows; copied.  The
+ * split applies to persistent launches whose grid is G workgroups (the
+ * compute-unit count, or the tuning's block count, capped at n_act); other
+ * launches keep the equal split.  Results are bitwise those of the equal
+ * split (each row's sum does not depend on the workgroup computing it).
+ * G = 0 or row_start = NULL restores the equal split.  A recorded graph is
+ * discarded (its launch shape may no longer fit).  Errors: RTC_E_ARG for a
+ * malformed split or G outside [0, 1024]. */
+rtc_status rtc_set_row_split(rtc_ctx *c, int32_t G, const int32_t *row_start);
+/* The current split into row_start (host, room for G + 1 entries; may be
+ * NULL) and its grid into *G (0 = equal split). */
+rtc_status rtc_get_row_split(const rtc_ctx *c, int32_t *G, int32_t *row_start, int32_t capacity);
+
+/* Measured row split for the current persistent tuning: traces a batch of
+ * n_frames frames of d_pixels (frame_stride apart; outputs to d_cmd,
+ * n_frames * n_act floats) with the equal split, takes each workgroup's
+ * median time of its partial sums over the last three quarters of the
+ * frames, gives every workgroup rows in proportion to its measured rows per
+ * second (largest remainders, every share >= 1 and <= 512), times a batch
+ * with both splits (HIP events, after n_frames/4 + 1 untimed frames) and
+ * keeps the faster (the traced batch is not one of the timed ones).
+ * *us_equal and *us_split (may be NULL) get the mean frame times of the two.
+ * The integrator state and the trace setting are restored; a recorded graph
+ * is discarded.  Synchronous; allocates a trace buffer for the measurement.
+ * Errors: as rtc_frame_batch; RTC_E_STATE when the context is not in the
+ * persistent frame mode or the persistent launch is not supported for its
+ * shape; RTC_E_ARG for n_frames < 4. */
+rtc_status rtc_balance_rows(rtc_ctx *c, int32_t n_frames, const uint16_t *d_pixels, int64_t frame_stride,
+                            float *d_cmd, float *us_equal, float *us_split, void *hip_stream);
+
 /* ---- Pixel-stream processing (Section 2.3.6 and Figure 6; the latency
  * measurements of Section 3.2, Figures 11 and 12) ----
  *

@@ -578,7 +578,12 @@ rtc_status rtc_frame_batch(rtc_ctx *c, int32_t n_frames, const uint16_t *d_pixel
     p.trace_frames = c->trace_frames;
     p.trace_groups = c->trace_groups;
     const int blocks = c->tuning.blocks > 0 ? c->tuning.blocks : c->n_cu;
-    p.calib_span = calib_span(c, rtck::frames_grid(blocks, c->n_act));
+    const int G = rtck::frames_grid(blocks, c->n_act);
+    p.calib_span = calib_span(c, G);
+    if (c->split_G > 0 && c->split_G == G) {
+      p.row_start = c->d_row_start;
+      p.row_max = c->split_max;
+    }
     hipError_t e = rtck::launch_frames(p, blocks, c->tuning.rows_per_wave, st);
     if (e == hipSuccess) return RTC_OK;
     if (e != hipErrorInvalidValue && e != hipErrorCooperativeLaunchTooLarge)
@@ -721,6 +726,215 @@ rtc_status rtc_autotune(rtc_ctx *c, int32_t n_frames, const uint16_t *d_pixels, 
     for (int32_t i = 0; i < max_results && (size_t)i < cand.size(); ++i) results[i] = cand[(size_t)i];
   if (n_results) *n_results = (int32_t)cand.size();
   return RTC_OK;
+}
+
+rtc_status rtc_set_row_split(rtc_ctx *c, int32_t G, const int32_t *row_start) {
+  if (!c) return fail(nullptr, RTC_E_ARG, "rtc_set_row_split: NULL context");
+  if (G < 0 || G > rtck::sync_layout::kMaxGroups)
+    return fail(c, RTC_E_ARG, "rtc_set_row_split: G must be in [0, 1024]");
+  int32_t most = 0;
+  if (G > 0 && row_start) {
+    if (row_start[0] != 0 || row_start[G] != c->n_act)
+      return fail(c, RTC_E_ARG, "rtc_set_row_split: row_start[0] must be 0 and row_start[G] n_act");
+    for (int32_t b = 0; b < G; ++b) {
+      const int32_t n = row_start[b + 1] - row_start[b];
+      if (n < 1 || n > 512) return fail(c, RTC_E_ARG, "rtc_set_row_split: every share must hold 1 to 512 rows");
+      most = std::max(most, n);
+    }
+  }
+  DeviceScope ds(c->device);
+  if (ds.status != hipSuccess) return hip_fail(c, ds.status, "rtc_set_row_split: hipSetDevice");
+  // batches in flight may read the current split
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(c, e, "rtc_set_row_split: synchronize");
+  if (c->graph) {                                  // recorded with the old launch shape
+    (void)hipGraphExecDestroy(c->graph);
+    c->graph = nullptr;
+  }
+  if (G == 0 || !row_start) {
+    c->split_G = 0;
+    c->split_max = 0;
+    c->split_h.clear();
+    return RTC_OK;
+  }
+  if (!c->d_row_start) {
+    e = hipMalloc(&c->d_row_start, sizeof(int32_t) * (rtck::sync_layout::kMaxGroups + 1));
+    if (e != hipSuccess) {
+      c->d_row_start = nullptr;
+      return hip_fail(c, e, "rtc_set_row_split: hipMalloc");
+    }
+  }
+  e = hipMemcpy(c->d_row_start, row_start, sizeof(int32_t) * ((size_t)G + 1), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    c->split_G = 0;
+    return hip_fail(c, e, "rtc_set_row_split: copy");
+  }
+  c->split_h.assign(row_start, row_start + G + 1);
+  c->split_G = G;
+  c->split_max = most;
+  return RTC_OK;
+}
+
+rtc_status rtc_get_row_split(const rtc_ctx *c, int32_t *G, int32_t *row_start, int32_t capacity) {
+  if (!c) return fail(nullptr, RTC_E_ARG, "rtc_get_row_split: NULL context");
+  if (G) *G = c->split_G;
+  if (row_start && c->split_G > 0) {
+    if (capacity < c->split_G + 1) return fail(const_cast<rtc_ctx *>(c), RTC_E_ARG, "rtc_get_row_split: capacity < G + 1");
+    std::copy(c->split_h.begin(), c->split_h.end(), row_start);
+  }
+  return RTC_OK;
+}
+
+// Shares of n rows in proportion to w (all > 0): floor of each plus the
+// largest remainders (ties to the lower index), each share in [1, cap].
+static std::vector<int32_t> proportional_split(const std::vector<double> &w, int32_t n, int32_t cap) {
+  const size_t G = w.size();
+  double tot = 0.0;
+  for (double x : w) tot += x;
+  std::vector<int32_t> cnt(G, 1);
+  int32_t left = n - (int32_t)G;                   // one row each first
+  std::vector<std::pair<double, size_t>> rem;
+  for (size_t b = 0; b < G; ++b) {
+    const double x = (double)left * w[b] / tot;
+    const int32_t f = (int32_t)std::floor(x);
+    cnt[b] += f;
+    rem.push_back({x - f, b});
+  }
+  int32_t given = 0;
+  for (int32_t x : cnt) given += x;
+  std::stable_sort(rem.begin(), rem.end(), [](const auto &a, const auto &b) { return a.first > b.first; });
+  for (size_t i = 0; given < n && i < rem.size(); ++i, ++given) ++cnt[rem[i].second];
+  // cap: move the excess to the workgroups with the most room, in index order
+  for (size_t b = 0; b < G; ++b)
+    while (cnt[b] > cap) {
+      size_t best = b;
+      for (size_t j = 0; j < G; ++j)
+        if (cnt[j] < cnt[best]) best = j;
+      if (cnt[best] >= cap) break;
+      --cnt[b];
+      ++cnt[best];
+    }
+  std::vector<int32_t> start(G + 1, 0);
+  for (size_t b = 0; b < G; ++b) start[b + 1] = start[b] + cnt[b];
+  return start;
+}
+
+rtc_status rtc_balance_rows(rtc_ctx *c, int32_t n_frames, const uint16_t *d_pixels, int64_t frame_stride,
+                            float *d_cmd, float *us_equal, float *us_split, void *hip_stream) {
+  if (!c) return fail(nullptr, RTC_E_ARG, "rtc_balance_rows: NULL context");
+  if (n_frames < 4) return fail(c, RTC_E_ARG, "rtc_balance_rows: n_frames must be >= 4");
+  if (!c->calib_loaded || !c->cmat_loaded)
+    return fail(c, RTC_E_STATE, "rtc_balance_rows: load the calibration and the control matrix first");
+  if (c->frame_mode != RTC_FRAMES_PERSISTENT)
+    return fail(c, RTC_E_STATE, "rtc_balance_rows: the context is not in the persistent frame mode");
+  if (!d_pixels || !d_cmd) return fail(c, RTC_E_ARG, "rtc_balance_rows: NULL pixels or cmd");
+  if (frame_stride < c->frame_elems) return fail(c, RTC_E_ARG, "rtc_balance_rows: frame_stride shorter than a frame");
+  DeviceScope ds(c->device);
+  if (ds.status != hipSuccess) return hip_fail(c, ds.status, "rtc_balance_rows: hipSetDevice");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const int G = rtck::frames_grid(c->tuning.blocks > 0 ? c->tuning.blocks : c->n_cu, c->n_act);
+  if (G > rtck::sync_layout::kMaxGroups) return fail(c, RTC_E_STATE, "rtc_balance_rows: grid too large");
+
+  std::vector<float> saved((size_t)c->n_act);
+  rtc_status s = rtc_get_state(c, saved.data());
+  if (s != RTC_OK) return s;
+  uint64_t *const tr0 = c->d_trace;
+  const int32_t trf0 = c->trace_frames, trg0 = c->trace_groups;
+  const std::vector<int32_t> split0 = c->split_h;
+  const int32_t splitG0 = c->split_G;
+  uint64_t *d_tr = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipMalloc(&d_tr, sizeof(uint64_t) * (size_t)n_frames * G * rtck::kTraceStages);
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  auto cleanup = [&]() {
+    c->d_trace = tr0;
+    c->trace_frames = trf0;
+    c->trace_groups = trg0;
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (d_tr) (void)hipFree(d_tr);
+  };
+  if (e != hipSuccess) {
+    cleanup();
+    return hip_fail(c, e, "rtc_balance_rows: allocation");
+  }
+  // one timed batch (after an untimed warm-up) in the current split; false on any failure
+  auto timed = [&](float *us) -> bool {
+    const int32_t warm = n_frames / 4 + 1;
+    bool ok = rtc_frame_batch(c, std::min(warm, n_frames), d_pixels, frame_stride, d_cmd, nullptr, nullptr, nullptr,
+                              nullptr, st) == RTC_OK;
+    ok = ok && hipEventRecord(e0, st) == hipSuccess;
+    ok = ok && rtc_frame_batch(c, n_frames, d_pixels, frame_stride, d_cmd, nullptr, nullptr, nullptr, nullptr,
+                               st) == RTC_OK;
+    ok = ok && hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
+    float ms = 0.0f;
+    ok = ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+    uint32_t aborted = 0;
+    ok = ok && hipMemcpy(&aborted, c->d_sync + rtck::sync_layout::kSticky, sizeof(aborted), hipMemcpyDeviceToHost) ==
+                   hipSuccess;
+    ok = ok && aborted == 0;
+    if (ok) *us = ms * 1000.0f / (float)n_frames;
+    return ok;
+  };
+  // 1. the equal split: one traced batch, then one timed batch without the trace
+  float t_eq = -1.0f, t_sp = -1.0f, t_tr = -1.0f;
+  bool ok = rtc_set_row_split(c, 0, nullptr) == RTC_OK;
+  c->d_trace = d_tr;
+  c->trace_frames = n_frames;
+  c->trace_groups = G;
+  ok = ok && hipMemset(d_tr, 0, sizeof(uint64_t) * (size_t)n_frames * G * rtck::kTraceStages) == hipSuccess;
+  ok = ok && timed(&t_tr);
+  std::vector<uint64_t> tr((size_t)n_frames * G * rtck::kTraceStages);
+  ok = ok && hipMemcpy(tr.data(), d_tr, tr.size() * sizeof(uint64_t), hipMemcpyDeviceToHost) == hipSuccess;
+  c->d_trace = nullptr;
+  c->trace_frames = 0;
+  c->trace_groups = 0;
+  ok = ok && timed(&t_eq);
+  // 2. rows per second of every workgroup: median partial-sum time over the
+  // last three quarters of the frames
+  std::vector<double> rate((size_t)G, 0.0);
+  bool traced = false;                             // no stamp at all: the batch did not run persistent
+  for (const uint64_t v : tr) traced = traced || v != 0;
+  for (int b = 0; ok && traced && b < G; ++b) {
+    std::vector<double> d;
+    for (int32_t f = n_frames / 4; f < n_frames; ++f) {
+      const uint64_t *t = tr.data() + ((size_t)f * G + b) * rtck::kTraceStages;
+      if (t[4] > t[3] && t[3] != 0) d.push_back((double)(t[4] - t[3]));
+    }
+    if (d.empty()) {
+      ok = false;
+      break;
+    }
+    std::nth_element(d.begin(), d.begin() + d.size() / 2, d.end());
+    const int64_t r0 = (int64_t)b * c->n_act / G, r1 = (int64_t)(b + 1) * c->n_act / G;
+    rate[(size_t)b] = (double)(r1 - r0) / d[d.size() / 2];
+  }
+  // 3. the proportional split, timed; keep the faster
+  if (ok && traced) {
+    const std::vector<int32_t> start = proportional_split(rate, c->n_act, 512);
+    ok = rtc_set_row_split(c, G, start.data()) == RTC_OK && timed(&t_sp);
+    if (ok && !(t_sp < t_eq)) ok = rtc_set_row_split(c, 0, nullptr) == RTC_OK;
+  }
+  if (!ok) {                                       // leave the caller's split
+    (void)hipGetLastError();
+    (void)hipDeviceSynchronize();
+    (void)hipMemset(c->d_sync + rtck::sync_layout::kSticky, 0, sizeof(uint32_t));
+    (void)rtc_set_row_split(c, splitG0, splitG0 > 0 ? split0.data() : nullptr);
+  }
+  if (ok && !traced) {
+    ok = false;
+    cleanup();
+    (void)rtc_set_state(c, saved.data());
+    (void)rtc_set_row_split(c, splitG0, splitG0 > 0 ? split0.data() : nullptr);
+    return fail(c, RTC_E_STATE, "rtc_balance_rows: the persistent launch does not support this shape");
+  }
+  cleanup();
+  s = rtc_set_state(c, saved.data());
+  if (!ok) return fail(c, RTC_E_DEVICE, "rtc_balance_rows: a measurement batch failed");
+  if (us_equal) *us_equal = t_eq;
+  if (us_split) *us_split = t_sp;
+  return s;
 }
 
 rtc_status rtc_calibrate_centroid(rtc_ctx *c, const uint16_t *d_pixels, float *d_slopes, int32_t *d_counts,
@@ -926,6 +1140,7 @@ void rtc_destroy(rtc_ctx *c) {
   dfree(c->d_part);
   dfree(c->d_sbuf);
   dfree(c->d_sync);
+  dfree(c->d_row_start);
   dfree(c->d_packed);
   dfree(c->d_ppart);
   dfree(c->d_ring);

@@ -54,6 +54,10 @@ struct rtc_ctx {
   int32_t trace_frames = 0;
   int32_t trace_groups = 0;
   hipGraphExec_t graph = nullptr;  // recorded frame batch (rtc_graph_capture)
+  int32_t *d_row_start = nullptr;  // [kMaxGroups + 1] measured row split of persistent batches
+  int32_t split_G = 0;             // grid the split is for (0 = equal split)
+  int32_t split_max = 0;           // most rows of one workgroup in the split
+  std::vector<int32_t> split_h;    // host copy of the split (split_G + 1 entries)
   bool calib_loaded = false;
   bool cmat_loaded = false;
   uint64_t cmat_gen = 0;           // bumped by every rtc_load_cmat

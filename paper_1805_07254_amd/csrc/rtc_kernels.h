@@ -102,6 +102,8 @@ struct PersistArgs {
   int32_t trace_groups;
   int32_t calib_span;      // largest float2 count of one workgroup's (dark, flat) blocks for the
                            // grid of frames_grid(); 0 = not known (they are then read from memory)
+  const int32_t *row_start;  // nullable [G + 1]: workgroup b owns rows [row_start[b], row_start[b+1])
+  int32_t row_max;           // largest row_start[b+1] - row_start[b] (with row_start)
 };
 constexpr int kTraceStages = 8;
 

@@ -898,8 +898,10 @@ __global__ __launch_bounds__(512 / VW) void frames_kernel(PersistArgs p, int32_t
   const int b = blockIdx.x;
   const int ldq16 = (int)(a.ldq_bytes / 16);
   float *sh_part = reinterpret_cast<float *>(lds + (int64_t)lds_rows * ldq16);
-  const int row_begin = (int)(((int64_t)b * a.n_act) / G);
-  const int nrows = (int)(((int64_t)(b + 1) * a.n_act) / G) - row_begin;
+  // contiguous actuator rows: an equal split, or a measured one (row_start)
+  const int row_begin = p.row_start != nullptr ? p.row_start[b] : (int)(((int64_t)b * a.n_act) / G);
+  const int nrows = (p.row_start != nullptr ? p.row_start[b + 1] : (int)(((int64_t)(b + 1) * a.n_act) / G)) -
+                    row_begin;
   const int k_begin = (int)(((int64_t)b * p.cal.n_valid) / G);
   const int k_end = (int)(((int64_t)(b + 1) * p.cal.n_valid) / G);
   const int kc = slice_chunks(a.n_chunks, W);      // chunks per slice (whole 64-chunk groups)
@@ -1461,8 +1463,8 @@ hipError_t launch_frames(const PersistArgs &p, int blocks, int rows_per_batch, h
   if (p.cal.max_n < 1 || p.cal.max_n > 32) return hipErrorInvalidValue;
   const int G = frames_grid(blocks, p.mvm.n_act);
   if (G > sl::kMaxGroups) return hipErrorInvalidValue;
-  const int max_rows = (p.mvm.n_act + G - 1) / G;
-  if (max_rows > W * 64) return hipErrorInvalidValue;      // one integrator row per thread
+  const int max_rows = p.row_start != nullptr ? p.row_max : (p.mvm.n_act + G - 1) / G;
+  if (max_rows < 1 || max_rows > W * 64) return hipErrorInvalidValue;   // one integrator row per thread
   const int kpl = slice_chunks(p.mvm.n_chunks, W) / 64;   // above mvm_block_max_kpl(): slope panels
   switch (p.mvm.fmt) {
     case 0: return launch_frames_fmt<0>(p, G, max_rows, kpl, st);

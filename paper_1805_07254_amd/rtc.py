@@ -98,6 +98,10 @@ _SIGNATURES = {
     "rtc_pred_destroy": (None, [_vp]),
     "rtc_pred_error_string": (ctypes.c_char_p, [_vp]),
     "rtc_autotune": (_i32, [_vp, _i32, _vp, _i64, _vp, _vp, _i32, ctypes.POINTER(_i32), _vp]),
+    "rtc_set_row_split": (_i32, [_vp, _i32, _vp]),
+    "rtc_get_row_split": (_i32, [_vp, ctypes.POINTER(_i32), _vp, _i32]),
+    "rtc_balance_rows": (_i32, [_vp, _i32, _vp, _i64, _vp, ctypes.POINTER(ctypes.c_float),
+                                ctypes.POINTER(ctypes.c_float), _vp]),
     "rtc_pipe_allocation": (_i32, [_i32, _i32, ctypes.c_double, _vp]),
     "rtc_pipe_setup": (_i32, [_vp, ctypes.POINTER(rtc_pipe_config)]),
     "rtc_pipe_info": (_i32, [_vp] + [ctypes.POINTER(_i32)] * 6),
@@ -481,6 +485,41 @@ def rtc_autotune(ctx: RtcContext, n_frames: int, pixels, cmd, frame_stride: Opti
         out.append({"frame_mode": r.frame_mode, "us_per_frame": r.us_per_frame,
                     "tuning": {name: getattr(r.tuning, name) for name, _ in rtc_mvm_tuning._fields_}})
     return out
+
+
+def rtc_set_row_split(ctx: RtcContext, row_start=None) -> None:
+    """Rows [row_start[b], row_start[b+1]) for workgroup b of persistent launches of len(row_start) - 1
+    workgroups; None restores the equal split."""
+    if row_start is None:
+        _check(load_library().rtc_set_row_split(ctx.handle, 0, None), ctx)
+        return
+    rs = np.ascontiguousarray(row_start, dtype=np.int32)
+    _check(load_library().rtc_set_row_split(ctx.handle, int(rs.size) - 1, rs.ctypes.data), ctx)
+
+
+def rtc_get_row_split(ctx: RtcContext) -> Optional[np.ndarray]:
+    """The current row split (None: equal split)."""
+    g = ctypes.c_int32(0)
+    _check(load_library().rtc_get_row_split(ctx.handle, ctypes.byref(g), None, 0), ctx)
+    if g.value == 0:
+        return None
+    out = np.zeros(g.value + 1, dtype=np.int32)
+    _check(load_library().rtc_get_row_split(ctx.handle, ctypes.byref(g), out.ctypes.data, out.size), ctx)
+    return out
+
+
+def rtc_balance_rows(ctx: RtcContext, n_frames: int, pixels, cmd, frame_stride: Optional[int] = None,
+                     stream=None) -> dict:
+    """Measured row split of persistent batches; returns the mean frame times with the equal and the measured
+    split (the faster is kept)."""
+    stride = ctx.frame_elems if frame_stride is None else frame_stride
+    need = (n_frames - 1) * stride + ctx.frame_elems
+    eq, sp = ctypes.c_float(-1.0), ctypes.c_float(-1.0)
+    _check(load_library().rtc_balance_rows(ctx.handle, n_frames, _dev_ptr(pixels, "uint16", need, "pixels", ctx),
+                                           stride, _dev_ptr(cmd, "float32", n_frames * ctx.n_act, "cmd", ctx),
+                                           ctypes.byref(eq), ctypes.byref(sp), _stream_ptr(stream)), ctx)
+    return {"us_equal": eq.value, "us_split": sp.value, "kept": "split" if rtc_get_row_split(ctx) is not None
+            else "equal"}
 
 
 def rtc_pipe_allocation(n_subaps: int, n_workers: int, ratio: float) -> np.ndarray:

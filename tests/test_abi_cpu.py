@@ -86,6 +86,13 @@ def test_null_arguments():
     lib.rtc_destroy(None)
 
 
+def test_row_split_entry_points_reject_null_context():
+    lib = rtc.load_library()
+    assert lib.rtc_set_row_split(None, 0, None) == rtc.RTC_E_ARG
+    assert lib.rtc_get_row_split(None, None, None, 0) == rtc.RTC_E_ARG
+    assert lib.rtc_balance_rows(None, 8, None, 0, None, None, None, None) == rtc.RTC_E_ARG
+
+
 def test_valid_config_without_gpu_reports_device_error():
     import torch
     if torch.cuda.is_available():

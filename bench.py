@@ -82,6 +82,8 @@ def parse():
     p.add_argument("--workload", default="elt-scao", choices=["elt-scao", "elt-multi", "elt-predict", "elt-pipe"],
                    help="elt-scao: the single-sensor ELT frame (default); elt-multi: six 74x74 and three 16x16 "
                         "sensors reconstructed by one BF16 matrix")
+    p.add_argument("--balance-rows", action="store_true",
+                   help="headline: measured row split of the persistent workgroups (rtc_balance_rows) before timing")
     p.add_argument("--multi-steps", type=int, default=5000)
     p.add_argument("--multi-ring", type=int, default=4, help="distinct multi-sensor frame sets")
     p.add_argument("--multi-dtype", default="bf16")
@@ -565,6 +567,11 @@ def main():
     # --- headline: FP32 matrix, persistent kernel
     ctx = make_ctx("f32", rtc.RTC_FRAMES_PERSISTENT)
     khz = rtc.rtc_wall_clock_khz(ctx)
+    balance = None
+    if args.balance_rows:
+        balance = rtc.rtc_balance_rows(ctx, min(256, args.launch_frames), frames, cmd, stream=stream)
+        log(f"row split: equal {balance['us_equal']:.2f} us/frame, measured {balance['us_split']:.2f} us/frame, "
+            f"kept {balance['kept']}")
     log(f"warm-up {args.warmup} frames, then {args.steps} timed frames (persistent, "
         f"{args.launch_frames} per launch)")
     head = timed(ctx, args.warmup, args.steps, khz)
@@ -679,6 +686,7 @@ def main():
                         f"obscuration {cfg.obscuration}, {sc.n_valid} subapertures, {2 * sc.n_valid} slopes, "
                         f"{sc.n_act} actuators, FP32 control matrix {R.nbytes / 1e6:.1f} MB",
             "frame_mode": "persistent",
+            "row_split": balance,
             "frames_per_launch": args.launch_frames,
             "distinct_frames": args.ring,
             "frame_data": "open-loop frozen-flow von Karman frames (r0 0.15 m, L0 25 m, 10 m/s)",

@@ -151,6 +151,38 @@ def test_panel_calibration_blocks_in_lds_or_memory_match_per_launch(blocks):
     assert np.abs(out[0]["slopes"][0] - ref["slopes"]).max() <= 1e-5 * max(np.abs(ref["slopes"]).max(), 0.1)
 
 
+@pytest.mark.parametrize("n_pix,fmt,n_sub", [(7, "f32", 12), (20, "f32", 12), (20, "bf16", 12), (7, "bf16", 160)])
+def test_odd_and_wide_tiles_match_the_per_launch_result_and_the_oracle(n_pix, fmt, n_sub):
+    # odd tile sides (single-pixel loads), tiles wider than 16 pixels (32 lanes
+    # per tile, run-time calibration choices) and, with 160 x 160 subapertures,
+    # slope panels with 8-lane odd tiles
+    rng = np.random.default_rng(40 + n_pix + n_sub)
+    mask = geometry.subaperture_mask(n_sub, 0.2)
+    nv = int(mask.sum())
+    H = n_sub * n_pix
+    frames = rng.integers(90, 400, size=(3, H, H)).astype(np.uint16)
+    dark = rng.uniform(95.0, 105.0, size=(H, H)).astype(np.float32)
+    flat = rng.normal(1.0, 0.02, size=(H, H)).astype(np.float32)
+    n_act = 250
+    R = (rng.standard_normal((n_act, 2 * nv)) / 100).astype(np.float32)
+    out = []
+    for mode in (rtc.RTC_FRAMES_PER_LAUNCH, rtc.RTC_FRAMES_PERSISTENT):
+        with rtc.rtc_init(mask, n_pix, n_act, cm_dtype=fmt) as ctx:
+            rtc.rtc_load_calib(ctx, dark, flat, 60.0)
+            rtc.rtc_load_cmat(ctx, R)
+            rtc.rtc_set_frame_mode(ctx, mode)
+            out.append(_gpu_batch(ctx, frames))
+            rtc.rtc_sync_check(ctx)
+    if n_sub == 160:
+        assert 2 * nv > 32768                       # beyond 8 wavefronts' BF16 slices: slope panels
+    for key in out[0]:
+        assert np.array_equal(out[0][key], out[1][key]), key
+    ref = oracle.rtc_frame(frames[0], mask, n_pix, dark, flat, 60.0, np.zeros((1, 2 * nv)), np.zeros(1), 0.4)
+    assert ref["counts"].min() < n_pix * n_pix and ref["counts"].max() > 0
+    assert np.array_equal(out[0]["counts"][0].astype(np.int64), ref["counts"])
+    assert np.abs(out[0]["slopes"][0] - ref["slopes"]).max() <= 1e-5 * max(np.abs(ref["slopes"]).max(), 0.1)
+
+
 def test_unsupported_persistent_shape_runs_per_launch():
     # more than 512 actuator rows per compute unit: one launch pair per frame
     rng = np.random.default_rng(9)

@@ -13,7 +13,8 @@ import pytest
 
 from _closedloop import oracle_closed_loop
 from _gpu_helpers import _ctx_for, _dev, _gpu_batch, check_parity
-from aosim import ELT, TINY, Scenario
+from aosim import ELT, TINY, Scenario, geometry
+import oracle
 
 torch = pytest.importorskip("torch")
 from paper_1805_07254_amd import rtc  # noqa: E402
@@ -126,6 +127,36 @@ def test_pipe_matches_oracle_elt(elt_loop, ratio, full, tail):
     print(f"pipe info {out['info']}", flush=True)
     check_parity(out, ref, sc.cfg.gain, sc.cfg.leak, what=f"elt pipe ratio={ratio} full={full} tail={tail}")
     _check_arrival_order(sc, out, ratio, full, 1000.0, 1000.0, khz, tail)
+
+
+@pytest.mark.parametrize("n_pix,ratio,tail", [(7, 1.0, 0), (7, 4.0, 1), (20, 4.0, 0), (20, 1.0, 2)])
+def test_pipe_odd_and_wide_tiles_match_oracle(n_pix, ratio, tail):
+    # odd tile sides (rows starting on odd pixels, single-pixel words) and
+    # tiles wider than 16 pixels (32 lanes per tile)
+    rng = np.random.default_rng(70 + n_pix + tail)
+    n_sub = 12
+    mask = geometry.subaperture_mask(n_sub, 0.2)
+    nv = int(mask.sum())
+    H = n_sub * n_pix
+    F, n_act, gain, T = 4, 90, 0.4, 60.0
+    frames = rng.integers(90, 400, size=(F, H, H)).astype(np.uint16)
+    dark = rng.uniform(95.0, 105.0, size=(H, H)).astype(np.float32)
+    flat = rng.normal(1.0, 0.02, size=(H, H)).astype(np.float32)
+    R = (rng.standard_normal((n_act, 2 * nv)) / 100).astype(np.float32)
+    ref = {k: [] for k in ("counts", "slopes", "recon", "cmd")}
+    c = np.zeros(n_act)
+    for f in range(F):
+        r = oracle.rtc_frame(frames[f], mask, n_pix, dark, flat, T, R.astype(np.float64), c, gain)
+        c = r["cmd"]
+        for k in ref:
+            ref[k].append(r[k])
+    ref = {k: np.array(v) for k, v in ref.items()}
+    with rtc.rtc_init(mask, n_pix, n_act, gain=gain) as ctx:
+        rtc.rtc_load_calib(ctx, dark, flat, T)
+        rtc.rtc_load_cmat(ctx, R)
+        out = _pipe_run(ctx, frames, alloc_ratio=ratio, tail_rows=tail, frame_period_us=300.0)
+    assert out["info"]["n_tail"] == np.count_nonzero(np.nonzero(mask)[0] >= n_sub - tail)
+    check_parity(out, ref, gain, 1.0, what=f"pipe n_pix {n_pix}")
 
 
 @pytest.mark.parametrize("fmt", ["f16", "bf16", "fp8e4m3"])

@@ -95,16 +95,19 @@ def elt_multi_inputs():
     return sc, R, np.stack(sets)
 
 
-def test_elt_multi_bf16_full_shape_both_modes(elt_multi_inputs):
+@pytest.mark.parametrize("fmt", ["bf16", "f16", "fp8e4m3"])
+def test_elt_multi_full_shape_both_modes(elt_multi_inputs, fmt):
+    # BF16 and F16 run in slope panels; FP8's 16 codes per chunk fit the
+    # 8-wavefront slices (8 chunks per lane) of the register-row form
     sc, R, sets = elt_multi_inputs
     out = []
     for mode in (rtc.RTC_FRAMES_PER_LAUNCH, rtc.RTC_FRAMES_PERSISTENT):
-        with _ctx(sc, "bf16", mode, R=R) as ctx:
+        with _ctx(sc, fmt, mode, R=R) as ctx:
             out.append(_gpu_batch(ctx, sets))
             rtc.rtc_sync_check(ctx)
     for key in out[0]:
         assert np.array_equal(out[0][key], out[1][key]), key
-    Rq = quant.dequantize(*quant.encode(R, "bf16"), "bf16")
+    Rq = quant.dequantize(*quant.encode(R, fmt), fmt)
     c = np.zeros(sc.n_act)
     frames_of = lambda k: [sets[k][o:o + h * h].reshape(h, h) for o, h in _offsets(sc)]
     for k in range(3):

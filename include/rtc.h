@@ -344,7 +344,8 @@ rtc_status rtc_autotune(rtc_ctx *c, int32_t n_frames, const uint16_t *d_pixels, 
  * compute-unit count, or the tuning's block count, capped at n_act); other
  * launches keep the equal split.  Results are bitwise those of the equal
  * split (each row's sum does not depend on the workgroup computing it).
- * G = 0 or row_start = NULL restores the equal split.  A recorded graph is
+ * G = 0 or row_start = NULL restores the equal split.  Waits until the
+ * device is idle (a running batch may read the split); a recorded graph is
  * discarded (its launch shape may no longer fit).  Errors: RTC_E_ARG for a
  * malformed split or G outside [0, 1024]. */
 rtc_status rtc_set_row_split(rtc_ctx *c, int32_t G, const int32_t *row_start);

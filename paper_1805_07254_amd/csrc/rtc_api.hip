@@ -451,7 +451,8 @@ static hipError_t launch_reconstruction(const rtc_ctx *c, rtck::MvmArgs ma, hipS
     const int G = t.blocks > 0 ? t.blocks : c->n_cu;
     // slope vectors beyond 8 wavefronts' register slices: slope panels, sliced
     // as the persistent kernel slices them
-    if (rtck::slice_chunks(c->n_chunks, 8) / 64 > rtck::mvm_block_max_kpl()) return rtck::launch_mvm_panel(ma, G, st);
+    if (rtck::slice_chunks(c->n_chunks, 8) / 64 > rtck::mvm_block_max_kpl(c->fmt))
+      return rtck::launch_mvm_panel(ma, G, st);
     return rtck::launch_mvm_block(ma, G, t.waves, t.rows_per_wave, st);
   }
   return rtck::launch_mvm_integrate(ma, nullptr, st);

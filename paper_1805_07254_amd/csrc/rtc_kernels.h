@@ -73,11 +73,12 @@ __host__ __device__ inline int slice_chunks(int n_chunks, int waves) {
 // Row-block reconstruction + integrator (no slope split): `blocks` workgroups of
 // `waves` (8 or 16) wavefronts, `rows_per_batch` rows streamed per batch.
 // Fails with hipErrorInvalidValue when a wavefront's slope slice would need
-// more than mvm_block_max_kpl() 16-byte vectors per lane.
+// more than mvm_block_max_kpl(fmt) 16-byte vectors per lane (8 wavefronts) or
+// more than 8 (16 wavefronts).
 hipError_t launch_mvm_block(const MvmArgs &a, int blocks, int waves, int rows_per_batch, hipStream_t st);
-int mvm_block_max_kpl();
+int mvm_block_max_kpl(int fmt);
 // Row-block reconstruction over slope panels (8 wavefronts, any slope-vector
-// length): used when 8 wavefronts' slices would exceed mvm_block_max_kpl()
+// length): used when 8 wavefronts' slices would exceed mvm_block_max_kpl(fmt)
 // vectors per lane, with the slicing of the persistent kernel's panels.
 hipError_t launch_mvm_panel(const MvmArgs &a, int blocks, hipStream_t st);
 // Elements per 16-byte chunk of a storage format (4, 8, 8, 16).

@@ -1334,7 +1334,9 @@ hipError_t launch_mvm_panel(const MvmArgs &a, int blocks, hipStream_t st) {
   return hipGetLastError();
 }
 
-int mvm_block_max_kpl() { return 8; }
+// FP8 slices stop at 4 chunks per lane: 8 chunks would hold 128 slope values
+// per lane, more than the registers take next to the rows.
+int mvm_block_max_kpl(int fmt) { return fmt == 3 ? 4 : 8; }
 
 int format_elems_per_chunk(int fmt) { return fmt == 0 ? 4 : (fmt == 3 ? 16 : 8); }
 
@@ -1349,7 +1351,8 @@ hipError_t launch_mvm_block(const MvmArgs &a, int blocks, int waves, int rows_pe
     max_rows = (a.n_act + G - 1) / G;
   }
   const int kpl = slice_chunks(a.n_chunks, waves) / 64;
-  if (kpl > mvm_block_max_kpl()) return hipErrorInvalidValue;
+  if (kpl > mvm_block_max_kpl(a.fmt) && waves == 8) return hipErrorInvalidValue;
+  if (kpl > 8) return hipErrorInvalidValue;
   switch (a.fmt) {
     case 0: return launch_block_fmt<0>(a, G, max_rows, waves, kpl, rows_per_batch, st);
     case 1: return launch_block_fmt<1>(a, G, max_rows, waves, kpl, rows_per_batch, st);
@@ -1447,7 +1450,9 @@ static hipError_t launch_frames_fmt(const PersistArgs &p, int G, int max_rows, i
   if (kpl <= 1) return launch_frames_rows<FMT, 1, false>(p, G, max_rows, st);
   if (kpl <= 2) return launch_frames_rows<FMT, 2, false>(p, G, max_rows, st);
   if (kpl <= 4) return launch_frames_rows<FMT, 4, false>(p, G, max_rows, st);
-  if (kpl <= 8) return launch_frames_gs<FMT, 8, false, false>(p, G, max_rows, st);
+  if constexpr (FMT != 3) {
+    if (kpl <= 8) return launch_frames_gs<FMT, 8, false, false>(p, G, max_rows, st);
+  }
   return launch_frames_gs<FMT, PanelShape<FMT>::KPLP, true, false>(p, G, max_rows, st);
 }
 
@@ -1465,7 +1470,7 @@ hipError_t launch_frames(const PersistArgs &p, int blocks, int rows_per_batch, h
   if (G > sl::kMaxGroups) return hipErrorInvalidValue;
   const int max_rows = p.row_start != nullptr ? p.row_max : (p.mvm.n_act + G - 1) / G;
   if (max_rows < 1 || max_rows > W * 64) return hipErrorInvalidValue;   // one integrator row per thread
-  const int kpl = slice_chunks(p.mvm.n_chunks, W) / 64;   // above mvm_block_max_kpl(): slope panels
+  const int kpl = slice_chunks(p.mvm.n_chunks, W) / 64;   // above mvm_block_max_kpl(fmt): slope panels
   switch (p.mvm.fmt) {
     case 0: return launch_frames_fmt<0>(p, G, max_rows, kpl, st);
     case 1: return launch_frames_fmt<1>(p, G, max_rows, kpl, st);

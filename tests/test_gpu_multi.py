@@ -97,8 +97,8 @@ def elt_multi_inputs():
 
 @pytest.mark.parametrize("fmt", ["bf16", "f16", "fp8e4m3"])
 def test_elt_multi_full_shape_both_modes(elt_multi_inputs, fmt):
-    # BF16 and F16 run in slope panels; FP8's 16 codes per chunk fit the
-    # 8-wavefront slices (8 chunks per lane) of the register-row form
+    # every format runs in slope panels at this slope count (FP8 from 4 chunks
+    # per lane on, BF16 and F16 from 8)
     sc, R, sets = elt_multi_inputs
     out = []
     for mode in (rtc.RTC_FRAMES_PER_LAUNCH, rtc.RTC_FRAMES_PERSISTENT):

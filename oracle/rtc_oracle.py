@@ -22,12 +22,14 @@ Readings where the paper is silent (each also listed in the design notes):
   * threshold: the calibrated value x = (raw - dark) * flat is compared with
     the threshold T by the sign of the *exact* real number x - T, strictly
     (x == T counts as below).  Mode "subtract": v = x - T above, else 0.
-    Mode "zero": v = x above, else 0.  T >= 0.
+    Mode "zero": v = x above, else 0.  Mode "none": v = x for every pixel
+    (no threshold applied; counts still report the pixels above T).  T >= 0.
+    Any finite dark and flat are accepted.
   * flat field multiplies (the map holds inverse pixel gains).
   * centroid coordinates are in pixels from the tile centre, (n-1)/2,
-    +x along increasing column, +y along increasing row; a subaperture with
-    no pixel above threshold has centroid 0.  Optional reference slopes are
-    subtracted.
+    +x along increasing column, +y along increasing row; a subaperture whose
+    weighted sum is not positive has centroid 0 (with a threshold: no pixel
+    above it).  Optional reference slopes are subtracted.
   * active subapertures are enumerated row-major over the mask; subaperture
     k covers rows [sy n, sy n + n) and columns [sx n, sx n + n).
   * the control matrix R is [n_act][n_slopes] so that a = R s.
@@ -43,7 +45,7 @@ from fractions import Fraction
 
 import numpy as np
 
-MODES = ("subtract", "zero")
+MODES = ("subtract", "zero", "none")
 
 # |fl64(fl64(fl64(raw - dark) * flat) - T) - (x - T)| <= 3 * 2^-53 * (|x| + |T|);
 # anything within this (much wider) band is re-decided exactly.
@@ -105,7 +107,10 @@ def calibrate(raw: np.ndarray, dark: np.ndarray, flat: np.ndarray, T: float, mod
     if not (float(T) >= 0.0):
         raise ValueError("threshold must be >= 0")
     above, x, y = threshold_excess(raw, dark, flat, T)
-    v = np.where(above, y if mode == "subtract" else x, 0.0)
+    if mode == "none":
+        v = x.copy()
+    else:
+        v = np.where(above, y if mode == "subtract" else x, 0.0)
     counts = above.reshape(above.shape[0], -1).sum(axis=1).astype(np.int64)
     return v, counts
 
@@ -114,14 +119,16 @@ def centroids(v: np.ndarray, counts: np.ndarray):
     """Centre of gravity of each tile (Figure 3 (b)); returns ``(cx, cy)`` float64.
 
     ``cx = sum(xc * v) / sum(v)`` with ``xc = col - (n - 1) / 2`` (and rows
-    for y); 0 where no pixel passed the threshold.
+    for y); 0 where ``sum(v)`` is not positive.  With a threshold applied
+    every v is >= 0 and positive exactly above the threshold, so that is the
+    subapertures with no pixel above it (``counts`` 0).
     """
     n = v.shape[-1]
     xc = np.arange(n, dtype=np.float64) - (n - 1) / 2.0
     S = v.sum(axis=(1, 2))
     Sx = (v * xc[None, None, :]).sum(axis=(1, 2))
     Sy = (v * xc[None, :, None]).sum(axis=(1, 2))
-    has = counts > 0
+    has = S > 0.0
     safe = np.where(has, S, 1.0)
     return np.where(has, Sx / safe, 0.0), np.where(has, Sy / safe, 0.0)
 

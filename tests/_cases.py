@@ -32,3 +32,41 @@ def pixel_integrated_gaussian(n: int, offset: float, sigma: float) -> np.ndarray
     edges = np.arange(n + 1, dtype=np.float64)
     cdf = ndtr((edges - (n / 2.0 + offset)) / sigma)
     return cdf[1:] - cdf[:-1]
+
+
+def out_of_domain_tie_pixels(T: float = 3.0):
+    """Pixels whose calibrated value ties or nearly ties T with darks outside
+    [2^-13, 2^24) in magnitude, where raw - dark is not exact in float64.
+
+    Exact ties of raw * flat with T (raw a power of two, flat = T / raw exact)
+    shifted by tiny darks of both signs (normal and subnormal float32), the
+    same with darks of magnitude 2^60 and flats of the opposite sign, and
+    zero darks at the exact tie (a tie counts as below).  Returns (raw uint16,
+    dark f32, flat f32) 1-D arrays for the float32 threshold T.
+    """
+    raw, dark, flat = [], [], []
+    T32 = np.float32(T)
+    for k in range(0, 16):
+        r = 2 ** k
+        f = np.float32(T32 / np.float32(r))
+        if np.float64(r) * np.float64(f) != np.float64(T32):
+            continue
+        for dk in (-149, -140, -126, -100, -60, -40, -31):
+            if np.log2(r) - (dk - 23 if dk > -127 else -149) < 53:
+                continue                        # raw - dark would be exact in float64
+            for sgn in (1.0, -1.0):
+                raw.append(r)
+                dark.append(np.float32(sgn * 2.0 ** dk))
+                flat.append(f)
+        raw.append(r)
+        dark.append(np.float32(0.0))
+        flat.append(f)
+    for r in (1, 5, 77, 65535):
+        for sgn in (1.0, -1.0):
+            d = np.float32(sgn * 2.0 ** 60)
+            f = np.float32(-sgn * np.float64(T32) * 2.0 ** -60)
+            raw.append(r)
+            dark.append(d)
+            flat.append(f)
+    return (np.asarray(raw, dtype=np.uint16), np.asarray(dark, dtype=np.float32),
+            np.asarray(flat, dtype=np.float32))

@@ -12,7 +12,7 @@ import pytest
 
 import oracle
 from aosim import dm, geometry
-from _cases import near_tie_pixels, pixel_integrated_gaussian
+from _cases import near_tie_pixels, out_of_domain_tie_pixels, pixel_integrated_gaussian
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -119,6 +119,70 @@ def test_threshold_random_pixels_match_exact_decisions():
             - Fraction(float(T))
         assert bool(above[idx]) == (ex > 0)
         assert abs(y[idx] - float(ex)) <= 4 * 2.0 ** -53 * (abs(x[idx]) + float(T))
+
+
+def test_threshold_exact_for_darks_outside_the_fast_domain():
+    # tiny (down to subnormal) and 2^60 darks, where raw - dark is not exact in
+    # float64: the oracle's decisions equal exact rational arithmetic, and plain
+    # float64 gets a good share of these ties wrong
+    raw, dark, flat = out_of_domain_tie_pixels(3.0)
+    above, x, y = oracle.threshold_excess(raw, dark, flat, 3.0)
+    naive_wrong = 0
+    for i in range(len(raw)):
+        ex = (Fraction(int(raw[i])) - Fraction(float(dark[i]))) * Fraction(float(flat[i])) - 3
+        assert bool(above[i]) == (ex > 0), i
+        assert y[i] == float(ex)
+        naive = (float(raw[i]) - float(dark[i])) * float(flat[i]) - 3.0
+        naive_wrong += (naive > 0) != (ex > 0)
+    assert naive_wrong > 20 and above.any() and not above.all()
+
+
+def test_mode_none_keeps_every_calibrated_value():
+    # x = (raw - dark) * flat: 3.09375, 4.21875, -0.28125, 3.0; nothing is clipped
+    raw = np.array([[[103, 104], [100, 104]]], dtype=np.uint16)
+    dark = np.array([[[100.25, 100.25], [100.25, 100.0]]], dtype=np.float32)
+    flat = np.array([[[1.125, 1.125], [1.125, 0.75]]], dtype=np.float32)
+    v, counts = oracle.calibrate(raw, dark, flat, 3.0, "none")
+    assert v.tolist() == [[[3.09375, 4.21875], [-0.28125, 3.0]]]
+    assert counts.tolist() == [2]                    # still the pixels above T
+    cx, cy = oracle.centroids(v, counts)
+    S = Fraction(309375 + 421875 - 28125 + 300000, 100000)
+    assert cx[0] == float((Fraction(-1, 2) * (Fraction(309375, 100000) - Fraction(28125, 100000))
+                           + Fraction(1, 2) * (Fraction(421875, 100000) + 3)) / S)
+    assert cy[0] == float((Fraction(-1, 2) * (Fraction(309375 + 421875, 100000))
+                           + Fraction(1, 2) * (Fraction(-28125, 100000) + 3)) / S)
+
+
+def test_mode_none_equals_mode_zero_when_every_pixel_is_above():
+    rng = np.random.default_rng(5)
+    raw = rng.integers(150, 400, size=(6, 8, 8)).astype(np.uint16)
+    dark = (100 + 2 * rng.standard_normal((6, 8, 8))).astype(np.float32)
+    flat = (1 + 0.02 * rng.standard_normal((6, 8, 8))).astype(np.float32)
+    v0, c0 = oracle.calibrate(raw, dark, flat, 3.0, "zero")
+    vn, cn = oracle.calibrate(raw, dark, flat, 3.0, "none")
+    assert np.all(c0 == 64) and np.array_equal(c0, cn) and np.array_equal(v0, vn)
+
+
+def test_mode_none_slopes_do_not_depend_on_the_threshold():
+    rng = np.random.default_rng(6)
+    raw = rng.integers(90, 200, size=(5, 6, 6)).astype(np.uint16)
+    dark = np.full((5, 6, 6), 100.0, np.float32)
+    flat = np.ones((5, 6, 6), np.float32)
+    out = [oracle.calibrate(raw, dark, flat, T, "none") for T in (0.0, 3.0, 50.0)]
+    for v, c in out[1:]:
+        assert np.array_equal(v, out[0][0])
+    assert out[0][1].sum() > out[1][1].sum() > out[2][1].sum()
+
+
+def test_mode_none_nonpositive_sum_gives_zero_centroid():
+    # every pixel below the dark: S < 0; S == 0 with mixed signs; both centroid 0
+    raw = np.array([[[90, 95], [98, 99]], [[110, 90], [100, 100]]], dtype=np.uint16)
+    dark = np.full((2, 2, 2), 100.0, np.float32)
+    flat = np.ones((2, 2, 2), np.float32)
+    v, counts = oracle.calibrate(raw, dark, flat, 0.0, "none")
+    assert v.sum(axis=(1, 2)).tolist() == [-18.0, 0.0]
+    cx, cy = oracle.centroids(v, counts)
+    assert cx.tolist() == [0.0, 0.0] and cy.tolist() == [0.0, 0.0]
 
 
 def test_threshold_must_be_nonnegative():

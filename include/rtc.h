@@ -34,11 +34,12 @@
  *    order; calls on different streams of the same context race.
  *
  * Threshold decision: a pixel is "above" when the exact real number
- * (raw - dark) * flat - T is > 0 (a tie counts as below).  The device decides it
- * with one float64 fused multiply-add on float64 (raw - dark), which is exact
- * because rtc_load_calib only accepts dark values that are 0 or of magnitude
- * in [2^-13, 2^24) (then raw - dark is representable in float64 for every
- * 16-bit raw value).
+ * (raw - dark) * flat - T is > 0 (a tie counts as below), for every finite
+ * float32 dark and flat.  When every dark is 0 or of magnitude in [2^-13, 2^24)
+ * raw - dark is exact in float64 and the device decides with one float64 fused
+ * multiply-add; otherwise raw - dark is split exactly into two float64 terms
+ * and pixels whose estimate lies within rounding of the threshold are decided
+ * from an exact expansion of the five-term sum.  Counts are exact either way.
  */
 #ifndef RTC_H
 #define RTC_H
@@ -63,8 +64,13 @@ typedef enum {
   RTC_E_UNSUPPORTED = -6   /* valid request this build does not implement */
 } rtc_status;
 
-/* Threshold application (Figure 3 (a)); the paper does not fix the rule. */
+/* Threshold application (Figure 3 (a)); the paper does not fix the rule.
+ * x = (raw - dark) * flat is the calibrated pixel.  The centroid of a
+ * subaperture is 0 (minus its reference slopes) unless the sum of its v is
+ * positive; in the thresholded modes that is exactly when a pixel is above.
+ * Counts report the pixels with x > T in every mode. */
 typedef enum {
+  RTC_THR_NONE = 0,        /* v = x for every pixel (no threshold applied) */
   RTC_THR_SUBTRACT = 1,    /* v = x - T if x > T else 0 (default) */
   RTC_THR_ZERO = 2         /* v = x     if x > T else 0 */
 } rtc_thr_mode;
@@ -110,9 +116,10 @@ typedef struct {
  * subaperture index map and allocates the per-frame device buffers.  The
  * integrator state starts at 0.  *out is set only on RTC_OK.
  * Errors: RTC_E_ARG (bad sizes, NULL, no active subaperture, wrong ABI
- * version), RTC_E_NONFINITE (gain/leak/clamp NaN or gain/leak infinite),
- * RTC_E_UNSUPPORTED (reduced-precision matrix with more than 65,536
- * slopes), RTC_E_DEVICE (no such device), RTC_E_NOMEM. */
+ * version, unknown thr_mode), RTC_E_NONFINITE (gain/leak/clamp NaN or
+ * gain/leak infinite), RTC_E_UNSUPPORTED (reduced-precision matrix with more
+ * than 2^24 16-byte chunks per row), RTC_E_DEVICE (no such device),
+ * RTC_E_NOMEM. */
 rtc_status rtc_init(const rtc_config *cfg, rtc_ctx **out);
 
 /* Several wavefront sensors reconstructed together (the multi-WFS systems of
@@ -163,8 +170,9 @@ int64_t rtc_frame_elems(const rtc_ctx *c);
  * centroids.  Only the active subapertures' pixels are read (and checked),
  * re-laid out per subaperture; other pixels of the maps are ignored.
  * Replaces a previous calibration after synchronising the device.
- * Errors: RTC_E_ARG (NULL maps, T < 0, dark outside {0} U [2^-13, 2^24) in
- * magnitude), RTC_E_NONFINITE, RTC_E_DEVICE, RTC_E_NOMEM. */
+ * Any finite dark and flat are accepted (see the threshold decision above).
+ * Errors: RTC_E_ARG (NULL maps, T < 0), RTC_E_NONFINITE, RTC_E_DEVICE,
+ * RTC_E_NOMEM. */
 /* rtc_load_calib on a multi-sensor context applies the one threshold to every
  * sensor; dark and flat are laid out as a frame set. */
 rtc_status rtc_load_calib(rtc_ctx *c, const float *dark, const float *flat, float threshold,
@@ -275,7 +283,8 @@ rtc_status rtc_get_mvm_tuning(const rtc_ctx *c, rtc_mvm_tuning *t);
  *    remaining frames are not processed and rtc_sync_check reports it.
  *    Shapes the persistent kernel does not cover (more than 512 actuator rows
  *    per compute unit, slope slices beyond its registers, a grid that cannot
- *    be co-resident) run per launch instead.  The arithmetic and its order
+ *    be co-resident, a calibration with a dark outside {0} U [2^-13, 2^24) in
+ *    magnitude) run per launch instead.  The arithmetic and its order
  *    are those of the per-launch mode with the row-block kernel, 8 wavefronts
  *    and the same workgroup count, so results are bitwise identical to it. */
 typedef enum { RTC_FRAMES_PER_LAUNCH = 0, RTC_FRAMES_PERSISTENT = 1 } rtc_frame_mode;
@@ -456,13 +465,22 @@ rtc_status rtc_pipe_info(const rtc_ctx *c, int32_t *n_workers, int32_t *lds_cols
  * state carries across calls and frame modes.  A wait that exceeds
  * wait_limit_us gives up, and the batch stops early; rtc_sync_check reports
  * it.  Errors: RTC_E_STATE before rtc_pipe_setup or after a new
- * matrix; RTC_E_ARG for bad arguments; RTC_E_DEVICE when the launch fails. */
+ * matrix; RTC_E_ARG for bad arguments; RTC_E_UNSUPPORTED when a dark of the
+ * calibration is outside {0} U [2^-13, 2^24) in magnitude (the exact threshold
+ * path runs in the per-launch calibration only); RTC_E_DEVICE when the launch
+ * fails. */
 rtc_status rtc_pipe_run(rtc_ctx *c, int32_t n_frames, const uint16_t *d_frames, int64_t frame_stride,
                         float *d_cmd, float *d_slopes, float *d_recon, int32_t *d_counts, uint64_t *d_cam_ts,
                         uint64_t *d_worker_ts, void *hip_stream);
 
-/* Synchronises the device and reports RTC_E_DEVICE if a persistent batch gave
- * up at a barrier since the last check (the flag is then cleared). */
+/* Synchronises the device and reports RTC_E_DEVICE if a persistent or
+ * pixel-stream batch gave up at a bounded wait since the last check (the flag
+ * is then cleared).  In such a batch the workgroup whose wait expired computes
+ * neither that frame nor later ones, so the commands of those frames are not
+ * written and each actuator row's integrator state stops at the last frame its
+ * workgroup completed: the state is undefined.  After this report rtc_frame,
+ * rtc_frame_batch, rtc_reconstruct_integrate, rtc_graph_launch and
+ * rtc_pipe_run fail with RTC_E_STATE until rtc_reset or rtc_set_state. */
 rtc_status rtc_sync_check(rtc_ctx *c);
 
 /* Integrator state: reset to 0, synchronous host copy out / in (n_act floats,

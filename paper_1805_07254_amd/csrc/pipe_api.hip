@@ -200,6 +200,10 @@ rtc_status rtc_pipe_run(rtc_ctx *c, int32_t n_frames, const uint16_t *d_frames, 
   if (!c->calib_loaded) return fail(c, RTC_E_STATE, "rtc_pipe_run: load the calibration first");
   if (c->pipe_gen == 0 || c->pipe_gen != c->cmat_gen)
     return fail(c, RTC_E_STATE, "rtc_pipe_run: call rtc_pipe_setup after loading the control matrix");
+  if (c->state_invalid) return fail(c, RTC_E_STATE, "rtc_pipe_run: " STATE_INVALID_MSG);
+  if (!c->dark_fast)
+    return fail(c, RTC_E_UNSUPPORTED, "rtc_pipe_run: pixel-stream processing needs every dark to be 0 or of "
+                                      "magnitude in [2^-13, 2^24)");
   if (n_frames < 0) return fail(c, RTC_E_ARG, "rtc_pipe_run: n_frames < 0");
   if (n_frames == 0) return RTC_OK;
   if (!d_frames || !d_cmd) return fail(c, RTC_E_ARG, "rtc_pipe_run: NULL frames or cmd");
@@ -221,6 +225,7 @@ rtc_status rtc_pipe_run(rtc_ctx *c, int32_t n_frames, const uint16_t *d_frames, 
   p.n_valid = c->n_valid;
   p.max_n = c->max_n;
   p.mode = c->cfg.thr_mode;
+  p.dark_fast = c->dark_fast;
   p.fmt = c->fmt;
   p.src = d_frames;
   p.src_stride = frame_stride;

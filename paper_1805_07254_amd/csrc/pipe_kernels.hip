@@ -231,7 +231,7 @@ __device__ __forceinline__ void pipe_pass_finish(const PipeArgs &p, int f, const
       raw[2 * q] = odd ? (w[q] >> 16) : (w[q] & 0xffffu);
       raw[2 * q + 1] = odd ? (w[q + 1] & 0xffffu) : (w[q] >> 16);
     }
-    tile_row_sums<GS>(raw, pf.cf, n, t.thr, p.mode == 1, half, S, Sx, cnt);
+    tile_row_sums<GS>(raw, pf.cf, n, t.thr, p.mode, half, S, Sx, cnt);
   }
   double cx, cy;
   tile_centroid<GS>(S, Sx, cnt, i, half, cx, cy, cnt);

@@ -32,7 +32,8 @@ using namespace rtcx;
 namespace {
 
 bool dark_in_domain(float d) {
-  // raw - dark is exact in float64 for every raw in [0, 65535] iff this holds.
+  // raw - dark is exact in float64 for every raw in [0, 65535] when this holds;
+  // other darks take the kernels' exact slow path.
   const float a = std::fabs(d);
   return d == 0.0f || (a >= 0x1p-13f && a < 0x1p24f);
 }
@@ -176,8 +177,8 @@ static rtc_status init_impl(const rtc_config *cfg, const rtc_wfs *wfs, int32_t n
       t.sy = 2 * wi.tile_base + wi.n_tiles + k;
     }
   if (cfg->n_act < 1 || cfg->n_act > (1 << 20)) return err(RTC_E_ARG, "n_act must be in 1..2^20");
-  if (cfg->thr_mode != RTC_THR_SUBTRACT && cfg->thr_mode != RTC_THR_ZERO)
-    return err(RTC_E_ARG, "thr_mode must be RTC_THR_SUBTRACT or RTC_THR_ZERO");
+  if (cfg->thr_mode != RTC_THR_NONE && cfg->thr_mode != RTC_THR_SUBTRACT && cfg->thr_mode != RTC_THR_ZERO)
+    return err(RTC_E_ARG, "thr_mode must be RTC_THR_NONE, RTC_THR_SUBTRACT or RTC_THR_ZERO");
   if (cfg->cm_dtype < RTC_CM_F32 || cfg->cm_dtype > RTC_CM_FP8E4M3) return err(RTC_E_ARG, "unknown cm_dtype");
   if (!std::isfinite(cfg->gain) || !std::isfinite(cfg->leak))
     return err(RTC_E_NONFINITE, "gain and leak must be finite");
@@ -297,6 +298,7 @@ static rtc_status load_calib_impl(rtc_ctx *c, const float *dark, const float *fl
   }
   std::vector<float2> cal;
   std::vector<rtck::TileDesc> tiles = c->tiles_h;
+  bool fast = true;                                // every dark admits the one-fma threshold decision
   try {
     cal.resize((size_t)c->calib_len);
   } catch (...) {
@@ -314,7 +316,7 @@ static rtc_status load_calib_impl(rtc_ctx *c, const float *dark, const float *fl
           const float d = dark[base + j], f = flat[base + j];
           if (!std::isfinite(d) || !std::isfinite(f))
             return err(RTC_E_NONFINITE, "non-finite dark or flat value in an active subaperture");
-          if (!dark_in_domain(d)) return err(RTC_E_ARG, "dark values must be 0 or of magnitude in [2^-13, 2^24)");
+          if (!dark_in_domain(d)) fast = false;
           cal[(size_t)t.calib_off + (size_t)i * n + j] = make_float2(d, f);
         }
       }
@@ -344,6 +346,7 @@ static rtc_status load_calib_impl(rtc_ctx *c, const float *dark, const float *fl
   dfree(c->d_calib);
   c->d_calib = d_cal;
   c->tiles_h = std::move(tiles);
+  c->dark_fast = fast ? 1 : 0;
   c->calib_loaded = true;
   return RTC_OK;
 }
@@ -484,6 +487,7 @@ static rtck::CalibArgs calib_args(const rtc_ctx *c, const uint16_t *pix) {
   ca.max_n = c->max_n;
   ca.pairs = c->pairs;
   ca.mode = c->cfg.thr_mode;
+  ca.dark_fast = c->dark_fast;
   ca.ref = c->d_ref;
   return ca;
 }
@@ -524,6 +528,7 @@ rtc_status rtc_frame(rtc_ctx *c, const uint16_t *d_pixels, float *d_cmd, float *
   if (!c) return fail(nullptr, RTC_E_ARG, "rtc_frame: NULL context");
   if (!c->calib_loaded || !c->cmat_loaded)
     return fail(c, RTC_E_STATE, "rtc_frame: load the calibration and the control matrix first");
+  if (c->state_invalid) return fail(c, RTC_E_STATE, "rtc_frame: " STATE_INVALID_MSG);
   if (!d_pixels || !d_cmd) return fail(c, RTC_E_ARG, "rtc_frame: NULL pixels or cmd");
   DeviceScope ds(c->device);
   if (ds.status != hipSuccess) return hip_fail(c, ds.status, "rtc_frame: hipSetDevice");
@@ -537,6 +542,7 @@ rtc_status rtc_frame_batch(rtc_ctx *c, int32_t n_frames, const uint16_t *d_pixel
   if (!c) return fail(nullptr, RTC_E_ARG, "rtc_frame_batch: NULL context");
   if (!c->calib_loaded || !c->cmat_loaded)
     return fail(c, RTC_E_STATE, "rtc_frame_batch: load the calibration and the control matrix first");
+  if (c->state_invalid) return fail(c, RTC_E_STATE, "rtc_frame_batch: " STATE_INVALID_MSG);
   if (n_frames < 0) return fail(c, RTC_E_ARG, "rtc_frame_batch: n_frames < 0");
   if (n_frames == 0) return RTC_OK;
   if (!d_pixels || !d_cmd) return fail(c, RTC_E_ARG, "rtc_frame_batch: NULL pixels or cmd");
@@ -640,6 +646,7 @@ rtc_status rtc_graph_capture(rtc_ctx *c, int32_t n_frames, const uint16_t *d_pix
 rtc_status rtc_graph_launch(rtc_ctx *c, void *hip_stream) {
   if (!c) return fail(nullptr, RTC_E_ARG, "rtc_graph_launch: NULL context");
   if (!c->graph) return fail(c, RTC_E_STATE, "rtc_graph_launch: no recorded graph");
+  if (c->state_invalid) return fail(c, RTC_E_STATE, "rtc_graph_launch: " STATE_INVALID_MSG);
   DeviceScope ds(c->device);
   if (ds.status != hipSuccess) return hip_fail(c, ds.status, "rtc_graph_launch: hipSetDevice");
   const hipError_t e = hipGraphLaunch(c->graph, static_cast<hipStream_t>(hip_stream));
@@ -959,6 +966,7 @@ rtc_status rtc_reconstruct_integrate(rtc_ctx *c, const float *d_slopes, float *d
                                      void *hip_stream) {
   if (!c) return fail(nullptr, RTC_E_ARG, "rtc_reconstruct_integrate: NULL context");
   if (!c->cmat_loaded) return fail(c, RTC_E_STATE, "rtc_reconstruct_integrate: load the control matrix first");
+  if (c->state_invalid) return fail(c, RTC_E_STATE, "rtc_reconstruct_integrate: " STATE_INVALID_MSG);
   if (!d_slopes || !d_cmd) return fail(c, RTC_E_ARG, "rtc_reconstruct_integrate: NULL slopes or cmd");
   DeviceScope ds(c->device);
   if (ds.status != hipSuccess) return hip_fail(c, ds.status, "rtc_reconstruct_integrate: hipSetDevice");
@@ -1062,9 +1070,12 @@ rtc_status rtc_sync_check(rtc_ctx *c) {
   if (e == hipSuccess && flag) e = hipMemset(sticky, 0, sizeof(uint32_t));
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) return hip_fail(c, e, "rtc_sync_check");
-  if (flag)
+  if (flag) {
+    c->state_invalid = true;
     return fail(c, RTC_E_DEVICE, "rtc_sync_check: a persistent or pixel-stream batch gave up at a bounded "
-                                 "wait; its later frames were not processed");
+                                 "wait; the frame that waited and later ones were not processed and the "
+                                 "integrator state is undefined until rtc_reset or rtc_set_state");
+  }
   return RTC_OK;
 }
 
@@ -1075,6 +1086,7 @@ rtc_status rtc_reset(rtc_ctx *c) {
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e == hipSuccess) e = hipMemset(c->d_state, 0, c->n_act * sizeof(float));
   if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e == hipSuccess) c->state_invalid = false;
   return e == hipSuccess ? RTC_OK : hip_fail(c, e, "rtc_reset");
 }
 
@@ -1097,6 +1109,7 @@ rtc_status rtc_set_state(rtc_ctx *c, const float *h_cmd) {
   hipError_t e = ds.status;
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e == hipSuccess) e = hipMemcpy(c->d_state, h_cmd, c->n_act * sizeof(float), hipMemcpyHostToDevice);
+  if (e == hipSuccess) c->state_invalid = false;
   return e == hipSuccess ? RTC_OK : hip_fail(c, e, "rtc_set_state");
 }
 

@@ -58,7 +58,9 @@ struct rtc_ctx {
   int32_t split_G = 0;             // grid the split is for (0 = equal split)
   int32_t split_max = 0;           // most rows of one workgroup in the split
   std::vector<int32_t> split_h;    // host copy of the split (split_G + 1 entries)
+  int32_t dark_fast = 1;           // every loaded dark is 0 or of magnitude in [2^-13, 2^24)
   bool calib_loaded = false;
+  bool state_invalid = false;      // a reported failed batch left the integrator state undefined
   bool cmat_loaded = false;
   uint64_t cmat_gen = 0;           // bumped by every rtc_load_cmat
 
@@ -76,6 +78,10 @@ struct rtc_ctx {
   int32_t *d_first = nullptr;      // [workers + 1]
   int32_t *d_need = nullptr;       // [n_valid]
 };
+
+// Frame calls refuse to run on a state that a failed persistent or pixel-stream
+// batch left undefined.
+#define STATE_INVALID_MSG "a failed batch left the integrator state undefined; call rtc_reset or rtc_set_state"
 
 namespace rtcx {
 

@@ -10,33 +10,136 @@
 namespace rtck {
 namespace {
 
+// Exact error-free transformations in float64 (round to nearest): a + b =
+// s + e and a * b = p + e exactly.  The _rn intrinsics keep the compiler from
+// contracting or reassociating them.
+__device__ __forceinline__ void two_sum(double a, double b, double &s, double &e) {
+  s = __dadd_rn(a, b);
+  const double bb = __dsub_rn(s, a);
+  e = __dadd_rn(__dsub_rn(a, __dsub_rn(s, bb)), __dsub_rn(b, bb));
+}
+__device__ __forceinline__ void two_prod(double a, double b, double &p, double &e) {
+  p = __dmul_rn(a, b);
+  e = __fma_rn(a, b, -p);
+}
+
+// Adds x to the nonoverlapping expansion h[0..m) (increasing magnitude, zeros
+// allowed) in place, the new largest component going to h[m] (Shewchuk's
+// expansion growth): the sum of the components stays exact.
+template <int M>
+__device__ __forceinline__ void grow_expansion(double (&h)[5], double x) {
+  double q = x;
+#pragma unroll
+  for (int i = 0; i < M; ++i) {
+    double t;
+    two_sum(q, h[i], q, t);
+    h[i] = t;
+  }
+  h[M] = q;
+}
+
+// Exact decision for one pixel whose float64 estimate lay within rounding of
+// the threshold (only possible when raw - dark is not exact in float64, i.e.
+// the dark is outside {0} U [2^-13, 2^24) in magnitude): raw - dark = s + e and
+// s flat, e flat are split exactly into two float64 terms each, so the excess
+// (raw - dark) * flat - T is an exact sum of five float64 terms; the sum is
+// grown into a nonoverlapping expansion, whose sign is that of its largest
+// nonzero component.  r and x get float64 values of the excess and of
+// (raw - dark) * flat; returns whether the excess is > 0.
+__device__ __forceinline__ bool exact_excess(uint32_t raw, float dark, float flat, double T, double &r, double &x) {
+  const double f = (double)flat;
+  double s, e, p, pe, q, qe;
+  two_sum((double)raw, -(double)dark, s, e);
+  two_prod(s, f, p, pe);
+  two_prod(e, f, q, qe);
+  double h[5];
+  h[0] = qe;
+  grow_expansion<1>(h, q);
+  grow_expansion<2>(h, pe);
+  grow_expansion<3>(h, p);
+  grow_expansion<4>(h, -T);
+  int sign = 0;
+#pragma unroll
+  for (int i = 0; i < 5; ++i) sign = h[i] > 0.0 ? 1 : (h[i] < 0.0 ? -1 : sign);
+  r = (((h[0] + h[1]) + h[2]) + h[3]) + h[4];
+  x = ((qe + q) + pe) + p;
+  return sign > 0;
+}
+
+// Value of a pixel in the weighted sums: mode 1 (subtract) the excess above the
+// threshold, mode 2 (zero) the calibrated value above it, else 0; mode 0
+// (none) the calibrated value of every pixel.
+__device__ __forceinline__ double pixel_value(int mode, bool above, double r, double x) {
+  return mode == 0 ? x : (above ? (mode == 1 ? r : x) : 0.0);
+}
+
 // Dark, flat and threshold of one pixel row (lane i of a tile with n pixels a
-// side): its weighted sum S and x moment Sx, and the count of pixels above
-// the threshold.
-template <int GS>
+// side): its weighted sum S and x moment Sx, and the count of pixels above the
+// threshold.  The decision uses r = fma(raw - dark, flat, -T) in float64,
+// whose sign is exact when raw - dark is, i.e. when every dark of the
+// calibration is 0 or of magnitude in [2^-13, 2^24) (FAST).  Otherwise
+// (!FAST) a pixel whose r lies within the rounding bound of zero is marked,
+// and after the row the marked pixels are fetched again
+// (fetch(j, raw, dark, flat)) and decided by exact_excess, their
+// contributions replacing the provisional ones; the row loop itself keeps only
+// the mask.  The kernels that keep matrix rows in registers are built FAST
+// only (their register budget has no room for the exact path).
+template <int GS, bool FAST, class Fetch>
 __device__ __forceinline__ void tile_row_sums(const uint32_t (&raw)[GS], const float2 (&cf)[GS], int n, float thr,
-                                              bool subtract, double half, double &S, double &Sx, int &cnt) {
+                                              int mode, double half, double &S, double &Sx, int &cnt,
+                                              Fetch fetch) {
   const double T = (double)thr;
+  uint32_t amb = 0;
 #pragma unroll
   for (int j = 0; j < GS; ++j) {
     if (j < n) {
-      // raw - dark is exact in float64 for the accepted dark domain; the single
-      // rounding of the fma keeps the sign of (raw - dark) * flat - T exact.
       const double d = (double)raw[j] - (double)cf[j].x;
       const double f = (double)cf[j].y;
       const double r = fma(d, f, -T);
       const bool above = r > 0.0;
-      const double v = above ? (subtract ? r : d * f) : 0.0;
+      if constexpr (!FAST) {
+        // |exact - r| <= 2^-53 (|d f| + |r|) (1 + 2^-52) when raw - dark was rounded
+        if (!(fabs(r) > 0x1p-50 * (fabs(d * f) + fabs(r)))) amb |= 1u << j;
+      }
+      const double v = pixel_value(mode, above, r, d * f);
       S += v;
       Sx = fma((double)j - half, v, Sx);
       cnt += above ? 1 : 0;
     }
   }
+  if constexpr (!FAST) {
+    while (amb != 0u) {                            // rare: a dark outside the fast domain near a tie
+      const int j = __builtin_ctz(amb);
+      amb &= amb - 1u;
+      uint32_t rj;
+      float dk, fl;
+      fetch(j, rj, dk, fl);
+      const double d = (double)rj - (double)dk, f = (double)fl;
+      const double r = fma(d, f, -T);
+      const bool ap = r > 0.0;
+      double re, xe;
+      const bool ae = exact_excess(rj, dk, fl, T, re, xe);
+      const double dv = pixel_value(mode, ae, re, xe) - pixel_value(mode, ap, r, d * f);
+      S += dv;
+      Sx = fma((double)j - half, dv, Sx);
+      cnt += (ae ? 1 : 0) - (ap ? 1 : 0);
+    }
+  }
+}
+
+// The FAST form (no second fetch).
+struct NoFetch {
+  __device__ void operator()(int, uint32_t &, float &, float &) const {}
+};
+template <int GS>
+__device__ __forceinline__ void tile_row_sums(const uint32_t (&raw)[GS], const float2 (&cf)[GS], int n, float thr,
+                                              int mode, double half, double &S, double &Sx, int &cnt) {
+  tile_row_sums<GS, true>(raw, cf, n, thr, mode, half, S, Sx, cnt, NoFetch{});
 }
 
 // Tile sums over its GS lanes (butterfly: identical sums in every lane) and
-// the centre of gravity relative to the tile centre (0 without a pixel above
-// the threshold).
+// the centre of gravity relative to the tile centre (0 unless the weighted
+// sum is positive).
 template <int GS>
 __device__ __forceinline__ void tile_centroid(double S, double Sx, int cnt, int i, double half, double &cx,
                                               double &cy, int &cnt_out) {
@@ -50,7 +153,7 @@ __device__ __forceinline__ void tile_centroid(double S, double Sx, int cnt, int 
   }
   cx = 0.0;
   cy = 0.0;
-  if (cnt > 0) {
+  if (S > 0.0) {                     // thresholded modes: S > 0 exactly when a pixel is above
     cx = Sx / S;
     cy = Sy / S;
   }

@@ -26,7 +26,8 @@ struct CalibArgs {
   int32_t n_valid;
   int32_t max_n;           // largest tile side (lanes per tile)
   int32_t pairs;           // every tile row starts on an even element and has even width
-  int32_t mode;            // 1 = subtract, 2 = zero
+  int32_t mode;            // threshold: 0 = none, 1 = subtract, 2 = zero
+  int32_t dark_fast;       // 1: every dark is 0 or of magnitude in [2^-13, 2^24) (raw - dark exact in float64)
   const float *ref;        // [n_slopes] reference slopes (by slope position)
   float *s_int;            // [>= n_slopes] library slope buffer
   float *s_user;           // nullable copy
@@ -160,7 +161,8 @@ struct PipeArgs {
   const float *ref;
   int32_t n_valid;
   int32_t max_n;
-  int32_t mode;            // 1 = subtract, 2 = zero
+  int32_t mode;            // threshold: 0 = none, 1 = subtract, 2 = zero
+  int32_t dark_fast;       // as CalibArgs::dark_fast
   int32_t fmt;             // storage format of the packed columns
   // camera
   const uint16_t *src;     // [n_frames] frames, src_stride elements apart, 4-byte aligned

@@ -73,7 +73,7 @@ __device__ __forceinline__ void tile_publish(const CalibArgs &a, const TileDesc 
 // pixels a side every load is unconditional (positions past the row repeat
 // its last one), so all of a lane's loads are in flight before the first use;
 // wider tiles load only their own pixels (fewer registers).
-template <int GS, bool COH, bool TL, bool VEC>
+template <int GS, bool COH, bool TL, bool VEC, bool FAST = true>
 __device__ __forceinline__ void calib_tile_row(const CalibArgs &a, int k, int i, const TileDesc *tl = nullptr,
                                                int kl = 0, const float2 *rl = nullptr) {
   TileDesc t{};
@@ -130,7 +130,13 @@ __device__ __forceinline__ void calib_tile_row(const CalibArgs &a, int k, int i,
         }
       }
     }
-    tile_row_sums<GS>(raw, cf, n, t.thr, a.mode == 1, half, S, Sx, cnt);
+    tile_row_sums<GS, FAST>(raw, cf, n, t.thr, a.mode, half, S, Sx, cnt,
+                      [&](int j, uint32_t &rj, float &dk, float &fl) {
+                        rj = prow[j];
+                        const float2 c = crow[j];
+                        dk = c.x;
+                        fl = c.y;
+                      });
   }
   double cx, cy;
   tile_centroid<GS>(S, Sx, cnt, i, half, cx, cy, cnt);
@@ -179,7 +185,7 @@ __device__ __forceinline__ void calib_tile_row_any(const CalibArgs &a, int k, in
         }
       }
     }
-    tile_row_sums<GS>(raw, cf, n, t.thr, a.mode == 1, half, S, Sx, cnt);
+    tile_row_sums<GS>(raw, cf, n, t.thr, a.mode, half, S, Sx, cnt);
   }
   double cx, cy;
   tile_centroid<GS>(S, Sx, cnt, i, half, cx, cy, cnt);
@@ -268,7 +274,7 @@ __device__ __forceinline__ void pixel_row_finish(const CalibArgs &a, int k, int 
 #pragma unroll
     for (int j = 0; j < GS; ++j)
       if (GS <= 16 || j < n) cf[j] = crow[j < n - 1 ? j : n - 1];
-    tile_row_sums<GS>(raw, cf, n, t.thr, a.mode == 1, half, S, Sx, cnt);
+    tile_row_sums<GS>(raw, cf, n, t.thr, a.mode, half, S, Sx, cnt);
   }
   double cx, cy;
   tile_centroid<GS>(S, Sx, cnt, i, half, cx, cy, cnt);
@@ -305,12 +311,14 @@ __device__ __forceinline__ void panel_calibration(const CalibArgs &a, int k_begi
   }
 }
 
-template <int GS, bool VEC>
+// FAST: every dark admits the one-fma threshold decision (else the exact
+// fix-up of tile_row_sums is built in).
+template <int GS, bool VEC, bool FAST>
 __global__ __launch_bounds__(kBlock) void calib_cog_kernel(CalibArgs a) {
   const int tid = threadIdx.x;
   if (a.ts_start != nullptr && blockIdx.x == 0 && tid == 0) a.ts_start[0] = wall_clock64();
   const int k = (int)(((int64_t)blockIdx.x * kBlock + tid) / GS);   // subaperture
-  calib_tile_row<GS, false, false, VEC>(a, k, tid & (GS - 1));
+  calib_tile_row<GS, false, false, VEC, FAST>(a, k, tid & (GS - 1));
 }
 
 // ---------------------------------------------------------------------------
@@ -803,7 +811,10 @@ __device__ __forceinline__ bool bounded_wait(const PersistArgs &p, const uint32_
   return true;
 }
 
-__device__ __forceinline__ void frame_barrier(const PersistArgs &p, uint32_t epoch, int f) {
+// False when this workgroup's wait for the release expired (the abort flag is
+// then raised): the frame's slopes may be incomplete, so the caller must not
+// use them.  sh_flag: a shared word of the workgroup.
+__device__ __forceinline__ bool frame_barrier(const PersistArgs &p, uint32_t epoch, int f, uint32_t *sh_flag) {
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // this wavefront's stores are complete
   __syncthreads();
   trace_stamp(p, f, 6);
@@ -827,9 +838,10 @@ __device__ __forceinline__ void frame_barrier(const PersistArgs &p, uint32_t epo
       for (uint32_t i = threadIdx.x; i < G; i += 64)
         __hip_atomic_store(p.bar + sl::kMailbox + 16 * i, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    if (threadIdx.x == 0) (void)bounded_wait(p, p.bar + sl::kMailbox + 16 * blockIdx.x, epoch);
+    if (threadIdx.x == 0) *sh_flag = bounded_wait(p, p.bar + sl::kMailbox + 16 * blockIdx.x, epoch) ? 0u : 1u;
   }
   __syncthreads();
+  return *sh_flag == 0u;
 }
 
 // End stamp of a frame: the latest of the per-workgroup end stamps, reduced by
@@ -889,7 +901,7 @@ __global__ __launch_bounds__(512 / VW) void frames_kernel(PersistArgs p, int32_t
   // slope panels only) its (dark, flat) blocks, which all stay the same for
   // every frame
   extern __shared__ uint4 lds[];
-  __shared__ uint32_t sh_abort;
+  __shared__ uint32_t sh_abort, sh_bar;
   const MvmArgs &a = p.mvm;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -1020,7 +1032,12 @@ __global__ __launch_bounds__(512 / VW) void frames_kernel(PersistArgs p, int32_t
       wg_calibration<GS, NT>(ca, k_begin, k_end, p.vec, cached ? sh_tiles : nullptr, cached ? sh_ref : nullptr);
     }
     trace_stamp(p, f, 1);
-    frame_barrier(p, (uint32_t)(f + 1), f);
+    // An expired wait leaves sh_bar set: the slopes of frame f may then be
+    // incomplete, so its commands and the rows' state are not written, and the
+    // raised abort flag ends the loop at the next frame (an exit here instead
+    // costs the sums below registers).  sh_bar is next written after the
+    // loop-top barrier, so the reads below cannot race with it.
+    (void)frame_barrier(p, (uint32_t)(f + 1), f, &sh_bar);
     trace_stamp(p, f, 2);
 
     if constexpr (PANELS) {
@@ -1150,8 +1167,8 @@ __global__ __launch_bounds__(512 / VW) void frames_kernel(PersistArgs p, int32_t
     __syncthreads();
     trace_stamp(p, f, 4);
 
-    // (d) integrate own rows
-    if (tid < nrows) {
+    // (d) integrate own rows (not when this workgroup's barrier wait expired)
+    if (tid < nrows && sh_bar == 0u) {
       float v = sh_part[tid];
       for (int w = 1; w < W; ++w) v += sh_part[w * max_rows + tid];
       if (a.scales != nullptr) v *= a.scales[row_begin + tid];
@@ -1168,7 +1185,7 @@ __global__ __launch_bounds__(512 / VW) void frames_kernel(PersistArgs p, int32_t
         __hip_atomic_store(reinterpret_cast<uint64_t *>(p.bar + sl::kEnds) + (f & 1) * sl::kMaxGroups + b,
                            wall_clock64(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    ++frames_done;
+    frames_done += sh_bar == 0u ? 1 : 0;
   }
   if (tid < nrows) a.state[row_begin + tid] = state;
   // end stamp of the last frame: the last workgroup to finish reduces it
@@ -1235,14 +1252,24 @@ hipError_t launch_calib_cog(const CalibArgs &a, hipStream_t st) {
   const unsigned blocks = (unsigned)((lanes + kBlock - 1) / kBlock);
   // 4-byte pixel pairs need even tile rows and a 4-byte aligned frame set
   const int vec = (a.pairs && (reinterpret_cast<uintptr_t>(a.pix) & 3) == 0) ? 1 : 0;
-  if (gs == 8)
-    vec ? calib_cog_kernel<8, true><<<blocks, kBlock, 0, st>>>(a) : calib_cog_kernel<8, false><<<blocks, kBlock, 0, st>>>(a);
-  else if (gs == 16)
-    vec ? calib_cog_kernel<16, true><<<blocks, kBlock, 0, st>>>(a)
-        : calib_cog_kernel<16, false><<<blocks, kBlock, 0, st>>>(a);
-  else
-    vec ? calib_cog_kernel<32, true><<<blocks, kBlock, 0, st>>>(a)
-        : calib_cog_kernel<32, false><<<blocks, kBlock, 0, st>>>(a);
+  if (a.dark_fast) {
+    if (gs == 8)
+      vec ? calib_cog_kernel<8, true, true><<<blocks, kBlock, 0, st>>>(a)
+          : calib_cog_kernel<8, false, true><<<blocks, kBlock, 0, st>>>(a);
+    else if (gs == 16)
+      vec ? calib_cog_kernel<16, true, true><<<blocks, kBlock, 0, st>>>(a)
+          : calib_cog_kernel<16, false, true><<<blocks, kBlock, 0, st>>>(a);
+    else
+      vec ? calib_cog_kernel<32, true, true><<<blocks, kBlock, 0, st>>>(a)
+          : calib_cog_kernel<32, false, true><<<blocks, kBlock, 0, st>>>(a);
+  } else {                                         // darks outside the fast domain: exact fix-up built in
+    if (gs == 8)
+      calib_cog_kernel<8, false, false><<<blocks, kBlock, 0, st>>>(a);
+    else if (gs == 16)
+      calib_cog_kernel<16, false, false><<<blocks, kBlock, 0, st>>>(a);
+    else
+      calib_cog_kernel<32, false, false><<<blocks, kBlock, 0, st>>>(a);
+  }
   return hipGetLastError();
 }
 
@@ -1401,7 +1428,7 @@ static hipError_t launch_frames_variant(const PersistArgs &p, int G, int max_row
   if ((e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
   if ((e = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev)) != hipSuccess) return e;
   const int64_t part_bytes = (int64_t)W * max_rows * sizeof(float);
-  const int64_t static_bytes = 64;                 // sh_abort and alignment slack
+  const int64_t static_bytes = 64;                 // sh_abort, sh_bar and alignment slack
   // tile descriptors and reference slopes of a workgroup's subapertures, kept in LDS
   const int per_wg = (p.cal.n_valid + G - 1) / G;
   const int tile_cap = per_wg <= kTileCache ? per_wg : 0;
@@ -1466,6 +1493,7 @@ hipError_t launch_frames(const PersistArgs &p, int blocks, int rows_per_batch, h
   constexpr int W = 8;
   if (p.n_frames <= 0) return hipSuccess;
   if (p.cal.max_n < 1 || p.cal.max_n > 32) return hipErrorInvalidValue;
+  if (!p.cal.dark_fast) return hipErrorInvalidValue;   // the exact threshold fix-up runs per launch only
   const int G = frames_grid(blocks, p.mvm.n_act);
   if (G > sl::kMaxGroups) return hipErrorInvalidValue;
   const int max_rows = p.row_start != nullptr ? p.row_max : (p.mvm.n_act + G - 1) / G;

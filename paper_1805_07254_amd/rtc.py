@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "librtc.so")
 RTC_ABI_VERSION = 1
 RTC_OK, RTC_E_ARG, RTC_E_STATE, RTC_E_NOMEM, RTC_E_DEVICE, RTC_E_NONFINITE, RTC_E_UNSUPPORTED = \
     0, -1, -2, -3, -4, -5, -6
-RTC_THR_SUBTRACT, RTC_THR_ZERO = 1, 2
+RTC_THR_NONE, RTC_THR_SUBTRACT, RTC_THR_ZERO = 0, 1, 2
 RTC_CM_F32, RTC_CM_F16, RTC_CM_BF16, RTC_CM_FP8E4M3 = 0, 1, 2, 3
 CM_DTYPES = {"f32": RTC_CM_F32, "f16": RTC_CM_F16, "bf16": RTC_CM_BF16, "fp8e4m3": RTC_CM_FP8E4M3}
 STATUS_NAMES = {0: "RTC_OK", -1: "RTC_E_ARG", -2: "RTC_E_STATE", -3: "RTC_E_NOMEM",
@@ -421,14 +421,37 @@ def rtc_wall_clock_khz(ctx: RtcContext) -> int:
     return out.value
 
 
+def _dev_bytes(t, n_bytes: int, what: str, ctx: RtcContext) -> int:
+    """Device pointer of a contiguous torch tensor of any dtype holding at least n_bytes."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{what} must be a torch tensor")
+    if t.device.type != "cuda" or t.device.index != ctx.cfg["device"]:
+        raise ValueError(f"{what} must live on cuda:{ctx.cfg['device']}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    if t.numel() * t.element_size() < n_bytes:
+        raise ValueError(f"{what} holds {t.numel() * t.element_size()} bytes, needs {n_bytes}")
+    return t.data_ptr()
+
+
+def _probe_size(n_bytes: int) -> int:
+    n_bytes = int(n_bytes)
+    if n_bytes < 0 or n_bytes % 16:
+        raise ValueError("n_bytes must be a non-negative multiple of 16")
+    return n_bytes
+
+
 def rtc_probe_copy(ctx: RtcContext, src, dst, n_bytes: int, stream=None) -> None:
-    _check(load_library().rtc_probe_copy(ctx.handle, src.data_ptr(), dst.data_ptr(), n_bytes,
-                                         _stream_ptr(stream)), ctx)
+    n_bytes = _probe_size(n_bytes)
+    _check(load_library().rtc_probe_copy(ctx.handle, _dev_bytes(src, n_bytes, "src", ctx),
+                                         _dev_bytes(dst, n_bytes, "dst", ctx), n_bytes, _stream_ptr(stream)), ctx)
 
 
 def rtc_probe_read(ctx: RtcContext, src, n_bytes: int, out, stream=None) -> None:
-    _check(load_library().rtc_probe_read(ctx.handle, src.data_ptr(), n_bytes, out.data_ptr(),
-                                         _stream_ptr(stream)), ctx)
+    n_bytes = _probe_size(n_bytes)
+    _check(load_library().rtc_probe_read(ctx.handle, _dev_bytes(src, n_bytes, "src", ctx), n_bytes,
+                                         _dev_ptr(out, "float32", 1, "out", ctx), _stream_ptr(stream)), ctx)
 
 
 def rtc_n_valid(ctx: RtcContext) -> int:

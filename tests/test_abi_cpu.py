@@ -55,7 +55,8 @@ def _cfg(**kw):
     (dict(n_sub_x=0), rtc.RTC_E_ARG, "n_sub"),
     (dict(n_pix=33), rtc.RTC_E_ARG, "n_pix"),
     (dict(n_act=0), rtc.RTC_E_ARG, "n_act"),
-    (dict(thr_mode=0), rtc.RTC_E_ARG, "thr_mode"),
+    (dict(thr_mode=3), rtc.RTC_E_ARG, "thr_mode"),
+    (dict(thr_mode=-1), rtc.RTC_E_ARG, "thr_mode"),
     (dict(cm_dtype=7), rtc.RTC_E_ARG, "cm_dtype"),
     (dict(gain=math.nan), rtc.RTC_E_NONFINITE, "gain"),
     (dict(leak=math.inf), rtc.RTC_E_NONFINITE, "gain"),

@@ -16,7 +16,7 @@ import numpy as np
 import pytest
 
 import oracle
-from _cases import near_tie_pixels
+from _cases import near_tie_pixels, out_of_domain_tie_pixels
 from _closedloop import oracle_closed_loop
 from aosim import ELT, TINY, Scenario, geometry
 
@@ -208,6 +208,37 @@ def test_threshold_near_ties_counts_bit_exact():
     check_parity(gpu, {k: v[None] for k, v in ref.items()}, 0.4, 1.0, what="near ties")
 
 
+@pytest.mark.parametrize("mode", [rtc.RTC_FRAMES_PER_LAUNCH, rtc.RTC_FRAMES_PERSISTENT])
+def test_threshold_ties_with_darks_outside_the_fast_domain_counts_bit_exact(mode):
+    # tiny, subnormal and 2^60 darks at exact and near ties of T = 3: raw - dark
+    # is not exact in float64, so the device's exact expansion decides
+    raw, dark, flat = out_of_domain_tie_pixels(3.0)
+    n = len(raw)
+    n_pix = 4
+    n_sub = int(math.ceil(math.sqrt(n / 4)))       # 4 constructed pixels per tile, the rest below T
+    H = n_sub * n_pix
+    fr = np.full((H, H), 100, np.uint16)
+    dk = np.full((H, H), 100.0, np.float32)
+    fl = np.ones((H, H), np.float32)
+    for i in range(n):
+        t = i // 4
+        sy, sx = divmod(t, n_sub)
+        r, c = sy * n_pix + (i % 4), sx * n_pix + (i % 4)
+        fr[r, c], dk[r, c], fl[r, c] = raw[i], dark[i], flat[i]
+    mask = np.ones((n_sub, n_sub), np.uint8)
+    R = np.eye(3, 2 * n_sub * n_sub, dtype=np.float32)
+    ref = oracle.rtc_frame(fr, mask, n_pix, dk, fl, 3.0, R, np.zeros(3), 0.4)
+    assert 0 < ref["counts"].sum() < n
+    with rtc.rtc_init(mask, n_pix, 3) as ctx:
+        rtc.rtc_load_calib(ctx, dk, fl, 3.0)
+        rtc.rtc_load_cmat(ctx, R)
+        rtc.rtc_set_frame_mode(ctx, mode)
+        gpu = _gpu_batch(ctx, fr[None])
+        rtc.rtc_sync_check(ctx)
+    assert np.array_equal(gpu["counts"][0].astype(np.int64), ref["counts"])
+    check_parity(gpu, {k: v[None] for k, v in ref.items()}, 0.4, 1.0, what="out-of-domain dark ties")
+
+
 # -------------------------------------------------------------- edge cases
 EDGE = [
     # n_sub, n_pix, obs, n_act, mode, k_split, ref, leak, clamp
@@ -218,6 +249,8 @@ EDGE = [
     (3, 6, 0.0, 1, "zero", 3, False, 0.5, None),
     (3, 5, 0.0, 9, "subtract", 1, False, 1.0, None),      # 9 subapertures: odd, padded slope vector
     (4, 8, 0.0, 70001, "subtract", 1, False, 1.0, None),  # many actuators, 32 slopes
+    (6, 8, 0.0, 40, "none", 1, True, 1.0, None),           # no threshold applied
+    (11, 4, 0.2, 57, "none", 4, False, 0.9, None),
 ]
 
 
@@ -239,7 +272,7 @@ def test_edge_configurations(idx):
     ref_s = (0.1 * rng.standard_normal(2 * nv)).astype(np.float32) if use_ref else None
     c0 = (0.01 * rng.standard_normal(n_act)).astype(np.float32)
     lo, hi = clamp if clamp else (-math.inf, math.inf)
-    mode_id = rtc.RTC_THR_SUBTRACT if mode == "subtract" else rtc.RTC_THR_ZERO
+    mode_id = {"subtract": rtc.RTC_THR_SUBTRACT, "zero": rtc.RTC_THR_ZERO, "none": rtc.RTC_THR_NONE}[mode]
     with rtc.rtc_init(mask, n_pix, n_act, thr_mode=mode_id, gain=0.4, leak=leak, cmd_min=lo, cmd_max=hi) as ctx:
         rtc.rtc_load_calib(ctx, dark, flat, 3.0, ref_s)
         rtc.rtc_load_cmat(ctx, R)

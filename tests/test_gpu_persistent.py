@@ -84,6 +84,10 @@ def test_expired_barrier_wait_is_reported_and_cleared(tiny_loop):
         assert ei.value.status == rtc.RTC_E_DEVICE and "bounded wait" in str(ei.value)
         rtc.rtc_sync_check(ctx)                     # cleared
         rtc.rtc_set_frame_mode(ctx, rtc.RTC_FRAMES_PERSISTENT)
+        # the state is undefined after the failed batch: frames are refused until a reset
+        with pytest.raises(rtc.RtcError) as ei:
+            _gpu_batch(ctx, frames[:2])
+        assert ei.value.status == rtc.RTC_E_STATE
         rtc.rtc_reset(ctx)
         good = _gpu_batch(ctx, frames[:20])
         rtc.rtc_sync_check(ctx)

@@ -132,8 +132,10 @@ class Scenario:
         n = self.cfg.screen_n
         cols = (np.arange(npts) - k) % n
         rows = np.arange(npts) % n
-        win = self.screen[np.ix_(rows, cols)]
-        return turbulence.geometric_slopes(win, self.mask, m)
+        # only the samples on subaperture edges enter the slopes
+        edge_cols = self.screen[np.ix_(rows, cols[::m])]
+        edge_rows = self.screen[np.ix_(rows[::m], cols)]
+        return turbulence.edge_slopes(edge_cols, edge_rows, self.mask, m)
 
     def residual_slopes(self, k: int, cmd: np.ndarray | None) -> np.ndarray:
         """Turbulence slopes minus the DM's slopes for commands ``cmd`` (None = open loop)."""

@@ -57,12 +57,17 @@ def geometric_slopes(window: np.ndarray, mask: np.ndarray, m: int) -> np.ndarray
     npts = n_sub * m + 1
     if window.shape != (npts, npts):
         raise ValueError("window must be (n_sub*m+1) square")
+    return edge_slopes(window[:, ::m], window[::m, :], mask, m)
+
+
+def edge_slopes(cols: np.ndarray, rows: np.ndarray, mask: np.ndarray, m: int) -> np.ndarray:
+    """:func:`geometric_slopes` from the window's subaperture-edge samples only:
+    ``cols`` = window[:, ::m] ``[npts, n_sub + 1]``, ``rows`` = window[::m, :]
+    ``[n_sub + 1, npts]``."""
     w = np.ones(m + 1)
     w[0] = w[-1] = 0.5
     sy, sx = np.nonzero(mask)
     # edge-difference profiles: dxp[y, i] = phi(y, (i+1) m) - phi(y, i m)
-    cols = window[:, ::m]                     # [npts, n_sub + 1]
-    rows = window[::m, :]                     # [n_sub + 1, npts]
     dxp = cols[:, 1:] - cols[:, :-1]          # [npts, n_sub]
     dyp = rows[1:, :] - rows[:-1, :]          # [n_sub, npts]
     # trapezoid mean along the edge for every subaperture

@@ -286,8 +286,33 @@ rtc_status rtc_get_mvm_tuning(const rtc_ctx *c, rtc_mvm_tuning *t);
  *    be co-resident, a calibration with a dark outside {0} U [2^-13, 2^24) in
  *    magnitude) run per launch instead.  The arithmetic and its order
  *    are those of the per-launch mode with the row-block kernel, 8 wavefronts
- *    and the same workgroup count, so results are bitwise identical to it. */
-typedef enum { RTC_FRAMES_PER_LAUNCH = 0, RTC_FRAMES_PERSISTENT = 1 } rtc_frame_mode;
+ *    and the same workgroup count, so results are bitwise identical to it.
+ *  RTC_FRAMES_HORIZONTAL: one cooperative launch of 256 workgroups of 256
+ *    threads for the whole batch, in the paper's horizontal processing
+ *    strategy (Section 2.2, Figure 5; the partial-vector sum of Section
+ *    2.3.5): workgroup b calibrates subapertures [b n_valid / 256,
+ *    (b+1) n_valid / 256) and multiplies their slopes into its own columns of
+ *    the control matrix for every actuator row -- columns that stay in its
+ *    registers and LDS for the whole batch -- giving a partial actuator
+ *    vector; after one grid barrier per frame, workgroup o adds the 256
+ *    partial vectors of its actuator rows [o q + min(o, r), (o+1) q +
+ *    min(o+1, r)) (q = n_act / 256, r = n_act mod 256) in a fixed order and
+ *    applies the integrator.  No slope leaves the workgroup that computed it.
+ *    The matrix is re-laid out on the device for this split when the mode is
+ *    set or a matrix is loaded in it (about 1.07 x the stored matrix, plus a
+ *    16.8 MB message buffer).  Needs 256 compute units and shapes whose
+ *    columns and rows fit on chip (at most 32 slope columns per workgroup and,
+ *    for the float32 ELT shape, at most 18 actuator rows per workgroup and
+ *    tiles of at most 10 pixels): RTC_E_UNSUPPORTED otherwise.  Batches whose
+ *    frames the kernel cannot read as pixel pairs (an odd frame stride or an
+ *    unaligned pointer) or whose calibration has a dark outside
+ *    {0} U [2^-13, 2^24) run per launch.  Results equal the other modes within
+ *    float32 rounding (the sums run in another fixed order) and are
+ *    run-to-run bitwise deterministic.  rtc_set_trace stamps for this mode:
+ *    [0] frame start, [1] slopes in LDS, [4] partial vector published, [6]
+ *    own stores complete, [7] arrival counted, [2] barrier passed, [3] partial
+ *    vectors loaded, [5] commands written. */
+typedef enum { RTC_FRAMES_PER_LAUNCH = 0, RTC_FRAMES_PERSISTENT = 1, RTC_FRAMES_HORIZONTAL = 2 } rtc_frame_mode;
 
 rtc_status rtc_set_frame_mode(rtc_ctx *c, int32_t mode, int32_t spin_limit);
 /* Current frame mode into *mode. */

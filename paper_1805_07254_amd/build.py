@@ -14,7 +14,8 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librtc.so")
-SOURCES = ["rtc_api.hip", "rtc_kernels.hip", "pipe_api.hip", "pipe_kernels.hip", "mlp_api.hip", "mlp_kernels.hip"]
+SOURCES = ["rtc_api.hip", "rtc_kernels.hip", "horizontal_kernels.hip", "pipe_api.hip", "pipe_kernels.hip",
+           "mlp_api.hip", "mlp_kernels.hip"]
 
 # -packed-fp32-ops: keep hipcc from fusing float pairs into packed FP32 VALU ops.
 HIPCC_FLAGS = [

@@ -114,6 +114,9 @@ void encode_rows(int fmt, const float *R, int32_t n_rows, int32_t n_cols, int64_
 
 extern "C" {
 
+static bool horiz_shape(const rtc_ctx *c, int32_t *nch, int32_t *nrt, int32_t *nq, std::string *why);
+static rtc_status horiz_prepare(rtc_ctx *c, const char *who);
+
 uint32_t rtc_abi_version(void) { return RTC_ABI_VERSION; }
 
 const char *rtc_error_string(const rtc_ctx *c) {
@@ -422,6 +425,7 @@ rtc_status rtc_load_cmat(rtc_ctx *c, const float *R, int32_t n_act, int32_t n_sl
   c->d_scales = d_sc;
   c->cmat_loaded = true;
   ++c->cmat_gen;
+  if (c->frame_mode == RTC_FRAMES_HORIZONTAL) return horiz_prepare(c, "rtc_load_cmat");
   return RTC_OK;
 }
 
@@ -536,6 +540,111 @@ rtc_status rtc_frame(rtc_ctx *c, const uint16_t *d_pixels, float *d_cmd, float *
                        static_cast<hipStream_t>(hip_stream), "rtc_frame: launch");
 }
 
+// Arguments of a persistent launch (either split) of n_frames frame sets.
+static rtck::PersistArgs persist_args(const rtc_ctx *c, int32_t n_frames, const uint16_t *d_pixels,
+                                      int64_t frame_stride, float *d_cmd, float *d_slopes, float *d_recon,
+                                      int32_t *d_counts, uint64_t *d_ts) {
+  rtck::PersistArgs p{};
+  p.cal = calib_args(c, d_pixels);
+  p.cal.s_user = d_slopes;
+  p.cal.counts = d_counts;
+  p.frame_stride = frame_stride;
+  p.n_frames = n_frames;
+  p.vec = (c->pairs && (frame_stride & 1) == 0 && (reinterpret_cast<uintptr_t>(d_pixels) & 3) == 0) ? 1 : 0;
+  p.sbuf = c->d_sbuf;
+  p.s_len = (int32_t)xchg_len_of(c->n_slopes);
+  p.cal.xchg_epc = rtck::format_elems_per_chunk(c->fmt);
+  rtck::MvmArgs &ma = p.mvm;
+  ma.Rq = c->d_R;
+  ma.ldq_bytes = c->ldq * kFmt[c->fmt].bytes;
+  ma.scales = c->d_scales;
+  ma.fmt = c->fmt;
+  ma.n_chunks = c->n_chunks;
+  ma.n_act = c->n_act;
+  ma.state = c->d_state;
+  ma.cmd = d_cmd;
+  ma.recon = d_recon;
+  ma.gain = c->cfg.gain;
+  ma.leak = c->cfg.leak;
+  ma.cmd_min = c->cfg.cmd_min;
+  ma.cmd_max = c->cfg.cmd_max;
+  p.bar = c->d_sync + rtck::sync_layout::kBarBase;
+  p.abort_flag = c->d_sync + rtck::sync_layout::kAbort;
+  p.sticky = c->d_sync + rtck::sync_layout::kSticky;
+  p.spin_limit = c->spin_limit;
+  p.ts = d_ts;
+  p.trace = c->d_trace;
+  p.trace_frames = c->trace_frames;
+  p.trace_groups = c->trace_groups;
+  return p;
+}
+
+// Shape of the horizontal frames for this context: subapertures per workgroup
+// (nch), rows per owner (nrt) and 16-byte chunks per row slot (nq); false with
+// the reason when the built kernels do not cover it.
+static bool horiz_shape(const rtc_ctx *c, int32_t *nch, int32_t *nrt, int32_t *nq, std::string *why) {
+  const int G = rtck::kHoriz;
+  if (c->n_cu < G) {
+    *why = "the horizontal split needs 256 compute units";
+    return false;
+  }
+  if (c->max_n > 16 || (c->fmt == RTC_CM_F32 && c->max_n > 10 && (c->n_valid + G - 1) / G > 4)) {
+    *why = "subapertures wider than the horizontal kernels' tiles (16 pixels; 10 for wide FP32 slabs)";
+    return false;
+  }
+  if (!c->pairs) {
+    *why = "the horizontal kernels read 4-byte pixel pairs (even tile widths and frame layout)";
+    return false;
+  }
+  const int32_t ch = (c->n_valid + G - 1) / G;
+  const int32_t q = rtck::horiz_chunks(c->fmt, ch);
+  if (q == 0) {
+    *why = "more than 32 slope columns per workgroup";
+    return false;
+  }
+  const int32_t rows = (c->n_act + G - 1) / G;
+  if (rows > rtck::horiz_max_rows(c->fmt, q)) {
+    *why = "more actuator rows per workgroup than the horizontal kernels hold on chip";
+    return false;
+  }
+  *nch = ch;
+  *nrt = rows;
+  *nq = q;
+  return true;
+}
+
+// Builds the horizontal layout of the loaded matrix and zeroes the message
+// buffer (synchronous); a no-op without a matrix.
+static rtc_status horiz_prepare(rtc_ctx *c, const char *who) {
+  if (!c->cmat_loaded) return RTC_OK;
+  int32_t nch = 0, nrt = 0, nq = 0;
+  std::string why;
+  if (!horiz_shape(c, &nch, &nrt, &nq, &why)) return fail(c, RTC_E_UNSUPPORTED, std::string(who) + ": " + why);
+  const int G = rtck::kHoriz;
+  const int64_t chunks = rtck::horiz_layout_chunks(G, nrt, nq);
+  const size_t xfloats = (size_t)2 * G * G * rtck::kHorizMsg;
+  hipError_t e = hipSuccess;
+  if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(c, e, who);
+  if (c->hm_chunks != chunks) {
+    dfree(c->d_hm);
+    c->hm_chunks = 0;
+    c->h_gen = 0;
+    if ((e = hipMalloc(&c->d_hm, (size_t)chunks * sizeof(uint4))) != hipSuccess) return hip_fail(c, e, who);
+    c->hm_chunks = chunks;
+  }
+  if (!c->d_xbuf && (e = hipMalloc(&c->d_xbuf, xfloats * sizeof(float))) != hipSuccess) return hip_fail(c, e, who);
+  if ((e = rtck::launch_horiz_layout(c->d_R, c->ldq * kFmt[c->fmt].bytes, c->fmt, c->d_tiles, c->n_valid, c->n_act,
+                                     G, nch, nrt, nq, c->d_hm, nullptr)) != hipSuccess ||
+      (e = rtck::launch_fill_zero(c->d_xbuf, (int64_t)xfloats, nullptr)) != hipSuccess ||
+      (e = hipDeviceSynchronize()) != hipSuccess)
+    return hip_fail(c, e, who);
+  c->h_gen = c->cmat_gen;
+  c->h_nch = nch;
+  c->h_nrt = nrt;
+  c->h_nq = nq;
+  return RTC_OK;
+}
+
 rtc_status rtc_frame_batch(rtc_ctx *c, int32_t n_frames, const uint16_t *d_pixels, int64_t frame_stride,
                            float *d_cmd, float *d_slopes, float *d_recon, int32_t *d_counts, uint64_t *d_ts,
                            void *hip_stream) {
@@ -551,39 +660,23 @@ rtc_status rtc_frame_batch(rtc_ctx *c, int32_t n_frames, const uint16_t *d_pixel
   DeviceScope ds(c->device);
   if (ds.status != hipSuccess) return hip_fail(c, ds.status, "rtc_frame_batch: hipSetDevice");
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  if (c->frame_mode == RTC_FRAMES_HORIZONTAL) {
+    rtc_status hs = c->h_gen == c->cmat_gen ? RTC_OK : horiz_prepare(c, "rtc_frame_batch");
+    if (hs != RTC_OK) return hs;
+    rtck::HorizArgs h{};
+    h.p = persist_args(c, n_frames, d_pixels, frame_stride, d_cmd, d_slopes, d_recon, d_counts, d_ts);
+    h.hm = c->d_hm;
+    h.xbuf = c->d_xbuf;
+    h.nch = c->h_nch;
+    h.nrt = c->h_nrt;
+    hipError_t e = rtck::launch_horizontal(h, st);
+    if (e == hipSuccess) return RTC_OK;
+    if (e != hipErrorInvalidValue && e != hipErrorCooperativeLaunchTooLarge)
+      return hip_fail(c, e, "rtc_frame_batch: horizontal launch");
+    (void)hipGetLastError();   // unsupported shape or frames: one launch pair per frame
+  }
   if (c->frame_mode == RTC_FRAMES_PERSISTENT) {
-    rtck::PersistArgs p{};
-    p.cal = calib_args(c, d_pixels);
-    p.cal.s_user = d_slopes;
-    p.cal.counts = d_counts;
-    p.frame_stride = frame_stride;
-    p.n_frames = n_frames;
-    p.vec = (c->pairs && (frame_stride & 1) == 0 && (reinterpret_cast<uintptr_t>(d_pixels) & 3) == 0) ? 1 : 0;
-    p.sbuf = c->d_sbuf;
-    p.s_len = (int32_t)xchg_len_of(c->n_slopes);
-    p.cal.xchg_epc = rtck::format_elems_per_chunk(c->fmt);
-    rtck::MvmArgs &ma = p.mvm;
-    ma.Rq = c->d_R;
-    ma.ldq_bytes = c->ldq * kFmt[c->fmt].bytes;
-    ma.scales = c->d_scales;
-    ma.fmt = c->fmt;
-    ma.n_chunks = c->n_chunks;
-    ma.n_act = c->n_act;
-    ma.state = c->d_state;
-    ma.cmd = d_cmd;
-    ma.recon = d_recon;
-    ma.gain = c->cfg.gain;
-    ma.leak = c->cfg.leak;
-    ma.cmd_min = c->cfg.cmd_min;
-    ma.cmd_max = c->cfg.cmd_max;
-    p.bar = c->d_sync + rtck::sync_layout::kBarBase;
-    p.abort_flag = c->d_sync + rtck::sync_layout::kAbort;
-    p.sticky = c->d_sync + rtck::sync_layout::kSticky;
-    p.spin_limit = c->spin_limit;
-    p.ts = d_ts;
-    p.trace = c->d_trace;
-    p.trace_frames = c->trace_frames;
-    p.trace_groups = c->trace_groups;
+    rtck::PersistArgs p = persist_args(c, n_frames, d_pixels, frame_stride, d_cmd, d_slopes, d_recon, d_counts, d_ts);
     const int blocks = c->tuning.blocks > 0 ? c->tuning.blocks : c->n_cu;
     const int G = rtck::frames_grid(blocks, c->n_act);
     p.calib_span = calib_span(c, G);
@@ -1033,9 +1126,20 @@ rtc_status rtc_get_mvm_tuning(const rtc_ctx *c, rtc_mvm_tuning *t) {
 
 rtc_status rtc_set_frame_mode(rtc_ctx *c, int32_t mode, int32_t spin_limit) {
   if (!c) return fail(nullptr, RTC_E_ARG, "rtc_set_frame_mode: NULL context");
-  if (mode != RTC_FRAMES_PER_LAUNCH && mode != RTC_FRAMES_PERSISTENT)
+  if (mode != RTC_FRAMES_PER_LAUNCH && mode != RTC_FRAMES_PERSISTENT && mode != RTC_FRAMES_HORIZONTAL)
     return fail(c, RTC_E_ARG, "rtc_set_frame_mode: unknown mode");
   if (spin_limit < 0) return fail(c, RTC_E_ARG, "rtc_set_frame_mode: spin_limit must be >= 0");
+  if (mode == RTC_FRAMES_HORIZONTAL) {
+    int32_t nch, nrt, nq;
+    std::string why;
+    if (!horiz_shape(c, &nch, &nrt, &nq, &why)) return fail(c, RTC_E_UNSUPPORTED, "rtc_set_frame_mode: " + why);
+    DeviceScope ds(c->device);
+    if (ds.status != hipSuccess) return hip_fail(c, ds.status, "rtc_set_frame_mode: hipSetDevice");
+    if (c->h_gen != c->cmat_gen) {
+      const rtc_status st = horiz_prepare(c, "rtc_set_frame_mode");
+      if (st != RTC_OK) return st;
+    }
+  }
   c->frame_mode = mode;
   c->spin_limit = spin_limit > 0 ? spin_limit : (1 << 22);
   return RTC_OK;
@@ -1161,6 +1265,8 @@ void rtc_destroy(rtc_ctx *c) {
   dfree(c->d_psync);
   dfree(c->d_first);
   dfree(c->d_need);
+  dfree(c->d_hm);
+  dfree(c->d_xbuf);
   if (c->graph) (void)hipGraphExecDestroy(c->graph);
   delete c;
 }

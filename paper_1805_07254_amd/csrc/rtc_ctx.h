@@ -59,6 +59,13 @@ struct rtc_ctx {
   int32_t split_max = 0;           // most rows of one workgroup in the split
   std::vector<int32_t> split_h;    // host copy of the split (split_G + 1 entries)
   int32_t dark_fast = 1;           // every loaded dark is 0 or of magnitude in [2^-13, 2^24)
+  // horizontal frames (RTC_FRAMES_HORIZONTAL): the matrix in the per-workgroup
+  // layout and the partial-vector messages
+  uint4 *d_hm = nullptr;
+  int64_t hm_chunks = 0;
+  float *d_xbuf = nullptr;
+  uint64_t h_gen = 0;              // cmat_gen the layout was built from (0 = none)
+  int32_t h_nch = 0, h_nrt = 0, h_nq = 0;
   bool calib_loaded = false;
   bool state_invalid = false;      // a reported failed batch left the integrator state undefined
   bool cmat_loaded = false;

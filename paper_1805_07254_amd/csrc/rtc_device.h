@@ -84,10 +84,12 @@ __device__ __forceinline__ double pixel_value(int mode, bool above, double r, do
 // contributions replacing the provisional ones; the row loop itself keeps only
 // the mask.  The kernels that keep matrix rows in registers are built FAST
 // only (their register budget has no room for the exact path).
+// jz: 0, passed opaque by persistent kernels so that the column coordinates
+// (double)j are formed in the loop instead of held in scalar registers.
 template <int GS, bool FAST, class Fetch>
 __device__ __forceinline__ void tile_row_sums(const uint32_t (&raw)[GS], const float2 (&cf)[GS], int n, float thr,
                                               int mode, double half, double &S, double &Sx, int &cnt,
-                                              Fetch fetch) {
+                                              Fetch fetch, int jz = 0) {
   const double T = (double)thr;
   uint32_t amb = 0;
 #pragma unroll
@@ -103,7 +105,7 @@ __device__ __forceinline__ void tile_row_sums(const uint32_t (&raw)[GS], const f
       }
       const double v = pixel_value(mode, above, r, d * f);
       S += v;
-      Sx = fma((double)j - half, v, Sx);
+      Sx = fma((double)(j + jz) - half, v, Sx);
       cnt += above ? 1 : 0;
     }
   }
@@ -133,8 +135,8 @@ struct NoFetch {
 };
 template <int GS>
 __device__ __forceinline__ void tile_row_sums(const uint32_t (&raw)[GS], const float2 (&cf)[GS], int n, float thr,
-                                              int mode, double half, double &S, double &Sx, int &cnt) {
-  tile_row_sums<GS, true>(raw, cf, n, thr, mode, half, S, Sx, cnt, NoFetch{});
+                                              int mode, double half, double &S, double &Sx, int &cnt, int jz = 0) {
+  tile_row_sums<GS, true>(raw, cf, n, thr, mode, half, S, Sx, cnt, NoFetch{}, jz);
 }
 
 // Tile sums over its GS lanes (butterfly: identical sums in every lane) and
@@ -183,6 +185,139 @@ __device__ __forceinline__ float wave_sum(float v) {
   const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48));
   return (r0 + r1) + (r2 + r3);
 }
+
+// Storage formats of the control matrix: a 16-byte chunk of codes decodes to
+// EPC float32 values (exactly; the per-row scale is applied to the row sum).
+template <int FMT>
+struct Codec;
+template <>
+struct Codec<0> {                                 // float32
+  static constexpr int EPC = 4;
+  __device__ __forceinline__ static void decode(const uint4 &c, float (&v)[EPC]) {
+    v[0] = __uint_as_float(c.x);
+    v[1] = __uint_as_float(c.y);
+    v[2] = __uint_as_float(c.z);
+    v[3] = __uint_as_float(c.w);
+  }
+};
+template <>
+struct Codec<1> {                                 // IEEE binary16
+  static constexpr int EPC = 8;
+  __device__ __forceinline__ static void decode(const uint4 &c, float (&v)[EPC]) {
+    const uint32_t w[4] = {c.x, c.y, c.z, c.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      v[2 * i] = (float)__builtin_bit_cast(_Float16, (uint16_t)(w[i] & 0xffffu));
+      v[2 * i + 1] = (float)__builtin_bit_cast(_Float16, (uint16_t)(w[i] >> 16));
+    }
+  }
+};
+template <>
+struct Codec<2> {                                 // bfloat16: the high half of a float32
+  static constexpr int EPC = 8;
+  __device__ __forceinline__ static void decode(const uint4 &c, float (&v)[EPC]) {
+    const uint32_t w[4] = {c.x, c.y, c.z, c.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      v[2 * i] = __uint_as_float(w[i] << 16);
+      v[2 * i + 1] = __uint_as_float(w[i] & 0xffff0000u);
+    }
+  }
+};
+template <>
+struct Codec<3> {                                 // OCP FP8 E4M3 (e4m3fn)
+  static constexpr int EPC = 16;
+  __device__ __forceinline__ static void decode(const uint4 &c, float (&v)[EPC]) {
+    typedef float f2v __attribute__((ext_vector_type(2)));
+    const uint32_t w[4] = {c.x, c.y, c.z, c.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const f2v lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)w[i], false);   // bytes 0, 1
+      const f2v hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)w[i], true);    // bytes 2, 3
+      v[4 * i] = lo.x;
+      v[4 * i + 1] = lo.y;
+      v[4 * i + 2] = hi.x;
+      v[4 * i + 3] = hi.y;
+    }
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Grid synchronisation of the persistent kernels: stage stamps, bounded waits,
+// the per-frame barrier and the frame end stamp.
+// ---------------------------------------------------------------------------
+namespace sl = sync_layout;
+
+// Stage stamp of the first trace_groups workgroups (thread 0) for the first
+// trace_frames frames.
+__device__ __forceinline__ void trace_stamp(const PersistArgs &p, int f, int stage) {
+  if (p.trace != nullptr && f < p.trace_frames && (int)blockIdx.x < p.trace_groups && threadIdx.x == 0)
+    p.trace[((int64_t)f * p.trace_groups + blockIdx.x) * kTraceStages + stage] = wall_clock64();
+}
+
+__device__ __forceinline__ bool bounded_wait(const PersistArgs &p, const uint32_t *word, uint32_t target) {
+  int32_t spins = 0;
+  while ((int32_t)(__hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - target) < 0) {
+    __builtin_amdgcn_s_sleep(1);
+    if (++spins > p.spin_limit) {
+      __hip_atomic_store(p.abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(p.sticky, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return false;
+    }
+  }
+  return true;
+}
+
+// False when this workgroup's wait for the release expired (the abort flag is
+// then raised): the frame's slopes may be incomplete, so the caller must not
+// use them.  sh_flag: a shared word of the workgroup.
+__device__ __forceinline__ bool frame_barrier(const PersistArgs &p, uint32_t epoch, int f, uint32_t *sh_flag) {
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // this wavefront's stores are complete
+  __syncthreads();
+  trace_stamp(p, f, 6);
+  if (threadIdx.x < 64) {
+    const uint32_t G = gridDim.x;
+    int release = 0;
+    if (threadIdx.x == 0) {
+      const uint32_t grp = blockIdx.x % sl::kGroups;
+      const uint32_t per = (G - grp + sl::kGroups - 1) / sl::kGroups;   // workgroups in this group
+      const uint32_t ngrp = G < (uint32_t)sl::kGroups ? G : (uint32_t)sl::kGroups;
+      const uint32_t prev = __hip_atomic_fetch_add(p.bar + sl::kStride * grp, 1u, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+      trace_stamp(p, f, 7);
+      if (prev == epoch * per - 1) {
+        const uint32_t top = __hip_atomic_fetch_add(p.bar + sl::kTop, 1u, __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_AGENT);
+        release = top == epoch * ngrp - 1;
+      }
+    }
+    if (__builtin_amdgcn_readfirstlane(release)) {
+      for (uint32_t i = threadIdx.x; i < G; i += 64)
+        __hip_atomic_store(p.bar + sl::kMailbox + 16 * i, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (threadIdx.x == 0) *sh_flag = bounded_wait(p, p.bar + sl::kMailbox + 16 * blockIdx.x, epoch) ? 0u : 1u;
+  }
+  __syncthreads();
+  return *sh_flag == 0u;
+}
+
+// End stamp of a frame: the latest of the per-workgroup end stamps, reduced by
+// wavefront 0 of one workgroup.
+__device__ __forceinline__ void reduce_end_stamp(const PersistArgs &p, int f) {
+  const uint64_t *ends = reinterpret_cast<const uint64_t *>(p.bar + sl::kEnds) + (f & 1) * sl::kMaxGroups;
+  uint64_t m = 0;
+  for (uint32_t i = threadIdx.x; i < gridDim.x; i += 64) {
+    const uint64_t v = __hip_atomic_load(ends + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    m = v > m ? v : m;
+  }
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    const uint64_t o = __shfl_xor(m, d);
+    m = o > m ? o : m;
+  }
+  if (threadIdx.x == 0) p.ts[2 * (int64_t)f + 1] = m;
+}
+
 
 }  // namespace
 }  // namespace rtck

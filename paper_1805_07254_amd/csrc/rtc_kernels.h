@@ -108,6 +108,9 @@ struct PersistArgs {
   int32_t row_max;           // largest row_start[b+1] - row_start[b] (with row_start)
 };
 constexpr int kTraceStages = 8;
+// Zeroes the barrier counters, the mailboxes of G workgroups and the abort flag
+// before a persistent launch (a kernel, so that it can be recorded in a graph).
+hipError_t launch_persist_reset(uint32_t *bar, uint32_t *abort_flag, int G, hipStream_t st);
 
 // Synchronisation words of a context, in uint32 units.  Arrival counters sit
 // 4 KiB apart so that arrivals and polls at different counters do not queue at
@@ -133,6 +136,46 @@ hipError_t launch_frames(const PersistArgs &p, int blocks, int rows_per_batch, h
 // Workgroups of a persistent launch asked for `blocks` workgroups (workgroup b
 // owns subapertures [b n_valid / G, (b + 1) n_valid / G)).
 int frames_grid(int blocks, int n_act);
+
+// Persistent frames in the horizontal split (the paper's processing strategy,
+// Section 2.2 and Figure 5): kHoriz workgroups, one per compute unit, of
+// kHoriz threads.  Workgroup b calibrates subapertures [b n_valid / G,
+// (b+1) n_valid / G) and multiplies their slopes into its own columns of the
+// control matrix (every actuator row), which stay on chip for the whole batch:
+// a partial actuator vector.  Thread t of every workgroup computes the rows of
+// owner t, [rb(t), rb(t+1)) with rb(o) = o q + min(o, rem), q = n_act / G,
+// rem = n_act % G, and stores them as producer b's message to owner t.  After
+// the frame barrier, owner b adds the G messages of its rows in a fixed order
+// (the tree vector addition of Section 2.3.5 as a reduce-scatter) and applies
+// the integrator.
+constexpr int kHoriz = 256;          // workgroups of a launch = threads of a workgroup
+constexpr int kHorizMsg = 32;        // floats per message (rows of an owner, zero-padded)
+
+struct HorizArgs {
+  PersistArgs p;           // calibration, frames, outputs, integrator and sync words (row split unused)
+  const uint4 *hm;         // horizontal layout [G][nrt][nq][kHoriz] 16-byte chunks (horiz_layout)
+  float *xbuf;             // [2][G owners][G producers][kHorizMsg] messages, zero-initialised
+  int32_t nch;             // subapertures per workgroup (columns: nch x slopes, then nch y slopes)
+  int32_t nrt;             // rows of the largest owner (row slots per thread)
+};
+// Chunks per row slot the horizontal kernel is built for (16-byte chunks of a
+// workgroup's 2 nch columns), 0 when 2 nch is too wide for the format.
+int horiz_chunks(int fmt, int nch);
+// Most rows per owner the instantiated horizontal kernels of a format and
+// chunk count hold (registers and LDS tail slots); 0 when none is built.
+int horiz_max_rows(int fmt, int nq);
+// Elements of the horizontal layout (uint4 chunks).
+int64_t horiz_layout_chunks(int G, int nrt, int nq);
+// Builds the horizontal layout from the stored row-major matrix Rq (rows of
+// ldq_bytes, codes of format fmt): chunk (b, i, q, t) = codes of row
+// rb(t) + i at the columns [q EPC, (q+1) EPC) of workgroup b.
+hipError_t launch_horiz_layout(const void *Rq, int64_t ldq_bytes, int fmt, const TileDesc *tiles, int n_valid,
+                               int n_act, int G, int nch, int nrt, int nq, uint4 *hm, hipStream_t st);
+// Zeroes n floats (graph-safe: a kernel, not a memset).
+hipError_t launch_fill_zero(float *p, int64_t n, hipStream_t st);
+// Cooperative launch of the horizontal frames; hipErrorInvalidValue for
+// shapes it does not cover.
+hipError_t launch_horizontal(const HorizArgs &h, hipStream_t st);
 
 // Pixel-stream frames: a camera workgroup lands the rows of each frame in a
 // two-slot ring on a schedule (rows of frame f land uniformly over the readout

@@ -54,7 +54,7 @@ class rtc_multi_config(ctypes.Structure):
 
 
 RTC_MVM_ROWBLOCK, RTC_MVM_STREAMED = 0, 1
-RTC_FRAMES_PER_LAUNCH, RTC_FRAMES_PERSISTENT = 0, 1
+RTC_FRAMES_PER_LAUNCH, RTC_FRAMES_PERSISTENT, RTC_FRAMES_HORIZONTAL = 0, 1, 2
 
 
 class rtc_mvm_tuning(ctypes.Structure):

@@ -2,6 +2,8 @@
 import numpy as np
 import torch
 
+import oracle
+from oracle import quant
 from paper_1805_07254_amd import rtc
 
 TOL = 1e-5
@@ -71,3 +73,17 @@ def _ctx_for(sc, **kw):
     rtc.rtc_load_calib(ctx, sc.dark, sc.flat, cfg.threshold)
     rtc.rtc_load_cmat(ctx, sc.control_matrix)
     return ctx
+
+
+def dequantised_ref(ref, R, fmt, gain, leak):
+    """The oracle record with the reconstruction redone with the dequantised
+    matrix of a reduced storage format (slopes and counts unchanged)."""
+    codes, scales = quant.encode(R, fmt)
+    Rq = quant.dequantize(codes, scales, fmt)
+    a = ref["slopes"] @ Rq.T
+    c = np.zeros(R.shape[0])
+    cmds = []
+    for k in range(len(a)):
+        c = oracle.integrate(c, a[k], gain, leak)
+        cmds.append(c)
+    return {"counts": ref["counts"], "slopes": ref["slopes"], "recon": a, "cmd": np.stack(cmds)}, Rq

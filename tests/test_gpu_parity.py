@@ -343,11 +343,13 @@ def test_call_order_and_failed_loads_leave_state_intact():
         with pytest.raises(rtc.RtcError) as ei:
             rtc.rtc_load_calib(ctx, bad, flat, 3.0)
         assert ei.value.status == rtc.RTC_E_NONFINITE
+        # a dark outside the one-fma domain is accepted (decided exactly per launch)
         tiny = dark.copy()
         tiny[12, 12] = 1e-5
-        with pytest.raises(rtc.RtcError) as ei:
-            rtc.rtc_load_calib(ctx, tiny, flat, 3.0)
-        assert ei.value.status == rtc.RTC_E_ARG and "2^-13" in str(ei.value)
+        rtc.rtc_load_calib(ctx, tiny, flat, 3.0)
+        rtc.rtc_frame(ctx, pix, cmd)
+        rtc.rtc_reset(ctx)
+        rtc.rtc_load_calib(ctx, dark, flat, 3.0)
         # pixels outside the active subapertures are never read, so they are not checked
         corner = dark.copy()
         corner[0, 0] = np.nan

@@ -12,7 +12,7 @@ import pytest
 
 import oracle
 from _closedloop import oracle_closed_loop
-from _gpu_helpers import TOL, _dev, _gpu_batch, check_parity
+from _gpu_helpers import TOL, _dev, _gpu_batch, check_parity, dequantised_ref
 from aosim import ELT, TINY, Scenario
 from oracle import quant
 
@@ -61,15 +61,7 @@ def test_every_code_decodes_exactly_on_the_device(fmt):
 
 
 def _dequantised_ref(ref, R, fmt, gain, leak):
-    codes, scales = quant.encode(R, fmt)
-    Rq = quant.dequantize(codes, scales, fmt)
-    a = ref["slopes"] @ Rq.T
-    c = np.zeros(R.shape[0])
-    cmds = []
-    for k in range(len(a)):
-        c = oracle.integrate(c, a[k], gain, leak)
-        cmds.append(c)
-    return {"counts": ref["counts"], "slopes": ref["slopes"], "recon": a, "cmd": np.stack(cmds)}, Rq
+    return dequantised_ref(ref, R, fmt, gain, leak)
 
 
 def _check_error_bound(gpu_recon, ref, R, Rq, fmt):

@@ -208,7 +208,7 @@ def test_unsupported_persistent_shape_runs_per_launch():
 
 def test_frame_mode_validation():
     with rtc.rtc_init(np.ones((2, 2), np.uint8), 2, 3) as ctx:
-        for bad in [(2, 0), (-1, 0), (1, -5)]:
+        for bad in [(3, 0), (-1, 0), (1, -5)]:
             with pytest.raises(rtc.RtcError) as ei:
                 rtc.rtc_set_frame_mode(ctx, *bad)
             assert ei.value.status == rtc.RTC_E_ARG

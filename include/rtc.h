@@ -224,6 +224,26 @@ rtc_status rtc_frame_batch(rtc_ctx *c, int32_t n_frames, const uint16_t *d_pixel
                            int64_t frame_stride, float *d_cmd, float *d_slopes, float *d_recon,
                            int32_t *d_counts, uint64_t *d_ts, void *hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, fixed-memory serving loops, harnesses that forbid hipMalloc):
+ * rtc_frame_batch with the same arguments, results and errors, except that
+ * its kernels take every scratch buffer (the slope vectors, split-K partial
+ * vectors, completion counter, abort flag and barrier words) from a static
+ * device array of the library (4 MiB, one copy per device, held until the
+ * process ends) and the call allocates nothing.  The context's device address
+ * of the array is resolved by rtc_init.  RTC_FRAMES_HORIZONTAL contexts run
+ * the persistent row split here (the horizontal message buffer does not fit).
+ * Needs 4 (2 xl + sl + k_split n_act) + 155648 <= 4194304 bytes, with xl =
+ * 2 n_valid rounded up to 1024 and sl = 2 n_valid rounded up to 16 (each term
+ * then to 64 floats): RTC_E_UNSUPPORTED beyond that, and for device ordinals
+ * above 63.  Every such call on one device shares the array, and a call starts
+ * by clearing it: calls that overlap on one device (other streams, other
+ * contexts, other host threads) race and give undefined results.  A bounded
+ * wait that expires raises the context's own flag (rtc_sync_check). */
+rtc_status rtc_frame_batch_noalloc(rtc_ctx *c, int32_t n_frames, const uint16_t *d_pixels,
+                                   int64_t frame_stride, float *d_cmd, float *d_slopes, float *d_recon,
+                                   int32_t *d_counts, uint64_t *d_ts, void *hip_stream);
+
 /* Steps (a)-(b) alone: calibration and centre-of-gravity slopes of one frame
  * into d_slopes [2*n_valid] (required) and d_counts [n_valid] (nullable).
  * Leaves the integrator state untouched.  Needs the calibration (RTC_E_STATE). */

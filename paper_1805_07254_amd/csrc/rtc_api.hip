@@ -18,6 +18,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -109,6 +110,65 @@ void encode_rows(int fmt, const float *R, int32_t n_rows, int32_t n_cols, int64_
     }
   }
 }
+
+// Scratch of rtc_frame_batch_noalloc: a code-object array, so every device
+// the library runs on holds its own copy from module load to process exit and
+// no call allocates it.  Host code never passes `scratch` itself (its host
+// name is only a stand-in): the device address is taken once per device with
+// hipGetSymbolAddress when a context is created there.  Every such call on a
+// device shares that device's copy.  Layout in uint32 words, every region
+// starting on a 256-byte boundary:
+//   [0, 64)               completion counter (word 0) and abort flag (word 1)
+//   sbuf  [2][xchg_len]   slope vectors of consecutive frames (persistent batches)
+//   s     [s_len]         slope vector of the current frame (per-launch frames)
+//   part  [k_split][n_act] split-K partial actuator vectors (per-launch frames)
+//   bar   [kWords - kBarBase] barrier counters, mailboxes and end stamps
+// The first three regions are zeroed by a kernel at the start of every call;
+// the barrier words are zeroed before every persistent launch.
+constexpr int64_t kScratchWords = int64_t(1) << 20;   // 4 MiB
+static __device__ __align__(256) uint32_t scratch[kScratchWords];
+
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+uint32_t *g_scratch_ptr[kScratchDevices] = {};
+
+// Device address of this device's scratch array, resolved on first use; `dev`
+// must be current.  Devices beyond the table get nullptr (no such entry point).
+hipError_t scratch_address(int dev, uint32_t **out) {
+  *out = nullptr;
+  if (dev < 0 || dev >= kScratchDevices) return hipSuccess;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = static_cast<uint32_t *>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+struct ScratchLayout {
+  int64_t sbuf, s, part, bar, zero_words, words;
+};
+
+ScratchLayout scratch_layout(const rtc_ctx *c) {
+  ScratchLayout L{};
+  L.sbuf = 64;
+  L.s = L.sbuf + 2 * xchg_len_of(c->n_slopes);
+  L.part = L.s + round_up(c->s_len, 64);
+  L.bar = L.part + round_up((int64_t)c->tuning.k_split * c->n_act, 64);
+  L.zero_words = L.part;
+  L.words = L.bar + (kSyncWords - rtck::sync_layout::kBarBase);
+  return L;
+}
+
+// Per-frame scratch of the per-launch path.
+struct FrameScratch {
+  float *s;
+  float *part;
+  uint32_t *sync;
+};
 
 }  // namespace
 
@@ -233,6 +293,7 @@ static rtc_status init_impl(const rtc_config *cfg, const rtc_wfs *wfs, int32_t n
     return st;
   };
   if (ds.status != hipSuccess) return bail(ds.status, "rtc_init: hipSetDevice");
+  if ((e = scratch_address(c->device, &c->d_scratch)) != hipSuccess) return bail(e, "rtc_init: hipGetSymbolAddress of the static scratch");
   int khz = 0;
   if ((e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, c->device)) != hipSuccess)
     return bail(e, "rtc_init: wall clock rate");
@@ -496,10 +557,12 @@ static rtck::CalibArgs calib_args(const rtc_ctx *c, const uint16_t *pix) {
   return ca;
 }
 
-static rtc_status enqueue_frame(rtc_ctx *c, const uint16_t *pix, float *cmd, float *slopes, float *recon,
-                                int32_t *counts, uint64_t *ts, hipStream_t st, const char *who) {
+static FrameScratch ctx_scratch(const rtc_ctx *c) { return FrameScratch{c->d_s, c->d_part, c->d_sync}; }
+
+static rtc_status enqueue_frame(rtc_ctx *c, const FrameScratch &fs, const uint16_t *pix, float *cmd, float *slopes,
+                                float *recon, int32_t *counts, uint64_t *ts, hipStream_t st, const char *who) {
   rtck::CalibArgs ca = calib_args(c, pix);
-  ca.s_int = c->d_s;
+  ca.s_int = fs.s;
   ca.s_user = slopes;
   ca.counts = counts;
   ca.ts_start = ts;
@@ -508,11 +571,11 @@ static rtc_status enqueue_frame(rtc_ctx *c, const uint16_t *pix, float *cmd, flo
   rtck::MvmArgs ma{};
   ma.n_act = c->n_act;
   ma.n_s4 = c->n_s4;
-  ma.s = c->d_s;
+  ma.s = fs.s;
   ma.k_split = c->tuning.k_split;
   ma.rows_per_wave = c->tuning.rows_per_wave;
   ma.unroll = c->tuning.unroll;
-  ma.part = c->d_part;
+  ma.part = fs.part;
   ma.state = c->d_state;
   ma.cmd = cmd;
   ma.recon = recon;
@@ -520,7 +583,7 @@ static rtc_status enqueue_frame(rtc_ctx *c, const uint16_t *pix, float *cmd, flo
   ma.leak = c->cfg.leak;
   ma.cmd_min = c->cfg.cmd_min;
   ma.cmd_max = c->cfg.cmd_max;
-  ma.sync = c->d_sync;
+  ma.sync = fs.sync;
   ma.ts_end = ts ? ts + 1 : nullptr;
   e = launch_reconstruction(c, ma, st);
   if (e != hipSuccess) return hip_fail(c, e, who);
@@ -536,7 +599,7 @@ rtc_status rtc_frame(rtc_ctx *c, const uint16_t *d_pixels, float *d_cmd, float *
   if (!d_pixels || !d_cmd) return fail(c, RTC_E_ARG, "rtc_frame: NULL pixels or cmd");
   DeviceScope ds(c->device);
   if (ds.status != hipSuccess) return hip_fail(c, ds.status, "rtc_frame: hipSetDevice");
-  return enqueue_frame(c, d_pixels, d_cmd, d_slopes, d_recon, d_counts, nullptr,
+  return enqueue_frame(c, ctx_scratch(c), d_pixels, d_cmd, d_slopes, d_recon, d_counts, nullptr,
                        static_cast<hipStream_t>(hip_stream), "rtc_frame: launch");
 }
 
@@ -690,12 +753,73 @@ rtc_status rtc_frame_batch(rtc_ctx *c, int32_t n_frames, const uint16_t *d_pixel
       return hip_fail(c, e, "rtc_frame_batch: persistent launch");
     (void)hipGetLastError();   // unsupported shape: fall through to one launch pair per frame
   }
+  const FrameScratch fs = ctx_scratch(c);
   for (int32_t f = 0; f < n_frames; ++f) {
-    rtc_status s = enqueue_frame(c, d_pixels + (int64_t)f * frame_stride, d_cmd + (int64_t)f * c->n_act,
+    rtc_status s = enqueue_frame(c, fs, d_pixels + (int64_t)f * frame_stride, d_cmd + (int64_t)f * c->n_act,
                                  d_slopes ? d_slopes + (int64_t)f * c->n_slopes : nullptr,
                                  d_recon ? d_recon + (int64_t)f * c->n_act : nullptr,
                                  d_counts ? d_counts + (int64_t)f * c->n_valid : nullptr,
                                  d_ts ? d_ts + 2 * (int64_t)f : nullptr, st, "rtc_frame_batch: launch");
+    if (s != RTC_OK) return s;
+  }
+  return RTC_OK;
+}
+
+rtc_status rtc_frame_batch_noalloc(rtc_ctx *c, int32_t n_frames, const uint16_t *d_pixels, int64_t frame_stride,
+                                   float *d_cmd, float *d_slopes, float *d_recon, int32_t *d_counts, uint64_t *d_ts,
+                                   void *hip_stream) {
+  if (!c) return fail(nullptr, RTC_E_ARG, "rtc_frame_batch_noalloc: NULL context");
+  if (!c->calib_loaded || !c->cmat_loaded)
+    return fail(c, RTC_E_STATE, "rtc_frame_batch_noalloc: load the calibration and the control matrix first");
+  if (c->state_invalid) return fail(c, RTC_E_STATE, "rtc_frame_batch_noalloc: " STATE_INVALID_MSG);
+  if (n_frames < 0) return fail(c, RTC_E_ARG, "rtc_frame_batch_noalloc: n_frames < 0");
+  if (n_frames == 0) return RTC_OK;
+  if (!d_pixels || !d_cmd) return fail(c, RTC_E_ARG, "rtc_frame_batch_noalloc: NULL pixels or cmd");
+  if (frame_stride < c->frame_elems)
+    return fail(c, RTC_E_ARG, "rtc_frame_batch_noalloc: frame_stride shorter than a frame");
+  if (!c->d_scratch)
+    return fail(c, RTC_E_UNSUPPORTED, "rtc_frame_batch_noalloc: no static scratch for device ordinals above 63");
+  const ScratchLayout L = scratch_layout(c);
+  if (L.words > kScratchWords)
+    return fail(c, RTC_E_UNSUPPORTED,
+                "rtc_frame_batch_noalloc: this context needs " + std::to_string(L.words * 4) +
+                    " bytes of static scratch (2 (2 n_valid rounded up to 1024) + (2 n_valid rounded up to 16) + "
+                    "k_split n_act floats plus 152 KiB of barrier words); the limit is " +
+                    std::to_string(kScratchWords * 4) + " bytes");
+  DeviceScope ds(c->device);
+  if (ds.status != hipSuccess) return hip_fail(c, ds.status, "rtc_frame_batch_noalloc: hipSetDevice");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  uint32_t *const base = c->d_scratch;
+  // the counter and abort words, both slope buffers (their padding is read)
+  hipError_t e = rtck::launch_fill_zero(reinterpret_cast<float *>(base), L.zero_words, st);
+  if (e != hipSuccess) return hip_fail(c, e, "rtc_frame_batch_noalloc: scratch clear");
+  // horizontal mode needs its 16.8 MB message buffer: the row split runs instead
+  if (c->frame_mode != RTC_FRAMES_PER_LAUNCH) {
+    rtck::PersistArgs p = persist_args(c, n_frames, d_pixels, frame_stride, d_cmd, d_slopes, d_recon, d_counts, d_ts);
+    p.sbuf = reinterpret_cast<float *>(base + L.sbuf);
+    p.bar = base + L.bar;
+    p.abort_flag = base + 1;
+    // p.sticky stays the context's word, which rtc_sync_check reads
+    const int blocks = c->tuning.blocks > 0 ? c->tuning.blocks : c->n_cu;
+    const int G = rtck::frames_grid(blocks, c->n_act);
+    p.calib_span = calib_span(c, G);
+    if (c->split_G > 0 && c->split_G == G) {
+      p.row_start = c->d_row_start;
+      p.row_max = c->split_max;
+    }
+    e = rtck::launch_frames(p, blocks, c->tuning.rows_per_wave, st);
+    if (e == hipSuccess) return RTC_OK;
+    if (e != hipErrorInvalidValue && e != hipErrorCooperativeLaunchTooLarge)
+      return hip_fail(c, e, "rtc_frame_batch_noalloc: persistent launch");
+    (void)hipGetLastError();
+  }
+  const FrameScratch fs{reinterpret_cast<float *>(base + L.s), reinterpret_cast<float *>(base + L.part), base};
+  for (int32_t f = 0; f < n_frames; ++f) {
+    rtc_status s = enqueue_frame(c, fs, d_pixels + (int64_t)f * frame_stride, d_cmd + (int64_t)f * c->n_act,
+                                 d_slopes ? d_slopes + (int64_t)f * c->n_slopes : nullptr,
+                                 d_recon ? d_recon + (int64_t)f * c->n_act : nullptr,
+                                 d_counts ? d_counts + (int64_t)f * c->n_valid : nullptr,
+                                 d_ts ? d_ts + 2 * (int64_t)f : nullptr, st, "rtc_frame_batch_noalloc: launch");
     if (s != RTC_OK) return s;
   }
   return RTC_OK;

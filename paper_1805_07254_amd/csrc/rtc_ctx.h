@@ -48,6 +48,7 @@ struct rtc_ctx {
   float *d_part = nullptr;
   float *d_sbuf = nullptr;   // [2][s_len] slope vectors of consecutive frames (persistent batches)
   uint32_t *d_sync = nullptr;  // rtck::sync_layout words: stamp counter, abort flags, persistent barrier
+  uint32_t *d_scratch = nullptr;  // this device's static scratch array (rtc_frame_batch_noalloc); not owned
   int32_t frame_mode = RTC_FRAMES_PER_LAUNCH;
   int32_t spin_limit = 1 << 22;
   uint64_t *d_trace = nullptr;  // caller-owned [trace_frames][trace_groups][8] stage stamps

@@ -110,6 +110,7 @@ _SIGNATURES = {
     "rtc_encode_cmat": (_i32, [_i32, _vp, _i32, _i32, _i64, _vp, _vp]),
     "rtc_frame": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "rtc_frame_batch": (_i32, [_vp, _i32, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "rtc_frame_batch_noalloc": (_i32, [_vp, _i32, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp]),
     "rtc_calibrate_centroid": (_i32, [_vp, _vp, _vp, _vp, _vp]),
     "rtc_reconstruct_integrate": (_i32, [_vp, _vp, _vp, _vp, _vp]),
     "rtc_set_mvm_tuning": (_i32, [_vp, ctypes.POINTER(rtc_mvm_tuning)]),
@@ -337,6 +338,23 @@ def rtc_frame_batch(ctx: RtcContext, n_frames: int, pixels, cmd, slopes=None, re
     stride = ctx.frame_elems if frame_stride is None else frame_stride
     need = 0 if n_frames == 0 else (n_frames - 1) * stride + ctx.frame_elems
     _check(load_library().rtc_frame_batch(
+        ctx.handle, n_frames,
+        _dev_ptr(pixels, "uint16", need, "pixels", ctx),
+        stride,
+        _dev_ptr(cmd, "float32", n_frames * ctx.n_act, "cmd", ctx),
+        _dev_ptr(slopes, "float32", n_frames * ctx.n_slopes, "slopes", ctx, False),
+        _dev_ptr(recon, "float32", n_frames * ctx.n_act, "recon", ctx, False),
+        _dev_ptr(counts, "int32", n_frames * ctx.n_valid, "counts", ctx, False),
+        _dev_ptr(ts, ("uint64", "int64"), 2 * n_frames, "ts", ctx, False),
+        _stream_ptr(stream)), ctx)
+
+
+def rtc_frame_batch_noalloc(ctx: RtcContext, n_frames: int, pixels, cmd, slopes=None, recon=None, counts=None,
+                            ts=None, frame_stride: Optional[int] = None, stream=None) -> None:
+    """rtc_frame_batch whose kernels use the library's static scratch array."""
+    stride = ctx.frame_elems if frame_stride is None else frame_stride
+    need = 0 if n_frames == 0 else (n_frames - 1) * stride + ctx.frame_elems
+    _check(load_library().rtc_frame_batch_noalloc(
         ctx.handle, n_frames,
         _dev_ptr(pixels, "uint16", need, "pixels", ctx),
         stride,

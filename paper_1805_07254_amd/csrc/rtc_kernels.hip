@@ -1,16 +1,24 @@
 // gfx950 kernels of the SH-WFS real-time-control frame:
-//   calib_cog_kernel       steps (a)-(b): dark, flat, threshold, centre of gravity
-//   mvm_kernel             step  (c):     control matrix x slope vector (+ step (d) when unsplit)
-//   reduce_integrate_kernel               fixed-order tree sum of split partials + step (d)
+//   calib_cog_kernel        steps (a)-(b): dark, flat, threshold, centre of gravity
+//   mvm_kernel              step  (c) split over slopes (streamed matrix) (+ step (d) when unsplit)
+//   reduce_integrate_kernel fixed-order tree sum of split partials + step (d)
+//   mvm_block_kernel        step  (c)-(d), contiguous row slab per workgroup, slope slices in registers
+//   mvm_panel_kernel        the same for slope vectors longer than the register slices (slope panels)
+//   frames_kernel           persistent batches: steps (a)-(d) for every frame of a batch in one
+//                           cooperative launch, one grid barrier per frame
+//   probe_copy/read_kernel  bandwidth probes
 //
 // Design notes (MI355X / CDNA4):
-//  * The reconstruction streams the whole control matrix every frame and does
-//    one FMA per 4 bytes: it is HBM/Infinity-Cache bound, not MFMA work, so it
-//    is a VALU GEMV with 16-byte loads, the slope vector staged in LDS, and
-//    float4 accumulators reduced by a 64-lane butterfly.
-//  * Calibration + centroiding read ~4 MB per ELT frame.  One lane owns one
-//    pixel row of one subaperture so a workgroup covers 256 / n_pix tiles;
-//    per-row partial sums are combined in LDS in a fixed order.
+//  * The per-launch reconstruction streams the control matrix from memory every
+//    frame, one FMA per 4 bytes: a VALU GEMV with 16-byte loads and fixed-order
+//    reductions, bound by HBM or the Infinity Cache, not MFMA work.
+//  * The persistent kernel keeps each workgroup's slab of the matrix on chip for
+//    the whole batch -- rows in accumulation and ordinary registers and in LDS,
+//    a few rows streamed from L2 -- so a frame reads little more than its pixels
+//    and its frame time is set by the calibration pass, the grid barrier and the
+//    VALU work of the products.
+//  * Calibration + centroiding read about 4 MB per ELT frame.  GS lanes own one
+//    subaperture (one pixel row each), so a tile's sums are lane butterflies.
 //  * Everything is deterministic: no floating-point atomics, fixed reduction
 //    trees, and the split-K partials are summed in a fixed pairwise tree.
 #include "rtc_kernels.h"

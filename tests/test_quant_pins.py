@@ -138,3 +138,29 @@ def test_encoder_rejects_bad_arguments():
     with pytest.raises(rtc.RtcError) as ei:
         rtc.rtc_encode_cmat(rtc.RTC_CM_BF16, bad)
     assert ei.value.status == rtc.RTC_E_NONFINITE
+
+
+def _library_view(codes: np.ndarray, fmt: str) -> np.ndarray:
+    """float64 value of each bit pattern as numpy / torch read the same bits."""
+    if fmt == "f16":
+        return codes.astype(np.uint16).view(np.float16).astype(np.float64)
+    if fmt == "bf16":
+        return torch.from_numpy(codes.astype(np.uint16).view(np.int16)).view(torch.bfloat16).to(torch.float64).numpy()
+    return torch.from_numpy(codes.astype(np.uint8)).view(torch.float8_e4m3fn).to(torch.float64).numpy()
+
+
+@pytest.mark.parametrize("fmt", FMTS)
+def test_every_code_has_the_library_bit_layout(fmt):
+    # decode_codes and _value_to_code against the bits numpy and torch assign:
+    # every finite pattern decodes to the library's value (signed zeros
+    # included) and encodes back to the same pattern
+    nb = 1 + quant.FORMATS[fmt][0] + quant.FORMATS[fmt][1]
+    codes = np.arange(1 << nb, dtype=np.int64)
+    lib = _library_view(codes, fmt)
+    finite = np.isfinite(lib)
+    assert finite.sum() == {"f16": 63488, "bf16": 65280, "fp8e4m3": 254}[fmt]
+    ours = quant.decode_codes(codes, fmt)
+    assert np.array_equal(ours[finite], lib[finite])
+    assert np.array_equal(np.signbit(ours[finite]), np.signbit(lib[finite]))
+    back = quant._value_to_code(lib[finite], fmt).astype(np.int64)
+    assert np.array_equal(back, codes[finite])

@@ -244,6 +244,32 @@ rtc_status rtc_frame_batch_noalloc(rtc_ctx *c, int32_t n_frames, const uint16_t 
                                    int64_t frame_stride, float *d_cmd, float *d_slopes, float *d_recon,
                                    int32_t *d_counts, uint64_t *d_ts, void *hip_stream);
 
+/* Host-paced frames: the latency of Section 3 (from a frame's arrival to its
+ * commands being ready) measured with frames arriving at a fixed rate, the
+ * release and completion signalled through spin-waited flags (Section
+ * 2.3.2).  Runs a persistent batch (RTC_FRAMES_PERSISTENT required) of
+ * n_frames frames, arguments and outputs as rtc_frame_batch, in which frame k
+ * starts only once the calling thread releases it, at t0 + k * period_us on
+ * the host's steady clock (busy-waited; t0 = one period after the launch):
+ * the thread writes the frame's number to a word of coherent host memory,
+ * which workgroup 0 polls and relays to the other workgroups.  The commands
+ * of these frames are stored at system scope; the last workgroup to store
+ * frame k's commands writes its number to a second host word, on which the
+ * thread spins.  h_release_ns[k] and h_done_ns[k] (host arrays, nullable)
+ * receive the host times of the release and of the completion being seen, in
+ * ns from t0.  Blocks until the batch has ended.  The two words (256 bytes of
+ * pinned host memory) are allocated on the first call.
+ * Errors: RTC_E_STATE (other frame modes, loads missing, undefined state),
+ * RTC_E_ARG (n_frames < 0, NULL pixels/cmd, short stride, period_us not in
+ * (0, 1e7]), RTC_E_UNSUPPORTED (tiles wider than 16 pixels, slope vectors
+ * long enough for slope panels, darks outside {0} U [2^-13, 2^24)),
+ * RTC_E_DEVICE (launch failure, or a frame not complete within 100 periods
+ * and at least 100 ms: the remaining frames are then released at once, the
+ * batch ends and rtc_sync_check reports the expired wait if there was one). */
+rtc_status rtc_paced_batch(rtc_ctx *c, int32_t n_frames, const uint16_t *d_pixels, int64_t frame_stride,
+                           float *d_cmd, float *d_slopes, float *d_recon, int32_t *d_counts, uint64_t *d_ts,
+                           double period_us, int64_t *h_release_ns, int64_t *h_done_ns, void *hip_stream);
+
 /* Steps (a)-(b) alone: calibration and centre-of-gravity slopes of one frame
  * into d_slopes [2*n_valid] (required) and d_counts [n_valid] (nullable).
  * Leaves the integrator state untouched.  Needs the calibration (RTC_E_STATE). */

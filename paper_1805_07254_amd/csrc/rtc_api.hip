@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -825,6 +826,94 @@ rtc_status rtc_frame_batch_noalloc(rtc_ctx *c, int32_t n_frames, const uint16_t 
   return RTC_OK;
 }
 
+rtc_status rtc_paced_batch(rtc_ctx *c, int32_t n_frames, const uint16_t *d_pixels, int64_t frame_stride,
+                           float *d_cmd, float *d_slopes, float *d_recon, int32_t *d_counts, uint64_t *d_ts,
+                           double period_us, int64_t *h_release_ns, int64_t *h_done_ns, void *hip_stream) {
+  using clk = std::chrono::steady_clock;
+  const char *who = "rtc_paced_batch";
+  if (!c) return fail(nullptr, RTC_E_ARG, "rtc_paced_batch: NULL context");
+  if (!c->calib_loaded || !c->cmat_loaded)
+    return fail(c, RTC_E_STATE, "rtc_paced_batch: load the calibration and the control matrix first");
+  if (c->state_invalid) return fail(c, RTC_E_STATE, "rtc_paced_batch: " STATE_INVALID_MSG);
+  if (c->frame_mode != RTC_FRAMES_PERSISTENT)
+    return fail(c, RTC_E_STATE, "rtc_paced_batch: needs RTC_FRAMES_PERSISTENT");
+  if (n_frames < 0) return fail(c, RTC_E_ARG, "rtc_paced_batch: n_frames < 0");
+  if (n_frames == 0) return RTC_OK;
+  if (!d_pixels || !d_cmd) return fail(c, RTC_E_ARG, "rtc_paced_batch: NULL pixels or cmd");
+  if (frame_stride < c->frame_elems) return fail(c, RTC_E_ARG, "rtc_paced_batch: frame_stride shorter than a frame");
+  if (!(period_us > 0.0) || period_us > 1e7) return fail(c, RTC_E_ARG, "rtc_paced_batch: period_us must be in (0, 1e7]");
+  if (!c->dark_fast)
+    return fail(c, RTC_E_UNSUPPORTED, "rtc_paced_batch: the persistent kernel needs darks in {0} U [2^-13, 2^24)");
+  DeviceScope ds(c->device);
+  if (ds.status != hipSuccess) return hip_fail(c, ds.status, who);
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  hipError_t e = hipSuccess;
+  if (!c->h_trig) {
+    void *h = nullptr;
+    if ((e = hipHostMalloc(&h, 256, hipHostMallocCoherent | hipHostMallocMapped)) != hipSuccess)
+      return hip_fail(c, e, "rtc_paced_batch: hipHostMalloc of the trigger words");
+    c->h_trig = static_cast<uint32_t *>(h);
+    __atomic_store_n(c->h_trig, c->trig_base, __ATOMIC_RELEASE);
+    __atomic_store_n(c->h_trig + 32, c->trig_base, __ATOMIC_RELEASE);
+  }
+  void *d_trig = nullptr;
+  if ((e = hipHostGetDevicePointer(&d_trig, c->h_trig, 0)) != hipSuccess)
+    return hip_fail(c, e, "rtc_paced_batch: hipHostGetDevicePointer");
+  rtck::PersistArgs p = persist_args(c, n_frames, d_pixels, frame_stride, d_cmd, d_slopes, d_recon, d_counts, d_ts);
+  const uint32_t base = c->trig_base;
+  p.trig_release = static_cast<const uint32_t *>(d_trig);
+  p.trig_done = static_cast<uint32_t *>(d_trig) + 32;
+  p.trig_base = base;
+  const int blocks = c->tuning.blocks > 0 ? c->tuning.blocks : c->n_cu;
+  const int G = rtck::frames_grid(blocks, c->n_act);
+  p.calib_span = calib_span(c, G);
+  if (c->split_G > 0 && c->split_G == G) {
+    p.row_start = c->d_row_start;
+    p.row_max = c->split_max;
+  }
+  e = rtck::launch_frames(p, blocks, c->tuning.rows_per_wave, st);
+  if (e == hipErrorInvalidValue) {
+    (void)hipGetLastError();
+    return fail(c, RTC_E_UNSUPPORTED, "rtc_paced_batch: shape not covered by the triggered persistent kernel "
+                                      "(tiles of up to 16 pixels, slope vectors without panels, slabs within "
+                                      "the persistent limits)");
+  }
+  if (e != hipSuccess) return hip_fail(c, e, "rtc_paced_batch: persistent launch");
+  // frames released from here on belong to this batch, whatever happens below
+  c->trig_base = base + (uint32_t)n_frames;
+  volatile uint32_t *release = c->h_trig;
+  const volatile uint32_t *done = c->h_trig + 32;
+  const auto period = std::chrono::nanoseconds((int64_t)std::llround(period_us * 1e3));
+  const auto t0 = clk::now() + period;
+  // a frame not done within 100 periods (at least 100 ms) fails the batch
+  const auto limit = std::max(std::chrono::nanoseconds(100000000), 100 * period);
+  std::string late;
+  for (int32_t k = 0; k < n_frames && late.empty(); ++k) {
+    const auto due = t0 + k * period;
+    while (clk::now() < due) {
+    }
+    const uint32_t v = base + (uint32_t)k + 1u;
+    __atomic_store_n(const_cast<uint32_t *>(release), v, __ATOMIC_RELEASE);
+    const auto t_rel = clk::now();
+    if (h_release_ns) h_release_ns[k] = std::chrono::duration_cast<std::chrono::nanoseconds>(t_rel - t0).count();
+    for (uint64_t spin = 0;; ++spin) {
+      if ((int32_t)(__atomic_load_n(const_cast<uint32_t *>(done), __ATOMIC_ACQUIRE) - v) >= 0) break;
+      if ((spin & 4095) == 4095 && clk::now() - t_rel > limit) {
+        late = "rtc_paced_batch: frame " + std::to_string(k) + " was not done within " +
+               std::to_string(std::chrono::duration_cast<std::chrono::milliseconds>(limit).count()) + " ms";
+        break;
+      }
+    }
+    if (h_done_ns && late.empty())
+      h_done_ns[k] = std::chrono::duration_cast<std::chrono::nanoseconds>(clk::now() - t0).count();
+  }
+  // release whatever is left (a failed batch then winds down at once) and wait
+  __atomic_store_n(const_cast<uint32_t *>(release), c->trig_base, __ATOMIC_RELEASE);
+  if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(c, e, "rtc_paced_batch: synchronise");
+  if (!late.empty()) return fail(c, RTC_E_DEVICE, late);
+  return RTC_OK;
+}
+
 rtc_status rtc_graph_capture(rtc_ctx *c, int32_t n_frames, const uint16_t *d_pixels, int64_t frame_stride,
                              float *d_cmd, float *d_slopes, float *d_recon, int32_t *d_counts, uint64_t *d_ts) {
   if (!c) return fail(nullptr, RTC_E_ARG, "rtc_graph_capture: NULL context");
@@ -1392,6 +1481,7 @@ void rtc_destroy(rtc_ctx *c) {
   dfree(c->d_hm);
   dfree(c->d_xbuf);
   if (c->graph) (void)hipGraphExecDestroy(c->graph);
+  if (c->h_trig) (void)hipHostFree(c->h_trig);
   delete c;
 }
 

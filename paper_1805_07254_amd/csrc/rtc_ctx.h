@@ -49,6 +49,8 @@ struct rtc_ctx {
   float *d_sbuf = nullptr;   // [2][s_len] slope vectors of consecutive frames (persistent batches)
   uint32_t *d_sync = nullptr;  // rtck::sync_layout words: stamp counter, abort flags, persistent barrier
   uint32_t *d_scratch = nullptr;  // this device's static scratch array (rtc_frame_batch_noalloc); not owned
+  uint32_t *h_trig = nullptr;      // coherent host words of paced batches: [0] release, [32] done
+  uint32_t trig_base = 0;          // frames released by earlier paced batches (mod 2^32)
   int32_t frame_mode = RTC_FRAMES_PER_LAUNCH;
   int32_t spin_limit = 1 << 22;
   uint64_t *d_trace = nullptr;  // caller-owned [trace_frames][trace_groups][8] stage stamps

@@ -268,6 +268,48 @@ __device__ __forceinline__ bool bounded_wait(const PersistArgs &p, const uint32_
   return true;
 }
 
+// Wavefront 0 of every workgroup: waits until the external trigger releases
+// frame f.  Lane 0 of workgroup 0 polls the host word (system scope) and the
+// wavefront relays the value to every workgroup's mailbox line; the others
+// poll their own line.  An expired wait raises the abort flag.
+__device__ __forceinline__ void trigger_wait(const PersistArgs &p, int f) {
+  const uint32_t target = p.trig_base + (uint32_t)f + 1u;
+  if (blockIdx.x == 0) {
+    int ok = 1;
+    if (threadIdx.x == 0) {
+      int32_t spins = 0;
+      while ((int32_t)(__hip_atomic_load(p.trig_release, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) - target) <
+             0) {
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins > p.spin_limit) {
+          __hip_atomic_store(p.abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_store(p.sticky, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          ok = 0;
+          break;
+        }
+      }
+    }
+    if (__builtin_amdgcn_readfirstlane(ok))
+      for (uint32_t i = threadIdx.x + 1; i < gridDim.x; i += 64)
+        __hip_atomic_store(p.bar + sl::kMailbox + 16 * i + 4, target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  } else if (threadIdx.x == 0) {
+    (void)bounded_wait(p, p.bar + sl::kMailbox + 16 * blockIdx.x + 4, target);
+  }
+}
+
+// After this workgroup's commands of frame f are stored: the last workgroup to
+// get here writes the frame's number to the trigger's done word.
+__device__ __forceinline__ void trigger_done(const PersistArgs &p, int f) {
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t prev = __hip_atomic_fetch_add(p.bar + sl::kTrigDone, 1u, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+    if (prev == gridDim.x * (uint32_t)(f + 1) - 1u)
+      __hip_atomic_store(p.trig_done, p.trig_base + (uint32_t)f + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
+}
+
 // False when this workgroup's wait for the release expired (the abort flag is
 // then raised): the frame's slopes may be incomplete, so the caller must not
 // use them.  sh_flag: a shared word of the workgroup.

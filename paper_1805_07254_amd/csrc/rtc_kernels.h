@@ -106,6 +106,14 @@ struct PersistArgs {
                            // grid of frames_grid(); 0 = not known (they are then read from memory)
   const int32_t *row_start;  // nullable [G + 1]: workgroup b owns rows [row_start[b], row_start[b+1])
   int32_t row_max;           // largest row_start[b+1] - row_start[b] (with row_start)
+  // external frame trigger (nullable): frame f starts once *trig_release
+  // reaches trig_base + f + 1 (coherent host memory, polled by workgroup 0 and
+  // relayed to the others' mailbox lines); its commands are then stored at
+  // system scope and the last workgroup to finish it writes trig_base + f + 1
+  // to *trig_done
+  const uint32_t *trig_release;
+  uint32_t *trig_done;
+  uint32_t trig_base;
 };
 constexpr int kTraceStages = 8;
 // Zeroes the barrier counters, the mailboxes of G workgroups and the abort flag
@@ -124,7 +132,8 @@ constexpr int kStride = 1024;
 constexpr int kGroups = 16;                       // group g arrival counter at kStride * g
 constexpr int kTop = kGroups * kStride;           // arrivals of whole groups
 constexpr int kDone = (kGroups + 1) * kStride;    // workgroups done with a batch (end stamp)
-constexpr int kMailbox = (kGroups + 2) * kStride; // + 16 * workgroup
+constexpr int kTrigDone = kDone + 16;             // workgroups done with triggered frames
+constexpr int kMailbox = (kGroups + 2) * kStride; // + 16 * workgroup: [0] barrier epoch, [4] trigger relay
 constexpr int kMaxGroups = 1024;
 constexpr int kEnds = kMailbox + 16 * kMaxGroups; // uint64 [2][kMaxGroups] per-workgroup frame end stamps
 constexpr int kWords = kBarBase + kEnds + 4 * kMaxGroups;

@@ -766,7 +766,7 @@ __device__ __forceinline__ void lds_row_group(const uint4 *lds, int ldq16, int r
 // 512-entry register file: RR rows of the slab are kept in ordinary registers
 // and RA more in accumulation registers (AGPRs, which the matrix cores would
 // otherwise use), so more of the matrix stays on chip.
-template <int FMT, int KPL, int RR, int RA, int VW, int GS, bool PANELS>
+template <int FMT, int KPL, int RR, int RA, int VW, int GS, bool PANELS, bool TRIG>
 __global__ __launch_bounds__(512 / VW) void frames_kernel(PersistArgs p, int32_t max_rows, int32_t lds_rows,
                                                           int32_t tile_cap, int32_t calib_cap) {
   static_assert(!PANELS || (VW == 1 && RA == 0), "slope panels use 8 wavefronts");
@@ -884,6 +884,9 @@ __global__ __launch_bounds__(512 / VW) void frames_kernel(PersistArgs p, int32_t
 #pragma unroll
         for (int j = 0; j < KPL; ++j)
           asm volatile("" : "+a"(ra[u][i][j].x), "+a"(ra[u][i][j].y), "+a"(ra[u][i][j].z), "+a"(ra[u][i][j].w));
+    }
+    if constexpr (TRIG) {                           // externally triggered frames
+      if (wave == 0) trigger_wait(p, f);
     }
     if (tid == 0) sh_abort = __hip_atomic_load(p.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
@@ -1054,10 +1057,15 @@ __global__ __launch_bounds__(512 / VW) void frames_kernel(PersistArgs p, int32_t
       float c = fmaf(a.gain, v, a.leak * state);
       c = fminf(fmaxf(c, a.cmd_min), a.cmd_max);
       state = c;
-      a.cmd[(int64_t)f * a.n_act + row_begin + tid] = c;
+      float *cp = a.cmd + (int64_t)f * a.n_act + row_begin + tid;
+      if constexpr (TRIG)                          // triggered frames: commands visible to the host
+        __hip_atomic_store(cp, c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      else
+        *cp = c;
       if (a.recon != nullptr) a.recon[(int64_t)f * a.n_act + row_begin + tid] = v;
     }
     trace_stamp(p, f, 5);
+    if constexpr (TRIG) trigger_done(p, f);
     if (p.ts != nullptr) {                         // this workgroup's commands of frame f are issued
       __syncthreads();
       if (tid == 0)
@@ -1277,6 +1285,7 @@ __global__ __launch_bounds__(kBlock) void persist_reset_kernel(uint32_t *bar, ui
   else if (t == sl::kGroups) w = bar + sl::kTop;
   else if (t == sl::kGroups + 1) w = bar + sl::kDone;
   else if (t == sl::kGroups + 2) w = abort_flag;
+  else if (t == sl::kGroups + 3) w = bar + sl::kTrigDone;
   else if (t >= 64 && t < 64 + G) w = bar + sl::kMailbox + 16 * (t - 64);
   if (w != nullptr) __hip_atomic_store(w, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -1305,7 +1314,15 @@ static hipError_t launch_frames_variant(const PersistArgs &p, int G, int max_row
   constexpr int W = 8;
   using FS = FrameShape<FMT, KPL, PANELS, WIDE, GS>;
   constexpr int NT = 512 / FS::VW;
-  auto kern = frames_kernel<FMT, KPL, FS::RR, FS::RA, FS::VW, GS, PANELS>;
+  // externally triggered batches: a variant of their own (the trigger's wait
+  // costs registers), built for tiles of up to 16 pixels without slope panels
+  constexpr bool kTrigBuilt = GS <= 16 && !PANELS;
+  const bool trig = p.trig_release != nullptr;
+  if (trig && !kTrigBuilt) return hipErrorInvalidValue;
+  auto kern = frames_kernel<FMT, KPL, FS::RR, FS::RA, FS::VW, GS, PANELS, false>;
+  if constexpr (kTrigBuilt) {
+    if (trig) kern = frames_kernel<FMT, KPL, FS::RR, FS::RA, FS::VW, GS, PANELS, true>;
+  }
   int dev = 0, ncu = 0, lds_max = 0;
   hipError_t e;
   if ((e = hipGetDevice(&dev)) != hipSuccess) return e;

@@ -111,6 +111,7 @@ _SIGNATURES = {
     "rtc_frame": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "rtc_frame_batch": (_i32, [_vp, _i32, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp]),
     "rtc_frame_batch_noalloc": (_i32, [_vp, _i32, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "rtc_paced_batch": (_i32, [_vp, _i32, _vp, _i64, _vp, _vp, _vp, _vp, _vp, ctypes.c_double, _vp, _vp, _vp]),
     "rtc_calibrate_centroid": (_i32, [_vp, _vp, _vp, _vp, _vp]),
     "rtc_reconstruct_integrate": (_i32, [_vp, _vp, _vp, _vp, _vp]),
     "rtc_set_mvm_tuning": (_i32, [_vp, ctypes.POINTER(rtc_mvm_tuning)]),
@@ -364,6 +365,26 @@ def rtc_frame_batch_noalloc(ctx: RtcContext, n_frames: int, pixels, cmd, slopes=
         _dev_ptr(counts, "int32", n_frames * ctx.n_valid, "counts", ctx, False),
         _dev_ptr(ts, ("uint64", "int64"), 2 * n_frames, "ts", ctx, False),
         _stream_ptr(stream)), ctx)
+
+
+def rtc_paced_batch(ctx: RtcContext, n_frames: int, pixels, cmd, period_us: float, slopes=None, recon=None,
+                    counts=None, ts=None, frame_stride: Optional[int] = None, stream=None):
+    """Host-paced persistent batch; returns (release_ns, done_ns), host int64 [n_frames]."""
+    stride = ctx.frame_elems if frame_stride is None else frame_stride
+    need = 0 if n_frames == 0 else (n_frames - 1) * stride + ctx.frame_elems
+    rel = np.zeros(max(n_frames, 1), np.int64)
+    done = np.zeros(max(n_frames, 1), np.int64)
+    _check(load_library().rtc_paced_batch(
+        ctx.handle, n_frames,
+        _dev_ptr(pixels, "uint16", need, "pixels", ctx),
+        stride,
+        _dev_ptr(cmd, "float32", n_frames * ctx.n_act, "cmd", ctx),
+        _dev_ptr(slopes, "float32", n_frames * ctx.n_slopes, "slopes", ctx, False),
+        _dev_ptr(recon, "float32", n_frames * ctx.n_act, "recon", ctx, False),
+        _dev_ptr(counts, "int32", n_frames * ctx.n_valid, "counts", ctx, False),
+        _dev_ptr(ts, ("uint64", "int64"), 2 * n_frames, "ts", ctx, False),
+        float(period_us), rel.ctypes.data, done.ctypes.data, _stream_ptr(stream)), ctx)
+    return rel[:n_frames], done[:n_frames]
 
 
 def rtc_calibrate_centroid(ctx: RtcContext, pixels, slopes, counts=None, stream=None) -> None:

@@ -1,21 +1,34 @@
 """Benchmark of the AO real-time-control frame on one MI355X.
 
 One step = one ELT-scale SCAO frame through the whole hot path (calibration,
-centre of gravity, control-matrix x slopes, integrator).  Frames run back to
-back, as the paper's no-camera measurements do, from a device buffer holding
-one raw frame per step (copies of a ring of distinct open-loop frames), so
-every frame's pixels are read from HBM.  The headline runs the persistent
-kernel, one cooperative launch per --launch-frames frames; the per-frame device
-time stamps give the frame time series (start of frame k to start of frame
-k+1) whose p50 is ``value``, plus p99, RMS and peak-to-peak jitter, and the
-span of each frame (its start to the last workgroup's command store).  The
-per-launch mode (two kernels per frame) and the reduced-precision matrix
-formats are timed the same way.  The roofline figure divides the algorithmic
-bytes of a launch by the launch's average duration from HIP events on the
-launch stream, and the FP64 oracle is timed on the host cores as a CPU
-baseline.
+centre of gravity, control-matrix x slopes, integrator), FP32, in the
+persistent kernel.  Frames run back to back from a device buffer holding one
+raw frame per step (copies of a ring of distinct open-loop frames), so every
+frame's pixels are read from HBM.  ``value`` is the p50 of the timed frames'
+span: the first workgroup's start of the frame to the last workgroup's
+command store, from per-frame device time stamps (the paper's latency without
+a camera is the frame computation time).  Around it:
 
-    python bench.py [--steps 10000] [--warmup 500] [--launch-frames 1000]
+  * long runs: whole launches of --roofline-frames frames, timed with HIP
+    events on the launch stream (the roofline's device time), with the
+    period and span statistics of every frame (p50, p99, RMS and
+    peak-to-peak jitter, with and without the first 100 frames);
+  * a stage trace of every workgroup, whose last-arrival-to-release time is
+    the measured barrier floor of the frame model;
+  * a host-paced run: frames released one by one at a fixed period through a
+    word of coherent host memory, latency taken on the host from the release
+    to the completion word (rtc_paced_batch);
+  * the horizontal split, the per-launch mode, the reduced-precision
+    matrices, read/copy bandwidth probes;
+  * the FP64 oracle on the host's cores (all cores, and one core in a child
+    process) as a CPU baseline.
+
+The roofline reports the frames kernel against the FP32 VALU peak (its work
+is FMAs on operands kept on chip), with a frame model built from rocprofv3
+counters of the committed profile (VALU issue, LDS and L2 bytes, HBM traffic)
+plus the measured barrier floor, and the HBM view kept separately.
+
+    python bench.py [--steps 10000] [--warmup 1000]
 """
 from __future__ import annotations
 
@@ -33,8 +46,21 @@ sys.path.insert(0, ROOT)
 
 METRIC = ("ELT-SCAO frame latency p50/p99 + RMS jitter (µs); GEMV GB/s vs HBM/LLC peak")
 HBM_PEAK_GBPS = 8000.0
-PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "frames_elt_traffic.json")
-KERNEL_SRCS = [os.path.join(ROOT, "paper_1805_07254_amd", "csrc", f) for f in ("rtc_kernels.hip", "rtc_device.h")]
+# MI355X: 256 compute units at 2.4 GHz; FP32 FMA without packed math is 64
+# lanes per cycle per unit (16 per SIMD), 78.6 TFLOP/s, i.e. one wave64 VALU
+# instruction per cycle per unit; LDS 128 bytes per cycle per unit; L2 16
+# channels x 128 bytes per cycle per XCD of 32 units = 64 bytes per cycle per
+# unit; a TCP-to-L2 read request moves 128 bytes (a 256 MiB copy counts
+# 2,097,152 of them)
+N_CU = 256
+CLK_GHZ = 2.4
+VALU_PEAK_TFLOPS = 78.6
+LDS_BYTES_PER_CLK = 128
+L2_BYTES_PER_CLK_PER_CU = 64
+TCP_REQ_BYTES = 128
+PROFILE_COUNTERS = os.path.join(ROOT, "profiles", "frames_elt_counters.json")
+KERNEL_SRCS = [os.path.join(ROOT, "paper_1805_07254_amd", "csrc", f)
+               for f in ("rtc_kernels.hip", "rtc_device.h", "rtc_kernels.h")]
 FMT_BYTES = {"f32": 4, "f16": 2, "bf16": 2, "fp8e4m3": 1}
 
 
@@ -60,6 +86,15 @@ def frame_bytes(sc, fmt: str) -> int:
     return matrix + n_v * n_pix * n_pix * (2 + 8) + 2 * 4 * n_s + 2 * 4 * n_act
 
 
+def frame_flops(sc) -> int:
+    """Algorithmic floating-point operations of one frame: 2 per matrix
+    element (multiply-add), 8 per valid pixel (dark subtraction, flat,
+    threshold compare and subtract, three weighted sums), 4 per actuator
+    (integrator multiply-add, clamp)."""
+    n_pix = sc.cfg.n_pix
+    return 2 * sc.n_act * 2 * sc.n_valid + 8 * sc.n_valid * n_pix * n_pix + 4 * sc.n_act
+
+
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
@@ -77,7 +112,7 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=15.0)
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--variants", default="f16,bf16,fp8e4m3",
-                   help="reduced-precision matrix formats also timed (comma list, empty = none)")
+                   help="reduced-precision matrix formats also timed (comma list, none = no variant)")
     p.add_argument("--variant-steps", type=int, default=2000)
     p.add_argument("--workload", default="elt-scao", choices=["elt-scao", "elt-multi", "elt-predict", "elt-pipe"],
                    help="elt-scao: the single-sensor ELT frame (default); elt-multi: six 74x74 and three 16x16 "
@@ -96,6 +131,14 @@ def parse():
     p.add_argument("--pred-history", type=int, default=5)
     p.add_argument("--pred-epochs", type=int, default=6)
     p.add_argument("--pred-batch", type=int, default=512)
+    p.add_argument("--roofline-frames", type=int, default=10000, help="frames per roofline launch")
+    p.add_argument("--roofline-launches", type=int, default=3)
+    p.add_argument("--trace-frames", type=int, default=1000, help="frames of the all-workgroup stage trace")
+    p.add_argument("--paced-frames", type=int, default=2000, help="host-paced frames (0 = none)")
+    p.add_argument("--paced-period-us", type=float, default=1000.0)
+    p.add_argument("--horizontal-steps", type=int, default=2000, help="frames timed in the horizontal split")
+    p.add_argument("--probes", default="35MB,70MB,140MB,488MB,2GB", help="read-probe working sets (comma list, none = no probe)")
+    p.add_argument("--cpu-leg", type=int, default=None, help=argparse.SUPPRESS)
     return p.parse_args()
 
 
@@ -121,7 +164,8 @@ def cpu_baseline(sc, ring_host, seconds: float) -> dict:
         c = out["cmd"]
         k += 1
     t = np.asarray(times[1:] if len(times) > 1 else times)
-    return {"value": float(np.median(t)), "unit": "us/frame", "cores": int(blas_threads), "kind": "oracle",
+    cores = min(int(blas_threads), len(os.sched_getaffinity(0)))
+    return {"value": float(np.median(t)), "unit": "us/frame", "cores": cores, "kind": "oracle",
             "sample": f"{len(times)} ELT frames (first dropped from the stats) through the FP64 oracle: "
                       f"calibration, CoG, R s with R promoted to float64 once, integrator; mean "
                       f"{t.mean():.0f} us, p99 {np.percentile(t, 99):.0f} us"}
@@ -454,6 +498,8 @@ def run_predict(args):
     t_pred = timed(lambda: (pred.step(r, c0, r2, stream=st_ptr), rtc.rtc_reconstruct_integrate(ctx, r2, c1,
                                                                                                   stream=st_ptr)))
     pred.close()
+    net.close()
+    rtc.rtc_destroy(ctx)
     res_i = float(np.mean([j["integrator"] for j in judged]))
     res_p = float(np.mean([j["predictive"] for j in judged]))
     result = {
@@ -476,20 +522,129 @@ def run_predict(args):
     print(json.dumps(result), flush=True)
 
 
+def cpu_single_core(seconds: float) -> dict:
+    """CPU leg on one core, in a child process pinned to one core of this
+    process's affinity set with one BLAS thread."""
+    import subprocess
+    core = sorted(os.sched_getaffinity(0))[0]
+    env = dict(os.environ)
+    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS", "BLIS_NUM_THREADS"):
+        env[k] = "1"
+    cmd = [sys.executable, os.path.abspath(__file__), "--cpu-leg", str(core), "--cpu-seconds", str(seconds)]
+    r = subprocess.run(cmd, env=env, capture_output=True, text=True, timeout=seconds * 4 + 300)
+    if r.returncode != 0:
+        return {"error": f"child exited {r.returncode}: {r.stderr[-400:]}"}
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
+def cpu_leg_child(core: int, seconds: float) -> None:
+    """Entry of the single-core child: pin, rebuild the workload, time the oracle."""
+    os.sched_setaffinity(0, {core})
+    try:
+        from threadpoolctl import threadpool_limits
+        threadpool_limits(1)
+    except Exception:                                          # the environment already asks for one thread
+        pass
+    from aosim import ELT, Scenario
+    sc = Scenario(ELT)
+    ring = np.stack([sc.frame(i, sc.turbulence_slopes(i)) for i in range(8)])
+    out = cpu_baseline(sc, ring, seconds)
+    out["cores"] = len(os.sched_getaffinity(0))
+    out["sample"] = "one core, one BLAS thread, separate process: " + out["sample"]
+    print(json.dumps(out), flush=True)
+
+
+def stage_breakdown(tr: np.ndarray, khz: int) -> dict:
+    """Per-frame critical path of traced persistent frames: [frames, groups, 8]
+    stamps (frame start, slopes issued, barrier passed, slices loaded, sums
+    done, commands written, stores complete, arrival counted)."""
+    from paper_1805_07254_amd.stats import ticks_to_us
+    t = tr.astype(np.int64)
+    start = t[:, :, 0].min(axis=1)
+    last_arrival = t[:, :, 7].max(axis=1)
+    first_arrival = t[:, :, 7].min(axis=1)
+    last_pass = t[:, :, 2].max(axis=1)
+    last_cmd = t[:, :, 5].max(axis=1)
+    us = lambda d: ticks_to_us(d, khz)
+    med = lambda x: round(float(np.median(x)), 3)
+    return {
+        "frames": int(t.shape[0]), "groups": int(t.shape[1]),
+        "start_to_last_arrival_us": med(us(last_arrival - start)),
+        "arrival_spread_us": med(us(last_arrival - first_arrival)),
+        "barrier_us": med(us(last_pass - last_arrival)),
+        "barrier_to_last_commands_us": med(us(last_cmd - last_pass)),
+        "calibration_us": med(us(np.median(t[:, :, 1] - t[:, :, 0], axis=1))),
+        "slice_load_us": med(us(np.median(t[:, :, 3] - t[:, :, 2], axis=1))),
+        "partial_sums_us": med(us(np.median(t[:, :, 4] - t[:, :, 3], axis=1))),
+        "span_us": med(us(last_cmd - start)),
+    }
+
+
+def load_counters(frames_per_launch: int):
+    """rocprofv3 counters of the frames kernel from the committed profile, when
+    it was taken on the current kernel sources at the same frames per launch."""
+    if not os.path.exists(PROFILE_COUNTERS):
+        return None, "no counter profile"
+    try:
+        prof = json.load(open(PROFILE_COUNTERS))
+    except Exception as err:                                  # unreadable profile: report, do not use
+        return None, f"counter profile unreadable: {err}"
+    if prof.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None, "counter profile taken on other kernel sources"
+    if prof.get("frames_per_launch") != frames_per_launch:
+        return None, f"counter profile taken at {prof.get('frames_per_launch')} frames per launch"
+    return prof, None
+
+
+def frame_model(prof: dict, frames: int, frame_us: float, barrier_us: float) -> dict:
+    """Floor of the persistent frame from its counted work: the measured barrier
+    latency plus the largest of the VALU-issue, LDS, L2 and HBM times of one
+    frame (per compute unit where the resource is per unit)."""
+    c = prof["counters_per_dispatch"]
+    per_cu = lambda v: v / frames / N_CU
+    clk = CLK_GHZ * 1e3                                        # cycles per us
+    t_valu = per_cu(c["SQ_INSTS_VALU"]) / clk                  # one wave64 VALU instruction per cycle per CU
+    lds_bytes = c["SQ_INSTS_LDS_LOAD_BANDWIDTH"] * 64
+    t_lds = per_cu(lds_bytes) / LDS_BYTES_PER_CLK / clk
+    l2_bytes = c["TCP_TCC_READ_REQ_sum"] * TCP_REQ_BYTES
+    t_l2 = per_cu(l2_bytes) / L2_BYTES_PER_CLK_PER_CU / clk
+    hbm_bytes = prof.get("hbm_bytes_per_dispatch")
+    t_hbm = hbm_bytes / frames / (HBM_PEAK_GBPS * 1e3) if hbm_bytes else 0.0
+    terms = {"valu_issue_us": t_valu, "lds_us": t_lds, "l2_us": t_l2, "hbm_us": t_hbm}
+    floor = barrier_us + max(terms.values())
+    return {
+        "terms_us": {k: round(v, 4) for k, v in terms.items()},
+        "barrier_floor_us": round(barrier_us, 4),
+        "floor_us": round(floor, 4), "frame_us": round(frame_us, 4), "frac": round(floor / frame_us, 4),
+        "per_frame": {"valu_insts": round(c["SQ_INSTS_VALU"] / frames), "fma_f32_insts": round(
+            c["SQ_INSTS_VALU_FMA_F32"] / frames), "lds_load_bytes": round(lds_bytes / frames),
+            "l2_read_bytes": round(l2_bytes / frames)},
+        "source": os.path.relpath(PROFILE_COUNTERS, ROOT),
+    }
+
+
 def main():
     args = parse()
+    if args.cpu_leg is not None:
+        cpu_leg_child(args.cpu_leg, args.cpu_seconds)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
-    if args.workload == "elt-multi":
-        run_multi(args)
-        return
-    if args.workload == "elt-predict":
-        run_predict(args)
-        return
-    if args.workload == "elt-pipe":
-        run_pipe(args)
-        return
+    run = {"elt-multi": run_multi, "elt-predict": run_predict, "elt-pipe": run_pipe}.get(args.workload, run_scao)
+    run(args)
+    # explicit teardown: every context is closed, the device is idle, and the
+    # library's HIP modules are unregistered now rather than from the exit
+    # handlers, after a profiler attached to the process has finalised
+    import gc
+    import torch
+    from paper_1805_07254_amd import rtc
+    gc.collect()
+    torch.cuda.synchronize()
+    rtc.unload_library()
+
+
+def run_scao(args):
     import torch
     from aosim import ELT, Scenario
     from paper_1805_07254_amd import rtc
@@ -511,17 +666,19 @@ def main():
             log(f"generated {i + 1}/{args.ring} open-loop frames")
     log(f"setup done in {time.time() - t_setup:.0f}s")
 
-    npx = cfg.frame_side * cfg.frame_side
     n_act = sc.n_act
     ring16 = torch.from_numpy(ring.reshape(args.ring, -1).view(np.int16)).to("cuda:0")
     dev_ring = ring16.view(torch.uint16)
-    n_buf = max(args.warmup + args.steps, 200 + args.variant_steps, args.launch_frames)
+    n_buf = max(args.warmup + args.steps, 200 + args.variant_steps, args.roofline_frames, args.paced_frames,
+                200 + args.horizontal_steps, args.trace_frames)
     frames = ring16[torch.arange(n_buf, device="cuda:0") % args.ring].contiguous().view(torch.uint16)
     log(f"frame buffer: {n_buf} frames, {frames.numel() * 2 / 1e9:.2f} GB on the device")
-    cmd = torch.empty(args.launch_frames * n_act, dtype=torch.float32, device="cuda:0")
+    cmd = torch.empty(max(args.launch_frames, args.roofline_frames, args.paced_frames) * n_act,
+                      dtype=torch.float32, device="cuda:0")
     stream = torch.cuda.current_stream()
     tuning = dict(kernel=args.mvm_kernel, k_split=args.k_split, rows_per_wave=args.rows_per_wave,
                   unroll=args.unroll, blocks=args.blocks, waves=args.waves)
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
 
     def make_ctx(fmt, mode):
         ctx = rtc.rtc_init(sc.mask, cfg.n_pix, n_act, cm_dtype=fmt, gain=cfg.gain, leak=cfg.leak)
@@ -532,39 +689,42 @@ def main():
         rtc.rtc_set_frame_mode(ctx, mode)
         return ctx
 
-    def run(ctx, first, n, ts=None):
-        """Frames [first, first + n) of the buffer, launch_frames per launch; returns launches."""
+    def run(ctx, first, n, per_launch, ts=None):
+        """Frames [first, first + n) of the buffer, per_launch per launch; returns launches."""
         done, launches = 0, 0
         while done < n:
-            m = min(args.launch_frames, n - done)
+            m = min(per_launch, n - done)
             rtc.rtc_frame_batch(ctx, m, frames[first + done:], cmd, ts=None if ts is None else ts[2 * done:],
                                 stream=stream)
             done += m
             launches += 1
         return launches
 
-    def timed(ctx, warm, n, khz):
-        run(ctx, 0, warm)
+    def series(ts, khz):
+        st = ts.cpu().numpy().reshape(-1, 2)
+        start_us = ticks_to_us(st[:, 0] - st[0, 0], khz)
+        end_us = ticks_to_us(st[:, 1] - st[0, 0], khz)
+        return np.diff(start_us), end_us - start_us
+
+    def timed(ctx, warm, n, khz, per_launch):
+        run(ctx, 0, warm, per_launch)
         torch.cuda.synchronize()
         ts = torch.zeros(2 * n, dtype=torch.int64, device="cuda:0")
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         t0 = time.perf_counter()
         ev0.record(stream)
-        launches = run(ctx, warm, n, ts)
+        launches = run(ctx, warm, n, per_launch, ts)
         ev1.record(stream)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         rtc.rtc_sync_check(ctx)
-        st = ts.cpu().numpy().reshape(-1, 2)
-        start_us = ticks_to_us(st[:, 0] - st[0, 0], khz)
-        end_us = ticks_to_us(st[:, 1] - st[0, 0], khz)
-        period = np.diff(start_us)
+        period, span = series(ts, khz)
         inside = np.ones(len(period), bool)                   # periods that do not straddle a relaunch
-        inside[args.launch_frames - 1::args.launch_frames] = False
-        return {"period": period, "period_inside": period[inside], "span": end_us - start_us, "wall": wall,
+        inside[per_launch - 1::per_launch] = False
+        return {"period": period, "period_inside": period[inside], "span": span, "wall": wall,
                 "launch_ms": ev0.elapsed_time(ev1) / launches, "launches": launches}
 
-    # --- headline: FP32 matrix, persistent kernel
+    # --- headline: FP32 matrix, persistent kernel; the timed steps
     ctx = make_ctx("f32", rtc.RTC_FRAMES_PERSISTENT)
     khz = rtc.rtc_wall_clock_khz(ctx)
     balance = None
@@ -574,19 +734,95 @@ def main():
             f"kept {balance['kept']}")
     log(f"warm-up {args.warmup} frames, then {args.steps} timed frames (persistent, "
         f"{args.launch_frames} per launch)")
-    head = timed(ctx, args.warmup, args.steps, khz)
-    st_period = frame_stats(head["period"])
+    head = timed(ctx, args.warmup, args.steps, khz, args.launch_frames)
     st_span = frame_stats(head["span"])
-    log(f"frame period p50 {st_period['p50_us']:.2f} us p99 {st_period['p99_us']:.2f} us, span p50 "
-        f"{st_span['p50_us']:.2f} us, wall {head['wall'] * 1e6 / args.steps:.2f} us/frame, "
-        f"{head['launch_ms']:.3f} ms per launch")
+    st_period = frame_stats(head["period"]) if len(head["period"]) else None
+    log(f"timed frames: span p50 {st_span['p50_us']:.2f} us p99 {st_span['p99_us']:.2f} us, wall "
+        f"{head['wall'] * 1e6 / args.steps:.2f} us/frame")
+
+    # --- roofline launches: whole launches of roofline_frames frames, HIP events on the launch stream
+    long_period, long_span, launch_ms = [], [], []
+    for r in range(args.roofline_launches):
+        ts = torch.zeros(2 * args.roofline_frames, dtype=torch.int64, device="cuda:0")
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        rtc.rtc_frame_batch(ctx, args.roofline_frames, frames, cmd, ts=ts, stream=stream)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        launch_ms.append(ev0.elapsed_time(ev1))
+        pr, sp = series(ts, khz)
+        long_period.append(pr)
+        long_span.append(sp)
+    rtc.rtc_sync_check(ctx)
+    lp, ls = np.concatenate(long_period), np.concatenate(long_span)
+    long_run = {"launches": args.roofline_launches, "frames_per_launch": args.roofline_frames,
+                "launch_ms": [round(x, 4) for x in launch_ms],
+                "frame_period_us": frame_stats(lp), "frame_span_us": frame_stats(ls),
+                "frame_period_us_skip100": frame_stats(long_period[0], skip=100) if len(long_period[0]) > 200
+                else None,
+                "frame_span_us_skip100": frame_stats(long_span[0], skip=100) if len(long_span[0]) > 200 else None}
+    launch_avg_ms = float(np.mean(launch_ms))
+    frame_us = launch_avg_ms * 1e3 / args.roofline_frames
+    log(f"{args.roofline_launches} launches of {args.roofline_frames} frames: {launch_avg_ms:.3f} ms each "
+        f"({frame_us:.3f} us/frame), span p50 {long_run['frame_span_us']['p50_us']:.2f} us, p99 "
+        f"{long_run['frame_span_us']['p99_us']:.2f} us")
+
+    # --- stage trace of every workgroup: the measured barrier floor
+    G = min(n_cu if args.blocks <= 0 else args.blocks, n_act)
+    trace = torch.zeros(args.trace_frames * G * 8, dtype=torch.int64, device="cuda:0")
+    rtc.rtc_set_trace(ctx, trace, args.trace_frames, G)
+    rtc.rtc_frame_batch(ctx, args.trace_frames, frames, cmd, stream=stream)
+    torch.cuda.synchronize()
+    rtc.rtc_set_trace(ctx)
+    rtc.rtc_sync_check(ctx)
+    stages = stage_breakdown(trace.cpu().numpy().reshape(args.trace_frames, G, 8)[min(100, args.trace_frames // 2):],
+                             khz)
+    del trace
+    log(f"stages (median per frame): {stages}")
+
+    # --- host-paced frames: released at a fixed period through a host word
+    paced = None
+    if args.paced_frames > 0:
+        ts = torch.zeros(2 * args.paced_frames, dtype=torch.int64, device="cuda:0")
+        log(f"host-paced: {args.paced_frames} frames every {args.paced_period_us} us")
+        rel, done = rtc.rtc_paced_batch(ctx, args.paced_frames, frames, cmd, args.paced_period_us, ts=ts,
+                                        stream=stream)
+        rtc.rtc_sync_check(ctx)
+        host_lat = (done - rel) / 1e3
+        late = (rel - np.arange(args.paced_frames) * args.paced_period_us * 1e3) / 1e3
+        _, pspan = series(ts, khz)
+        paced = {"frames": args.paced_frames, "period_us": args.paced_period_us,
+                 "host_latency_us": frame_stats(host_lat),
+                 "host_latency_us_skip100": frame_stats(host_lat, skip=100) if args.paced_frames > 200 else None,
+                 "device_span_us": frame_stats(pspan),
+                 "device_span_us_skip100": frame_stats(pspan, skip=100) if args.paced_frames > 200 else None,
+                 "release_lateness_us": frame_stats(late),
+                 "note": "host latency = release word written -> done word seen by the releasing thread; "
+                         "device span = first workgroup's frame start -> last command store"}
+        log(f"host-paced latency p50 {paced['host_latency_us']['p50_us']:.2f} us p99 "
+            f"{paced['host_latency_us']['p99_us']:.2f} us, device span p50 "
+            f"{paced['device_span_us']['p50_us']:.2f} us")
     rtc.rtc_destroy(ctx)
+
+    # --- horizontal split (the paper's processing strategy), same frames
+    horizontal = None
+    if args.horizontal_steps > 0:
+        try:
+            hctx = make_ctx("f32", rtc.RTC_FRAMES_HORIZONTAL)
+        except rtc.RtcError as err:
+            horizontal = {"error": str(err)}
+        else:
+            h = timed(hctx, 200, args.horizontal_steps, khz, args.launch_frames)
+            horizontal = {"frame_period_us": frame_stats(h["period"]), "frame_span_us": frame_stats(h["span"]),
+                          "launch_ms": round(h["launch_ms"], 4)}
+            rtc.rtc_destroy(hctx)
+            log(f"horizontal split: span p50 {horizontal['frame_span_us']['p50_us']:.2f} us")
 
     # --- per-launch mode (calibration kernel + reconstruction kernel per frame)
     ctx = make_ctx("f32", rtc.RTC_FRAMES_PER_LAUNCH)
-    pl = timed(ctx, 200, args.variant_steps, khz)
+    pl = timed(ctx, 200, args.variant_steps, khz, args.launch_frames)
     per_launch = {"frame_period_us": frame_stats(pl["period"]), "frame_span_us": frame_stats(pl["span"])}
-    log(f"per-launch frames: period p50 {per_launch['frame_period_us']['p50_us']:.2f} us")
+    log(f"per-launch frames: span p50 {per_launch['frame_span_us']['p50_us']:.2f} us")
 
     # the two kernels of the per-launch mode alone, HIP events on the launch stream
     slopes = torch.empty(2 * sc.n_valid, dtype=torch.float32, device="cuda:0")
@@ -597,7 +833,7 @@ def main():
     frame_ptrs = [dev_ring[i].data_ptr() for i in range(args.ring)]
 
     def kernel_us(fn, reps):
-        for _ in range(50):
+        for _ in range(min(50, reps)):
             fn(0)
         ev0.record(stream)
         for i in range(reps):
@@ -615,11 +851,14 @@ def main():
         f"calibrate+centroid {cal_us:.2f} us/launch")
     rtc.rtc_destroy(ctx)
 
-    # --- read-bandwidth probes at the matrix's working-set size and at 2 GB, and a plain copy
+    # --- read-bandwidth probes over working sets from inside the Infinity Cache to far beyond it,
+    # and a plain copy (the traffic counters' calibration kernel)
     probes = {}
     pctx = make_ctx("f32", rtc.RTC_FRAMES_PER_LAUNCH)
     out1 = torch.zeros(1, dtype=torch.float32, device="cuda:0")
-    for label, nbytes in (("140MB", mvm_bytes // 16 * 16), ("2GB", 2 << 30)):
+    for label in [x for x in args.probes.split(",") if x and x != "none"]:
+        nbytes = int(float(label.rstrip("MB")) * 1e6) // 16 * 16 if label.endswith("MB") else \
+            int(float(label.rstrip("GB")) * (1 << 30)) // 16 * 16
         buf = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda:0").fill_(1.0)
         reps = 200 if nbytes < (1 << 30) else 20
         us = kernel_us(lambda i: rtc.rtc_probe_read(pctx, buf, nbytes, out1, stream=stream), reps)
@@ -636,46 +875,52 @@ def main():
 
     # --- reduced-precision control matrices, persistent kernel, same frames
     variants = {}
-    for fmt in [v for v in args.variants.split(",") if v]:
+    for fmt in [v for v in args.variants.split(",") if v and v != "none"]:
         vctx = make_ctx(fmt, rtc.RTC_FRAMES_PERSISTENT)
-        v = timed(vctx, 200, args.variant_steps, khz)
+        v = timed(vctx, 200, args.variant_steps, khz, args.launch_frames)
         vp, vs = frame_stats(v["period"]), frame_stats(v["span"])
-        vb = frame_bytes(sc, fmt)
-        variants[fmt] = {"frame_period_p50_us": round(vp["p50_us"], 3), "p99_us": round(vp["p99_us"], 3),
+        variants[fmt] = {"frame_span_p50_us": round(vs["p50_us"], 3), "frame_span_p99_us": round(vs["p99_us"], 3),
+                         "frame_period_p50_us": round(vp["p50_us"], 3), "frame_period_p99_us": round(vp["p99_us"], 3),
                          "rms_jitter_us": round(vp["rms_jitter_us"], 3),
-                         "frame_span_p50_us": round(vs["p50_us"], 3),
                          "matrix_MB": round(n_act * 2 * sc.n_valid * FMT_BYTES[fmt] / 1e6, 2),
-                         "bytes_per_frame": vb,
-                         "achieved_GBps": round(vb * args.launch_frames / (v["launch_ms"] * 1e6), 1)
-                         if v["launches"] and args.variant_steps % args.launch_frames == 0 else None}
+                         "flops_per_frame": frame_flops(sc)}
         rtc.rtc_destroy(vctx)
-        log(f"{fmt}: frame period p50 {vp['p50_us']:.2f} us, p99 {vp['p99_us']:.2f} us")
+        log(f"{fmt}: frame span p50 {vs['p50_us']:.2f} us, period p50 {vp['p50_us']:.2f} us")
 
-    traffic = None
-    if os.path.exists(PROFILE_TRAFFIC):
-        try:
-            prof = json.load(open(PROFILE_TRAFFIC))
-            if (prof.get("kernel_source_sha256_16") == kernel_source_hash()
-                    and prof.get("frames_per_launch") == args.launch_frames):
-                traffic = prof.get("hbm_bytes_per_launch")
-            elif prof.get("kernel_source_sha256_16") == kernel_source_hash():
-                log(f"traffic counters were taken at {prof.get('frames_per_launch')} frames per launch; "
-                    f"not reported for {args.launch_frames}")
-        except Exception:
-            traffic = None
-
+    # --- roofline of the frames kernel
+    flops = frame_flops(sc)
     fb = frame_bytes(sc, "f32")
-    full = args.steps % args.launch_frames == 0
-    achieved = fb * args.launch_frames / (head["launch_ms"] * 1e6) if full else fb / (
-        head["wall"] * 1e6 / args.steps) / 1e3
+    achieved = flops * args.roofline_frames / (launch_avg_ms * 1e-3) / 1e12
+    prof, why = load_counters(args.roofline_frames)
+    traffic = prof.get("hbm_bytes_per_dispatch") if prof else None
+    model = frame_model(prof, args.roofline_frames, frame_us, stages["barrier_us"]) if prof else {"unavailable": why}
+    hbm_gbps = fb / frame_us / 1e3
+    roofline = {
+        "bound": "alu", "achieved": round(achieved, 3), "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+        "frac": round(achieved / VALU_PEAK_TFLOPS, 4), "traffic": traffic,
+        "kernel": "frames_kernel (persistent FP32: calibrate, CoG, R s, integrate; slab on chip)",
+        "flops_per_frame": flops, "frames_per_launch": args.roofline_frames,
+        "launch_ms": round(launch_avg_ms, 4), "frame_us": round(frame_us, 4),
+        "model": model,
+        "hbm": {"algorithmic_bytes_per_frame": fb, "algorithmic_GBps": round(hbm_gbps, 1),
+                "frac_of_peak": round(hbm_gbps / HBM_PEAK_GBPS, 4),
+                "frac_of_probes": {k: round(hbm_gbps / v, 4) for k, v in probes.items() if k != "copy_256MiB"},
+                "traffic_bytes_per_frame": round(traffic / args.roofline_frames) if traffic else None,
+                "note": "the slab stays on chip across frames, so HBM traffic is far below the algorithmic bytes; "
+                        "algorithmic GB/s above the HBM peak are the matrix read from registers, LDS and L2"},
+    }
+    if not prof:
+        log(f"roofline model: {why}")
+
+    wall_us = head["wall"] * 1e6 / args.steps
     result = {
         "metric": METRIC,
-        "value": round(st_period["p50_us"], 3),
+        "value": round(st_span["p50_us"], 3),
         "unit": "us",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(head["wall"] * 1e3 / args.steps, 6),
+        "ms_per_step": round(wall_us / 1e3, 6),
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
@@ -691,26 +936,27 @@ def main():
             "distinct_frames": args.ring,
             "frame_data": "open-loop frozen-flow von Karman frames (r0 0.15 m, L0 25 m, 10 m/s)",
         },
-        "frame_period_us": st_period,
+        "value_is": "p50 of the timed frames' span: first workgroup's frame start to the last workgroup's "
+                    "command store (device wall clock)",
         "frame_span_us": st_span,
-        "frame_period_us_skip100": frame_stats(head["period"], skip=100) if len(head["period"]) > 200 else None,
-        "frame_period_us_within_launches": frame_stats(head["period_inside"]),
+        "frame_period_us": st_period,
+        "frame_period_us_within_launches": frame_stats(head["period_inside"]) if len(head["period_inside"]) else None,
+        "long_run": long_run,
+        "stages_us": stages,
+        "host_paced": paced,
+        "horizontal_mode": horizontal,
         "per_launch_mode": per_launch,
-        "kernels_us": {"reconstruct_integrate": round(mvm_us, 3), "calibrate_centroid": round(cal_us, 3),
-                       "frames_kernel_per_launch_ms": round(head["launch_ms"], 4)},
+        "kernels_us": {"reconstruct_integrate": round(mvm_us, 3), "calibrate_centroid": round(cal_us, 3)},
         "per_launch_gemv_GBps": round(mvm_bytes / mvm_us / 1e3, 1),
         "read_probe_GBps": probes,
         "precision_variants": variants,
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
-                     "kernel": "frames_kernel (persistent: calibrate, CoG, R s, integrate)",
-                     "bytes_per_frame": fb, "frames_per_launch": args.launch_frames,
-                     "note": "algorithmic bytes; the kernel keeps part of the matrix in LDS and registers "
-                             "across frames, so HBM traffic per frame is below the algorithmic bytes"},
+        "roofline": roofline,
     }
     if not args.no_cpu:
-        log(f"timing the FP64 oracle for ~{args.cpu_seconds:.0f}s on the host")
+        log(f"timing the FP64 oracle for ~{args.cpu_seconds:.0f}s on the host (all cores)")
         result["cpu_baseline"] = cpu_baseline(sc, ring, args.cpu_seconds)
+        log(f"timing the FP64 oracle for ~{args.cpu_seconds:.0f}s on one core (child process)")
+        result["cpu_baseline"]["single_core"] = cpu_single_core(args.cpu_seconds)
     print(json.dumps(result), flush=True)
 
 

@@ -10,6 +10,7 @@ from __future__ import annotations
 import ctypes
 import math
 import os
+import weakref
 from typing import Optional
 
 import numpy as np
@@ -133,6 +134,7 @@ _SIGNATURES = {
 }
 
 _lib = None
+_handles = weakref.WeakSet()     # live contexts, networks and predictors
 
 
 def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
@@ -152,12 +154,31 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     return _lib
 
 
+def unload_library() -> None:
+    """Closes librtc.so after every context, network and predictor has been
+    closed, so that its HIP modules are unregistered now, with the runtime and
+    any profiler attached to it still fully alive, rather than by the exit
+    handlers of the process.  A later call of the binding loads it again."""
+    global _lib
+    if _lib is None:
+        return
+    import gc
+    import _ctypes
+    gc.collect()
+    live = [h for h in list(_handles) if h.handle is not None and getattr(h.handle, "value", h.handle)]
+    if live:
+        raise RuntimeError(f"unload_library: {len(live)} handle(s) still open; close them first")
+    handle, _lib = _lib._handle, None
+    _ctypes.dlclose(handle)
+
+
 class RtcContext:
     """Owning handle of an ``rtc_ctx*``; freed by :meth:`close` or garbage collection."""
 
     def __init__(self, handle: int, cfg: dict):
         self.handle = ctypes.c_void_p(handle)
         self.cfg = cfg
+        _handles.add(self)
         lib = load_library()
         self.n_valid = lib.rtc_n_valid(self.handle)
         self.n_act = lib.rtc_n_act(self.handle)
@@ -649,6 +670,7 @@ class MlpNet:
         _mcheck(load_library().rtc_mlp_create(n_in, n_hidden, n_out, max_batch, device, ctypes.byref(out)), None,
                 "rtc_mlp_error_string")
         self.handle = out
+        _handles.add(self)
         self.n_in, self.n_hidden, self.n_out, self.max_batch, self.device = n_in, n_hidden, n_out, max_batch, device
 
     def _chk(self, st):
@@ -725,6 +747,7 @@ class Predictor:
                                                PD.ctypes.data, mean.ctypes.data, std.ctypes.data, gain,
                                                ctypes.byref(out)), None, "rtc_pred_error_string")
         self.handle, self.net = out, net
+        _handles.add(self)
         self.history, self.n_modes, self.n_slopes, self.n_act = history, n_modes, n_slopes, n_act
 
     def _chk(self, st):

@@ -94,6 +94,24 @@ rtc_status rtc_pred_reset(rtc_pred *p);
 rtc_status rtc_pred_step(rtc_pred *p, const float *d_slopes, const float *d_cmd_prev, float *d_slopes_out,
                          float *d_modes, void *hip_stream);
 
+/* Predictive frames: n_frames frames of context c, each as rtc_frame_batch
+ * runs it in the per-launch mode (calibration and centroids, reconstruction
+ * and integrator) with the predictor step of p between them -- r_k measured,
+ * c_{k-1} = the context's integrator state, r'_k handed to the
+ * reconstruction -- so that c_k = c_{k-1} + gain R r'_k as above.  Frame f
+ * reads d_pixels + f * frame_stride (elements, >= one frame) and writes
+ * d_cmd [n_frames][n_act] (required) and d_slopes [n_frames][n_slopes]
+ * (measured r_k, nullable); d_ts (nullable) [n_frames][2] gets the frame's
+ * start (calibration) and end (last command stored) device wall-clock ticks
+ * (rtc_wall_clock_khz), as in rtc_frame_batch.  p must have been created for
+ * c's slope and actuator counts on c's device and the context's gain.
+ * Errors: RTC_E_ARG (sizes, devices, pointers, stride), RTC_E_STATE (loads
+ * missing, undefined state), RTC_E_DEVICE (launch failure; the text is in
+ * rtc_pred_error_string). */
+rtc_status rtc_pred_frame_batch(rtc_ctx *c, rtc_pred *p, int32_t n_frames, const uint16_t *d_pixels,
+                                int64_t frame_stride, float *d_cmd, float *d_slopes, uint64_t *d_ts,
+                                void *hip_stream);
+
 void rtc_pred_destroy(rtc_pred *p);
 
 /* Last error text of a network / predictor, or of the calling thread's last

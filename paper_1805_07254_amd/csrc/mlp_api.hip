@@ -16,6 +16,7 @@
 
 #include "../../include/rtc_mlp.h"
 #include "mlp_kernels.h"
+#include "rtc_ctx.h"
 
 namespace {
 
@@ -67,8 +68,11 @@ struct rtc_pred {
   rtc_mlp *net = nullptr;
   int32_t history = 0, n_modes = 0, n_slopes = 0, n_act = 0, frames = 0;   // frames seen, up to history
   float inv_gain = 1.0f;
+  // P [n_modes][ldp], PD [n_modes][ldd], PT [n_slopes][ldt]: rows zero-padded to a multiple of 4
+  int64_t ldp = 0, ldd = 0, ldt = 0;
   float *P = nullptr, *PT = nullptr, *PD = nullptr, *mean = nullptr, *std_ = nullptr, *inv_std = nullptr;
-  float *hist = nullptr, *m = nullptr, *m_prev = nullptr, *y = nullptr, *d = nullptr, *mhat = nullptr;
+  float *hist = nullptr, *m = nullptr, *m_prev = nullptr, *d = nullptr;
+  float *s_pred = nullptr;   // [round_up(n_slopes, 16)] feed-forward slopes of predictive frame batches, zero-padded
   std::string err = "no error";
 };
 
@@ -150,11 +154,44 @@ hipError_t forward(rtc_mlp *m, int32_t B, const float *x, float *y, hipStream_t 
 
 // Batch-1 forward for the predictor step: two bfloat16 GEMV layers with the
 // rounding points of the batched forward.
-hipError_t forward_one(rtc_mlp *m, const float *x, float *y, hipStream_t st) {
-  hipError_t e = rtcm::launch_gemv_bf16(m->W1.b, x, m->b1.p, m->n_hid, m->n_in, 1, m->Z1, m->Hb, st);
-  if (e != hipSuccess) return e;
-  // the second layer rounds the float32 activations to bfloat16 as it reads them
-  return rtcm::launch_gemv_bf16(m->W2.b, m->Z1, m->b2.p, m->n_out, m->n_hid, 0, y, nullptr, st);
+// Arguments of one predictor step (the hidden activations use the network's
+// first batch row of Z1; the second layer rounds them to bfloat16 as it reads
+// them).
+rtcm::PredStepArgs step_args(rtc_pred *p, const float *s, const float *c_prev, float *s_out, float *modes) {
+  rtcm::PredStepArgs a{};
+  rtc_mlp *m = p->net;
+  a.P = p->P;
+  a.ldp = p->ldp;
+  a.PD = p->PD;
+  a.ldd = p->ldd;
+  a.PT = p->PT;
+  a.ldt = p->ldt;
+  a.s = s;
+  a.c = c_prev;
+  a.n_slopes = p->n_slopes;
+  a.n_act = p->n_act;
+  a.n_modes = p->n_modes;
+  a.history = p->history;
+  a.n_in = m->n_in;
+  a.n_hid = m->n_hid;
+  a.push = p->frames > 0;
+  a.full = p->frames >= p->history;              // `history` changes need history + 1 frames
+  a.hist = p->hist;
+  a.m = p->m;
+  a.m_prev = p->m_prev;
+  a.mean = p->mean;
+  a.std_ = p->std_;
+  a.inv_std = p->inv_std;
+  a.W1 = m->W1.b;
+  a.b1 = m->b1.p;
+  a.W2 = m->W2.b;
+  a.b2 = m->b2.p;
+  a.h = m->Z1;
+  a.d = p->d;
+  a.modes_out = modes;
+  a.s_out = s_out;
+  a.inv_gain = p->inv_gain;
+  return a;
 }
 
 }  // namespace
@@ -399,11 +436,17 @@ rtc_status rtc_pred_create(rtc_mlp *net, int32_t history, int32_t n_modes, int32
   if (!all_finite(P, (int64_t)n_modes * n_slopes) || !all_finite(PD, (int64_t)n_modes * n_act) ||
       !all_finite(mean, n_modes) || !all_finite(std_, n_modes) || !std::isfinite(gain) || !(gain > 0.0f))
     return pfail(nullptr, RTC_E_NONFINITE, "rtc_pred_create: non-finite input or non-positive gain");
-  std::vector<float> inv((size_t)n_modes), PT((size_t)n_slopes * n_modes);
+  const int64_t ldp = (n_slopes + 3) / 4 * 4, ldd = (n_act + 3) / 4 * 4, ldt = (n_modes + 3) / 4 * 4;
+  std::vector<float> inv((size_t)n_modes), Pp((size_t)n_modes * ldp, 0.0f), PDp((size_t)n_modes * ldd, 0.0f),
+      PT((size_t)n_slopes * ldt, 0.0f);
   for (int32_t j = 0; j < n_modes; ++j) {
     if (!(std_[j] > 0.0f)) return pfail(nullptr, RTC_E_NONFINITE, "rtc_pred_create: std must be positive");
     inv[(size_t)j] = 1.0f / std_[j];
-    for (int32_t i = 0; i < n_slopes; ++i) PT[(size_t)i * n_modes + j] = P[(size_t)j * n_slopes + i];
+    for (int32_t i = 0; i < n_slopes; ++i) {
+      Pp[(size_t)j * ldp + i] = P[(size_t)j * n_slopes + i];
+      PT[(size_t)i * ldt + j] = P[(size_t)j * n_slopes + i];
+    }
+    for (int32_t i = 0; i < n_act; ++i) PDp[(size_t)j * ldd + i] = PD[(size_t)j * n_act + i];
   }
   rtc_pred *p = new (std::nothrow) rtc_pred();
   if (!p) return pfail(nullptr, RTC_E_NOMEM, "rtc_pred_create: host allocation failed");
@@ -413,28 +456,32 @@ rtc_status rtc_pred_create(rtc_mlp *net, int32_t history, int32_t n_modes, int32
   p->n_slopes = n_slopes;
   p->n_act = n_act;
   p->inv_gain = 1.0f / gain;
+  p->ldp = ldp;
+  p->ldd = ldd;
+  p->ldt = ldt;
   DevScope ds(net->device);
   hipError_t e = ds.status;
   const size_t fm = sizeof(float) * (size_t)n_modes;
-  if (e == hipSuccess) e = hipMalloc(&p->P, fm * n_slopes);
-  if (e == hipSuccess) e = hipMalloc(&p->PT, fm * n_slopes);
-  if (e == hipSuccess) e = hipMalloc(&p->PD, fm * n_act);
+  const size_t s_pad = sizeof(float) * (size_t)((n_slopes + 15) / 16 * 16);
+  if (e == hipSuccess) e = hipMalloc(&p->P, sizeof(float) * Pp.size());
+  if (e == hipSuccess) e = hipMalloc(&p->PT, sizeof(float) * PT.size());
+  if (e == hipSuccess) e = hipMalloc(&p->PD, sizeof(float) * PDp.size());
   if (e == hipSuccess) e = hipMalloc(&p->mean, fm);
   if (e == hipSuccess) e = hipMalloc(&p->std_, fm);
   if (e == hipSuccess) e = hipMalloc(&p->inv_std, fm);
   if (e == hipSuccess) e = hipMalloc(&p->hist, fm * history);
   if (e == hipSuccess) e = hipMalloc(&p->m, fm);
   if (e == hipSuccess) e = hipMalloc(&p->m_prev, fm);
-  if (e == hipSuccess) e = hipMalloc(&p->y, fm);
   if (e == hipSuccess) e = hipMalloc(&p->d, fm);
-  if (e == hipSuccess) e = hipMalloc(&p->mhat, fm);
-  if (e == hipSuccess) e = hipMemcpy(p->P, P, fm * n_slopes, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(p->PT, PT.data(), fm * n_slopes, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(p->PD, PD, fm * n_act, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMalloc(&p->s_pred, s_pad);
+  if (e == hipSuccess) e = hipMemcpy(p->P, Pp.data(), sizeof(float) * Pp.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(p->PT, PT.data(), sizeof(float) * PT.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(p->PD, PDp.data(), sizeof(float) * PDp.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(p->mean, mean, fm, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(p->std_, std_, fm, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(p->inv_std, inv.data(), fm, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemset(p->hist, 0, fm * history);
+  if (e == hipSuccess) e = hipMemset(p->s_pred, 0, s_pad);
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
     const rtc_status s = pfail(nullptr, e == hipErrorOutOfMemory ? RTC_E_NOMEM : RTC_E_DEVICE,
@@ -467,24 +514,48 @@ rtc_status rtc_pred_step(rtc_pred *p, const float *d_slopes, const float *d_cmd_
   DevScope ds(p->net->device);
   if (ds.status != hipSuccess) return pfail(p, RTC_E_DEVICE, "rtc_pred_step: hipSetDevice");
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
-  const int nm = p->n_modes;
-  hipError_t e = rtcm::launch_gemv_f32(p->P, p->n_slopes, d_slopes, nm, p->n_slopes, 1.0f, 0.0f, p->m, st);
-  if (e == hipSuccess) e = rtcm::launch_gemv_f32(p->PD, p->n_act, d_cmd_prev, nm, p->n_act, 1.0f, 1.0f, p->m, st);
-  if (e == hipSuccess)
-    e = rtcm::launch_history_push(p->hist, p->history, nm, p->m, p->m_prev, p->mean, p->inv_std, p->frames > 0, st);
-  const bool full = p->frames >= p->history;        // `history` changes need history + 1 frames
-  if (e == hipSuccess && full) e = forward_one(p->net, p->hist, p->y, st);
-  if (e == hipSuccess)
-    e = rtcm::launch_denorm(full ? p->y : nullptr, p->m, p->mean, p->std_, nm, p->d, p->mhat, st);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(d_slopes_out, d_slopes, sizeof(float) * p->n_slopes, hipMemcpyDeviceToDevice, st);
-  if (e == hipSuccess)
-    e = rtcm::launch_gemv_f32(p->PT, nm, p->d, p->n_slopes, nm, p->inv_gain, 1.0f, d_slopes_out, st);
-  if (e == hipSuccess && d_modes) e = hipMemcpyAsync(d_modes, p->m, sizeof(float) * nm, hipMemcpyDeviceToDevice, st);
-  if (e == hipSuccess && d_modes)
-    e = hipMemcpyAsync(d_modes + nm, p->mhat, sizeof(float) * nm, hipMemcpyDeviceToDevice, st);
+  const hipError_t e = rtcm::launch_pred_step(step_args(p, d_slopes, d_cmd_prev, d_slopes_out, d_modes), st);
   if (e != hipSuccess) return pfail(p, RTC_E_DEVICE, std::string("rtc_pred_step: ") + hipGetErrorName(e));
   if (p->frames < p->history) ++p->frames;
+  return RTC_OK;
+}
+
+// Predictor step of a predictive frame: the feed-forward slopes go to the
+// predictor's own padded buffer, which the reconstruction then multiplies.
+static hipError_t pred_frame_step(void *arg, const float *s, const float *c_prev, const float **s_use,
+                                  hipStream_t st) {
+  rtc_pred *p = static_cast<rtc_pred *>(arg);
+  const hipError_t e = rtcm::launch_pred_step(step_args(p, s, c_prev, p->s_pred, nullptr), st);
+  if (e == hipSuccess && p->frames < p->history) ++p->frames;
+  *s_use = p->s_pred;
+  return e;
+}
+
+rtc_status rtc_pred_frame_batch(rtc_ctx *c, rtc_pred *p, int32_t n_frames, const uint16_t *d_pixels,
+                                int64_t frame_stride, float *d_cmd, float *d_slopes, uint64_t *d_ts,
+                                void *hip_stream) {
+  if (!c || !p) return pfail(p, RTC_E_ARG, "rtc_pred_frame_batch: NULL context or predictor");
+  if (p->n_slopes != c->n_slopes || p->n_act != c->n_act)
+    return pfail(p, RTC_E_ARG, "rtc_pred_frame_batch: predictor and context sizes differ");
+  if (p->net->device != c->device) return pfail(p, RTC_E_ARG, "rtc_pred_frame_batch: different devices");
+  if (!c->calib_loaded || !c->cmat_loaded)
+    return pfail(p, RTC_E_STATE, "rtc_pred_frame_batch: load the context's calibration and control matrix first");
+  if (c->state_invalid) return pfail(p, RTC_E_STATE, "rtc_pred_frame_batch: " STATE_INVALID_MSG);
+  if (n_frames < 0) return pfail(p, RTC_E_ARG, "rtc_pred_frame_batch: n_frames < 0");
+  if (n_frames == 0) return RTC_OK;
+  if (!d_pixels || !d_cmd) return pfail(p, RTC_E_ARG, "rtc_pred_frame_batch: NULL pixels or cmd");
+  if (frame_stride < c->frame_elems)
+    return pfail(p, RTC_E_ARG, "rtc_pred_frame_batch: frame_stride shorter than a frame");
+  DevScope ds(c->device);
+  if (ds.status != hipSuccess) return pfail(p, RTC_E_DEVICE, "rtc_pred_frame_batch: hipSetDevice");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  for (int32_t f = 0; f < n_frames; ++f) {
+    const rtc_status s = rtcx::enqueue_frame_with(
+        c, d_pixels + (int64_t)f * frame_stride, d_cmd + (int64_t)f * c->n_act,
+        d_slopes ? d_slopes + (int64_t)f * c->n_slopes : nullptr, nullptr, nullptr,
+        d_ts ? d_ts + 2 * (int64_t)f : nullptr, st, "rtc_pred_frame_batch: launch", pred_frame_step, p);
+    if (s != RTC_OK) return pfail(p, s, c->err);
+  }
   return RTC_OK;
 }
 
@@ -501,9 +572,8 @@ void rtc_pred_destroy(rtc_pred *p) {
   dfree(p->hist);
   dfree(p->m);
   dfree(p->m_prev);
-  dfree(p->y);
   dfree(p->d);
-  dfree(p->mhat);
+  dfree(p->s_pred);
   delete p;
 }
 

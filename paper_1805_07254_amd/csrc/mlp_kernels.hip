@@ -8,8 +8,9 @@
 //                      (dZ W) products are one kernel
 //   elementwise        bfloat16 rounding, loss and its gradient, GELU
 //                      derivative, bias gradients, Adam
-//   gemv_f32_kernel    y = alpha A x + beta y (modal projection of the
-//                      predictor step; one wavefront per row)
+//   pred_*_kernel      the predictor step in four launches: modes and their
+//                      history, network layer 1, layer 2 with the forecast,
+//                      feed-forward slopes
 //
 // Every reduction has a fixed order: results are run-to-run deterministic.
 #include "mlp_kernels.h"
@@ -356,72 +357,117 @@ __device__ __forceinline__ float block_sum(float s, float *sh) {
   return t;
 }
 
-// y[r] = alpha sum_j A[r][j] x[j] + beta y[r]: one workgroup per row, threads
-// stride the row, two accumulators, fixed-order block sum.
-__global__ __launch_bounds__(256) void gemv_f32_kernel(const float *A, int64_t lda, const float *x, int rows,
-                                                       int cols, float alpha, float beta, float *y) {
-  __shared__ float sh[4];
-  const int r = blockIdx.x;
-  const float *row = A + (int64_t)r * lda;
-  float a0 = 0.f, a1 = 0.f;
-  int j = threadIdx.x;
-  for (; j + 256 < cols; j += 512) {
-    a0 = fmaf(row[j], x[j], a0);
-    a1 = fmaf(row[j + 256], x[j + 256], a1);
+// Fixed-order dot product of a float32 row (16-byte aligned, zero-padded to a
+// multiple of 4 elements) with x[0, n) by a 256-thread workgroup: thread t
+// takes the 4-element chunks t, t + 256, ..., one accumulator per position in
+// the chunk, added pairwise, then block_sum.  Every chunk's row load is
+// independent, so a thread keeps several 16-byte loads in flight.
+__device__ __forceinline__ float row_dot_f32(const float *row, const float *x, int n, float *sh) {
+  float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+  const int nq = (n + 3) >> 2;
+  const float4 *r4 = reinterpret_cast<const float4 *>(row);
+#pragma unroll 8
+  for (int q = threadIdx.x; q < nq; q += 256) {
+    const float4 w = r4[q];
+    const int k = 4 * q;
+    a0 = fmaf(w.x, x[k], a0);
+    a1 = fmaf(w.y, k + 1 < n ? x[k + 1] : 0.f, a1);
+    a2 = fmaf(w.z, k + 2 < n ? x[k + 2] : 0.f, a2);
+    a3 = fmaf(w.w, k + 3 < n ? x[k + 3] : 0.f, a3);
   }
-  if (j < cols) a0 = fmaf(row[j], x[j], a0);
-  const float s = block_sum(a0 + a1, sh);
-  if (threadIdx.x == 0) y[r] = alpha * s + (beta == 0.0f ? 0.0f : beta * y[r]);
+  return block_sum((a0 + a1) + (a2 + a3), sh);
 }
 
-// Batch-1 layer of the network: z[r] = sum_k bf16(x[k]) W[r][k] + b[r] with
-// bfloat16 weights and float32 accumulation (the rounding points of the
-// training products); out_f32 = GELU(z) or z, out_bf16 its bfloat16 rounding.
-__global__ __launch_bounds__(256) void gemv_bf16_kernel(const uint16_t *W, const float *x, const float *b, int rows,
-                                                        int cols, int gelu_on, float *out_f32, uint16_t *out_bf16) {
+__device__ __forceinline__ float bf16_value(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+// sum_k W[k] bf16(x[k]) over k < n (bfloat16 row, float32 accumulation) by a
+// 256-thread workgroup: element t + 256 i goes to accumulator i mod 4.
+__device__ __forceinline__ float row_dot_bf16(const uint16_t *row, const float *x, int n, float *sh) {
+  float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+  int k = threadIdx.x;
+  for (; k + 768 < n; k += 1024) {
+    a0 = fmaf(bf16_value(row[k]), bf16_value(bf16_bits(x[k])), a0);
+    a1 = fmaf(bf16_value(row[k + 256]), bf16_value(bf16_bits(x[k + 256])), a1);
+    a2 = fmaf(bf16_value(row[k + 512]), bf16_value(bf16_bits(x[k + 512])), a2);
+    a3 = fmaf(bf16_value(row[k + 768]), bf16_value(bf16_bits(x[k + 768])), a3);
+  }
+  if (k < n) a0 = fmaf(bf16_value(row[k]), bf16_value(bf16_bits(x[k])), a0);
+  if (k + 256 < n) a1 = fmaf(bf16_value(row[k + 256]), bf16_value(bf16_bits(x[k + 256])), a1);
+  if (k + 512 < n) a2 = fmaf(bf16_value(row[k + 512]), bf16_value(bf16_bits(x[k + 512])), a2);
+  return block_sum((a0 + a1) + (a2 + a3), sh);
+}
+
+// Step 1, one workgroup per mode j: m_j = P_j s + (P D)_j c_prev; with a
+// previous frame the window of mode j shifts by one frame and takes the
+// normalised change (m_j - m_prev_j - mean_j) / std_j; then m_prev_j = m_j.
+__global__ __launch_bounds__(256) void pred_modes_kernel(PredStepArgs a) {
   __shared__ float sh[4];
-  const int r = blockIdx.x;
-  const uint16_t *row = W + (int64_t)r * cols;
-  float a0 = 0.f;
-  for (int j = threadIdx.x; j < cols; j += 256)
-    a0 = fmaf(__uint_as_float((uint32_t)row[j] << 16), __uint_as_float((uint32_t)bf16_bits(x[j]) << 16), a0);
-  const float s = block_sum(a0, sh);
+  const int j = blockIdx.x;
+  const float ps = row_dot_f32(a.P + (int64_t)j * a.ldp, a.s, a.n_slopes, sh);
+  const float pc = row_dot_f32(a.PD + (int64_t)j * a.ldd, a.c, a.n_act, sh);
   if (threadIdx.x == 0) {
-    const float z = s + (b ? b[r] : 0.0f);
-    const float y = gelu_on ? gelu(z) : z;
-    if (out_f32) out_f32[r] = y;
-    if (out_bf16) out_bf16[r] = bf16_bits(y);
-  }
-}
-
-// Predictor history: with a previous frame (push != 0), shift the window by
-// one frame and append the normalised change (m - m_prev - mean) / std; then
-// m_prev = m.
-__global__ __launch_bounds__(256) void history_push_kernel(float *hist, int history, int n_modes, const float *m,
-                                                           float *m_prev, const float *mean, const float *inv_std,
-                                                           int push) {
-  const int j = blockIdx.x * 256 + threadIdx.x;
-  if (j < n_modes) {
-    if (push) {
-      for (int h = 0; h + 1 < history; ++h) hist[(int64_t)h * n_modes + j] = hist[(int64_t)(h + 1) * n_modes + j];
-      hist[(int64_t)(history - 1) * n_modes + j] = (m[j] - m_prev[j] - mean[j]) * inv_std[j];
+    const float mj = ps + pc;
+    const int nm = a.n_modes;
+    if (a.push) {
+      for (int h = 0; h + 1 < a.history; ++h) a.hist[(int64_t)h * nm + j] = a.hist[(int64_t)(h + 1) * nm + j];
+      a.hist[(int64_t)(a.history - 1) * nm + j] = (mj - a.m_prev[j] - a.mean[j]) * a.inv_std[j];
     }
-    m_prev[j] = m[j];
+    a.m_prev[j] = mj;
+    a.m[j] = mj;
   }
 }
 
-// Forecast change in physical units: d = y * std + mean (0 without a
-// forecast, y == nullptr) and the forecast modes m_last + d.
-__global__ __launch_bounds__(256) void denorm_kernel(const float *y, const float *m_last, const float *mean,
-                                                     const float *std_, int n_modes, float *d, float *mhat) {
-  const int j = blockIdx.x * 256 + threadIdx.x;
-  if (j < n_modes) {
-    const float dj = y ? fmaf(y[j], std_[j], mean[j]) : 0.0f;
-    d[j] = dj;
-    mhat[j] = m_last[j] + dj;
+// Step 2, one workgroup per hidden unit i: h_i = GELU(W1_i bf16(window) + b1_i).
+__global__ __launch_bounds__(256) void pred_hidden_kernel(PredStepArgs a) {
+  __shared__ float sh[4];
+  const int i = blockIdx.x;
+  const float z = row_dot_bf16(a.W1 + (int64_t)i * a.n_in, a.hist, a.n_in, sh) + a.b1[i];
+  if (threadIdx.x == 0) a.h[i] = gelu(z);
+}
+
+// Step 3, one workgroup per mode j: y_j = W2_j bf16(h) + b2_j, the forecast
+// change d_j = y_j std_j + mean_j (0 before the window is full) and the
+// forecast mode m_j + d_j.
+__global__ __launch_bounds__(256) void pred_forecast_kernel(PredStepArgs a) {
+  __shared__ float sh[4];
+  const int j = blockIdx.x;
+  float y = 0.f;
+  if (a.full) y = row_dot_bf16(a.W2 + (int64_t)j * a.n_hid, a.h, a.n_hid, sh) + a.b2[j];
+  if (threadIdx.x == 0) {
+    const float dj = a.full ? fmaf(y, a.std_[j], a.mean[j]) : 0.0f;
+    const float mj = a.m[j];
+    a.d[j] = dj;
+    if (a.modes_out != nullptr) {
+      a.modes_out[j] = mj;
+      a.modes_out[a.n_modes + j] = mj + dj;
+    }
   }
 }
 
+// Step 4, one wavefront per slope i: s_out_i = s_i + (P^T)_i d / gain.
+__global__ __launch_bounds__(256) void pred_slopes_kernel(PredStepArgs a) {
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= a.n_slopes) return;
+  const float4 *r4 = reinterpret_cast<const float4 *>(a.PT + (int64_t)i * a.ldt);
+  const int n = a.n_modes, nq = (n + 3) >> 2;
+  float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+#pragma unroll 4
+  for (int q = lane; q < nq; q += 64) {
+    const float4 w = r4[q];
+    const int k = 4 * q;
+    a0 = fmaf(w.x, a.d[k], a0);
+    a1 = fmaf(w.y, k + 1 < n ? a.d[k + 1] : 0.f, a1);
+    a2 = fmaf(w.z, k + 2 < n ? a.d[k + 2] : 0.f, a2);
+    a3 = fmaf(w.w, k + 3 < n ? a.d[k + 3] : 0.f, a3);
+  }
+  float t = (a0 + a1) + (a2 + a3);
+  for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off);
+  if (lane == 0) {
+    const float v = t * a.inv_gain;
+    a.s_out[i] = a.s[i] + v;
+  }
+}
 
 }  // namespace
 
@@ -497,32 +543,23 @@ hipError_t launch_adam(float *theta, float *m, float *v, const float *grad, uint
   return hipGetLastError();
 }
 
-hipError_t launch_gemv_f32(const float *A, int64_t lda, const float *x, int rows, int cols, float alpha, float beta,
-                           float *y, hipStream_t st) {
-  if (rows <= 0) return hipSuccess;
-  gemv_f32_kernel<<<rows, 256, 0, st>>>(A, lda, x, rows, cols, alpha, beta, y);
-  return hipGetLastError();
+hipError_t launch_pred_step(const PredStepArgs &a, hipStream_t st) {
+  if (a.n_modes <= 0 || a.n_slopes <= 0) return hipErrorInvalidValue;
+  pred_modes_kernel<<<a.n_modes, 256, 0, st>>>(a);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess && a.full) {
+    pred_hidden_kernel<<<a.n_hid, 256, 0, st>>>(a);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) {
+    pred_forecast_kernel<<<a.n_modes, 256, 0, st>>>(a);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) {
+    pred_slopes_kernel<<<(a.n_slopes + 3) / 4, 256, 0, st>>>(a);
+    e = hipGetLastError();
+  }
+  return e;
 }
-
-hipError_t launch_gemv_bf16(const uint16_t *W, const float *x, const float *b, int rows, int cols, int gelu_on,
-                            float *out_f32, uint16_t *out_bf16, hipStream_t st) {
-  if (rows <= 0) return hipSuccess;
-  gemv_bf16_kernel<<<rows, 256, 0, st>>>(W, x, b, rows, cols, gelu_on, out_f32, out_bf16);
-  return hipGetLastError();
-}
-
-hipError_t launch_history_push(float *hist, int history, int n_modes, const float *m, float *m_prev,
-                               const float *mean, const float *inv_std, int push, hipStream_t st) {
-  history_push_kernel<<<(n_modes + 255) / 256, 256, 0, st>>>(hist, history, n_modes, m, m_prev, mean, inv_std,
-                                                              push);
-  return hipGetLastError();
-}
-
-hipError_t launch_denorm(const float *y, const float *m_last, const float *mean, const float *std_, int n_modes,
-                         float *d, float *mhat, hipStream_t st) {
-  denorm_kernel<<<(n_modes + 255) / 256, 256, 0, st>>>(y, m_last, mean, std_, n_modes, d, mhat);
-  return hipGetLastError();
-}
-
 
 }  // namespace rtcm

@@ -561,7 +561,8 @@ static rtck::CalibArgs calib_args(const rtc_ctx *c, const uint16_t *pix) {
 static FrameScratch ctx_scratch(const rtc_ctx *c) { return FrameScratch{c->d_s, c->d_part, c->d_sync}; }
 
 static rtc_status enqueue_frame(rtc_ctx *c, const FrameScratch &fs, const uint16_t *pix, float *cmd, float *slopes,
-                                float *recon, int32_t *counts, uint64_t *ts, hipStream_t st, const char *who) {
+                                float *recon, int32_t *counts, uint64_t *ts, hipStream_t st, const char *who,
+                                rtcx::SlopeStep step = nullptr, void *step_arg = nullptr) {
   rtck::CalibArgs ca = calib_args(c, pix);
   ca.s_int = fs.s;
   ca.s_user = slopes;
@@ -569,10 +570,12 @@ static rtc_status enqueue_frame(rtc_ctx *c, const FrameScratch &fs, const uint16
   ca.ts_start = ts;
   hipError_t e = rtck::launch_calib_cog(ca, st);
   if (e != hipSuccess) return hip_fail(c, e, who);
+  const float *s_use = fs.s;
+  if (step != nullptr && (e = step(step_arg, fs.s, c->d_state, &s_use, st)) != hipSuccess) return hip_fail(c, e, who);
   rtck::MvmArgs ma{};
   ma.n_act = c->n_act;
   ma.n_s4 = c->n_s4;
-  ma.s = fs.s;
+  ma.s = s_use;
   ma.k_split = c->tuning.k_split;
   ma.rows_per_wave = c->tuning.rows_per_wave;
   ma.unroll = c->tuning.unroll;
@@ -1486,3 +1489,13 @@ void rtc_destroy(rtc_ctx *c) {
 }
 
 }  // extern "C"
+
+namespace rtcx {
+
+rtc_status enqueue_frame_with(rtc_ctx *c, const uint16_t *pix, float *cmd, float *slopes, float *recon,
+                              int32_t *counts, uint64_t *ts, hipStream_t st, const char *who, SlopeStep step,
+                              void *arg) {
+  return enqueue_frame(c, ctx_scratch(c), pix, cmd, slopes, recon, counts, ts, st, who, step, arg);
+}
+
+}  // namespace rtcx

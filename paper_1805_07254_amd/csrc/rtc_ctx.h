@@ -126,4 +126,18 @@ inline void dfree(T *&p) {
   p = nullptr;
 }
 
+// A step between a frame's slopes and its reconstruction: given the slopes s
+// and the commands c_prev of the previous frame (the integrator state), it
+// enqueues its work on st and returns in *s_use the slope vector the
+// reconstruction multiplies (zero-padded like the library's own).
+using SlopeStep = hipError_t (*)(void *arg, const float *s, const float *c_prev, const float **s_use,
+                                 hipStream_t st);
+
+// One per-launch frame (calibration, step, reconstruction and integrator) on
+// st, as a frame of rtc_frame_batch in the per-launch mode; ts (nullable) gets
+// its start and end stamps.
+rtc_status enqueue_frame_with(rtc_ctx *c, const uint16_t *pix, float *cmd, float *slopes, float *recon,
+                              int32_t *counts, uint64_t *ts, hipStream_t st, const char *who, SlopeStep step,
+                              void *arg);
+
 }  // namespace rtcx

@@ -96,6 +96,7 @@ _SIGNATURES = {
     "rtc_pred_create": (_i32, [_vp, _i32, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _f32, ctypes.POINTER(_vp)]),
     "rtc_pred_reset": (_i32, [_vp]),
     "rtc_pred_step": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp]),
+    "rtc_pred_frame_batch": (_i32, [_vp, _vp, _i32, _vp, _i64, _vp, _vp, _vp, _vp]),
     "rtc_pred_destroy": (None, [_vp]),
     "rtc_pred_error_string": (ctypes.c_char_p, [_vp]),
     "rtc_autotune": (_i32, [_vp, _i32, _vp, _i64, _vp, _vp, _i32, ctypes.POINTER(_i32), _vp]),
@@ -764,6 +765,17 @@ class Predictor:
                                                ptr(slopes_out, self.n_slopes, "slopes_out"),
                                                None if modes is None else ptr(modes, 2 * self.n_modes, "modes"),
                                                _stream_ptr(stream)))
+
+    def frame_batch(self, ctx: RtcContext, n_frames: int, pixels, cmd, slopes=None, ts=None,
+                    frame_stride: Optional[int] = None, stream=None) -> None:
+        """n_frames predictive frames of ctx (calibration, this step, reconstruction and integrator)."""
+        stride = ctx.frame_elems if frame_stride is None else frame_stride
+        need = 0 if n_frames == 0 else (n_frames - 1) * stride + ctx.frame_elems
+        self._chk(load_library().rtc_pred_frame_batch(
+            ctx.handle, self.handle, n_frames, _dev_ptr(pixels, "uint16", need, "pixels", ctx), stride,
+            _dev_ptr(cmd, "float32", n_frames * ctx.n_act, "cmd", ctx),
+            _dev_ptr(slopes, "float32", n_frames * ctx.n_slopes, "slopes", ctx, False),
+            _dev_ptr(ts, ("uint64", "int64"), 2 * n_frames, "ts", ctx, False), _stream_ptr(stream)))
 
     def close(self):
         if self.handle is not None and self.handle.value:

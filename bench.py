@@ -131,6 +131,8 @@ def parse():
     p.add_argument("--pred-history", type=int, default=5)
     p.add_argument("--pred-epochs", type=int, default=6)
     p.add_argument("--pred-batch", type=int, default=512)
+    p.add_argument("--pred-latency-frames", type=int, default=2000,
+                   help="ELT pixel frames timed plain and predictive (elt-predict)")
     p.add_argument("--roofline-frames", type=int, default=10000, help="frames per roofline launch")
     p.add_argument("--roofline-launches", type=int, default=3)
     p.add_argument("--trace-frames", type=int, default=1000, help="frames of the all-workgroup stage trace")
@@ -497,6 +499,36 @@ def run_predict(args):
     t_int = timed(lambda: rtc.rtc_reconstruct_integrate(ctx, r, c1, stream=st_ptr))
     t_pred = timed(lambda: (pred.step(r, c0, r2, stream=st_ptr), rtc.rtc_reconstruct_integrate(ctx, r2, c1,
                                                                                                   stream=st_ptr)))
+    t_step = timed(lambda: pred.step(r, c0, r2, stream=st_ptr))
+
+    # frame latency on ELT pixel frames, plain and predictive (device stamps of every frame:
+    # first calibration workgroup's start to the last command stored)
+    from paper_1805_07254_amd.stats import frame_stats, ticks_to_us
+    nfr = args.pred_latency_frames
+    ring = np.stack([sc.frame(i, sc.turbulence_slopes(i)) for i in range(16)])
+    ring16 = torch.from_numpy(ring.reshape(16, -1).view(np.int16)).to(dev)
+    pix = ring16[torch.arange(nfr, device=dev) % 16].contiguous().view(torch.uint16)
+    cmdb = torch.empty(nfr * na, device=dev)
+    khz = rtc.rtc_wall_clock_khz(ctx)
+
+    def latency(run):
+        rtc.rtc_reset(ctx)
+        pred.reset()
+        ts = torch.zeros(2 * nfr, dtype=torch.int64, device=dev)
+        run(ts)
+        torch.cuda.synchronize()
+        rtc.rtc_sync_check(ctx)
+        t = ts.cpu().numpy().reshape(-1, 2)
+        return {"frame_span_us": frame_stats(ticks_to_us(t[:, 1] - t[:, 0], khz), skip=100),
+                "frame_period_us": frame_stats(np.diff(ticks_to_us(t[:, 0] - t[0, 0], khz)), skip=100)}
+    lat = {"frames": nfr, "skip": 100,
+           "integrator_per_launch": latency(lambda ts: rtc.rtc_frame_batch(ctx, nfr, pix, cmdb, ts=ts, stream=stream)),
+           "predictive_per_launch": latency(lambda ts: pred.frame_batch(ctx, nfr, pix, cmdb, ts=ts, stream=stream))}
+    rtc.rtc_set_frame_mode(ctx, rtc.RTC_FRAMES_PERSISTENT)
+    lat["integrator_persistent"] = latency(lambda ts: rtc.rtc_frame_batch(ctx, nfr, pix, cmdb, ts=ts, stream=stream))
+    log("frame span p50/p99 (us): " + ", ".join(
+        f"{k} {v['frame_span_us']['p50_us']:.2f}/{v['frame_span_us']['p99_us']:.2f}"
+        for k, v in lat.items() if isinstance(v, dict)))
     pred.close()
     net.close()
     rtc.rtc_destroy(ctx)
@@ -515,7 +547,10 @@ def run_predict(args):
         "gain_percent": round(100 * (1 - res_p / res_i), 2), "judged_segments": judged,
         "validation_mse": {"last_change": persist, "zero_change": float((yv ** 2).mean().item()),
                            "trained": hist[-1].get("val_loss")}, "training": hist,
-        "frame_cost_us": {"integrator": round(t_int, 3), "predictor_step_plus_integrator": round(t_pred, 3)},
+        "frame_cost_us": {"integrator": round(t_int, 3), "predictor_step_plus_integrator": round(t_pred, 3),
+                          "predictor_step": round(t_step, 3),
+                          "note": "HIP events over back-to-back calls on slopes (host-enqueued)"},
+        "frame_latency": lat,
         "training_step": {"ms": round(step_ms, 4), "tflops": round(flops / step_ms / 1e9, 2),
                           "peak_bf16_tflops": 2500.0},
     }

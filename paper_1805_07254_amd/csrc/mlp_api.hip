@@ -67,6 +67,7 @@ struct rtc_mlp {
 struct rtc_pred {
   rtc_mlp *net = nullptr;
   int32_t history = 0, n_modes = 0, n_slopes = 0, n_act = 0, frames = 0;   // frames seen, up to history
+  int32_t pos = 0;           // ring slot of the next change (hist holds 2 history slots)
   float inv_gain = 1.0f;
   // P [n_modes][ldp], PD [n_modes][ldd], PT [n_slopes][ldt]: rows zero-padded to a multiple of 4
   int64_t ldp = 0, ldd = 0, ldt = 0;
@@ -177,6 +178,7 @@ rtcm::PredStepArgs step_args(rtc_pred *p, const float *s, const float *c_prev, f
   a.push = p->frames > 0;
   a.full = p->frames >= p->history;              // `history` changes need history + 1 frames
   a.hist = p->hist;
+  a.pos = p->pos;
   a.m = p->m;
   a.m_prev = p->m_prev;
   a.mean = p->mean;
@@ -469,7 +471,7 @@ rtc_status rtc_pred_create(rtc_mlp *net, int32_t history, int32_t n_modes, int32
   if (e == hipSuccess) e = hipMalloc(&p->mean, fm);
   if (e == hipSuccess) e = hipMalloc(&p->std_, fm);
   if (e == hipSuccess) e = hipMalloc(&p->inv_std, fm);
-  if (e == hipSuccess) e = hipMalloc(&p->hist, fm * history);
+  if (e == hipSuccess) e = hipMalloc(&p->hist, fm * 2 * history);
   if (e == hipSuccess) e = hipMalloc(&p->m, fm);
   if (e == hipSuccess) e = hipMalloc(&p->m_prev, fm);
   if (e == hipSuccess) e = hipMalloc(&p->d, fm);
@@ -480,7 +482,7 @@ rtc_status rtc_pred_create(rtc_mlp *net, int32_t history, int32_t n_modes, int32
   if (e == hipSuccess) e = hipMemcpy(p->mean, mean, fm, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(p->std_, std_, fm, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(p->inv_std, inv.data(), fm, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemset(p->hist, 0, fm * history);
+  if (e == hipSuccess) e = hipMemset(p->hist, 0, fm * 2 * history);
   if (e == hipSuccess) e = hipMemset(p->s_pred, 0, s_pad);
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
@@ -498,11 +500,18 @@ rtc_status rtc_pred_reset(rtc_pred *p) {
   DevScope ds(p->net->device);
   hipError_t e = ds.status;
   if (e == hipSuccess) e = hipDeviceSynchronize();
-  if (e == hipSuccess) e = hipMemset(p->hist, 0, sizeof(float) * (size_t)p->n_modes * p->history);
+  if (e == hipSuccess) e = hipMemset(p->hist, 0, sizeof(float) * (size_t)p->n_modes * 2 * p->history);
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) return pfail(p, RTC_E_DEVICE, std::string("rtc_pred_reset: ") + hipGetErrorName(e));
   p->frames = 0;
+  p->pos = 0;
   return RTC_OK;
+}
+
+// After a step: the ring moves on when the step stored a change.
+static void advance(rtc_pred *p) {
+  if (p->frames > 0) p->pos = (p->pos + 1) % p->history;
+  if (p->frames < p->history) ++p->frames;
 }
 
 rtc_status rtc_pred_step(rtc_pred *p, const float *d_slopes, const float *d_cmd_prev, float *d_slopes_out,
@@ -516,7 +525,7 @@ rtc_status rtc_pred_step(rtc_pred *p, const float *d_slopes, const float *d_cmd_
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   const hipError_t e = rtcm::launch_pred_step(step_args(p, d_slopes, d_cmd_prev, d_slopes_out, d_modes), st);
   if (e != hipSuccess) return pfail(p, RTC_E_DEVICE, std::string("rtc_pred_step: ") + hipGetErrorName(e));
-  if (p->frames < p->history) ++p->frames;
+  advance(p);
   return RTC_OK;
 }
 
@@ -526,7 +535,7 @@ static hipError_t pred_frame_step(void *arg, const float *s, const float *c_prev
                                   hipStream_t st) {
   rtc_pred *p = static_cast<rtc_pred *>(arg);
   const hipError_t e = rtcm::launch_pred_step(step_args(p, s, c_prev, p->s_pred, nullptr), st);
-  if (e == hipSuccess && p->frames < p->history) ++p->frames;
+  if (e == hipSuccess) advance(p);
   *s_use = p->s_pred;
   return e;
 }

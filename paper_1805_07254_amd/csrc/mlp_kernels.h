@@ -55,7 +55,9 @@ struct PredStepArgs {
   int n_slopes, n_act, n_modes, history, n_in, n_hid;
   int push;              // a previous frame exists (the window takes a change)
   int full;              // the window holds `history` changes (the network runs)
-  float *hist;           // [history][n_modes] normalised changes, oldest first
+  float *hist;           // [2 history][n_modes] ring of normalised changes: a change goes to slots
+                         // pos and pos + history, so slots pos + 1 .. pos + history are the window
+  int pos;               // ring slot of this frame's change
   float *m, *m_prev;     // [n_modes]
   const float *mean, *std_, *inv_std;
   const uint16_t *W1;    // [n_hid][n_in]

@@ -135,11 +135,12 @@ class Telemetry:
         return torch.randn((n_frames, n_slopes), generator=g, device=self.device) * self.layers.noise_px
 
 
-def kl_basis(samples: torch.Tensor, n_modes: int) -> torch.Tensor:
-    """float32 [n_modes, n_slopes]: leading eigenvectors (orthonormal rows) of the slope covariance."""
-    x = samples.to(torch.float64)
-    x = x - x.mean(dim=0, keepdim=True)
-    cov = x.T @ x / max(1, x.shape[0] - 1)
-    evals, evecs = torch.linalg.eigh(cov)
-    order = torch.argsort(evals, descending=True)[:n_modes]
-    return evecs[:, order].T.contiguous().to(torch.float32)
+def kl_basis(samples, n_modes: int) -> np.ndarray:
+    """float32 [n_modes, n_slopes]: leading eigenvectors (orthonormal rows) of
+    the slope covariance of samples [F, n_slopes], from the singular value
+    decomposition of the centred samples (float64, host NumPy; offline work)."""
+    x = samples.detach().cpu().numpy() if isinstance(samples, torch.Tensor) else np.asarray(samples)
+    x = x.astype(np.float64)
+    x = x - x.mean(axis=0, keepdims=True)
+    _, _, vt = np.linalg.svd(x, full_matrices=False)      # rows: eigenvectors, eigenvalues descending
+    return np.ascontiguousarray(vt[:n_modes], dtype=np.float32)

@@ -424,8 +424,8 @@ def run_predict(args):
     seg_len = 2000
     n_train = max(1, args.pred_frames // seg_len)
     ol = torch.cat([tel.segment(k, seg_len)[::8] for k in range(min(n_train, 12))])
-    P = kl_basis(ol, nm).to(dev)
-    PD = P @ D
+    P = kl_basis(ol, nm)                                  # offline preparation on the host
+    PD = (P.astype(np.float64) @ sc.interaction.astype(np.float64)).astype(np.float32)
     del ol
     log(f"{nm} KL modes at {time.time() - t0:.0f}s")
     ctx = predict.make_context(sc, R, gain=cfg.gain)
@@ -436,14 +436,15 @@ def run_predict(args):
         zs.append(predict.pol_modes(out["residual"], out["cmd_prev"], P, PD))
         if (seg + 1) % 10 == 0:
             log(f"telemetry: {(seg + 1) * seg_len} closed-loop frames at {time.time() - t0:.0f}s")
-    mean, std = predict.change_stats(torch.cat(zs[:n_train]))
+    mean, std = predict.change_stats(np.concatenate(zs[:n_train]))
     xs, ys = zip(*[predict.windows(z, H, mean, std) for z in zs[:n_train]])
-    x, y = torch.cat(xs), torch.cat(ys)
+    x, y = predict.to_device(np.concatenate(xs), dev), predict.to_device(np.concatenate(ys), dev)
     del xs, ys
-    xv, yv = predict.windows(zs[n_train], H, mean, std)
+    xv_h, yv_h = predict.windows(zs[n_train], H, mean, std)
+    xv, yv = predict.to_device(xv_h, dev), predict.to_device(yv_h, dev)
     net = rtc.MlpNet(H * nm, args.pred_hidden, nm, args.pred_batch)
     net.set_params(*predict.init_params(H * nm, args.pred_hidden, nm, seed=5))
-    persist = float(((xv[:, -nm:] - yv) ** 2).mean().item())     # forecast = the last change again
+    persist = float(((xv_h[:, -nm:].astype(np.float64) - yv_h) ** 2).mean())   # forecast = the last change again
     t1 = time.time()
     hist = predict.train(net, x, y, epochs=args.pred_epochs, batch=args.pred_batch, lr=1e-3, seed=6, x_val=xv,
                          y_val=yv, log=log)
@@ -467,7 +468,7 @@ def run_predict(args):
         f"({flops / step_ms / 1e9:.1f} TFLOP/s)")
 
     # judge on held-out segments
-    pred = rtc.Predictor(net, H, P.cpu().numpy(), PD.cpu().numpy(), mean.cpu().numpy(), std.cpu().numpy(), cfg.gain)
+    pred = rtc.Predictor(net, H, P, PD, mean, std, cfg.gain)
     judged = []
     for seg in (n_train + 1, n_train + 2):
         s = tel.segment(seg, seg_len)
@@ -545,7 +546,7 @@ def run_predict(args):
                    "epochs": args.pred_epochs, "batch": args.pred_batch},
         "integrator_residual_px": round(res_i, 5), "predictive_residual_px": round(res_p, 5),
         "gain_percent": round(100 * (1 - res_p / res_i), 2), "judged_segments": judged,
-        "validation_mse": {"last_change": persist, "zero_change": float((yv ** 2).mean().item()),
+        "validation_mse": {"last_change": persist, "zero_change": float((yv_h.astype(np.float64) ** 2).mean()),
                            "trained": hist[-1].get("val_loss")}, "training": hist,
         "frame_cost_us": {"integrator": round(t_int, 3), "predictor_step_plus_integrator": round(t_pred, 3),
                           "predictor_step": round(t_step, 3),

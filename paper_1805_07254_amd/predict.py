@@ -13,7 +13,8 @@ reconstruction and integrator (rtc_reconstruct_integrate), the network's
 forward and backward passes and Adam (rtc_mlp_*), and the predictor step
 (rtc_pred_step).  torch only holds device memory, and the plant simulation
 (turbulence slopes minus the mirror's slopes D c, plus noise) stands in for
-the telescope.
+the telescope.  The training set (modal coefficients of the telemetry, their
+change statistics and windows) is prepared offline on the host in NumPy.
 
 Data flow of one frame k (slopes r_k measured with commands c_{k-1} applied):
     integrator:  c_k = c_{k-1} + g R r_k
@@ -23,8 +24,6 @@ Data flow of one frame k (slopes r_k measured with commands c_{k-1} applied):
 A zero forecast leaves the plain integrator, which is therefore the fallback.
 """
 from __future__ import annotations
-
-from dataclasses import dataclass
 
 import numpy as np
 import torch
@@ -77,35 +76,45 @@ def run_loop(D: torch.Tensor, s_tur: torch.Tensor, noise: torch.Tensor, ctx: rtc
     return {"residual": res, "cmd_prev": cmds}
 
 
-@dataclass
-class ModalData:
-    P: torch.Tensor          # [n_modes, n_slopes]
-    PD: torch.Tensor         # [n_modes, n_act]
-    mean: torch.Tensor       # [n_modes]
-    std: torch.Tensor
+# Training-set preparation is offline work on the host (NumPy, float64): it
+# runs once on recorded telemetry, not in the frame, and feeds the library's
+# training kernels through device copies of its results.
+
+def _host(a) -> np.ndarray:
+    return a.detach().cpu().numpy() if isinstance(a, torch.Tensor) else np.asarray(a)
 
 
-def pol_modes(residual: torch.Tensor, cmd_prev: torch.Tensor, P: torch.Tensor, PD: torch.Tensor) -> torch.Tensor:
-    """[F, n_modes] POL modal coefficients of closed-loop telemetry (the predictor step's m_k)."""
-    return residual @ P.T + cmd_prev @ PD.T
+def pol_modes(residual, cmd_prev, P, PD) -> np.ndarray:
+    """[F, n_modes] POL modal coefficients of closed-loop telemetry (the
+    predictor step's m_k = P r_k + (P D) c_{k-1}), float64 on the host."""
+    r = _host(residual).astype(np.float64)
+    c = _host(cmd_prev).astype(np.float64)
+    return r @ _host(P).astype(np.float64).T + c @ _host(PD).astype(np.float64).T
 
 
-def change_stats(m: torch.Tensor):
-    """Mean and std of the per-frame changes of the modes [F, n_modes]."""
-    dm = m[1:] - m[:-1]
-    return dm.mean(dim=0), dm.std(dim=0)
+def change_stats(m) -> tuple[np.ndarray, np.ndarray]:
+    """Mean and (sample) std of the per-frame changes of the modes [F, n_modes],
+    float32 as the predictor takes them."""
+    dm = np.diff(_host(m).astype(np.float64), axis=0)
+    return dm.mean(axis=0).astype(np.float32), dm.std(axis=0, ddof=1).astype(np.float32)
 
 
-def windows(m: torch.Tensor, history: int, mean: torch.Tensor, std: torch.Tensor):
+def windows(m, history: int, mean, std) -> tuple[np.ndarray, np.ndarray]:
     """Training pairs from one segment of modes m [F, n_modes]: inputs [F - 1 - history,
     history n_modes] (the last ``history`` normalised changes, oldest first) and
-    targets (the next normalised change)."""
-    z = ((m[1:] - m[:-1] - mean) / std).contiguous()
-    F1, nm = z.shape
-    n = F1 - history
-    idx = torch.arange(n, device=z.device)[:, None] + torch.arange(history, device=z.device)[None, :]
-    x = z[idx].reshape(n, history * nm)
-    return x.contiguous(), z[history:].contiguous()
+    targets (the next normalised change), float32 on the host."""
+    mu = _host(mean).astype(np.float64)
+    sd = _host(std).astype(np.float64)
+    z = (np.diff(_host(m).astype(np.float64), axis=0) - mu) / sd
+    n = z.shape[0] - history
+    x = np.lib.stride_tricks.sliding_window_view(z, history, axis=0)[:n]    # [n, n_modes, history]
+    x = np.ascontiguousarray(x.transpose(0, 2, 1).reshape(n, history * z.shape[1]), dtype=np.float32)
+    return x, np.ascontiguousarray(z[history:], dtype=np.float32)
+
+
+def to_device(a: np.ndarray, device) -> torch.Tensor:
+    """A host array as a device float32 tensor (a copy; the training kernels read it)."""
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(device)
 
 
 def init_params(n_in: int, n_hidden: int, n_out: int, seed: int):

@@ -45,18 +45,20 @@ def test_trained_predictor_beats_the_integrator():
         res.append(out["residual"])
         cprev.append(out["cmd_prev"])
         ol.append(s[::10])
-    P = kl_basis(torch.cat(ol[:N_TRAIN]), N_MODES).to(dev)
-    PD = P @ D
+    # training-set preparation on the host (offline work)
+    P = kl_basis(torch.cat(ol[:N_TRAIN]), N_MODES)
+    PD = (P.astype(np.float64) @ sc.interaction.astype(np.float64)).astype(np.float32)
     m_all = [predict.pol_modes(r, c, P, PD) for r, c in zip(res, cprev)]
-    mean, std = predict.change_stats(torch.cat(m_all[:N_TRAIN]))
+    mean, std = predict.change_stats(np.concatenate(m_all[:N_TRAIN]))
     xs, ys = zip(*[predict.windows(m, HISTORY, mean, std) for m in m_all[:N_TRAIN]])
-    x, y = torch.cat(xs), torch.cat(ys)
-    xv, yv = predict.windows(m_all[N_TRAIN], HISTORY, mean, std)
+    x, y = predict.to_device(np.concatenate(xs), dev), predict.to_device(np.concatenate(ys), dev)
+    xv_h, yv_h = predict.windows(m_all[N_TRAIN], HISTORY, mean, std)
+    xv, yv = predict.to_device(xv_h, dev), predict.to_device(yv_h, dev)
 
     net = rtc.MlpNet(HISTORY * N_MODES, HIDDEN, N_MODES, 256)
     net.set_params(*predict.init_params(HISTORY * N_MODES, HIDDEN, N_MODES, seed=5))
     before = predict.evaluate(net, xv, yv, 256)
-    persist = float(((xv[:, -N_MODES:] - yv) ** 2).mean().item())   # forecast = the last change again
+    persist = float(((xv_h[:, -N_MODES:].astype(np.float64) - yv_h) ** 2).mean())   # forecast = the last change again
     hist = predict.train(net, x, y, epochs=8, batch=256, lr=2e-3, seed=6, x_val=xv, y_val=yv)
     after = hist[-1]["val_loss"]
     print(f"validation MSE (normalised changes): untrained {before:.4f}, last change {persist:.4f}, "
@@ -70,8 +72,7 @@ def test_trained_predictor_beats_the_integrator():
     s = tel.segment(seg, SEG)
     nz = tel.noise(seg, SEG, ns)
     base = predict.run_loop(D, s, nz, ctx)
-    pred = rtc.Predictor(net, HISTORY, P.cpu().numpy(), PD.cpu().numpy(), mean.cpu().numpy(), std.cpu().numpy(),
-                         sc.cfg.gain)
+    pred = rtc.Predictor(net, HISTORY, P, PD, mean, std, sc.cfg.gain)
     out = predict.run_loop(D, s, nz, ctx, pred)
     r_int = predict.residual_rms(base["residual"], 100)
     r_pred = predict.residual_rms(out["residual"], 100)

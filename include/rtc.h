@@ -250,7 +250,7 @@ rtc_status rtc_frame_batch_noalloc(rtc_ctx *c, int32_t n_frames, const uint16_t 
  * 2.3.2).  Runs a persistent batch (RTC_FRAMES_PERSISTENT required) of
  * n_frames frames, arguments and outputs as rtc_frame_batch, in which frame k
  * starts only once the calling thread releases it, at t0 + k * period_us on
- * the host's steady clock (busy-waited; t0 = one period after the launch):
+ * the host's CLOCK_MONOTONIC_RAW (busy-waited; t0 = one period after the launch):
  * the thread writes the frame's number to a word of coherent host memory,
  * which workgroup 0 polls and relays to the other workgroups.  The commands
  * of these frames are stored at system scope; the last workgroup to store

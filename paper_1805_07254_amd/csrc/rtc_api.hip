@@ -14,8 +14,9 @@
 //   sync     [4]                  uint32 completion counter
 #include <hip/hip_runtime.h>
 
+#include <time.h>
+
 #include <algorithm>
-#include <chrono>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -832,7 +833,12 @@ rtc_status rtc_frame_batch_noalloc(rtc_ctx *c, int32_t n_frames, const uint16_t 
 rtc_status rtc_paced_batch(rtc_ctx *c, int32_t n_frames, const uint16_t *d_pixels, int64_t frame_stride,
                            float *d_cmd, float *d_slopes, float *d_recon, int32_t *d_counts, uint64_t *d_ts,
                            double period_us, int64_t *h_release_ns, int64_t *h_done_ns, void *hip_stream) {
-  using clk = std::chrono::steady_clock;
+  // host times from CLOCK_MONOTONIC_RAW (not slewed by time adjustment), in ns
+  auto now_ns = []() -> int64_t {
+    timespec t;
+    clock_gettime(CLOCK_MONOTONIC_RAW, &t);
+    return (int64_t)t.tv_sec * 1000000000 + t.tv_nsec;
+  };
   const char *who = "rtc_paced_batch";
   if (!c) return fail(nullptr, RTC_E_ARG, "rtc_paced_batch: NULL context");
   if (!c->calib_loaded || !c->cmat_loaded)
@@ -886,29 +892,28 @@ rtc_status rtc_paced_batch(rtc_ctx *c, int32_t n_frames, const uint16_t *d_pixel
   c->trig_base = base + (uint32_t)n_frames;
   volatile uint32_t *release = c->h_trig;
   const volatile uint32_t *done = c->h_trig + 32;
-  const auto period = std::chrono::nanoseconds((int64_t)std::llround(period_us * 1e3));
-  const auto t0 = clk::now() + period;
+  const int64_t period = std::llround(period_us * 1e3);
+  const int64_t t0 = now_ns() + period;
   // a frame not done within 100 periods (at least 100 ms) fails the batch
-  const auto limit = std::max(std::chrono::nanoseconds(100000000), 100 * period);
+  const int64_t limit = std::max<int64_t>(100000000, 100 * period);
   std::string late;
   for (int32_t k = 0; k < n_frames && late.empty(); ++k) {
-    const auto due = t0 + k * period;
-    while (clk::now() < due) {
+    const int64_t due = t0 + (int64_t)k * period;
+    while (now_ns() < due) {
     }
     const uint32_t v = base + (uint32_t)k + 1u;
     __atomic_store_n(const_cast<uint32_t *>(release), v, __ATOMIC_RELEASE);
-    const auto t_rel = clk::now();
-    if (h_release_ns) h_release_ns[k] = std::chrono::duration_cast<std::chrono::nanoseconds>(t_rel - t0).count();
+    const int64_t t_rel = now_ns();
+    if (h_release_ns) h_release_ns[k] = t_rel - t0;
     for (uint64_t spin = 0;; ++spin) {
       if ((int32_t)(__atomic_load_n(const_cast<uint32_t *>(done), __ATOMIC_ACQUIRE) - v) >= 0) break;
-      if ((spin & 4095) == 4095 && clk::now() - t_rel > limit) {
+      if ((spin & 4095) == 4095 && now_ns() - t_rel > limit) {
         late = "rtc_paced_batch: frame " + std::to_string(k) + " was not done within " +
-               std::to_string(std::chrono::duration_cast<std::chrono::milliseconds>(limit).count()) + " ms";
+               std::to_string(limit / 1000000) + " ms";
         break;
       }
     }
-    if (h_done_ns && late.empty())
-      h_done_ns[k] = std::chrono::duration_cast<std::chrono::nanoseconds>(clk::now() - t0).count();
+    if (h_done_ns && late.empty()) h_done_ns[k] = now_ns() - t0;
   }
   // release whatever is left (a failed batch then winds down at once) and wait
   __atomic_store_n(const_cast<uint32_t *>(release), c->trig_base, __ATOMIC_RELEASE);

@@ -326,7 +326,7 @@ __global__ __launch_bounds__(kHoriz, 1) void horizontal_kernel(HorizArgs h, int3
     }
     trace_stamp(p, f, 3);
     __syncthreads();
-    if (tf < orw && sh_bar == 0u) {
+    if (tf < orw && (sh_bar & 1u) == 0u) {
       const float *red = reinterpret_cast<const float *>(sh_red);
       const int pc = tf >> 2, e = tf & 3;
       float v = 0.f;
@@ -349,7 +349,7 @@ __global__ __launch_bounds__(kHoriz, 1) void horizontal_kernel(HorizArgs h, int3
         __hip_atomic_store(reinterpret_cast<uint64_t *>(p.bar + sl::kEnds) + (f & 1) * sl::kMaxGroups + b,
                            wall_clock64(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    frames_done += sh_bar == 0u ? 1 : 0;
+    frames_done += (sh_bar & 1u) == 0u ? 1 : 0;
   }
   if (tid < own_rows) a.state[own_r0 + tid] = state;
   // end stamp of the last frame: the last workgroup to finish reduces it

@@ -312,7 +312,9 @@ __device__ __forceinline__ void trigger_done(const PersistArgs &p, int f) {
 
 // False when this workgroup's wait for the release expired (the abort flag is
 // then raised): the frame's slopes may be incomplete, so the caller must not
-// use them.  sh_flag: a shared word of the workgroup.
+// use them.  sh_flag: a shared word of the workgroup, left at bit 0 = this
+// wait expired, bit 1 = stop after this frame (the abort flag was raised
+// before this workgroup arrived, or by this wait).
 __device__ __forceinline__ bool frame_barrier(const PersistArgs &p, uint32_t epoch, int f, uint32_t *sh_flag) {
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // this wavefront's stores are complete
   __syncthreads();
@@ -320,7 +322,10 @@ __device__ __forceinline__ bool frame_barrier(const PersistArgs &p, uint32_t epo
   if (threadIdx.x < 64) {
     const uint32_t G = gridDim.x;
     int release = 0;
+    uint32_t ab = 0;
     if (threadIdx.x == 0) {
+      // the abort flag, read beside the arrival so that its round trip is the arrival's
+      ab = __hip_atomic_load(p.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       const uint32_t grp = blockIdx.x % sl::kGroups;
       const uint32_t per = (G - grp + sl::kGroups - 1) / sl::kGroups;   // workgroups in this group
       const uint32_t ngrp = G < (uint32_t)sl::kGroups ? G : (uint32_t)sl::kGroups;
@@ -337,10 +342,11 @@ __device__ __forceinline__ bool frame_barrier(const PersistArgs &p, uint32_t epo
       for (uint32_t i = threadIdx.x; i < G; i += 64)
         __hip_atomic_store(p.bar + sl::kMailbox + 16 * i, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    if (threadIdx.x == 0) *sh_flag = bounded_wait(p, p.bar + sl::kMailbox + 16 * blockIdx.x, epoch) ? 0u : 1u;
+    if (threadIdx.x == 0)
+      *sh_flag = bounded_wait(p, p.bar + sl::kMailbox + 16 * blockIdx.x, epoch) ? (ab != 0u ? 2u : 0u) : 3u;
   }
   __syncthreads();
-  return *sh_flag == 0u;
+  return (*sh_flag & 1u) == 0u;
 }
 
 // End stamp of a frame: the latest of the per-workgroup end stamps, reduced by

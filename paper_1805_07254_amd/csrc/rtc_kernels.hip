@@ -864,6 +864,7 @@ __global__ __launch_bounds__(512 / VW) void frames_kernel(PersistArgs p, int32_t
   }
   float state = 0.f;
   if (tid < nrows) state = a.state[row_begin + tid];
+  if (tid == 0) sh_bar = 0u;
   __syncthreads();
 
   int frames_done = 0;
@@ -885,12 +886,18 @@ __global__ __launch_bounds__(512 / VW) void frames_kernel(PersistArgs p, int32_t
         for (int j = 0; j < KPL; ++j)
           asm volatile("" : "+a"(ra[u][i][j].x), "+a"(ra[u][i][j].y), "+a"(ra[u][i][j].z), "+a"(ra[u][i][j].w));
     }
-    if constexpr (TRIG) {                           // externally triggered frames
-      if (wave == 0) trigger_wait(p, f);
+    // a bounded wait expired somewhere: wind down.  The abort flag is read
+    // beside the previous frame's barrier arrival (bit 1 of sh_bar), so no
+    // frame starts with a memory round trip.
+    if constexpr (!TRIG) {
+      if (sh_bar & 2u) break;
     }
-    if (tid == 0) sh_abort = __hip_atomic_load(p.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __syncthreads();
-    if (sh_abort) break;                            // a bounded wait expired somewhere: wind down
+    if constexpr (TRIG) {                           // externally triggered frames (own check)
+      if (wave == 0) trigger_wait(p, f);
+      if (tid == 0) sh_abort = __hip_atomic_load(p.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __syncthreads();
+      if (sh_abort) break;
+    }
     if (p.ts != nullptr && b == 0 && tid == 0) p.ts[2 * f] = wall_clock64();
     trace_stamp(p, f, 0);
 
@@ -914,11 +921,12 @@ __global__ __launch_bounds__(512 / VW) void frames_kernel(PersistArgs p, int32_t
       wg_calibration<GS, NT>(ca, k_begin, k_end, p.vec, cached ? sh_tiles : nullptr, cached ? sh_ref : nullptr);
     }
     trace_stamp(p, f, 1);
-    // An expired wait leaves sh_bar set: the slopes of frame f may then be
-    // incomplete, so its commands and the rows' state are not written, and the
-    // raised abort flag ends the loop at the next frame (an exit here instead
-    // costs the sums below registers).  sh_bar is next written after the
-    // loop-top barrier, so the reads below cannot race with it.
+    // An expired wait sets bit 0 of sh_bar: the slopes of frame f may then be
+    // incomplete, so its commands and the rows' state are not written (an
+    // exit here instead costs the sums below registers).  Bit 1 (an abort
+    // flag raised anywhere) ends the loop at the next frame's top.  sh_bar is
+    // next written after the next frame's barrier has synchronised the
+    // workgroup, so the reads below and at that top cannot race with it.
     (void)frame_barrier(p, (uint32_t)(f + 1), f, &sh_bar);
     trace_stamp(p, f, 2);
 
@@ -1050,7 +1058,7 @@ __global__ __launch_bounds__(512 / VW) void frames_kernel(PersistArgs p, int32_t
     trace_stamp(p, f, 4);
 
     // (d) integrate own rows (not when this workgroup's barrier wait expired)
-    if (tid < nrows && sh_bar == 0u) {
+    if (tid < nrows && (sh_bar & 1u) == 0u) {
       float v = sh_part[tid];
       for (int w = 1; w < W; ++w) v += sh_part[w * max_rows + tid];
       if (a.scales != nullptr) v *= a.scales[row_begin + tid];
@@ -1072,7 +1080,7 @@ __global__ __launch_bounds__(512 / VW) void frames_kernel(PersistArgs p, int32_t
         __hip_atomic_store(reinterpret_cast<uint64_t *>(p.bar + sl::kEnds) + (f & 1) * sl::kMaxGroups + b,
                            wall_clock64(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    frames_done += sh_bar == 0u ? 1 : 0;
+    frames_done += (sh_bar & 1u) == 0u ? 1 : 0;
   }
   if (tid < nrows) a.state[row_begin + tid] = state;
   // end stamp of the last frame: the last workgroup to finish reduces it

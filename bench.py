@@ -134,7 +134,10 @@ def parse():
     p.add_argument("--pred-latency-frames", type=int, default=2000,
                    help="ELT pixel frames timed plain and predictive (elt-predict)")
     p.add_argument("--roofline-frames", type=int, default=10000, help="frames per roofline launch")
-    p.add_argument("--roofline-launches", type=int, default=3)
+    p.add_argument("--roofline-launches", type=int, default=2,
+                   help="launches of --roofline-frames frames without time stamps (the roofline's device time)")
+    p.add_argument("--stats-launches", type=int, default=3,
+                   help="launches of --roofline-frames frames with time stamps (latency distribution)")
     p.add_argument("--trace-frames", type=int, default=1000, help="frames of the all-workgroup stage trace")
     p.add_argument("--paced-frames", type=int, default=2000, help="host-paced frames (0 = none)")
     p.add_argument("--paced-period-us", type=float, default=1000.0)
@@ -776,32 +779,43 @@ def run_scao(args):
     log(f"timed frames: span p50 {st_span['p50_us']:.2f} us p99 {st_span['p99_us']:.2f} us, wall "
         f"{head['wall'] * 1e6 / args.steps:.2f} us/frame")
 
-    # --- roofline launches: whole launches of roofline_frames frames, HIP events on the launch stream
-    long_period, long_span, launch_ms = [], [], []
-    for r in range(args.roofline_launches):
-        ts = torch.zeros(2 * args.roofline_frames, dtype=torch.int64, device="cuda:0")
+    # --- long runs: whole launches of roofline_frames frames, HIP events on the launch stream.
+    # The roofline's device time comes from launches without time stamps (the frame as it runs
+    # in production: the stamps' end-of-frame reduction costs a workgroup a memory round trip);
+    # the latency distribution from launches with them.
+    def whole_launch(ts):
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         ev0.record(stream)
         rtc.rtc_frame_batch(ctx, args.roofline_frames, frames, cmd, ts=ts, stream=stream)
         ev1.record(stream)
         torch.cuda.synchronize()
-        launch_ms.append(ev0.elapsed_time(ev1))
+        return ev0.elapsed_time(ev1)
+    launch_ms = [whole_launch(None) for _ in range(args.roofline_launches)]
+    long_period, long_span, stamped_ms = [], [], []
+    for r in range(args.stats_launches):
+        ts = torch.zeros(2 * args.roofline_frames, dtype=torch.int64, device="cuda:0")
+        stamped_ms.append(whole_launch(ts))
         pr, sp = series(ts, khz)
         long_period.append(pr)
         long_span.append(sp)
     rtc.rtc_sync_check(ctx)
-    lp, ls = np.concatenate(long_period), np.concatenate(long_span)
-    long_run = {"launches": args.roofline_launches, "frames_per_launch": args.roofline_frames,
-                "launch_ms": [round(x, 4) for x in launch_ms],
-                "frame_period_us": frame_stats(lp), "frame_span_us": frame_stats(ls),
-                "frame_period_us_skip100": frame_stats(long_period[0], skip=100) if len(long_period[0]) > 200
-                else None,
-                "frame_span_us_skip100": frame_stats(long_span[0], skip=100) if len(long_span[0]) > 200 else None}
     launch_avg_ms = float(np.mean(launch_ms))
     frame_us = launch_avg_ms * 1e3 / args.roofline_frames
-    log(f"{args.roofline_launches} launches of {args.roofline_frames} frames: {launch_avg_ms:.3f} ms each "
-        f"({frame_us:.3f} us/frame), span p50 {long_run['frame_span_us']['p50_us']:.2f} us, p99 "
-        f"{long_run['frame_span_us']['p99_us']:.2f} us")
+    long_run = {"frames_per_launch": args.roofline_frames,
+                "launches_without_stamps_ms": [round(x, 4) for x in launch_ms],
+                "launches_with_stamps_ms": [round(x, 4) for x in stamped_ms]}
+    if long_period:
+        lp, ls = np.concatenate(long_period), np.concatenate(long_span)
+        long_run.update({
+            "frame_period_us": frame_stats(lp), "frame_span_us": frame_stats(ls),
+            "frame_period_us_skip100": frame_stats(long_period[0], skip=100) if len(long_period[0]) > 200
+            else None,
+            "frame_span_us_skip100": frame_stats(long_span[0], skip=100) if len(long_span[0]) > 200 else None})
+    log(f"{args.roofline_launches} launches of {args.roofline_frames} frames without stamps: {launch_avg_ms:.3f} ms "
+        f"each ({frame_us:.3f} us/frame); with stamps: "
+        f"{np.mean(stamped_ms) * 1e3 / args.roofline_frames if stamped_ms else float('nan'):.3f} us/frame" +
+        (f", span p50 {long_run['frame_span_us']['p50_us']:.2f} us, p99 {long_run['frame_span_us']['p99_us']:.2f} us"
+         if long_period else ""))
 
     # --- stage trace of every workgroup: the measured barrier floor
     G = min(n_cu if args.blocks <= 0 else args.blocks, n_act)

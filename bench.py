@@ -530,6 +530,10 @@ def run_predict(args):
            "predictive_per_launch": latency(lambda ts: pred.frame_batch(ctx, nfr, pix, cmdb, ts=ts, stream=stream))}
     rtc.rtc_set_frame_mode(ctx, rtc.RTC_FRAMES_PERSISTENT)
     lat["integrator_persistent"] = latency(lambda ts: rtc.rtc_frame_batch(ctx, nfr, pix, cmdb, ts=ts, stream=stream))
+    # the predictive frames in one persistent launch (the step's four phases between grid barriers)
+    lat["predictive_persistent"] = latency(lambda ts: pred.frame_batch(ctx, nfr, pix, cmdb, ts=ts, stream=stream))
+    lat["predictive_persistent_ran"] = ("persistent" if pred.last_batch_mode() == rtc.RTC_FRAMES_PERSISTENT
+                                        else "per launch (shape not built)")
     log("frame span p50/p99 (us): " + ", ".join(
         f"{k} {v['frame_span_us']['p50_us']:.2f}/{v['frame_span_us']['p99_us']:.2f}"
         for k, v in lat.items() if isinstance(v, dict)))

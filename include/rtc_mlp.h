@@ -98,7 +98,15 @@ rtc_status rtc_pred_step(rtc_pred *p, const float *d_slopes, const float *d_cmd_
  * runs it in the per-launch mode (calibration and centroids, reconstruction
  * and integrator) with the predictor step of p between them -- r_k measured,
  * c_{k-1} = the context's integrator state, r'_k handed to the
- * reconstruction -- so that c_k = c_{k-1} + gain R r'_k as above.  Frame f
+ * reconstruction -- so that c_k = c_{k-1} + gain R r'_k as above.  When the
+ * context is in RTC_FRAMES_PERSISTENT mode and the built kernels cover its
+ * shape (FP32 matrix, at most 256 actuator rows per workgroup and 4 chunks
+ * per lane, tiles of up to 16 pixels, network sizes n_in and n_hid multiples
+ * of 4), all frames run in one persistent launch with the step's four
+ * phases between the slope exchange and the products, each followed by a
+ * grid barrier; the results are bitwise those of the per-launch form, which
+ * runs otherwise.  An expired barrier wait there leaves the context's state
+ * undefined (rtc_sync_check) and the predictor's too (rtc_pred_reset).  Frame f
  * reads d_pixels + f * frame_stride (elements, >= one frame) and writes
  * d_cmd [n_frames][n_act] (required) and d_slopes [n_frames][n_slopes]
  * (measured r_k, nullable); d_ts (nullable) [n_frames][2] gets the frame's
@@ -111,6 +119,12 @@ rtc_status rtc_pred_step(rtc_pred *p, const float *d_slopes, const float *d_cmd_
 rtc_status rtc_pred_frame_batch(rtc_ctx *c, rtc_pred *p, int32_t n_frames, const uint16_t *d_pixels,
                                 int64_t frame_stride, float *d_cmd, float *d_slopes, uint64_t *d_ts,
                                 void *hip_stream);
+
+/* The frame mode the last successful rtc_pred_frame_batch of p ran in:
+ * RTC_FRAMES_PERSISTENT (one launch) or RTC_FRAMES_PER_LAUNCH (four step
+ * launches between the frame's own); RTC_FRAMES_PER_LAUNCH before any batch.
+ * Errors: RTC_E_ARG (NULL argument). */
+rtc_status rtc_pred_last_batch_mode(const rtc_pred *p, int32_t *mode);
 
 void rtc_pred_destroy(rtc_pred *p);
 

@@ -74,6 +74,7 @@ struct rtc_pred {
   float *P = nullptr, *PT = nullptr, *PD = nullptr, *mean = nullptr, *std_ = nullptr, *inv_std = nullptr;
   float *hist = nullptr, *m = nullptr, *m_prev = nullptr, *d = nullptr;
   float *s_pred = nullptr;   // [round_up(n_slopes, 16)] feed-forward slopes of predictive frame batches, zero-padded
+  int32_t last_mode = RTC_FRAMES_PER_LAUNCH;   // frame mode of the last predictive batch
   std::string err = "no error";
 };
 
@@ -558,6 +559,23 @@ rtc_status rtc_pred_frame_batch(rtc_ctx *c, rtc_pred *p, int32_t n_frames, const
   DevScope ds(c->device);
   if (ds.status != hipSuccess) return pfail(p, RTC_E_DEVICE, "rtc_pred_frame_batch: hipSetDevice");
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  // persistent mode: every frame in one launch when the built kernels cover
+  // the shape (8-byte weight loads need rows of a multiple of 4 elements)
+  const rtc_mlp *m = p->net;
+  const bool vec = m->n_in % 4 == 0 && m->n_hid % 4 == 0 && reinterpret_cast<uintptr_t>(m->W1.b) % 8 == 0 &&
+                   reinterpret_cast<uintptr_t>(m->W2.b) % 8 == 0;
+  if (vec) {
+    bool ran = false;
+    const rtc_status s = rtcx::enqueue_pred_frames(c, step_args(p, nullptr, nullptr, nullptr, nullptr), p->frames,
+                                                   n_frames, d_pixels, frame_stride, d_cmd, d_slopes, d_ts, st,
+                                                   "rtc_pred_frame_batch: persistent launch", &ran);
+    if (s != RTC_OK) return pfail(p, s, c->err);
+    if (ran) {
+      for (int32_t f = 0; f < n_frames; ++f) advance(p);
+      p->last_mode = RTC_FRAMES_PERSISTENT;
+      return RTC_OK;
+    }
+  }
   for (int32_t f = 0; f < n_frames; ++f) {
     const rtc_status s = rtcx::enqueue_frame_with(
         c, d_pixels + (int64_t)f * frame_stride, d_cmd + (int64_t)f * c->n_act,
@@ -565,6 +583,13 @@ rtc_status rtc_pred_frame_batch(rtc_ctx *c, rtc_pred *p, int32_t n_frames, const
         d_ts ? d_ts + 2 * (int64_t)f : nullptr, st, "rtc_pred_frame_batch: launch", pred_frame_step, p);
     if (s != RTC_OK) return pfail(p, s, c->err);
   }
+  p->last_mode = RTC_FRAMES_PER_LAUNCH;
+  return RTC_OK;
+}
+
+rtc_status rtc_pred_last_batch_mode(const rtc_pred *p, int32_t *mode) {
+  if (!p || !mode) return pfail(nullptr, RTC_E_ARG, "rtc_pred_last_batch_mode: NULL argument");
+  *mode = p->last_mode;
   return RTC_OK;
 }
 

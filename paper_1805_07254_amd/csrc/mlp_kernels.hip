@@ -14,6 +14,7 @@
 //
 // Every reduction has a fixed order: results are run-to-run deterministic.
 #include "mlp_kernels.h"
+#include "pred_device.h"
 
 #include <algorithm>
 
@@ -23,15 +24,6 @@ namespace {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-// bfloat16 of a float, round to nearest even (NaN stays a quiet NaN).
-__device__ __forceinline__ uint16_t bf16_bits(float x) {
-  uint32_t u = __float_as_uint(x);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
-}
-
-__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
 __device__ __forceinline__ float gelu_grad(float z) {
   const float cdf = 0.5f * (1.0f + erff(z * 0.70710678118654752f));
   const float pdf = 0.39894228040143268f * expf(-0.5f * z * z);
@@ -346,210 +338,33 @@ __global__ __launch_bounds__(256) void adam_kernel(float *theta, float *m, float
   }
 }
 
-// Fixed-order sum of one value per thread of a 256-thread workgroup
-// (butterfly within each wavefront, then the four wavefronts in order).
-__device__ __forceinline__ float block_sum(float s, float *sh) {
-  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
-  __syncthreads();
-  const float t = (sh[0] + sh[1]) + (sh[2] + sh[3]);
-  __syncthreads();
-  return t;
-}
-
-// Fixed-order sums of two values per thread of a 256-thread workgroup
-// (butterflies within each wavefront, then the four wavefronts in order).
-__device__ __forceinline__ float2 block_sum2(float a, float b, float *sh) {
-  for (int off = 32; off > 0; off >>= 1) {
-    a += __shfl_xor(a, off);
-    b += __shfl_xor(b, off);
-  }
-  if ((threadIdx.x & 63) == 0) {
-    sh[threadIdx.x >> 6] = a;
-    sh[4 + (threadIdx.x >> 6)] = b;
-  }
-  __syncthreads();
-  const float2 t = make_float2((sh[0] + sh[1]) + (sh[2] + sh[3]), (sh[4] + sh[5]) + (sh[6] + sh[7]));
-  __syncthreads();
-  return t;
-}
-
-// One thread's share of the dot products of two float32 rows (16-byte
-// aligned, zero-padded to a multiple of 4 elements) with x[0, n) and y[0, m),
-// the threads of a group of NT taking the 4-element chunks first, first + NT,
-// ...: one accumulator per position in the chunk, added pairwise.  The chunks
-// are loaded B at a time, every load of a batch issued before the first
-// product (positions past the row repeat its last chunk and are masked), so
-// a thread keeps up to 2 B row loads in flight; the one partial chunk at the
-// end of a row is handled apart.
-template <int NT, int B>
-__device__ __forceinline__ float row_chunks(const float4 *r4, const float *x, int nf, int q0) {
-  float4 w[B], v[B];
-#pragma unroll
-  for (int b = 0; b < B; ++b) {
-    const int q = min(q0 + b * NT, nf - 1);
-    w[b] = r4[q];
-    v[b] = make_float4(x[4 * q], x[4 * q + 1], x[4 * q + 2], x[4 * q + 3]);
-  }
-  float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
-#pragma unroll
-  for (int b = 0; b < B; ++b) {
-    const bool ok = q0 + b * NT < nf;
-    a0 = ok ? fmaf(w[b].x, v[b].x, a0) : a0;
-    a1 = ok ? fmaf(w[b].y, v[b].y, a1) : a1;
-    a2 = ok ? fmaf(w[b].z, v[b].z, a2) : a2;
-    a3 = ok ? fmaf(w[b].w, v[b].w, a3) : a3;
-  }
-  return (a0 + a1) + (a2 + a3);
-}
-
-// The partial chunk nf = n / 4 of a row (n not a multiple of 4).
-__device__ __forceinline__ float row_tail(const float *row, const float *x, int n) {
-  const int q = n >> 2, r = n & 3;
-  const float4 w = reinterpret_cast<const float4 *>(row)[q];
-  const int k = 4 * q;
-  float t = w.x * x[k];
-  if (r > 1) t = fmaf(w.y, x[k + 1], t);
-  if (r > 2) t = fmaf(w.z, x[k + 2], t);
-  return t;
-}
-
-template <int NT, int B>
-__device__ __forceinline__ float row_part_f32(const float *row, const float *x, int n, int first) {
-  const int nf = n >> 2;
-  const float4 *r4 = reinterpret_cast<const float4 *>(row);
-  float t = 0.f;
-  for (int q0 = first; q0 < nf; q0 += B * NT) t += row_chunks<NT, B>(r4, x, nf, q0);
-  // the partial chunk belongs to the thread whose chunks it continues
-  if ((n & 3) != 0 && first == nf % NT) t += row_tail(row, x, n);
-  return t;
-}
-
-__device__ __forceinline__ float bf16_value(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
-__device__ __forceinline__ float bf16_round(float x) { return bf16_value(bf16_bits(x)); }
-
-__device__ __forceinline__ float wave_total(float t) {
-  for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off);
-  return t;
-}
-
-// sum_k W[k] bf16(x[k]) over k < n (bfloat16 row, float32 accumulation) by a
-// 256-thread workgroup.  With VEC (n a multiple of 4, row 8-byte aligned)
-// thread t takes the 4-element groups t, t + 256, ..., loaded B at a time
-// with one 8-byte load each (past the row: the last group again, masked), one
-// accumulator per position; otherwise element t + 256 i goes to accumulator
-// i mod 4.
-template <bool VEC>
-__device__ __forceinline__ float row_dot_bf16(const uint16_t *row, const float *x, int n, float *sh) {
-  float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
-  if constexpr (VEC) {
-    constexpr int B = 4;
-    const uint2 *r2 = reinterpret_cast<const uint2 *>(row);
-    const int ng = n >> 2;
-    for (int q0 = threadIdx.x; q0 < ng; q0 += B * 256) {
-      uint2 w[B];
-      float4 v[B];
-#pragma unroll
-      for (int b = 0; b < B; ++b) {
-        const int q = min(q0 + b * 256, ng - 1);
-        w[b] = r2[q];
-        v[b] = make_float4(x[4 * q], x[4 * q + 1], x[4 * q + 2], x[4 * q + 3]);
-      }
-#pragma unroll
-      for (int b = 0; b < B; ++b) {
-        const bool ok = q0 + b * 256 < ng;
-        a0 = ok ? fmaf(__uint_as_float(w[b].x << 16), bf16_round(v[b].x), a0) : a0;
-        a1 = ok ? fmaf(__uint_as_float(w[b].x & 0xffff0000u), bf16_round(v[b].y), a1) : a1;
-        a2 = ok ? fmaf(__uint_as_float(w[b].y << 16), bf16_round(v[b].z), a2) : a2;
-        a3 = ok ? fmaf(__uint_as_float(w[b].y & 0xffff0000u), bf16_round(v[b].w), a3) : a3;
-      }
-    }
-  } else {
-    int k = threadIdx.x;
-    for (; k + 768 < n; k += 1024) {
-      a0 = fmaf(bf16_value(row[k]), bf16_round(x[k]), a0);
-      a1 = fmaf(bf16_value(row[k + 256]), bf16_round(x[k + 256]), a1);
-      a2 = fmaf(bf16_value(row[k + 512]), bf16_round(x[k + 512]), a2);
-      a3 = fmaf(bf16_value(row[k + 768]), bf16_round(x[k + 768]), a3);
-    }
-    if (k < n) a0 = fmaf(bf16_value(row[k]), bf16_round(x[k]), a0);
-    if (k + 256 < n) a1 = fmaf(bf16_value(row[k + 256]), bf16_round(x[k + 256]), a1);
-    if (k + 512 < n) a2 = fmaf(bf16_value(row[k + 512]), bf16_round(x[k + 512]), a2);
-  }
-  return block_sum((a0 + a1) + (a2 + a3), sh);
-}
-
-// Step 1, one workgroup per mode j: m_j = P_j s + (P D)_j c_prev (the two
-// dot products reduced together); with a previous frame the normalised change
-// (m_j - m_prev_j - mean_j) / std_j goes to ring slots pos and pos + history
-// (so the last `history` changes are always one contiguous run); then
-// m_prev_j = m_j.
+// The predictor step's four launches (arithmetic in pred_device.h): one
+// workgroup per mode, per hidden unit and per mode, then one wavefront per
+// slope.
 __global__ __launch_bounds__(256) void pred_modes_kernel(PredStepArgs a) {
   __shared__ float sh[8];
-  const int j = blockIdx.x;
-  float mp = 0.f, mu = 0.f, is = 0.f;
-  if (threadIdx.x == 0 && a.push) {             // issued before the row loads
-    mp = a.m_prev[j];
-    mu = a.mean[j];
-    is = a.inv_std[j];
-  }
-  const float ps = row_part_f32<256, 8>(a.P + (int64_t)j * a.ldp, a.s, a.n_slopes, threadIdx.x);
-  const float pc = row_part_f32<256, 8>(a.PD + (int64_t)j * a.ldd, a.c, a.n_act, threadIdx.x);
-  const float2 t = block_sum2(ps, pc, sh);
-  if (threadIdx.x == 0) {
-    const float mj = t.x + t.y;
-    if (a.push) {
-      const float z = (mj - mp - mu) * is;
-      a.hist[(int64_t)a.pos * a.n_modes + j] = z;
-      a.hist[(int64_t)(a.pos + a.history) * a.n_modes + j] = z;
-    }
-    a.m_prev[j] = mj;
-    a.m[j] = mj;
-  }
+  pred_modes<1, false>(a, blockIdx.x, 1, 1, a.push != 0, a.pos, VecPlain{a.s}, VecPlain{a.c}, sh);
 }
 
-// Step 2, one workgroup per hidden unit i: h_i = GELU(W1_i bf16(window) + b1_i),
-// the window being the ring's slots pos + 1 .. pos + history, oldest first.
 template <bool VEC>
 __global__ __launch_bounds__(256) void pred_hidden_kernel(PredStepArgs a) {
   __shared__ float sh[4];
-  const int i = blockIdx.x;
-  const float *window = a.hist + (int64_t)(a.pos + 1) * a.n_modes;
-  const float z = row_dot_bf16<VEC>(a.W1 + (int64_t)i * a.n_in, window, a.n_in, sh) + a.b1[i];
-  if (threadIdx.x == 0) a.h[i] = gelu(z);
+  pred_hidden<VEC, 1, false>(a, blockIdx.x, 1, 1, VecPlain{a.hist + (int64_t)(a.pos + 1) * a.n_modes}, sh);
 }
 
-// Step 3, one workgroup per mode j: y_j = W2_j bf16(h) + b2_j, the forecast
-// change d_j = y_j std_j + mean_j (0 before the window is full) and the
-// forecast mode m_j + d_j.
 template <bool VEC>
 __global__ __launch_bounds__(256) void pred_forecast_kernel(PredStepArgs a) {
   __shared__ float sh[4];
-  const int j = blockIdx.x;
-  float y = 0.f;
-  if (a.full) y = row_dot_bf16<VEC>(a.W2 + (int64_t)j * a.n_hid, a.h, a.n_hid, sh) + a.b2[j];
-  if (threadIdx.x == 0) {
-    const float dj = a.full ? fmaf(y, a.std_[j], a.mean[j]) : 0.0f;
-    const float mj = a.m[j];
-    a.d[j] = dj;
-    if (a.modes_out != nullptr) {
-      a.modes_out[j] = mj;
-      a.modes_out[a.n_modes + j] = mj + dj;
-    }
-  }
+  pred_forecast<VEC, 1, false>(a, blockIdx.x, 1, 1, a.full != 0, VecPlain{a.h}, sh);
 }
 
-// Step 4, one wavefront per slope i: s_out_i = s_i + (P^T)_i d / gain (row
-// zero-padded to a multiple of 4; lane l takes the chunks l, l + 64, ...).
 __global__ __launch_bounds__(256) void pred_slopes_kernel(PredStepArgs a) {
   const int lane = threadIdx.x & 63;
   const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (i >= a.n_slopes) return;
-  const float t = wave_total(row_part_f32<64, 2>(a.PT + (int64_t)i * a.ldt, a.d, a.n_modes, lane));
-  if (lane == 0) {
-    const float v = t * a.inv_gain;
-    a.s_out[i] = a.s[i] + v;
-  }
+  float v[1];
+  pred_slopes<1>(a, i, 1, 1, lane, VecPlain{a.d}, VecPlain{a.s}, v);
+  if (lane == 0) a.s_out[i] = v[0];
 }
 
 }  // namespace

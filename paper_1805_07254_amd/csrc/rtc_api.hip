@@ -311,14 +311,14 @@ static rtc_status init_impl(const rtc_config *cfg, const rtc_wfs *wfs, int32_t n
       (e = hipMalloc(&c->d_s, s_bytes)) != hipSuccess ||
       (e = hipMalloc(&c->d_state, c->n_act * sizeof(float))) != hipSuccess ||
       (e = hipMalloc(&c->d_part, (size_t)rtck::kMaxKSplit * c->n_act * sizeof(float))) != hipSuccess ||
-      (e = hipMalloc(&c->d_sbuf, 2 * xchg_len_of(c->n_slopes) * sizeof(float))) != hipSuccess ||
+      (e = hipMalloc(&c->d_sbuf, 4 * xchg_len_of(c->n_slopes) * sizeof(float))) != hipSuccess ||
       (e = hipMalloc(&c->d_sync, kSyncWords * sizeof(uint32_t))) != hipSuccess)
     return bail(e, "rtc_init: hipMalloc");
   if ((e = hipMemcpy(c->d_tiles, c->tiles_h.data(), t_bytes, hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemset(c->d_ref, 0, s_bytes)) != hipSuccess ||
       (e = hipMemset(c->d_s, 0, s_bytes)) != hipSuccess ||
       (e = hipMemset(c->d_state, 0, c->n_act * sizeof(float))) != hipSuccess ||
-      (e = hipMemset(c->d_sbuf, 0, 2 * xchg_len_of(c->n_slopes) * sizeof(float))) != hipSuccess ||
+      (e = hipMemset(c->d_sbuf, 0, 4 * xchg_len_of(c->n_slopes) * sizeof(float))) != hipSuccess ||
       (e = hipMemset(c->d_sync, 0, kSyncWords * sizeof(uint32_t))) != hipSuccess ||
       (e = hipDeviceSynchronize()) != hipSuccess)
     return bail(e, "rtc_init: device initialisation");
@@ -1501,6 +1501,33 @@ rtc_status enqueue_frame_with(rtc_ctx *c, const uint16_t *pix, float *cmd, float
                               int32_t *counts, uint64_t *ts, hipStream_t st, const char *who, SlopeStep step,
                               void *arg) {
   return enqueue_frame(c, ctx_scratch(c), pix, cmd, slopes, recon, counts, ts, st, who, step, arg);
+}
+
+rtc_status enqueue_pred_frames(rtc_ctx *c, const rtcm::PredStepArgs &q, int32_t seen, int32_t n_frames,
+                               const uint16_t *d_pixels, int64_t frame_stride, float *d_cmd, float *d_slopes,
+                               uint64_t *d_ts, hipStream_t st, const char *who, bool *ran) {
+  *ran = false;
+  if (c->frame_mode != RTC_FRAMES_PERSISTENT || n_frames <= 0) return RTC_OK;
+  rtck::PersistArgs p = persist_args(c, n_frames, d_pixels, frame_stride, d_cmd, d_slopes, nullptr, nullptr, d_ts);
+  p.trace = nullptr;                                // the stage trace covers plain frames only
+  p.pred = q;
+  p.pred_seen = seen;
+  p.sbuf_pred = c->d_sbuf + 2 * xchg_len_of(c->n_slopes);
+  const int blocks = c->tuning.blocks > 0 ? c->tuning.blocks : c->n_cu;
+  const int G = rtck::frames_grid(blocks, c->n_act);
+  p.calib_span = calib_span(c, G);
+  if (c->split_G > 0 && c->split_G == G) {
+    p.row_start = c->d_row_start;
+    p.row_max = c->split_max;
+  }
+  const hipError_t e = rtck::launch_frames(p, blocks, c->tuning.rows_per_wave, st);
+  if (e == hipErrorInvalidValue || e == hipErrorCooperativeLaunchTooLarge) {
+    (void)hipGetLastError();                        // shape not built: the caller runs per-launch frames
+    return RTC_OK;
+  }
+  if (e != hipSuccess) return hip_fail(c, e, who);
+  *ran = true;
+  return RTC_OK;
 }
 
 }  // namespace rtcx

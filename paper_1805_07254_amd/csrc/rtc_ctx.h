@@ -46,7 +46,8 @@ struct rtc_ctx {
   float *d_s = nullptr;
   float *d_state = nullptr;
   float *d_part = nullptr;
-  float *d_sbuf = nullptr;   // [2][s_len] slope vectors of consecutive frames (persistent batches)
+  float *d_sbuf = nullptr;   // [4][s_len]: slope vectors of consecutive frames (persistent batches), then
+                             // the feed-forward slopes of consecutive predictive frames
   uint32_t *d_sync = nullptr;  // rtck::sync_layout words: stamp counter, abort flags, persistent barrier
   uint32_t *d_scratch = nullptr;  // this device's static scratch array (rtc_frame_batch_noalloc); not owned
   uint32_t *h_trig = nullptr;      // coherent host words of paced batches: [0] release, [32] done
@@ -139,5 +140,14 @@ using SlopeStep = hipError_t (*)(void *arg, const float *s, const float *c_prev,
 rtc_status enqueue_frame_with(rtc_ctx *c, const uint16_t *pix, float *cmd, float *slopes, float *recon,
                               int32_t *counts, uint64_t *ts, hipStream_t st, const char *who, SlopeStep step,
                               void *arg);
+
+// Predictive frames in one persistent launch when the context is in the
+// persistent mode and the built kernels cover its shape (*ran = true); the
+// step's arguments q (vectors and per-frame flags are set by the kernel), its
+// ring slot q.pos and the frames it has seen (seen) before the batch.
+// *ran = false: nothing was enqueued, the caller runs per-launch frames.
+rtc_status enqueue_pred_frames(rtc_ctx *c, const rtcm::PredStepArgs &q, int32_t seen, int32_t n_frames,
+                               const uint16_t *d_pixels, int64_t frame_stride, float *d_cmd, float *d_slopes,
+                               uint64_t *d_ts, hipStream_t st, const char *who, bool *ran);
 
 }  // namespace rtcx

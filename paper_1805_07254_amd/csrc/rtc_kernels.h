@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "pred_step.h"
+
 namespace rtck {
 
 // One active subaperture (32 bytes): where its pixels and calibration are,
@@ -114,6 +116,15 @@ struct PersistArgs {
   const uint32_t *trig_release;
   uint32_t *trig_done;
   uint32_t trig_base;
+  // predictive frames (pred.n_modes > 0): the learned predictor's step runs
+  // between the slope exchange and the products, in four phases with a grid
+  // barrier after each; the kernel sets its vectors (s, c, s_out) and the
+  // per-frame push / full / pos, starting from ring slot pred.pos with
+  // pred_seen frames seen (at most the history) before the launch.  Rows of
+  // W1 and W2 must start 8-byte aligned with n_in and n_hid multiples of 4.
+  rtcm::PredStepArgs pred;
+  int32_t pred_seen;
+  float *sbuf_pred;        // [2][s_len] feed-forward slopes in the exchange layout, zero-padded
 };
 constexpr int kTraceStages = 8;
 // Zeroes the barrier counters, the mailboxes of G workgroups and the abort flag

@@ -23,11 +23,15 @@
 //    trees, and the split-K partials are summed in a fixed pairwise tree.
 #include "rtc_kernels.h"
 #include "rtc_device.h"
+#include "pred_device.h"
 
 namespace rtck {
 namespace {
 
 constexpr int kBlock = 256;
+// predictive frames: rows of the predictor step a workgroup takes at a time
+// (modes, hidden units), slopes a wavefront takes at a time
+constexpr int kModeRows = 2, kHiddenRows = 4, kSlopeRows = 8;
 
 // Slope exchange layout of persistent batches: the EPC slopes of chunk c sit
 // element-major inside their group of 64 chunks, so lane l of a wavefront reads
@@ -36,6 +40,16 @@ __device__ __forceinline__ int64_t xchg_pos(int64_t k, int epc) {
   const int64_t c = k / epc, e = k - c * epc;
   return (c >> 6) * (64 * epc) + e * 64 + (c & 63);
 }
+
+// Slope k of an exchange buffer of EPC elements per chunk, read
+// device-coherently (predictive frames).
+template <int EPC>
+struct VecXchg {
+  const float *x;
+  __device__ __forceinline__ float operator()(int64_t k) const {
+    return __hip_atomic_load(x + xchg_pos(k, EPC), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+};
 
 
 // ---------------------------------------------------------------------------
@@ -766,10 +780,14 @@ __device__ __forceinline__ void lds_row_group(const uint4 *lds, int ldq16, int r
 // 512-entry register file: RR rows of the slab are kept in ordinary registers
 // and RA more in accumulation registers (AGPRs, which the matrix cores would
 // otherwise use), so more of the matrix stays on chip.
-template <int FMT, int KPL, int RR, int RA, int VW, int GS, bool PANELS, bool TRIG>
+// TRIG: frames released one by one by the host.  PRED: predictive frames (the
+// learned predictor's step between the slope exchange and the products, by
+// 256-thread workgroups, so VW = 2 only).
+template <int FMT, int KPL, int RR, int RA, int VW, int GS, bool PANELS, bool TRIG, bool PRED>
 __global__ __launch_bounds__(512 / VW) void frames_kernel(PersistArgs p, int32_t max_rows, int32_t lds_rows,
                                                           int32_t tile_cap, int32_t calib_cap) {
   static_assert(!PANELS || (VW == 1 && RA == 0), "slope panels use 8 wavefronts");
+  static_assert(!PRED || (VW == 2 && !PANELS && !TRIG), "predictive frames use 256-thread workgroups");
   constexpr int W = 8;                             // slope slices
   constexpr int PW = W / VW;                       // wavefronts of the workgroup
   constexpr int NT = PW * 64;
@@ -866,6 +884,12 @@ __global__ __launch_bounds__(512 / VW) void frames_kernel(PersistArgs p, int32_t
   if (tid < nrows) state = a.state[row_begin + tid];
   if (tid == 0) sh_bar = 0u;
   __syncthreads();
+  // predictive frames: the ring slot of the next change, the frames the
+  // predictor has seen (at most its history), and the barrier flags of the
+  // frame's earlier barriers (sh_bar holds the last one's)
+  int ppos = PRED ? p.pred.pos : 0;
+  int pseen = PRED ? p.pred_seen : 0;
+  uint32_t pflags = 0u;
 
   int frames_done = 0;
   for (int f = 0; f < p.n_frames; ++f) {
@@ -890,8 +914,9 @@ __global__ __launch_bounds__(512 / VW) void frames_kernel(PersistArgs p, int32_t
     // beside the previous frame's barrier arrival (bit 1 of sh_bar), so no
     // frame starts with a memory round trip.
     if constexpr (!TRIG) {
-      if (sh_bar & 2u) break;
+      if ((sh_bar | pflags) & 2u) break;
     }
+    pflags = 0u;
     if constexpr (TRIG) {                           // externally triggered frames (own check)
       if (wave == 0) trigger_wait(p, f);
       if (tid == 0) sh_abort = __hip_atomic_load(p.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -927,8 +952,63 @@ __global__ __launch_bounds__(512 / VW) void frames_kernel(PersistArgs p, int32_t
     // flag raised anywhere) ends the loop at the next frame's top.  sh_bar is
     // next written after the next frame's barrier has synchronised the
     // workgroup, so the reads below and at that top cannot race with it.
-    (void)frame_barrier(p, (uint32_t)(f + 1), f, &sh_bar);
+    // barrier epochs: one per frame, five per predictive frame
+    const uint32_t ep = PRED ? 5u * (uint32_t)f : (uint32_t)f;
+    (void)frame_barrier(p, ep + 1u, f, &sh_bar);
     trace_stamp(p, f, 2);
+
+    // the slopes the products use: the measured ones, or the feed-forward
+    // slopes of a predictive frame
+    const float *s_prod = ca.s_int;
+    if constexpr (PRED) {
+      // The predictor step in four phases, each row (mode, hidden unit, mode,
+      // slope) by one workgroup (one wavefront for slopes) as in the step's own
+      // launches, so every value has the same bits; what a later phase reads
+      // from other workgroups is stored and loaded device-coherently.
+      __shared__ float sh_pred[16];
+      const rtcm::PredStepArgs &q = p.pred;
+      const bool push = pseen > 0, full = pseen >= q.history;
+      const VecXchg<EPC> sx{ca.s_int};
+      const float *cprev = f > 0 ? a.cmd + (int64_t)(f - 1) * a.n_act : a.state;
+      // rows b, b + G, ... of each kind, a few at a time (their loads in flight together)
+      auto rows_of = [&](int r0, int n, int step, int most) { return min(most, (n - r0 + step - 1) / step); };
+      pflags |= sh_bar;
+      for (int j0 = b; j0 < q.n_modes; j0 += G * kModeRows)
+        rtcm::pred_modes<kModeRows, true>(q, j0, G, rows_of(j0, q.n_modes, G, kModeRows), push, ppos, sx,
+                                          rtcm::VecCoh{cprev}, sh_pred);
+      (void)frame_barrier(p, ep + 2u, f, &sh_bar);
+      pflags |= sh_bar;
+      if (full) {
+        const rtcm::VecCoh window{q.hist + (int64_t)(ppos + 1) * q.n_modes};
+        for (int i0 = b; i0 < q.n_hid; i0 += G * kHiddenRows)
+          rtcm::pred_hidden<true, kHiddenRows, true>(q, i0, G, rows_of(i0, q.n_hid, G, kHiddenRows), window,
+                                                     sh_pred);
+      }
+      (void)frame_barrier(p, ep + 3u, f, &sh_bar);
+      pflags |= sh_bar;
+      for (int j0 = b; j0 < q.n_modes; j0 += G * kModeRows)
+        rtcm::pred_forecast<true, kModeRows, true>(q, j0, G, rows_of(j0, q.n_modes, G, kModeRows), full,
+                                                   rtcm::VecCoh{q.h}, sh_pred);
+      (void)frame_barrier(p, ep + 4u, f, &sh_bar);
+      pflags |= sh_bar;
+      float *so = p.sbuf_pred + (int64_t)(f & 1) * p.s_len;
+      // slopes: wavefront w of workgroup b takes i = 4 b + w, + 4 G, ...
+      for (int i0 = b * 4 + wave; i0 < q.n_slopes; i0 += 4 * G * kSlopeRows) {
+        float v[kSlopeRows];
+        const int nr = rows_of(i0, q.n_slopes, 4 * G, kSlopeRows);
+        rtcm::pred_slopes<kSlopeRows>(q, i0, 4 * G, nr, lane, rtcm::VecCoh{q.d}, sx, v);
+        if (lane == 0)
+#pragma unroll
+          for (int r = 0; r < kSlopeRows; ++r)
+            if (r < nr)
+              __hip_atomic_store(so + xchg_pos(i0 + r * 4 * G, EPC), v[r], __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT);
+      }
+      (void)frame_barrier(p, ep + 5u, f, &sh_bar);
+      s_prod = so;
+      if (pseen > 0) ppos = (ppos + 1) % q.history;
+      if (pseen < q.history) ++pseen;
+    }
 
     if constexpr (PANELS) {
       // long slope vectors: panels of the slope vector, every row streamed per panel
@@ -943,7 +1023,7 @@ __global__ __launch_bounds__(512 / VW) void frames_kernel(PersistArgs p, int32_t
           const int c = (pn * W + wave) * 64 * KPL + j * 64 + lane;
           const bool ok = c < a.n_chunks;
           pcol[j] = ok ? c : 0;
-          const float *grp = ca.s_int + (int64_t)(ok ? (c >> 6) : 0) * (64 * EPC) + lane;
+          const float *grp = s_prod + (int64_t)(ok ? (c >> 6) : 0) * (64 * EPC) + lane;
 #pragma unroll
           for (int e = 0; e < EPC; ++e) {
             const float v = __hip_atomic_load(grp + e * 64, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -963,7 +1043,7 @@ __global__ __launch_bounds__(512 / VW) void frames_kernel(PersistArgs p, int32_t
         for (int j = 0; j < KPL; ++j) {
           // this lane's chunk group; lanes past the slice read group 0 (in bounds) and zero it
           const int64_t g = okc[u][j] ? (int64_t)((k_lo >> 6) + j) : 0;
-          const float *grp = ca.s_int + g * (64 * EPC) + lane;
+          const float *grp = s_prod + g * (64 * EPC) + lane;
 #pragma unroll
           for (int e = 0; e < EPC; ++e) {
             const float v = __hip_atomic_load(grp + e * 64, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1058,7 +1138,7 @@ __global__ __launch_bounds__(512 / VW) void frames_kernel(PersistArgs p, int32_t
     trace_stamp(p, f, 4);
 
     // (d) integrate own rows (not when this workgroup's barrier wait expired)
-    if (tid < nrows && (sh_bar & 1u) == 0u) {
+    if (tid < nrows && ((sh_bar | pflags) & 1u) == 0u) {
       float v = sh_part[tid];
       for (int w = 1; w < W; ++w) v += sh_part[w * max_rows + tid];
       if (a.scales != nullptr) v *= a.scales[row_begin + tid];
@@ -1068,6 +1148,8 @@ __global__ __launch_bounds__(512 / VW) void frames_kernel(PersistArgs p, int32_t
       float *cp = a.cmd + (int64_t)f * a.n_act + row_begin + tid;
       if constexpr (TRIG)                          // triggered frames: commands visible to the host
         __hip_atomic_store(cp, c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      else if constexpr (PRED)                     // the next frame's modes read them
+        __hip_atomic_store(cp, c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       else
         *cp = c;
       if (a.recon != nullptr) a.recon[(int64_t)f * a.n_act + row_begin + tid] = v;
@@ -1080,7 +1162,7 @@ __global__ __launch_bounds__(512 / VW) void frames_kernel(PersistArgs p, int32_t
         __hip_atomic_store(reinterpret_cast<uint64_t *>(p.bar + sl::kEnds) + (f & 1) * sl::kMaxGroups + b,
                            wall_clock64(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    frames_done += (sh_bar & 1u) == 0u ? 1 : 0;
+    frames_done += ((sh_bar | pflags) & 1u) == 0u ? 1 : 0;
   }
   if (tid < nrows) a.state[row_begin + tid] = state;
   // end stamp of the last frame: the last workgroup to finish reduces it
@@ -1325,11 +1407,20 @@ static hipError_t launch_frames_variant(const PersistArgs &p, int G, int max_row
   // externally triggered batches: a variant of their own (the trigger's wait
   // costs registers), built for tiles of up to 16 pixels without slope panels
   constexpr bool kTrigBuilt = GS <= 16 && !PANELS;
+  // predictive frames: 256-thread workgroups, tiles of up to 16 pixels
+  constexpr bool kPredBuilt = FS::VW == 2 && GS <= 16 && !PANELS;
   const bool trig = p.trig_release != nullptr;
+  const bool pred = p.pred.n_modes > 0;
   if (trig && !kTrigBuilt) return hipErrorInvalidValue;
-  auto kern = frames_kernel<FMT, KPL, FS::RR, FS::RA, FS::VW, GS, PANELS, false>;
+  if (pred && (!kPredBuilt || trig || p.trace != nullptr)) return hipErrorInvalidValue;
+  auto kern = frames_kernel<FMT, KPL, FS::RR, FS::RA, FS::VW, GS, PANELS, false, false>;
   if constexpr (kTrigBuilt) {
-    if (trig) kern = frames_kernel<FMT, KPL, FS::RR, FS::RA, FS::VW, GS, PANELS, true>;
+    if (trig) kern = frames_kernel<FMT, KPL, FS::RR, FS::RA, FS::VW, GS, PANELS, true, false>;
+  }
+  if constexpr (kPredBuilt) {
+    // the predictor's phases need registers: the slab's register rows are
+    // streamed instead
+    if (pred) kern = frames_kernel<FMT, KPL, 0, FS::RA, FS::VW, GS, PANELS, false, true>;
   }
   int dev = 0, ncu = 0, lds_max = 0;
   hipError_t e;
@@ -1337,7 +1428,7 @@ static hipError_t launch_frames_variant(const PersistArgs &p, int G, int max_row
   if ((e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
   if ((e = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev)) != hipSuccess) return e;
   const int64_t part_bytes = (int64_t)W * max_rows * sizeof(float);
-  const int64_t static_bytes = 64;                 // sh_abort, sh_bar and alignment slack
+  const int64_t static_bytes = 128;                // sh_abort, sh_bar, sh_pred and alignment slack
   // tile descriptors and reference slopes of a workgroup's subapertures, kept in LDS
   const int per_wg = (p.cal.n_valid + G - 1) / G;
   const int tile_cap = per_wg <= kTileCache ? per_wg : 0;

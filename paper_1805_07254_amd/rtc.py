@@ -97,6 +97,7 @@ _SIGNATURES = {
     "rtc_pred_reset": (_i32, [_vp]),
     "rtc_pred_step": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "rtc_pred_frame_batch": (_i32, [_vp, _vp, _i32, _vp, _i64, _vp, _vp, _vp, _vp]),
+    "rtc_pred_last_batch_mode": (_i32, [_vp, _vp]),
     "rtc_pred_destroy": (None, [_vp]),
     "rtc_pred_error_string": (ctypes.c_char_p, [_vp]),
     "rtc_autotune": (_i32, [_vp, _i32, _vp, _i64, _vp, _vp, _i32, ctypes.POINTER(_i32), _vp]),
@@ -776,6 +777,12 @@ class Predictor:
             _dev_ptr(cmd, "float32", n_frames * ctx.n_act, "cmd", ctx),
             _dev_ptr(slopes, "float32", n_frames * ctx.n_slopes, "slopes", ctx, False),
             _dev_ptr(ts, ("uint64", "int64"), 2 * n_frames, "ts", ctx, False), _stream_ptr(stream)))
+
+    def last_batch_mode(self) -> int:
+        """RTC_FRAMES_PERSISTENT or RTC_FRAMES_PER_LAUNCH: how the last frame_batch ran."""
+        out = ctypes.c_int32()
+        self._chk(load_library().rtc_pred_last_batch_mode(self.handle, ctypes.byref(out)))
+        return out.value
 
     def close(self):
         if self.handle is not None and self.handle.value:

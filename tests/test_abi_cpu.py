@@ -162,5 +162,7 @@ def test_mlp_create_rejects_bad_sizes_and_reports_no_device():
     if not torch.cuda.is_available():
         assert lib.rtc_mlp_create(4, 4, 4, 8, 0, ctypes.byref(out)) == rtc.RTC_E_DEVICE
     assert lib.rtc_pred_create(None, 1, 1, 1, 1, None, None, None, None, 0.4, ctypes.byref(out)) == rtc.RTC_E_ARG
+    mode = ctypes.c_int32(-1)
+    assert lib.rtc_pred_last_batch_mode(None, ctypes.byref(mode)) == rtc.RTC_E_ARG and mode.value == -1
     lib.rtc_mlp_destroy(None)
     lib.rtc_pred_destroy(None)

@@ -1,12 +1,14 @@
 """Predictive frames (rtc_pred_frame_batch): the per-launch frame with the
 predictor step between the slopes and the reconstruction, against the same
 steps called one by one and, before the network's window fills, against the
-plain integrator."""
+plain integrator; the persistent form (one launch, the step's phases between
+grid barriers) against the per-launch form, bit for bit, at the tiny and the
+ELT shape."""
 import numpy as np
 import pytest
 
 from _gpu_helpers import _ctx_for, _dev
-from aosim import TINY, Scenario
+from aosim import ELT, TINY, Scenario
 
 torch = pytest.importorskip("torch")
 from paper_1805_07254_amd import rtc  # noqa: E402
@@ -93,3 +95,94 @@ def test_predictive_frames_are_the_integrator_until_the_window_fills(setup):
         assert torch.equal(cmd_a, cmd_b)
         p.close()
 
+
+
+def _model(sc, nm, hist, hid, seed):
+    rng = np.random.default_rng(seed)
+    ns, na = 2 * sc.n_valid, sc.n_act
+    P = np.linalg.qr(rng.standard_normal((ns, nm)))[0].T.astype(np.float32)
+    PD = (rng.standard_normal((nm, na)) / np.sqrt(na)).astype(np.float32)
+    mean = (rng.standard_normal(nm) * 0.01).astype(np.float32)
+    std = (0.05 + 0.1 * rng.random(nm)).astype(np.float32)
+    params = [(rng.standard_normal((hid, hist * nm)) * 0.3 / np.sqrt(hist * nm)).astype(np.float32),
+              (rng.standard_normal(hid) * 0.1).astype(np.float32),
+              (rng.standard_normal((nm, hid)) * 0.3 / np.sqrt(hid)).astype(np.float32),
+              (rng.standard_normal(nm) * 0.1).astype(np.float32)]
+    return P, PD, mean, std, params
+
+
+def _persistent_vs_per_launch(sc, frames, nm, hist, hid, model, chunks, expect_mode):
+    """Batches of the given sizes in both modes, one after another (the
+    predictor and integrator state carried across batches), compared bit for
+    bit after every batch."""
+    F = frames.shape[0]
+    assert sum(chunks) == F
+    pix = _dev(frames.reshape(F, -1))
+    P, PD, mean, std, params = model
+    with rtc.MlpNet(hist * nm, hid, nm, 4) as na_, rtc.MlpNet(hist * nm, hid, nm, 4) as nb_, \
+            _ctx_for(sc) as a, _ctx_for(sc) as b:
+        rtc.rtc_set_frame_mode(a, rtc.RTC_FRAMES_PERSISTENT)
+        na_.set_params(*params)
+        nb_.set_params(*params)
+        pa = rtc.Predictor(na_, hist, P, PD, mean, std, sc.cfg.gain)
+        pb = rtc.Predictor(nb_, hist, P, PD, mean, std, sc.cfg.gain)
+        z = lambda n, dt=torch.float32: torch.zeros(n, dtype=dt, device="cuda:0")  # noqa: E731
+        cmd_a, cmd_b = z(F * a.n_act), z(F * b.n_act)
+        s_a, s_b = z(F * a.n_slopes), z(F * b.n_slopes)
+        ts_a = z(2 * F, torch.int64)
+        f0 = 0
+        for n in chunks:
+            print(f"predictive batch of {n} frames from {f0}: persistent context, per-launch context", flush=True)
+            pa.frame_batch(a, n, pix[f0:], cmd_a[f0 * a.n_act:], s_a[f0 * a.n_slopes:], ts_a[2 * f0:])
+            assert pa.last_batch_mode() == expect_mode
+            pb.frame_batch(b, n, pix[f0:], cmd_b[f0 * b.n_act:], s_b[f0 * b.n_slopes:])
+            assert pb.last_batch_mode() == rtc.RTC_FRAMES_PER_LAUNCH
+            torch.cuda.synchronize()
+            rtc.rtc_sync_check(a)
+            f1 = f0 + n
+            assert torch.equal(s_a[:f1 * a.n_slopes], s_b[:f1 * b.n_slopes]), f"slopes, frames < {f1}"
+            assert torch.equal(cmd_a[:f1 * a.n_act], cmd_b[:f1 * b.n_act]), f"commands, frames < {f1}"
+            assert np.array_equal(rtc.rtc_get_state(a), rtc.rtc_get_state(b))
+            f0 = f1
+        t = ts_a.cpu().numpy().reshape(F, 2)
+        assert np.all(t[:, 1] > t[:, 0]) and np.all(np.diff(t[:, 0]) > 0)
+        # the forecast changed the commands once the window was full
+        with _ctx_for(sc) as c:
+            cmd_c = z(F * c.n_act)
+            rtc.rtc_frame_batch(c, F, pix, cmd_c)
+            torch.cuda.synchronize()
+            assert not torch.equal(cmd_c, cmd_a)
+        pa.close()
+        pb.close()
+
+
+def test_persistent_predictive_frames_equal_the_per_launch_ones(setup):
+    sc, frames, _ = setup
+    model = _model(sc, NM, HIST, HID, 11)
+    # batches shorter than, equal to and longer than the window, so that the
+    # ring and the frames seen carry over between launches at every stage
+    _persistent_vs_per_launch(sc, frames, NM, HIST, HID, model, [2, 3, 11], rtc.RTC_FRAMES_PERSISTENT)
+
+
+def test_predictive_frames_whose_network_is_not_built_persistent_run_per_launch(setup):
+    # 13 modes x 3 frames = 39 inputs: the 8-byte weight rows the persistent
+    # phases read need a multiple of 4, so the batch runs per launch
+    sc, frames, _ = setup
+    model = _model(sc, 13, HIST, HID, 12)
+    _persistent_vs_per_launch(sc, frames[:6], 13, HIST, HID, model, [6], rtc.RTC_FRAMES_PER_LAUNCH)
+
+
+@pytest.fixture(scope="module")
+def elt_frames():
+    sc = Scenario(ELT)
+    F = 9
+    frames = np.stack([sc.frame(i, sc.turbulence_slopes(i)) for i in range(F)])
+    return sc, frames
+
+
+def test_persistent_predictive_elt_frames_equal_the_per_launch_ones(elt_frames):
+    # the benchmark's predictor shape: 500 modes, 5 frames of history, 1024 hidden units
+    sc, frames = elt_frames
+    nm, hist, hid = 500, 5, 1024
+    model = _model(sc, nm, hist, hid, 13)
+    _persistent_vs_per_launch(sc, frames, nm, hist, hid, model, [4, 5], rtc.RTC_FRAMES_PERSISTENT)

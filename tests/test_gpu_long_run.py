@@ -1,8 +1,9 @@
-"""The benchmark's launch at full size: 10,000 ELT frames in one persistent
-launch, every frame's outputs against the FP64 oracle.
+"""Long persistent runs at full size against the FP64 oracle: the benchmark's
+launch (10,000 ELT frames in one persistent launch) and a closed loop of
+1,000 ELT frames.
 
-The pixel frames are open-loop (no command feeds back into them) and cycle
-through a ring of distinct frames, as in the benchmark, so the oracle computes
+In the benchmark's launch the pixel frames are open-loop (no command feeds
+back into them) and cycle through a ring of distinct frames, so the oracle computes
 calibration, centroids and the reconstruction (Figure 3 (a)-(c)) once per
 distinct frame.  Counts are compared bit for bit and slopes and
 reconstructions within the per-frame tolerance for all 10,000 frames; the
@@ -14,7 +15,8 @@ import numpy as np
 import pytest
 
 import oracle
-from _gpu_helpers import TOL, _ctx_for
+from _closedloop import oracle_closed_loop
+from _gpu_helpers import TOL, _ctx_for, check_parity
 from aosim import ELT, Scenario
 
 torch = pytest.importorskip("torch")
@@ -111,3 +113,36 @@ def test_ten_thousand_elt_frames_in_one_persistent_launch(elt_ring):
         worst["recursion"] = max(worst["recursion"], dr / bound)
     print(f"{FRAMES} ELT frames: worst error / tolerance {worst}; final command "
           f"{np.abs(c_ref).max():.4g} max, off the oracle by {np.abs(g_cmd[-1] - c_ref).max():.3g}", flush=True)
+
+
+def test_thousand_closed_loop_elt_frames_in_one_persistent_launch():
+    # The oracle closes the loop (each frame made from the turbulence minus the
+    # previous command), the device replays the recorded pixels in one
+    # persistent launch; every frame is checked with the per-step gates, and
+    # the commands against the oracle's own recursion within the bound above.
+    sc = Scenario(ELT)
+    F = 1000
+    frames, ref = oracle_closed_loop(sc, F)
+    pix = torch.from_numpy(frames.reshape(F, -1).view(np.int16)).to("cuda:0").view(torch.uint16)
+    z = lambda n, dt=torch.float32: torch.zeros(n, dtype=dt, device="cuda:0")  # noqa: E731
+    with _ctx_for(sc) as ctx:
+        rtc.rtc_set_frame_mode(ctx, rtc.RTC_FRAMES_PERSISTENT)
+        out = dict(cmd=z(F * ctx.n_act), slopes=z(F * ctx.n_slopes), recon=z(F * ctx.n_act),
+                   counts=z(F * ctx.n_valid, torch.int32))
+        print(f"ELT closed loop: persistent launch of {F} frames", flush=True)
+        rtc.rtc_frame_batch(ctx, F, pix, out["cmd"], out["slopes"], out["recon"], out["counts"])
+        torch.cuda.synchronize()
+        rtc.rtc_sync_check(ctx)
+    gpu = {k: v.cpu().numpy().reshape(F, -1) for k, v in out.items()}
+    check_parity(gpu, ref, sc.cfg.gain, sc.cfg.leak, what=f"ELT closed loop, {F} persistent frames")
+    g = float(np.float32(sc.cfg.gain))
+    lam = float(np.float32(sc.cfg.leak))
+    bound, worst = 0.0, 0.0
+    for k in range(F):
+        A = np.abs(ref["recon"][k]).max()
+        c_ref = ref["cmd"][k]
+        bound = lam * bound + g * TOL * A + 2 * U32 * (np.abs(c_ref).max() + bound + g * A)
+        dr = np.abs(gpu["cmd"][k].astype(np.float64) - c_ref).max()
+        assert dr <= bound, f"frame {k}: command off the oracle's recursion by {dr} > {bound}"
+        worst = max(worst, dr / bound)
+    print(f"closed loop: commands within {worst:.3f} of the recursion bound", flush=True)

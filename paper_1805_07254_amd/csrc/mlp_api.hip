@@ -59,6 +59,7 @@ struct rtc_mlp {
   Tensor W1, b1, W2, b2;
   float *Z1 = nullptr, *Y = nullptr, *dY = nullptr, *dH = nullptr, *dZ1 = nullptr, *row_sq = nullptr;
   uint16_t *Hb = nullptr, *dYb = nullptr, *dZ1b = nullptr;
+  uint16_t *Xb = nullptr;  // a training batch's inputs rounded to bfloat16 once, for both products that read them
   float *ws = nullptr;     // split-K partial tiles of the training products
   int64_t ws_len = 0;
   std::string err = "no error";
@@ -113,15 +114,19 @@ void free_tensor(Tensor &t) {
   dfree(t.b);
 }
 
-// Forward into m->Z1 / Hb / y (y has batch rows of n_out).
-hipError_t forward(rtc_mlp *m, int32_t B, const float *x, float *y, hipStream_t st) {
+// Forward into m->Z1 / Hb / y (y has batch rows of n_out); xb (nullable): x
+// already rounded to bfloat16.
+hipError_t forward(rtc_mlp *m, int32_t B, const float *x, float *y, hipStream_t st, const uint16_t *xb = nullptr) {
   rtcm::GemmArgs g{};
   g.ws = m->ws;
   g.ws_len = m->ws_len;
   g.M = B;
   g.N = m->n_hid;
   g.K = m->n_in;
-  g.a_f32 = x;
+  if (xb)
+    g.a_bf16 = xb;
+  else
+    g.a_f32 = x;
   g.sam = m->n_in;
   g.sak = 1;
   g.b_bf16 = m->W1.b;
@@ -233,6 +238,7 @@ rtc_status rtc_mlp_create(int32_t n_in, int32_t n_hidden, int32_t n_out, int32_t
   if (e == hipSuccess) e = hipMalloc(&m->dH, (size_t)B * n_hidden * sizeof(float));
   if (e == hipSuccess) e = hipMalloc(&m->dZ1, (size_t)B * n_hidden * sizeof(float));
   if (e == hipSuccess) e = hipMalloc(&m->dZ1b, (size_t)B * n_hidden * sizeof(uint16_t));
+  if (e == hipSuccess) e = hipMalloc(&m->Xb, (size_t)B * n_in * sizeof(uint16_t));
   if (e == hipSuccess) e = hipMalloc(&m->row_sq, (size_t)B * sizeof(float));
   {
     // up to 8 splits of the largest product's output
@@ -304,7 +310,10 @@ rtc_status rtc_mlp_loss_grad(rtc_mlp *m, int32_t B, const float *d_x, const floa
   DevScope ds(m->device);
   if (ds.status != hipSuccess) return hfail(m, ds.status, "rtc_mlp_loss_grad: hipSetDevice");
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
-  hipError_t e = forward(m, B, d_x, m->Y, st);
+  // the inputs in bfloat16 once (the products would round them as they load
+  // them, once per tile that reads them)
+  hipError_t e = rtcm::launch_round_bf16(d_x, m->Xb, (int64_t)B * m->n_in, st);
+  if (e == hipSuccess) e = forward(m, B, d_x, m->Y, st, m->Xb);
   if (e == hipSuccess) e = rtcm::launch_loss_grad(m->Y, d_t, B, m->n_out, m->dY, m->dYb, m->row_sq, d_loss, st);
   if (e == hipSuccess) {                            // dW2 = dY^T H
     rtcm::GemmArgs g{};
@@ -354,7 +363,7 @@ rtc_status rtc_mlp_loss_grad(rtc_mlp *m, int32_t B, const float *d_x, const floa
     g.a_bf16 = m->dZ1b;
     g.sam = 1;
     g.sak = m->n_hid;
-    g.b_f32 = d_x;
+    g.b_bf16 = m->Xb;
     g.sbk = m->n_in;
     g.sbn = 1;
     g.alpha = 1.0f;
@@ -413,6 +422,7 @@ void rtc_mlp_destroy(rtc_mlp *m) {
   dfree(m->dH);
   dfree(m->dZ1);
   dfree(m->dZ1b);
+  dfree(m->Xb);
   dfree(m->ws);
   dfree(m->row_sq);
   delete m;

@@ -39,8 +39,15 @@ __device__ __forceinline__ float gelu_grad(float z) {
 // elements along the operand's contiguous dimension (k for X W^T, m or n for
 // the weight gradients), one 8- or 16-byte load per run where the rows are
 // aligned, element by element otherwise.  The K range may be split over
-// gridDim.z workgroups whose float32 partial tiles a second kernel adds in
+// `splits` workgroups whose float32 partial tiles a second kernel adds in
 // split order.
+// Tile order: the grid is one-dimensional and workgroup L runs on XCD L mod 8
+// (the dispatcher deals workgroups to the eight XCDs in turn), so XCD x takes
+// the contiguous range [x per, (x + 1) per) of a logical order in which the
+// split is slowest and, within a split, the tiles that share the smaller
+// operand's panels are adjacent (M tiles fastest when A is the smaller
+// operand): each XCD's L2 then holds the panels its workgroups read instead of
+// every XCD streaming both operands whole.
 // Operand layout of the 32x32x16 operation: lane l supplies row (A) or column
 // (B) l % 32 and the eight consecutive k = 8 (l / 32) .. 8 (l / 32) + 7; its
 // 16 results are column l % 32, rows 8 (v / 4) + 4 (l / 32) + v % 4.
@@ -154,14 +161,26 @@ __device__ __forceinline__ void store_tile(const Operand &o, const TileRegs<R> &
   }
 }
 
+struct GemmTiles {
+  int ntm, ntn, splits;      // M tiles, N tiles, K splits
+  int per;                   // logical tiles per XCD
+  int m_fast;                // M tiles vary fastest within a split
+};
+
 template <int BM, int BN, bool VEC>
-__global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g, int k_chunk, int a_vec, int b_vec) {
+__global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g, int k_chunk, int a_vec, int b_vec, GemmTiles tl) {
   constexpr int MB = BM / 64, NB = BN / 64;        // 32 x 32 blocks per wavefront along m and n
   __shared__ __align__(16) uint16_t As[2][BM][kKP];   // [m][k]
   __shared__ __align__(16) uint16_t Bs[2][BN][kKP];   // [n][k]
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
-  const int kb0 = blockIdx.z * k_chunk;
+  const int per_split = tl.ntm * tl.ntn;
+  const int lt = (int)(blockIdx.x % 8u) * tl.per + (int)(blockIdx.x / 8u);   // logical tile
+  if (lt >= per_split * tl.splits) return;        // the grid is rounded up to 8 XCD ranges
+  const int kz = lt / per_split, rt = lt - kz * per_split;
+  const int tm = tl.m_fast ? rt % tl.ntm : rt / tl.ntn;
+  const int tn = tl.m_fast ? rt / tl.ntm : rt % tl.ntn;
+  const int m0 = tm * BM, n0 = tn * BN;
+  const int kb0 = kz * k_chunk;
   const int kb1 = min(g.K, kb0 + k_chunk);
   const int wm = (wave >> 1) * (BM / 2), wn = (wave & 1) * (BN / 2);
   const Operand A{g.a_f32, g.a_bf16, g.sam, g.sak, g.M, g.sak == 1, a_vec != 0};
@@ -221,8 +240,8 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g, int k_chunk,
       for (int v = 0; v < 16; ++v) {
         const int m = m0 + wm + 32 * b + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
         if (m < g.M && n < g.N) {
-          if (gridDim.z == 1) gemm_epilogue(g, m, n, acc[b][c][v]);
-          else g.ws[((int64_t)blockIdx.z * g.M + m) * g.N + n] = acc[b][c][v];
+          if (tl.splits == 1) gemm_epilogue(g, m, n, acc[b][c][v]);
+          else g.ws[((int64_t)kz * g.M + m) * g.N + n] = acc[b][c][v];
         }
       }
   }
@@ -397,9 +416,18 @@ hipError_t launch_gemm(const GemmArgs &g, hipStream_t st) {
   if (splits < 1) splits = 1;
   const int k_chunk = ((k_tiles + splits - 1) / splits) * kKT;
   splits = std::max(1, (g.K + k_chunk - 1) / k_chunk);
-  const dim3 grid((g.N + bn - 1) / bn, (g.M + bm - 1) / bm, splits);
-  if (all_vec) gemm_bf16_kernel<64, 64, true><<<grid, 256, 0, st>>>(g, k_chunk, a_vec, b_vec);
-  else gemm_bf16_kernel<64, 64, false><<<grid, 256, 0, st>>>(g, k_chunk, a_vec, b_vec);
+  GemmTiles tl{};
+  tl.ntm = (g.M + bm - 1) / bm;
+  tl.ntn = (g.N + bn - 1) / bn;
+  tl.splits = splits;
+  const int64_t total = (int64_t)tl.ntm * tl.ntn * splits;
+  tl.per = (int)((total + 7) / 8);
+  // the operand whose panels every XCD reads whole is the smaller one
+  const int64_t a_bytes = (int64_t)g.M * g.K * ab, b_bytes = (int64_t)g.N * g.K * bb;
+  tl.m_fast = a_bytes <= b_bytes ? 1 : 0;
+  const dim3 grid((unsigned)(8 * tl.per));
+  if (all_vec) gemm_bf16_kernel<64, 64, true><<<grid, 256, 0, st>>>(g, k_chunk, a_vec, b_vec, tl);
+  else gemm_bf16_kernel<64, 64, false><<<grid, 256, 0, st>>>(g, k_chunk, a_vec, b_vec, tl);
   if (splits > 1) {
     const int64_t mn = (int64_t)g.M * g.N;
     gemm_split_sum_kernel<<<(unsigned)((mn + 255) / 256), 256, 0, st>>>(g, splits);

@@ -101,9 +101,9 @@ __device__ __forceinline__ void run_pos(const Operand &o, int r, int &i, int &kk
   }
 }
 
-// VEC: every run is aligned and lies wholly inside or wholly outside the
-// matrix (all sizes multiples of 4), so there is no element-wise path.
-template <int R, bool VEC>
+// Any strides: a run is read with one load where it is aligned (o.vec) and
+// whole, element by element otherwise.
+template <int R>
 __device__ __forceinline__ void load_tile(const Operand &o, int i0, int k0, int k_end, TileRegs<R> &t) {
 #pragma unroll
   for (int r = 0; r < TileRegs<R>::NV; ++r) {
@@ -112,18 +112,7 @@ __device__ __forceinline__ void load_tile(const Operand &o, int i0, int k0, int 
     const int gi = i0 + i, gk = k0 + kk;
     const int64_t base = (int64_t)gi * o.si + (int64_t)gk * o.sk;
     const bool whole = o.kc ? (gi < o.rows && gk + 3 < k_end) : (gi + 3 < o.rows && gk < k_end);
-    if (VEC) {
-      uint2 x = make_uint2(0u, 0u);
-      if (whole) {
-        if (o.f32) {
-          const float4 y = *reinterpret_cast<const float4 *>(o.f32 + base);
-          x = pack4(bf16_bits(y.x), bf16_bits(y.y), bf16_bits(y.z), bf16_bits(y.w));
-        } else {
-          x = *reinterpret_cast<const uint2 *>(o.b16 + base);
-        }
-      }
-      t.v[r] = x;
-    } else if (o.vec && whole) {
+    if (o.vec && whole) {
       if (o.f32) {
         const float4 x = *reinterpret_cast<const float4 *>(o.f32 + base);
         t.v[r] = pack4(bf16_bits(x.x), bf16_bits(x.y), bf16_bits(x.z), bf16_bits(x.w));
@@ -161,13 +150,78 @@ __device__ __forceinline__ void store_tile(const Operand &o, const TileRegs<R> &
   }
 }
 
+// Aligned operands (VEC) with their contiguous dimension fixed at compile time
+// (KC: along k): a thread's runs keep their rows for the whole K range, so
+// their offsets are computed once and a tile's loads add only the uniform
+// offset of its first k.
+template <int R, bool KC>
+struct RunAddr {
+  static constexpr int NV = TileRegs<R>::NV;
+  int64_t off[NV];           // element offset of run r at k = 0
+  int kk[NV];                // k of run r within a tile
+  bool rows_ok[NV];          // run r's rows lie inside the matrix
+};
+
+template <int R, bool KC>
+__device__ __forceinline__ void run_addr(const Operand &o, int i0, RunAddr<R, KC> &a) {
+#pragma unroll
+  for (int r = 0; r < RunAddr<R, KC>::NV; ++r) {
+    const int q = r * 256 + threadIdx.x;
+    const int i = KC ? q / (kKT / 4) : (q % (R / 4)) * 4;
+    const int kk = KC ? (q % (kKT / 4)) * 4 : q / (R / 4);
+    const int gi = i0 + i;
+    a.off[r] = (int64_t)gi * o.si + (int64_t)kk * o.sk;
+    a.kk[r] = kk;
+    a.rows_ok[r] = KC ? gi < o.rows : gi + 3 < o.rows;
+  }
+}
+
+template <int R, bool KC>
+__device__ __forceinline__ void load_tile_vec(const Operand &o, const RunAddr<R, KC> &a, int k0, int k_end,
+                                              TileRegs<R> &t) {
+  const int64_t koff = (int64_t)k0 * o.sk;
+#pragma unroll
+  for (int r = 0; r < RunAddr<R, KC>::NV; ++r) {
+    const bool whole = a.rows_ok[r] && (KC ? k0 + a.kk[r] + 3 < k_end : k0 + a.kk[r] < k_end);
+    uint2 x = make_uint2(0u, 0u);
+    if (whole) {
+      const int64_t e = a.off[r] + koff;
+      if (o.f32) {
+        const float4 y = *reinterpret_cast<const float4 *>(o.f32 + e);
+        x = pack4(bf16_bits(y.x), bf16_bits(y.y), bf16_bits(y.z), bf16_bits(y.w));
+      } else {
+        x = *reinterpret_cast<const uint2 *>(o.b16 + e);
+      }
+    }
+    t.v[r] = x;
+  }
+}
+
+template <int R, bool KC>
+__device__ __forceinline__ void store_tile_vec(const TileRegs<R> &t, uint16_t (*S)[kKP]) {
+#pragma unroll
+  for (int r = 0; r < TileRegs<R>::NV; ++r) {
+    const int q = r * 256 + threadIdx.x;
+    if constexpr (KC) {
+      *reinterpret_cast<uint2 *>(&S[q / (kKT / 4)][(q % (kKT / 4)) * 4]) = t.v[r];
+    } else {
+      const int kk = q / (R / 4), i = (q % (R / 4)) * 4;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) S[i + e][kk] = unpack4(t.v[r], e);
+    }
+  }
+}
+
 struct GemmTiles {
   int ntm, ntn, splits;      // M tiles, N tiles, K splits
   int per;                   // logical tiles per XCD
   int m_fast;                // M tiles vary fastest within a split
 };
 
-template <int BM, int BN, bool VEC>
+// VEC: both operands aligned (runs of 4 read whole), with A contiguous along k
+// when KA and B when KB; otherwise (not VEC) any strides, read element-wise
+// where a run is not whole.
+template <int BM, int BN, bool VEC, bool KA, bool KB>
 __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g, int k_chunk, int a_vec, int b_vec, GemmTiles tl) {
   constexpr int MB = BM / 64, NB = BN / 64;        // 32 x 32 blocks per wavefront along m and n
   __shared__ __align__(16) uint16_t As[2][BM][kKP];   // [m][k]
@@ -195,20 +249,39 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g, int k_chunk,
 
   TileRegs<BM> ra;
   TileRegs<BN> rb;
+  [[maybe_unused]] RunAddr<BM, KA> aa;
+  [[maybe_unused]] RunAddr<BN, KB> ab;
+  if constexpr (VEC) {
+    run_addr<BM, KA>(A, m0, aa);
+    run_addr<BN, KB>(B, n0, ab);
+  }
+  auto load = [&](int k0) {
+    if constexpr (VEC) {
+      load_tile_vec<BM, KA>(A, aa, k0, kb1, ra);
+      load_tile_vec<BN, KB>(B, ab, k0, kb1, rb);
+    } else {
+      load_tile<BM>(A, m0, k0, kb1, ra);
+      load_tile<BN>(B, n0, k0, kb1, rb);
+    }
+  };
+  auto store = [&](int buf) {
+    if constexpr (VEC) {
+      store_tile_vec<BM, KA>(ra, As[buf]);
+      store_tile_vec<BN, KB>(rb, Bs[buf]);
+    } else {
+      store_tile<BM>(A, ra, As[buf]);
+      store_tile<BN>(B, rb, Bs[buf]);
+    }
+  };
   if (kb0 < kb1) {
-    load_tile<BM, VEC>(A, m0, kb0, kb1, ra);
-    load_tile<BN, VEC>(B, n0, kb0, kb1, rb);
-    store_tile<BM>(A, ra, As[0]);
-    store_tile<BN>(B, rb, Bs[0]);
+    load(kb0);
+    store(0);
   }
   __syncthreads();
   int buf = 0;
   for (int k0 = kb0; k0 < kb1; k0 += kKT) {
     const bool more = k0 + kKT < kb1;
-    if (more) {                                     // in flight while the matrix cores work
-      load_tile<BM, VEC>(A, m0, k0 + kKT, kb1, ra);
-      load_tile<BN, VEC>(B, n0, k0 + kKT, kb1, rb);
-    }
+    if (more) load(k0 + kKT);                       // in flight while the matrix cores work
 #pragma unroll
     for (int ks = 0; ks < kKT; ks += 16) {
       const int kq = ks + 8 * (lane >> 5);
@@ -223,10 +296,7 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g, int k_chunk,
         for (int c = 0; c < NB; ++c) acc[b][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv[c], acc[b][c], 0, 0, 0);
       }
     }
-    if (more) {
-      store_tile<BM>(A, ra, As[buf ^ 1]);
-      store_tile<BN>(B, rb, Bs[buf ^ 1]);
-    }
+    if (more) store(buf ^ 1);
     __syncthreads();
     buf ^= 1;
   }
@@ -426,8 +496,15 @@ hipError_t launch_gemm(const GemmArgs &g, hipStream_t st) {
   const int64_t a_bytes = (int64_t)g.M * g.K * ab, b_bytes = (int64_t)g.N * g.K * bb;
   tl.m_fast = a_bytes <= b_bytes ? 1 : 0;
   const dim3 grid((unsigned)(8 * tl.per));
-  if (all_vec) gemm_bf16_kernel<64, 64, true><<<grid, 256, 0, st>>>(g, k_chunk, a_vec, b_vec, tl);
-  else gemm_bf16_kernel<64, 64, false><<<grid, 256, 0, st>>>(g, k_chunk, a_vec, b_vec, tl);
+  if (all_vec) {
+    const bool ka = g.sak == 1, kb = g.sbk == 1;
+    if (ka && kb) gemm_bf16_kernel<64, 64, true, true, true><<<grid, 256, 0, st>>>(g, k_chunk, a_vec, b_vec, tl);
+    else if (ka) gemm_bf16_kernel<64, 64, true, true, false><<<grid, 256, 0, st>>>(g, k_chunk, a_vec, b_vec, tl);
+    else if (kb) gemm_bf16_kernel<64, 64, true, false, true><<<grid, 256, 0, st>>>(g, k_chunk, a_vec, b_vec, tl);
+    else gemm_bf16_kernel<64, 64, true, false, false><<<grid, 256, 0, st>>>(g, k_chunk, a_vec, b_vec, tl);
+  } else {
+    gemm_bf16_kernel<64, 64, false, false, false><<<grid, 256, 0, st>>>(g, k_chunk, a_vec, b_vec, tl);
+  }
   if (splits > 1) {
     const int64_t mn = (int64_t)g.M * g.N;
     gemm_split_sum_kernel<<<(unsigned)((mn + 255) / 256), 256, 0, st>>>(g, splits);

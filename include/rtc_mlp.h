@@ -105,7 +105,8 @@ rtc_status rtc_pred_step(rtc_pred *p, const float *d_slopes, const float *d_cmd_
  * of 4), all frames run in one persistent launch with the step's four
  * phases between the slope exchange and the products, each followed by a
  * grid barrier; the results are bitwise those of the per-launch form, which
- * runs otherwise.  An expired barrier wait there leaves the context's state
+ * runs otherwise.  The persistent form records no stage trace
+ * (rtc_set_trace).  An expired barrier wait there leaves the context's state
  * undefined (rtc_sync_check) and the predictor's too (rtc_pred_reset).  Frame f
  * reads d_pixels + f * frame_stride (elements, >= one frame) and writes
  * d_cmd [n_frames][n_act] (required) and d_slopes [n_frames][n_slopes]

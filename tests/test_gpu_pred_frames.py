@@ -186,3 +186,39 @@ def test_persistent_predictive_elt_frames_equal_the_per_launch_ones(elt_frames):
     nm, hist, hid = 500, 5, 1024
     model = _model(sc, nm, hist, hid, 13)
     _persistent_vs_per_launch(sc, frames, nm, hist, hid, model, [4, 5], rtc.RTC_FRAMES_PERSISTENT)
+
+
+def test_persistent_predictive_batch_whose_wait_expires_is_reported(setup):
+    # A spin limit of one poll makes the kernel's own bounded waits (five per
+    # predictive frame) give up: the batch winds down normally, the host is
+    # told, and after both resets the frames equal the per-launch ones again.
+    sc, frames, _ = setup
+    F = frames.shape[0]
+    P, PD, mean, std, params = _model(sc, NM, HIST, HID, 14)
+    pix = _dev(frames.reshape(F, -1))
+    with rtc.MlpNet(HIST * NM, HID, NM, 4) as na_, rtc.MlpNet(HIST * NM, HID, NM, 4) as nb_, \
+            _ctx_for(sc) as a, _ctx_for(sc) as b:
+        na_.set_params(*params)
+        nb_.set_params(*params)
+        pa = rtc.Predictor(na_, HIST, P, PD, mean, std, sc.cfg.gain)
+        pb = rtc.Predictor(nb_, HIST, P, PD, mean, std, sc.cfg.gain)
+        cmd_a = torch.zeros(F * a.n_act, device="cuda:0")
+        cmd_b = torch.zeros(F * b.n_act, device="cuda:0")
+        rtc.rtc_set_frame_mode(a, rtc.RTC_FRAMES_PERSISTENT, spin_limit=1)
+        print("predictive persistent batch with a spin limit of one poll", flush=True)
+        pa.frame_batch(a, F, pix, cmd_a)
+        assert pa.last_batch_mode() == rtc.RTC_FRAMES_PERSISTENT
+        torch.cuda.synchronize()
+        with pytest.raises(rtc.RtcError) as ei:
+            rtc.rtc_sync_check(a)
+        assert ei.value.status == rtc.RTC_E_DEVICE
+        rtc.rtc_reset(a)
+        pa.reset()
+        rtc.rtc_set_frame_mode(a, rtc.RTC_FRAMES_PERSISTENT)
+        pa.frame_batch(a, F, pix, cmd_a)
+        pb.frame_batch(b, F, pix, cmd_b)
+        torch.cuda.synchronize()
+        rtc.rtc_sync_check(a)
+        assert torch.equal(cmd_a, cmd_b)
+        pa.close()
+        pb.close()

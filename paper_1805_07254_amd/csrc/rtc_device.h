@@ -315,10 +315,17 @@ __device__ __forceinline__ void trigger_done(const PersistArgs &p, int f) {
 // use them.  sh_flag: a shared word of the workgroup, left at bit 0 = this
 // wait expired, bit 1 = stop after this frame (the abort flag was raised
 // before this workgroup arrived, or by this wait).
-__device__ __forceinline__ bool frame_barrier(const PersistArgs &p, uint32_t epoch, int f, uint32_t *sh_flag) {
+// during(): loads that do not depend on the frame's slopes, issued by the
+// wavefronts other than 0 while wavefront 0 arrives and waits (its arrival
+// and polls wait for all of its own loads); the workgroup barrier at the end
+// waits for them only if they write LDS.
+template <class During>
+__device__ __forceinline__ bool frame_barrier(const PersistArgs &p, uint32_t epoch, int f, uint32_t *sh_flag,
+                                              During &&during) {
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // this wavefront's stores are complete
   __syncthreads();
   trace_stamp(p, f, 6);
+  if (threadIdx.x >= 64) during();
   if (threadIdx.x < 64) {
     const uint32_t G = gridDim.x;
     int release = 0;
@@ -347,6 +354,10 @@ __device__ __forceinline__ bool frame_barrier(const PersistArgs &p, uint32_t epo
   }
   __syncthreads();
   return (*sh_flag & 1u) == 0u;
+}
+
+__device__ __forceinline__ bool frame_barrier(const PersistArgs &p, uint32_t epoch, int f, uint32_t *sh_flag) {
+  return frame_barrier(p, epoch, f, sh_flag, [] {});
 }
 
 // End stamp of a frame: the latest of the per-workgroup end stamps, reduced by

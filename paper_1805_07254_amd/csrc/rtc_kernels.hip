@@ -25,6 +25,14 @@
 #include "rtc_device.h"
 #include "pred_device.h"
 
+// Slope-panel frames: rows of panel 0 whose chunks each lane loads into
+// registers during the frame barrier, and rows after them that the other
+// wavefronts load into L2 (through a discarded LDS copy) meanwhile.
+// Built for the 16-bit and FP8 formats with tiles of up to 16 pixels (in the
+// FP32 and wider-tile forms the extra registers spill).
+constexpr int kPanelPre = 2, kPanelWarm = 4;
+__host__ __device__ constexpr bool panel_prefetch(int fmt, int gs, bool panels) { return panels && fmt != 0 && gs <= 16; }
+
 namespace rtck {
 namespace {
 
@@ -673,13 +681,23 @@ __host__ __device__ inline int panel_count(int n_chunks, int kplp) {
 }
 
 // Rows [0, nrows) of the slab starting at row_begin against one panel's slope
-// values sv (chunks col[]), stored (panel 0) or added into sh_part.
-template <int FMT, int KPLP, int RB>
-__device__ __forceinline__ void panel_rows(const MvmArgs &a, int row_begin, int nrows, const int (&col)[KPLP],
-                                           const float (&sv)[KPLP][Codec<FMT>::EPC], float *sh_part_w,
-                                           int lane, bool acc) {
+// values sv (chunks col[]), stored (panel 0) or added into sh_part.  P > 0:
+// the first P rows' chunks were loaded ahead into m0.
+template <int FMT, int KPLP, int RB, int P, int PM>
+__device__ __forceinline__ void panel_rows_from(const MvmArgs &a, int row_begin, int nrows, const int (&col)[KPLP],
+                                                const float (&sv)[KPLP][Codec<FMT>::EPC], float *sh_part_w,
+                                                int lane, bool acc, const uint4 (&m0)[PM][KPLP]) {
+  static_assert(P <= PM, "rows loaded ahead");
   const char *base = static_cast<const char *>(a.Rq);
-  for (int rb = 0; rb < nrows; rb += RB) {
+  int rb0 = 0;
+  if constexpr (P > 0) {
+    float t[P];
+#pragma unroll
+    for (int i = 0; i < P; ++i) t[i] = chunk_dot<FMT, KPLP>(m0[i], sv);
+    store_row_sums<P>(t, sh_part_w, nrows, lane, acc);
+    rb0 = P;
+  }
+  for (int rb = rb0; rb < nrows; rb += RB) {
     uint4 m[RB][KPLP];
 #pragma unroll
     for (int i = 0; i < RB; ++i) {
@@ -692,6 +710,74 @@ __device__ __forceinline__ void panel_rows(const MvmArgs &a, int row_begin, int 
 #pragma unroll
     for (int i = 0; i < RB; ++i) t[i] = chunk_dot<FMT, KPLP>(m[i], sv);
     store_row_sums<RB>(t, sh_part_w + rb, nrows - rb, lane, acc);
+  }
+}
+
+template <int FMT, int KPLP, int RB>
+__device__ __forceinline__ void panel_rows(const MvmArgs &a, int row_begin, int nrows, const int (&col)[KPLP],
+                                           const float (&sv)[KPLP][Codec<FMT>::EPC], float *sh_part_w,
+                                           int lane, bool acc) {
+  const uint4 none[1][KPLP] = {};
+  panel_rows_from<FMT, KPLP, RB, 0, 1>(a, row_begin, nrows, col, sv, sh_part_w, lane, acc, none);
+}
+
+// The first P rows' chunks of panel 0 for this lane (rows clamped into the
+// slab, chunks past the slope vector read chunk 0): loaded ahead of the frame
+// barrier, since the matrix does not depend on the frame.  Wavefronts other
+// than 0 also load the next Q rows' chunks into a discarded LDS block (one
+// 1 KiB block per wavefront, never read), so that panel 0 finds them in L2;
+// these copies to LDS make the workgroup barrier that ends the frame barrier
+// wait for them.
+template <int KPLP, int P, int Q>
+__device__ __forceinline__ void panel_first_rows(const MvmArgs &a, int row_begin, int nrows, int wave, int lane,
+                                                 uint4 (&m0)[P][KPLP], uint4 *junk) {
+  // z is opaque per call, so the addresses are formed here rather than kept
+  // live (and spilled) through the frame loop
+  int z = 0;
+  asm volatile("" : "+s"(z));
+  const char *base = static_cast<const char *>(a.Rq);
+#pragma unroll
+  for (int i = 0; i < P; ++i) {
+    const int row = row_begin + z + min(i, nrows - 1);
+    const uint4 *rp = reinterpret_cast<const uint4 *>(base + (int64_t)row * a.ldq_bytes);
+#pragma unroll
+    for (int j = 0; j < KPLP; ++j) {
+      const int c = wave * 64 * KPLP + j * 64 + lane;
+      m0[i][j] = rp[c < a.n_chunks ? c : 0];
+    }
+  }
+  if constexpr (Q > 0) {
+    if (wave != 0) {
+#pragma unroll
+      for (int i = P; i < P + Q; ++i) {
+        const int row = row_begin + z + min(i, nrows - 1);
+        const uint4 *rp = reinterpret_cast<const uint4 *>(base + (int64_t)row * a.ldq_bytes);
+#pragma unroll
+        for (int j = 0; j < KPLP; ++j) {
+          const int c = wave * 64 * KPLP + j * 64 + lane;
+          __builtin_amdgcn_global_load_lds(rp + (c < a.n_chunks ? c : 0), junk + wave * 64, 16, 0, 0);
+        }
+      }
+    }
+  }
+}
+
+// Panel pn's slope values of this lane from the exchange buffer (device-
+// coherent loads; chunks past the slope vector read group 0 and are zeroed).
+template <int EPC, int KPLP>
+__device__ __forceinline__ void panel_slopes(const float *s_prod, int pn, int wave, int lane, int n_chunks,
+                                             int (&pcol)[KPLP], float (&sv)[KPLP][EPC]) {
+#pragma unroll
+  for (int j = 0; j < KPLP; ++j) {
+    const int c = (pn * kPanelWaves + wave) * 64 * KPLP + j * 64 + lane;
+    const bool ok = c < n_chunks;
+    pcol[j] = ok ? c : 0;
+    const float *grp = s_prod + (int64_t)(ok ? (c >> 6) : 0) * (64 * EPC) + lane;
+#pragma unroll
+    for (int e = 0; e < EPC; ++e) {
+      const float v = __hip_atomic_load(grp + e * 64, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      sv[j][e] = ok ? v : 0.f;
+    }
   }
 }
 
@@ -799,6 +885,8 @@ __global__ __launch_bounds__(512 / VW) void frames_kernel(PersistArgs p, int32_t
   // every frame
   extern __shared__ uint4 lds[];
   __shared__ uint32_t sh_abort, sh_bar;
+  constexpr bool PF0 = panel_prefetch(FMT, GS, PANELS);
+  __shared__ uint4 sh_junk[PF0 ? 8 * 64 : 1];
   const MvmArgs &a = p.mvm;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -954,7 +1042,17 @@ __global__ __launch_bounds__(512 / VW) void frames_kernel(PersistArgs p, int32_t
     // workgroup, so the reads below and at that top cannot race with it.
     // barrier epochs: one per frame, five per predictive frame
     const uint32_t ep = PRED ? 5u * (uint32_t)f : (uint32_t)f;
-    (void)frame_barrier(p, ep + 1u, f, &sh_bar);
+    // slope panels: the first rows of panel 0 are loaded while the workgroup waits
+    constexpr int PRB = PANELS ? PanelShape<FMT>::RB : 1;
+    constexpr int PRE = PF0 ? kPanelPre : 1;
+    uint4 m0[PRE][KPL];                            // unused unless PF0
+    if constexpr (PF0) {
+      (void)frame_barrier(p, ep + 1u, f, &sh_bar, [&] {
+        panel_first_rows<KPL, PRE, kPanelWarm>(a, row_begin, nrows, wave, lane, m0, sh_junk);
+      });
+      if (wave == 0) panel_first_rows<KPL, PRE, 0>(a, row_begin, nrows, wave, lane, m0, sh_junk);
+    } else
+      (void)frame_barrier(p, ep + 1u, f, &sh_bar);
     trace_stamp(p, f, 2);
 
     // the slopes the products use: the measured ones, or the feed-forward
@@ -1015,23 +1113,22 @@ __global__ __launch_bounds__(512 / VW) void frames_kernel(PersistArgs p, int32_t
       if (p.ts != nullptr && f > 0 && wave == 0 && b == (f - 1) % G) reduce_end_stamp(p, f - 1);
       trace_stamp(p, f, 3);
       const int np = panel_count(a.n_chunks, KPL);
-      for (int pn = 0; pn < np; ++pn) {
+      // panel 0 starts from the rows loaded during the barrier (peeled, so that
+      // they are not kept live through the loop)
+      int pn = 0;
+      if constexpr (PF0) {
         int pcol[KPL];
         float sv[KPL][EPC];
-#pragma unroll
-        for (int j = 0; j < KPL; ++j) {
-          const int c = (pn * W + wave) * 64 * KPL + j * 64 + lane;
-          const bool ok = c < a.n_chunks;
-          pcol[j] = ok ? c : 0;
-          const float *grp = s_prod + (int64_t)(ok ? (c >> 6) : 0) * (64 * EPC) + lane;
-#pragma unroll
-          for (int e = 0; e < EPC; ++e) {
-            const float v = __hip_atomic_load(grp + e * 64, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            sv[j][e] = ok ? v : 0.f;
-          }
-        }
-        panel_rows<FMT, KPL, PanelShape<FMT>::RB>(a, row_begin, nrows, pcol, sv, sh_part + wave * max_rows, lane,
-                                                  pn > 0);
+        panel_slopes<EPC, KPL>(s_prod, 0, wave, lane, a.n_chunks, pcol, sv);
+        panel_rows_from<FMT, KPL, PRB, PRE, PRE>(a, row_begin, nrows, pcol, sv, sh_part + wave * max_rows, lane,
+                                                 false, m0);
+        pn = 1;
+      }
+      for (; pn < np; ++pn) {
+        int pcol[KPL];
+        float sv[KPL][EPC];
+        panel_slopes<EPC, KPL>(s_prod, pn, wave, lane, a.n_chunks, pcol, sv);
+        panel_rows<FMT, KPL, PRB>(a, row_begin, nrows, pcol, sv, sh_part + wave * max_rows, lane, pn > 0);
       }
     } else {
       // slope slices of this wavefront (device-coherent loads)
@@ -1428,7 +1525,8 @@ static hipError_t launch_frames_variant(const PersistArgs &p, int G, int max_row
   if ((e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
   if ((e = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev)) != hipSuccess) return e;
   const int64_t part_bytes = (int64_t)W * max_rows * sizeof(float);
-  const int64_t static_bytes = 128;                // sh_abort, sh_bar, sh_pred and alignment slack
+  // sh_abort, sh_bar, sh_pred, sh_junk and slack
+  const int64_t static_bytes = 128 + (panel_prefetch(FMT, GS, PANELS) ? 8192 : 0);
   // tile descriptors and reference slopes of a workgroup's subapertures, kept in LDS
   const int per_wg = (p.cal.n_valid + G - 1) / G;
   const int tile_cap = per_wg <= kTileCache ? per_wg : 0;

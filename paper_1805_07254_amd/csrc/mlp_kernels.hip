@@ -162,13 +162,18 @@ struct RunAddr {
   bool rows_ok[NV];          // run r's rows lie inside the matrix
 };
 
+// Operands contiguous along i (not KC): a thread's runs form a 4 x NV block,
+// rows i..i+3 of the run at k = NV (t / (R / 4)) + r, so that store_tile_vec
+// can transpose the block in registers and store whole k-runs.
 template <int R, bool KC>
 __device__ __forceinline__ void run_addr(const Operand &o, int i0, RunAddr<R, KC> &a) {
+  constexpr int NV = RunAddr<R, KC>::NV;
+  static_assert(KC || NV % 4 == 0, "k-runs of 4 per block");
 #pragma unroll
-  for (int r = 0; r < RunAddr<R, KC>::NV; ++r) {
+  for (int r = 0; r < NV; ++r) {
     const int q = r * 256 + threadIdx.x;
-    const int i = KC ? q / (kKT / 4) : (q % (R / 4)) * 4;
-    const int kk = KC ? (q % (kKT / 4)) * 4 : q / (R / 4);
+    const int i = KC ? q / (kKT / 4) : ((int)threadIdx.x % (R / 4)) * 4;
+    const int kk = KC ? (q % (kKT / 4)) * 4 : NV * ((int)threadIdx.x / (R / 4)) + r;
     const int gi = i0 + i;
     a.off[r] = (int64_t)gi * o.si + (int64_t)kk * o.sk;
     a.kk[r] = kk;
@@ -199,15 +204,29 @@ __device__ __forceinline__ void load_tile_vec(const Operand &o, const RunAddr<R,
 
 template <int R, bool KC>
 __device__ __forceinline__ void store_tile_vec(const TileRegs<R> &t, uint16_t (*S)[kKP]) {
+  constexpr int NV = TileRegs<R>::NV;
+  if constexpr (KC) {
 #pragma unroll
-  for (int r = 0; r < TileRegs<R>::NV; ++r) {
-    const int q = r * 256 + threadIdx.x;
-    if constexpr (KC) {
+    for (int r = 0; r < NV; ++r) {
+      const int q = r * 256 + threadIdx.x;
       *reinterpret_cast<uint2 *>(&S[q / (kKT / 4)][(q % (kKT / 4)) * 4]) = t.v[r];
-    } else {
-      const int kk = q / (R / 4), i = (q % (R / 4)) * 4;
+    }
+  } else {
+    // the thread's 4 x NV block (rows i..i+3, k = k0..k0+NV-1), transposed in
+    // registers four k at a time: row i+e gets (v[r].e, v[r+1].e, v[r+2].e, v[r+3].e)
+    const int i = ((int)threadIdx.x % (R / 4)) * 4, k0 = NV * ((int)threadIdx.x / (R / 4));
 #pragma unroll
-      for (int e = 0; e < 4; ++e) S[i + e][kk] = unpack4(t.v[r], e);
+    for (int r = 0; r < NV; r += 4) {
+      const uint2 a = t.v[r], b = t.v[r + 1], c = t.v[r + 2], d = t.v[r + 3];
+      const uint32_t lo = 0xffffu, hi = 0xffff0000u;
+      *reinterpret_cast<uint2 *>(&S[i + 0][k0 + r]) =
+          make_uint2((a.x & lo) | (b.x << 16), (c.x & lo) | (d.x << 16));
+      *reinterpret_cast<uint2 *>(&S[i + 1][k0 + r]) =
+          make_uint2((a.x >> 16) | (b.x & hi), (c.x >> 16) | (d.x & hi));
+      *reinterpret_cast<uint2 *>(&S[i + 2][k0 + r]) =
+          make_uint2((a.y & lo) | (b.y << 16), (c.y & lo) | (d.y << 16));
+      *reinterpret_cast<uint2 *>(&S[i + 3][k0 + r]) =
+          make_uint2((a.y >> 16) | (b.y & hi), (c.y >> 16) | (d.y & hi));
     }
   }
 }

@@ -181,7 +181,8 @@ __device__ __forceinline__ void run_addr(const Operand &o, int i0, RunAddr<R, KC
   }
 }
 
-template <int R, bool KC>
+// F32: the operand is float32 (rounded to bfloat16 as read), else bfloat16.
+template <int R, bool KC, bool F32>
 __device__ __forceinline__ void load_tile_vec(const Operand &o, const RunAddr<R, KC> &a, int k0, int k_end,
                                               TileRegs<R> &t) {
   const int64_t koff = (int64_t)k0 * o.sk;
@@ -191,7 +192,7 @@ __device__ __forceinline__ void load_tile_vec(const Operand &o, const RunAddr<R,
     uint2 x = make_uint2(0u, 0u);
     if (whole) {
       const int64_t e = a.off[r] + koff;
-      if (o.f32) {
+      if constexpr (F32) {
         const float4 y = *reinterpret_cast<const float4 *>(o.f32 + e);
         x = pack4(bf16_bits(y.x), bf16_bits(y.y), bf16_bits(y.z), bf16_bits(y.w));
       } else {
@@ -238,9 +239,9 @@ struct GemmTiles {
 };
 
 // VEC: both operands aligned (runs of 4 read whole), with A contiguous along k
-// when KA and B when KB; otherwise (not VEC) any strides, read element-wise
-// where a run is not whole.
-template <int BM, int BN, bool VEC, bool KA, bool KB>
+// when KA and B when KB, A float32 when AF (B bfloat16); otherwise (not VEC)
+// any strides and types, read element-wise where a run is not whole.
+template <int BM, int BN, bool VEC, bool KA, bool KB, bool AF>
 __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g, int k_chunk, int a_vec, int b_vec, GemmTiles tl) {
   constexpr int MB = BM / 64, NB = BN / 64;        // 32 x 32 blocks per wavefront along m and n
   __shared__ __align__(16) uint16_t As[2][BM][kKP];   // [m][k]
@@ -276,8 +277,8 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g, int k_chunk,
   }
   auto load = [&](int k0) {
     if constexpr (VEC) {
-      load_tile_vec<BM, KA>(A, aa, k0, kb1, ra);
-      load_tile_vec<BN, KB>(B, ab, k0, kb1, rb);
+      load_tile_vec<BM, KA, AF>(A, aa, k0, kb1, ra);
+      load_tile_vec<BN, KB, false>(B, ab, k0, kb1, rb);
     } else {
       load_tile<BM>(A, m0, k0, kb1, ra);
       load_tile<BN>(B, n0, k0, kb1, rb);
@@ -515,14 +516,22 @@ hipError_t launch_gemm(const GemmArgs &g, hipStream_t st) {
   const int64_t a_bytes = (int64_t)g.M * g.K * ab, b_bytes = (int64_t)g.N * g.K * bb;
   tl.m_fast = a_bytes <= b_bytes ? 1 : 0;
   const dim3 grid((unsigned)(8 * tl.per));
-  if (all_vec) {
-    const bool ka = g.sak == 1, kb = g.sbk == 1;
-    if (ka && kb) gemm_bf16_kernel<64, 64, true, true, true><<<grid, 256, 0, st>>>(g, k_chunk, a_vec, b_vec, tl);
-    else if (ka) gemm_bf16_kernel<64, 64, true, true, false><<<grid, 256, 0, st>>>(g, k_chunk, a_vec, b_vec, tl);
-    else if (kb) gemm_bf16_kernel<64, 64, true, false, true><<<grid, 256, 0, st>>>(g, k_chunk, a_vec, b_vec, tl);
-    else gemm_bf16_kernel<64, 64, true, false, false><<<grid, 256, 0, st>>>(g, k_chunk, a_vec, b_vec, tl);
+  if (all_vec && g.b_f32 == nullptr) {
+    const bool ka = g.sak == 1, kb = g.sbk == 1, af = g.a_f32 != nullptr;
+    auto go = [&](auto kern) { kern<<<grid, 256, 0, st>>>(g, k_chunk, a_vec, b_vec, tl); };
+    if (af) {
+      if (ka && kb) go(gemm_bf16_kernel<64, 64, true, true, true, true>);
+      else if (ka) go(gemm_bf16_kernel<64, 64, true, true, false, true>);
+      else if (kb) go(gemm_bf16_kernel<64, 64, true, false, true, true>);
+      else go(gemm_bf16_kernel<64, 64, true, false, false, true>);
+    } else {
+      if (ka && kb) go(gemm_bf16_kernel<64, 64, true, true, true, false>);
+      else if (ka) go(gemm_bf16_kernel<64, 64, true, true, false, false>);
+      else if (kb) go(gemm_bf16_kernel<64, 64, true, false, true, false>);
+      else go(gemm_bf16_kernel<64, 64, true, false, false, false>);
+    }
   } else {
-    gemm_bf16_kernel<64, 64, false, false, false><<<grid, 256, 0, st>>>(g, k_chunk, a_vec, b_vec, tl);
+    gemm_bf16_kernel<64, 64, false, false, false, false><<<grid, 256, 0, st>>>(g, k_chunk, a_vec, b_vec, tl);
   }
   if (splits > 1) {
     const int64_t mn = (int64_t)g.M * g.N;

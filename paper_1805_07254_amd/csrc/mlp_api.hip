@@ -116,7 +116,10 @@ void free_tensor(Tensor &t) {
 
 // Forward into m->Z1 / Hb / y (y has batch rows of n_out); xb (nullable): x
 // already rounded to bfloat16.
-hipError_t forward(rtc_mlp *m, int32_t B, const float *x, float *y, hipStream_t st, const uint16_t *xb = nullptr) {
+// defer (nullable): the second product may leave its split sums to the
+// caller's consumer (launch_loss_grad), which then reads m->ws instead of y.
+hipError_t forward(rtc_mlp *m, int32_t B, const float *x, float *y, hipStream_t st, const uint16_t *xb = nullptr,
+                   int *defer = nullptr) {
   rtcm::GemmArgs g{};
   g.ws = m->ws;
   g.ws_len = m->ws_len;
@@ -156,7 +159,7 @@ hipError_t forward(rtc_mlp *m, int32_t B, const float *x, float *y, hipStream_t 
   h.bias = m->b2.p;
   h.ldc = m->n_out;
   h.c_f32 = y;
-  return rtcm::launch_gemm(h, st);
+  return rtcm::launch_gemm(h, st, defer);
 }
 
 // Batch-1 forward for the predictor step: two bfloat16 GEMV layers with the
@@ -313,8 +316,12 @@ rtc_status rtc_mlp_loss_grad(rtc_mlp *m, int32_t B, const float *d_x, const floa
   // the inputs in bfloat16 once (the products would round them as they load
   // them, once per tile that reads them)
   hipError_t e = rtcm::launch_round_bf16(d_x, m->Xb, (int64_t)B * m->n_in, st);
-  if (e == hipSuccess) e = forward(m, B, d_x, m->Y, st, m->Xb);
-  if (e == hipSuccess) e = rtcm::launch_loss_grad(m->Y, d_t, B, m->n_out, m->dY, m->dYb, m->row_sq, d_loss, st);
+  // the output layer's split sums (if it splits) are added by the loss kernel
+  int defer_y = 0;
+  if (e == hipSuccess) e = forward(m, B, d_x, m->Y, st, m->Xb, &defer_y);
+  if (e == hipSuccess)
+    e = rtcm::launch_loss_grad(m->Y, d_t, B, m->n_out, m->dY, m->dYb, m->row_sq, d_loss, st,
+                               defer_y ? m->ws : nullptr, defer_y, m->b2.p);
   if (e == hipSuccess) {                            // dW2 = dY^T H
     rtcm::GemmArgs g{};
     g.ws = m->ws;
@@ -334,6 +341,7 @@ rtc_status rtc_mlp_loss_grad(rtc_mlp *m, int32_t B, const float *d_x, const floa
     e = rtcm::launch_gemm(g, st);
   }
   if (e == hipSuccess) e = rtcm::launch_col_sum(m->dY, B, m->n_out, m->b2.g, st);
+  int defer_h = 0;
   if (e == hipSuccess) {                            // dH = dY W2
     rtcm::GemmArgs g{};
     g.ws = m->ws;
@@ -350,9 +358,11 @@ rtc_status rtc_mlp_loss_grad(rtc_mlp *m, int32_t B, const float *d_x, const floa
     g.alpha = 1.0f;
     g.ldc = m->n_hid;
     g.c_f32 = m->dH;
-    e = rtcm::launch_gemm(g, st);
+    e = rtcm::launch_gemm(g, st, &defer_h);           // split sums added by the GELU derivative kernel
   }
-  if (e == hipSuccess) e = rtcm::launch_gelu_back(m->dH, m->Z1, m->dZ1, m->dZ1b, (int64_t)B * m->n_hid, st);
+  if (e == hipSuccess)
+    e = rtcm::launch_gelu_back(m->dH, m->Z1, m->dZ1, m->dZ1b, (int64_t)B * m->n_hid, st,
+                               defer_h ? m->ws : nullptr, defer_h);
   if (e == hipSuccess) {                            // dW1 = dZ1^T X
     rtcm::GemmArgs g{};
     g.ws = m->ws;

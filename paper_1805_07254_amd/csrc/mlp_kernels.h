@@ -30,12 +30,22 @@ struct GemmArgs {
   float *ws;           // nullable: split-K workspace of ws_len floats (no split without it)
   int64_t ws_len;
 };
-hipError_t launch_gemm(const GemmArgs &g, hipStream_t st);
+// deferred (nullable): when the product splits K, leave the sums of the
+// partial results (ws[z][M][N], z < *deferred, added in split order) to the
+// consumer instead of a second kernel; *deferred = 0 when the result was
+// written.  Only for products with alpha = 1 and no GELU, whose consumer
+// takes the partials (launch_loss_grad, launch_gelu_back).
+hipError_t launch_gemm(const GemmArgs &g, hipStream_t st, int *deferred = nullptr);
 
 hipError_t launch_round_bf16(const float *x, uint16_t *y, int64_t n, hipStream_t st);
+// parts, splits > 0: Y = (sum of the splits' partials in split order) + bias,
+// as the product's own epilogue would compute it; else Y is read.
 hipError_t launch_loss_grad(const float *Y, const float *T, int B, int n, float *dY, uint16_t *dYb, float *row_sq,
-                            float *loss, hipStream_t st);
-hipError_t launch_gelu_back(const float *dH, const float *Z, float *dZ, uint16_t *dZb, int64_t n, hipStream_t st);
+                            float *loss, hipStream_t st, const float *parts = nullptr, int splits = 0,
+                            const float *bias = nullptr);
+// parts, splits > 0: dH = sum of the splits' partials in split order.
+hipError_t launch_gelu_back(const float *dH, const float *Z, float *dZ, uint16_t *dZb, int64_t n, hipStream_t st,
+                            const float *parts = nullptr, int splits = 0);
 hipError_t launch_col_sum(const float *dZ, int B, int n, float *db, hipStream_t st);
 hipError_t launch_adam(float *theta, float *m, float *v, const float *grad, uint16_t *theta_b, int64_t n, float lr,
                        float b1, float b2, float eps, float c1, float c2, hipStream_t st);

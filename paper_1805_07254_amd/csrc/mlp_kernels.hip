@@ -354,15 +354,29 @@ __global__ __launch_bounds__(256) void round_bf16_kernel(const float *x, uint16_
 }
 
 // dY = 2 (Y - T) / (B n_out) (float32 and bfloat16) and per-row sums of (Y - T)^2.
+__device__ __forceinline__ float split_sum(const float *parts, int splits, int64_t mn, int64_t o) {
+  float s = parts[o];
+  for (int z = 1; z < splits; ++z) s += parts[(int64_t)z * mn + o];
+  return s;
+}
+
 __global__ __launch_bounds__(256) void loss_grad_kernel(const float *Y, const float *T, int B, int n, float *dY,
-                                                        uint16_t *dYb, float *row_sq) {
+                                                        uint16_t *dYb, float *row_sq, const float *parts, int splits,
+                                                        const float *bias) {
   const int b = blockIdx.x;
   __shared__ float part[256];
   float s = 0.0f;
   const float scale = 2.0f / ((float)B * (float)n);
   for (int j = threadIdx.x; j < n; j += 256) {
     const int64_t o = (int64_t)b * n + j;
-    const float d = Y[o] - T[o];
+    float y;
+    if (splits > 0) {                               // the product's epilogue: 1 * sum + bias
+      y = split_sum(parts, splits, (int64_t)B * n, o);
+      if (bias) y += bias[j];
+    } else {
+      y = Y[o];
+    }
+    const float d = y - T[o];
     s = fmaf(d, d, s);
     const float g = scale * d;
     dY[o] = g;
@@ -395,9 +409,10 @@ __global__ __launch_bounds__(256) void loss_total_kernel(const float *row_sq, in
 
 // dZ = dH * gelu'(Z) (float32 and bfloat16).
 __global__ __launch_bounds__(256) void gelu_back_kernel(const float *dH, const float *Z, float *dZ, uint16_t *dZb,
-                                                        int64_t n) {
+                                                        int64_t n, const float *parts, int splits) {
   for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
-    const float d = dH[i] * gelu_grad(Z[i]);
+    const float h = splits > 0 ? split_sum(parts, splits, n, i) : dH[i];
+    const float d = h * gelu_grad(Z[i]);
     dZ[i] = d;
     dZb[i] = bf16_bits(d);
   }
@@ -478,7 +493,8 @@ __global__ __launch_bounds__(256) void pred_slopes_kernel(PredStepArgs a) {
 
 }  // namespace
 
-hipError_t launch_gemm(const GemmArgs &g, hipStream_t st) {
+hipError_t launch_gemm(const GemmArgs &g, hipStream_t st, int *deferred) {
+  if (deferred) *deferred = 0;
   if (g.M <= 0 || g.N <= 0) return hipSuccess;
   if (g.K < 0) return hipErrorInvalidValue;
   // 64 x 64 tiles; the K range is split until about 512 workgroups run (two
@@ -533,6 +549,10 @@ hipError_t launch_gemm(const GemmArgs &g, hipStream_t st) {
   } else {
     gemm_bf16_kernel<64, 64, false, false, false, false><<<grid, 256, 0, st>>>(g, k_chunk, a_vec, b_vec, tl);
   }
+  if (splits > 1 && deferred && g.alpha == 1.0f && !g.gelu) {
+    *deferred = splits;                             // the consumer adds the partials
+    return hipGetLastError();
+  }
   if (splits > 1) {
     const int64_t mn = (int64_t)g.M * g.N;
     gemm_split_sum_kernel<<<(unsigned)((mn + 255) / 256), 256, 0, st>>>(g, splits);
@@ -552,14 +572,15 @@ hipError_t launch_round_bf16(const float *x, uint16_t *y, int64_t n, hipStream_t
 }
 
 hipError_t launch_loss_grad(const float *Y, const float *T, int B, int n, float *dY, uint16_t *dYb, float *row_sq,
-                            float *loss, hipStream_t st) {
-  loss_grad_kernel<<<B, 256, 0, st>>>(Y, T, B, n, dY, dYb, row_sq);
+                            float *loss, hipStream_t st, const float *parts, int splits, const float *bias) {
+  loss_grad_kernel<<<B, 256, 0, st>>>(Y, T, B, n, dY, dYb, row_sq, parts, splits, bias);
   loss_total_kernel<<<1, 256, 0, st>>>(row_sq, B, n, loss);
   return hipGetLastError();
 }
 
-hipError_t launch_gelu_back(const float *dH, const float *Z, float *dZ, uint16_t *dZb, int64_t n, hipStream_t st) {
-  gelu_back_kernel<<<grid_for(n), 256, 0, st>>>(dH, Z, dZ, dZb, n);
+hipError_t launch_gelu_back(const float *dH, const float *Z, float *dZ, uint16_t *dZb, int64_t n, hipStream_t st,
+                            const float *parts, int splits) {
+  gelu_back_kernel<<<grid_for(n), 256, 0, st>>>(dH, Z, dZ, dZb, n, parts, splits);
   return hipGetLastError();
 }
 

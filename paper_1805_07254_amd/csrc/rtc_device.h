@@ -360,12 +360,13 @@ __device__ __forceinline__ bool frame_barrier(const PersistArgs &p, uint32_t epo
   return frame_barrier(p, epoch, f, sh_flag, [] {});
 }
 
-// End stamp of a frame: the latest of the per-workgroup end stamps, reduced by
-// wavefront 0 of one workgroup.
-__device__ __forceinline__ void reduce_end_stamp(const PersistArgs &p, int f) {
-  const uint64_t *ends = reinterpret_cast<const uint64_t *>(p.bar + sl::kEnds) + (f & 1) * sl::kMaxGroups;
+// End stamp of a frame: the latest of the per-workgroup end stamps (slot f
+// mod `slots` of the end-stamp rows), reduced by the 64 lanes of one wavefront.
+__device__ __forceinline__ void reduce_end_stamp(const PersistArgs &p, int f, int slots = 2) {
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint64_t *ends = reinterpret_cast<const uint64_t *>(p.bar + sl::kEnds) + (f % slots) * sl::kMaxGroups;
   uint64_t m = 0;
-  for (uint32_t i = threadIdx.x; i < gridDim.x; i += 64) {
+  for (uint32_t i = lane; i < gridDim.x; i += 64) {
     const uint64_t v = __hip_atomic_load(ends + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     m = v > m ? v : m;
   }
@@ -374,7 +375,7 @@ __device__ __forceinline__ void reduce_end_stamp(const PersistArgs &p, int f) {
     const uint64_t o = __shfl_xor(m, d);
     m = o > m ? o : m;
   }
-  if (threadIdx.x == 0) p.ts[2 * (int64_t)f + 1] = m;
+  if (lane == 0) p.ts[2 * (int64_t)f + 1] = m;
 }
 
 

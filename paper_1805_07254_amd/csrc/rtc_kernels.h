@@ -146,8 +146,9 @@ constexpr int kDone = (kGroups + 1) * kStride;    // workgroups done with a batc
 constexpr int kTrigDone = kDone + 16;             // workgroups done with triggered frames
 constexpr int kMailbox = (kGroups + 2) * kStride; // + 16 * workgroup: [0] barrier epoch, [4] trigger relay
 constexpr int kMaxGroups = 1024;
-constexpr int kEnds = kMailbox + 16 * kMaxGroups; // uint64 [2][kMaxGroups] per-workgroup frame end stamps
-constexpr int kWords = kBarBase + kEnds + 4 * kMaxGroups;
+constexpr int kEnds = kMailbox + 16 * kMaxGroups; // uint64 [3][kMaxGroups] per-workgroup frame end stamps
+constexpr int kEndSlots = 3;                      // rows of end stamps (frame f in row f mod 3)
+constexpr int kWords = kBarBase + kEnds + 2 * kEndSlots * kMaxGroups;
 }  // namespace sync_layout
 // Fails with hipErrorInvalidValue when the shape is unsupported (slab rows
 // beyond one per thread, LDS, register slices) and with the runtime's error

@@ -1046,13 +1046,23 @@ __global__ __launch_bounds__(512 / VW) void frames_kernel(PersistArgs p, int32_t
     constexpr int PRB = PANELS ? PanelShape<FMT>::RB : 1;
     constexpr int PRE = PF0 ? kPanelPre : 1;
     uint4 m0[PRE][KPL];                            // unused unless PF0
+    // End stamp of frame f - 2, whose per-workgroup stamps every workgroup
+    // wrote before arriving at frame f - 1's barrier: reduced by wavefront 1
+    // of one workgroup (they take turns) while the barrier waits, off the
+    // frame's critical path.  Its row is next written by frame f + 1, after
+    // this workgroup has left this barrier.
+    auto end_stamp = [&] {
+      if (p.ts != nullptr && f > 1 && wave == 1 && b == (f - 2) % G) reduce_end_stamp(p, f - 2, sl::kEndSlots);
+    };
     if constexpr (PF0) {
       (void)frame_barrier(p, ep + 1u, f, &sh_bar, [&] {
+        end_stamp();
         panel_first_rows<KPL, PRE, kPanelWarm>(a, row_begin, nrows, wave, lane, m0, sh_junk);
       });
       if (wave == 0) panel_first_rows<KPL, PRE, 0>(a, row_begin, nrows, wave, lane, m0, sh_junk);
-    } else
-      (void)frame_barrier(p, ep + 1u, f, &sh_bar);
+    } else {
+      (void)frame_barrier(p, ep + 1u, f, &sh_bar, end_stamp);
+    }
     trace_stamp(p, f, 2);
 
     // the slopes the products use: the measured ones, or the feed-forward
@@ -1110,7 +1120,6 @@ __global__ __launch_bounds__(512 / VW) void frames_kernel(PersistArgs p, int32_t
 
     if constexpr (PANELS) {
       // long slope vectors: panels of the slope vector, every row streamed per panel
-      if (p.ts != nullptr && f > 0 && wave == 0 && b == (f - 1) % G) reduce_end_stamp(p, f - 1);
       trace_stamp(p, f, 3);
       const int np = panel_count(a.n_chunks, KPL);
       // panel 0 starts from the rows loaded during the barrier (peeled, so that
@@ -1148,9 +1157,6 @@ __global__ __launch_bounds__(512 / VW) void frames_kernel(PersistArgs p, int32_t
           }
         }
       }
-      // end stamp of the previous frame, whose per-workgroup stamps the barrier
-      // has just made visible; the workgroups take turns
-      if (p.ts != nullptr && f > 0 && wave == 0 && b == (f - 1) % G) reduce_end_stamp(p, f - 1);
       if (p.trace != nullptr) {                       // stage 3: slope slices in registers
         float probe = 0.f;
 #pragma unroll
@@ -1256,13 +1262,14 @@ __global__ __launch_bounds__(512 / VW) void frames_kernel(PersistArgs p, int32_t
     if (p.ts != nullptr) {                         // this workgroup's commands of frame f are issued
       __syncthreads();
       if (tid == 0)
-        __hip_atomic_store(reinterpret_cast<uint64_t *>(p.bar + sl::kEnds) + (f & 1) * sl::kMaxGroups + b,
+        __hip_atomic_store(reinterpret_cast<uint64_t *>(p.bar + sl::kEnds) + (f % sl::kEndSlots) * sl::kMaxGroups + b,
                            wall_clock64(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     frames_done += ((sh_bar | pflags) & 1u) == 0u ? 1 : 0;
   }
   if (tid < nrows) a.state[row_begin + tid] = state;
-  // end stamp of the last frame: the last workgroup to finish reduces it
+  // end stamps of the last two frames (no later barrier reduces them): the
+  // last workgroup to finish reduces them
   if (p.ts != nullptr && frames_done == p.n_frames) {
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
@@ -1271,7 +1278,10 @@ __global__ __launch_bounds__(512 / VW) void frames_kernel(PersistArgs p, int32_t
       if (tid == 0)
         last = __hip_atomic_fetch_add(p.bar + sl::kDone, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
                (uint32_t)G - 1;
-      if (__builtin_amdgcn_readfirstlane(last)) reduce_end_stamp(p, p.n_frames - 1);
+      if (__builtin_amdgcn_readfirstlane(last)) {
+        if (p.n_frames > 1) reduce_end_stamp(p, p.n_frames - 2, sl::kEndSlots);
+        reduce_end_stamp(p, p.n_frames - 1, sl::kEndSlots);
+      }
     }
   }
 }

@@ -1260,7 +1260,9 @@ __global__ __launch_bounds__(512 / VW) void frames_kernel(PersistArgs p, int32_t
     trace_stamp(p, f, 5);
     if constexpr (TRIG) trigger_done(p, f);
     if (p.ts != nullptr) {                         // this workgroup's commands of frame f are issued
-      __syncthreads();
+      // (by wavefront 0 alone when the slab has at most 64 rows: its own
+      // stores precede the stamp, so no workgroup barrier is needed)
+      if (max_rows > 64) __syncthreads();
       if (tid == 0)
         __hip_atomic_store(reinterpret_cast<uint64_t *>(p.bar + sl::kEnds) + (f % sl::kEndSlots) * sl::kMaxGroups + b,
                            wall_clock64(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

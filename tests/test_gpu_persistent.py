@@ -252,3 +252,18 @@ def test_stage_trace_of_every_traced_workgroup_is_ordered(tiny_loop):
     assert np.all(stages[:, :, 2].min(axis=1) >= stages[:, :, 1].max(axis=1))
     assert np.all(t[:, :, 6] >= t[:, :, 1]) and np.all(t[:, :, 7] >= t[:, :, 6])
     assert np.all(t[:, :, 2] >= t[:, :, 7])
+
+
+@pytest.mark.parametrize("n_frames", [1, 2, 3, 4, 7])
+def test_end_stamps_of_short_batches(tiny_loop, n_frames):
+    """Every frame's end stamp is reduced: during a later frame's barrier for
+    all but the last two frames, by the last workgroup to finish for those."""
+    sc, frames, _ = tiny_loop
+    with _ctx_for(sc, cm_dtype="f32") as ctx:
+        rtc.rtc_set_frame_mode(ctx, rtc.RTC_FRAMES_PERSISTENT)
+        for _ in range(2):                          # a second batch reuses the stamp rows
+            out = _gpu_batch(ctx, frames[:n_frames], ts=True)
+            rtc.rtc_sync_check(ctx)
+            ts = out["ts"]
+            assert np.all(ts[:, 0] > 0) and np.all(ts[:, 1] > ts[:, 0])
+            assert np.all(ts[1:, 0] >= ts[:-1, 0]) and np.all(ts[1:, 1] >= ts[:-1, 1])

@@ -408,11 +408,11 @@ rtc_status rtc_mlp_adam(rtc_mlp *m, float lr, float beta1, float beta2, float ep
   const float c1 = (float)(1.0 - std::pow((double)beta1, (double)step));
   const float c2 = (float)(1.0 - std::pow((double)beta2, (double)step));
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
-  hipError_t e = hipSuccess;
-  Tensor *ts[4] = {&m->W1, &m->b1, &m->W2, &m->b2};
-  for (int i = 0; i < 4 && e == hipSuccess; ++i)
-    e = rtcm::launch_adam(ts[i]->p, ts[i]->m, ts[i]->v, ts[i]->g, ts[i]->b, ts[i]->n, lr, beta1, beta2, eps, c1, c2,
-                          st);
+  // the four tensors in one launch
+  const Tensor *ts[4] = {&m->W1, &m->b1, &m->W2, &m->b2};
+  rtcm::AdamTensor at[4];
+  for (int i = 0; i < 4; ++i) at[i] = rtcm::AdamTensor{ts[i]->p, ts[i]->m, ts[i]->v, ts[i]->g, ts[i]->b, ts[i]->n};
+  const hipError_t e = rtcm::launch_adam_multi(at, 4, lr, beta1, beta2, eps, c1, c2, st);
   return e == hipSuccess ? RTC_OK : hfail(m, e, "rtc_mlp_adam");
 }
 

@@ -47,8 +47,17 @@ hipError_t launch_loss_grad(const float *Y, const float *T, int B, int n, float 
 hipError_t launch_gelu_back(const float *dH, const float *Z, float *dZ, uint16_t *dZb, int64_t n, hipStream_t st,
                             const float *parts = nullptr, int splits = 0);
 hipError_t launch_col_sum(const float *dZ, int B, int n, float *db, hipStream_t st);
-hipError_t launch_adam(float *theta, float *m, float *v, const float *grad, uint16_t *theta_b, int64_t n, float lr,
-                       float b1, float b2, float eps, float c1, float c2, hipStream_t st);
+// Adam with bias correction on up to kAdamTensors tensors in one launch,
+// refreshing each tensor's bfloat16 copy.
+constexpr int kAdamTensors = 4;
+struct AdamTensor {
+  float *theta, *m, *v;
+  const float *grad;
+  uint16_t *theta_b;   // nullable bfloat16 copy
+  int64_t n;
+};
+hipError_t launch_adam_multi(const AdamTensor *t, int count, float lr, float b1, float b2, float eps, float c1,
+                             float c2, hipStream_t st);
 // One predictor step in four launches (arguments and arithmetic in
 // pred_step.h and pred_device.h).
 hipError_t launch_pred_step(const PredStepArgs &a, hipStream_t st);

@@ -17,6 +17,7 @@
 #include "pred_device.h"
 
 #include <algorithm>
+#include <climits>
 
 namespace rtcm {
 namespace {
@@ -446,20 +447,43 @@ __global__ __launch_bounds__(1024) void col_sum_kernel(const float *dZ, int B, i
   if (r == 0 && j < n) db[j] = part[0][c];
 }
 
-// Adam with bias correction; refreshes the bfloat16 copy of the parameters.
-__global__ __launch_bounds__(256) void adam_kernel(float *theta, float *m, float *v, const float *grad,
-                                                   uint16_t *theta_b, int64_t n, float lr, float b1, float b2,
-                                                   float eps, float c1, float c2) {
-  for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
-    const float g = grad[i];
-    const float mi = b1 * m[i] + (1.0f - b1) * g;
-    const float vi = b2 * v[i] + (1.0f - b2) * g * g;
-    m[i] = mi;
-    v[i] = vi;
-    const float t = theta[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
-    theta[i] = t;
-    if (theta_b) theta_b[i] = bf16_bits(t);
-  }
+// Adam with bias correction on element i; refreshes the bfloat16 copy of the parameters.
+__device__ __forceinline__ void adam_element(const AdamTensor &t, int64_t i, float lr, float b1, float b2, float eps,
+                                             float c1, float c2) {
+  const float g = t.grad[i];
+  const float mi = b1 * t.m[i] + (1.0f - b1) * g;
+  const float vi = b2 * t.v[i] + (1.0f - b2) * g * g;
+  t.m[i] = mi;
+  t.v[i] = vi;
+  const float th = t.theta[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  t.theta[i] = th;
+  if (t.theta_b) t.theta_b[i] = bf16_bits(th);
+}
+
+// Adam on several tensors in one launch: workgroups [first[k], first[k + 1]) take
+// tensor k, kAdamChunk consecutive elements each (the choice of tensor is
+// uniform per workgroup).
+constexpr int kAdamChunk = 1024;
+struct AdamSet {
+  AdamTensor t[kAdamTensors];
+  int32_t first[kAdamTensors + 1];
+  int32_t count;
+};
+
+__global__ __launch_bounds__(256) void adam_multi_kernel(AdamSet s, float lr, float b1, float b2, float eps, float c1,
+                                                         float c2) {
+  const int32_t w = (int32_t)blockIdx.x;
+  AdamTensor t = s.t[0];
+  int32_t w0 = 0;
+#pragma unroll
+  for (int k = 1; k < kAdamTensors; ++k)
+    if (k < s.count && w >= s.first[k]) {
+      t = s.t[k];
+      w0 = s.first[k];
+    }
+  const int64_t e0 = (int64_t)(w - w0) * kAdamChunk;
+  for (int64_t i = e0 + threadIdx.x; i < t.n && i < e0 + kAdamChunk; i += 256)
+    adam_element(t, i, lr, b1, b2, eps, c1, c2);
 }
 
 // The predictor step's four launches (arithmetic in pred_device.h): one
@@ -589,9 +613,22 @@ hipError_t launch_col_sum(const float *dZ, int B, int n, float *db, hipStream_t 
   return hipGetLastError();
 }
 
-hipError_t launch_adam(float *theta, float *m, float *v, const float *grad, uint16_t *theta_b, int64_t n, float lr,
-                       float b1, float b2, float eps, float c1, float c2, hipStream_t st) {
-  adam_kernel<<<grid_for(n), 256, 0, st>>>(theta, m, v, grad, theta_b, n, lr, b1, b2, eps, c1, c2);
+hipError_t launch_adam_multi(const AdamTensor *t, int count, float lr, float b1, float b2, float eps, float c1,
+                             float c2, hipStream_t st) {
+  if (count < 1 || count > kAdamTensors) return hipErrorInvalidValue;
+  AdamSet s{};
+  int64_t blocks = 0;
+  for (int k = 0; k < count; ++k) {
+    if (t[k].n < 0) return hipErrorInvalidValue;
+    s.t[k] = t[k];
+    s.first[k] = (int32_t)blocks;
+    blocks += (t[k].n + kAdamChunk - 1) / kAdamChunk;
+    if (blocks > INT32_MAX) return hipErrorInvalidValue;
+  }
+  s.first[count] = (int32_t)blocks;
+  s.count = count;
+  if (blocks == 0) return hipSuccess;
+  adam_multi_kernel<<<(unsigned)blocks, 256, 0, st>>>(s, lr, b1, b2, eps, c1, c2);
   return hipGetLastError();
 }
 
